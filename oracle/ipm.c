@@ -1,0 +1,1041 @@
+/*
+ * CPU FP64 ORACLE -- test infrastructure only (see oracle.h).
+ *
+ * Primal-dual interior-point method for the parametric NLP of Sec. III eq. (1),
+ * in the order of Sec. IV:
+ *   barrier problem (eq. (3)), Lagrangian (eq. (4)), perturbed KKT conditions
+ *   (eq. (5)), Newton system (eq. (6)) reduced to the augmented system (eq. (7))
+ *   by eliminating the bound-multiplier steps, LDL^T with inertia and the
+ *   delta_x / delta_c inertia correction (Sec. IV "Step direction"), and the
+ *   fallback branches of Table I: backtracking filter line search (row 1),
+ *   second-order correction (row 2), tiny-step rule (row 4), hard feasibility
+ *   restoration (row 6, one level) and the monotone barrier update (row 7).
+ * The paper hands the constants and sub-rules of these branches to the IPOPT
+ * paper (Waechter & Biegler 2006); the published defaults are used, listed in
+ * ipmo_opts.
+ *
+ * Everything is dense: the full (n+m) x (n+m) matrix of eq. (7) is assembled
+ * with slacks (and, in restoration, the p/n elastic variables) as ordinary
+ * variables and factored by bk_factor.
+ *
+ * The method is run as a sequence of "passes" so that its state can be saved
+ * and replayed one step at a time (Sec. VI "Correctness"):
+ *   PH_INIT_Y  : least-squares equality multipliers at the current point;
+ *   PH_REGULAR : one iteration on the original problem;
+ *   PH_RESTO   : one iteration on the feasibility-restoration problem.
+ */
+#include <float.h>
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+#include "oracle.h"
+
+void* quad_nlp_new(const ipmo_quad_desc* d, const double* theta, nlp_t* out);
+void quad_nlp_free(void* p);
+void quad_cold_start(const ipmo_quad_desc* d, const double* theta, double* v);
+
+#define EPS DBL_EPSILON
+
+struct solver_s;
+static void grow_buffers(struct solver_s* S, int nv);
+
+/* ------------------------------------------------------------------ */
+/* one barrier-problem iterate (original problem or restoration problem) */
+typedef struct {
+    int n, m;
+    double *x, *y, *zl, *zu; /* zl/zu full length, zero on unbounded components */
+    double mu, tau, dx_last, theta_max, theta_min;
+    int tiny;
+    int nf, fcap;
+    double *fth, *fph;
+    int overflow;
+} sub_t;
+
+/* restoration NLP: min rho sum(p+n) + zeta/2 |D_R (x - x_R)|^2 s.t. c(x) - p + n = 0 */
+typedef struct {
+    nlp_t* P;
+    int n, m;
+    double *xR, *DR2;
+    double zeta, rho;
+    double *xl, *xu;
+    double *cb, *Jb, *Hb;
+} resto_ud;
+
+typedef struct solver_s {
+    nlp_t* P;
+    ipmo_opts o;
+    int phase, status, iter, init_filter;
+    sub_t main, rs;
+    nlp_t RP;
+    resto_ud RU;
+    double theta_R;
+    /* evaluation buffers, sized for the restoration problem */
+    double *g, *c, *J, *Hm, *K, *rhs, *wk, *dx, *dy, *dzl, *dzu, *xt, *ct, *csoc, *gphi, *rx;
+    double *dxs, *dys, *dzls, *dzus;
+    int *perm, *blk;
+    int cap_n;
+    double f;
+    /* statistics */
+    int st_resto_iter, st_soc_try, st_soc_acc, st_fact, st_resto_entries, st_tiny, st_passes;
+    double last_dx, last_dc, last_alpha, last_alpha_z;
+    int last_soc;
+} solver_t;
+
+/* ------------------------------------------------------------------ */
+static void sub_alloc(sub_t* T, int n, int m, int fcap) {
+    T->n = n; T->m = m;
+    T->x = (double*)calloc(n, sizeof(double));
+    T->y = (double*)calloc(m > 0 ? m : 1, sizeof(double));
+    T->zl = (double*)calloc(n, sizeof(double));
+    T->zu = (double*)calloc(n, sizeof(double));
+    T->fcap = fcap;
+    T->fth = (double*)calloc(fcap, sizeof(double));
+    T->fph = (double*)calloc(fcap, sizeof(double));
+    T->nf = 0;
+    T->overflow = 0;
+}
+
+static void sub_free(sub_t* T) {
+    free(T->x); free(T->y); free(T->zl); free(T->zu); free(T->fth); free(T->fph);
+}
+
+/* filter F = {(theta_F, phi_F)}: a point is rejected if theta >= theta_F and phi >= phi_F for
+ * some entry.  Entries dominated by a new entry are dropped (their forbidden region is
+ * contained in the new one), so the semantics do not change. */
+static void filter_add(sub_t* T, double th, double ph) {
+    int w = 0;
+    for (int i = 0; i < T->nf; ++i)
+        if (!(T->fth[i] >= th && T->fph[i] >= ph)) { T->fth[w] = T->fth[i]; T->fph[w] = T->fph[i]; ++w; }
+    T->nf = w;
+    if (T->nf >= T->fcap) { T->overflow = 1; return; }
+    T->fth[T->nf] = th;
+    T->fph[T->nf] = ph;
+    T->nf++;
+}
+
+static int filter_ok(const sub_t* T, double th, double ph) {
+    for (int i = 0; i < T->nf; ++i)
+        if (th >= T->fth[i] && ph >= T->fph[i]) return 0;
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* restoration NLP callbacks */
+static void r_f(void* ud, const double* x, double* out) {
+    resto_ud* R = (resto_ud*)ud;
+    double s = 0, q = 0;
+    for (int i = 0; i < R->m; ++i) s += x[R->n + i] + x[R->n + R->m + i];
+    for (int i = 0; i < R->n; ++i) { double e = x[i] - R->xR[i]; q += R->DR2[i] * e * e; }
+    *out = R->rho * s + 0.5 * R->zeta * q;
+}
+static void r_grad(void* ud, const double* x, double* g) {
+    resto_ud* R = (resto_ud*)ud;
+    for (int i = 0; i < R->n; ++i) g[i] = R->zeta * R->DR2[i] * (x[i] - R->xR[i]);
+    for (int i = 0; i < 2 * R->m; ++i) g[R->n + i] = R->rho;
+}
+static void r_c(void* ud, const double* x, double* c) {
+    resto_ud* R = (resto_ud*)ud;
+    R->P->c(R->P->ud, x, c);
+    for (int i = 0; i < R->m; ++i) c[i] += -x[R->n + i] + x[R->n + R->m + i];
+}
+static void r_jac(void* ud, const double* x, double* J) {
+    resto_ud* R = (resto_ud*)ud;
+    int n = R->n, m = R->m, N = n + 2 * m;
+    R->P->jac(R->P->ud, x, R->Jb);
+    memset(J, 0, (size_t)m * N * sizeof(double));
+    for (int i = 0; i < m; ++i) {
+        memcpy(J + (size_t)i * N, R->Jb + (size_t)i * n, n * sizeof(double));
+        J[(size_t)i * N + n + i] = -1.0;
+        J[(size_t)i * N + n + m + i] = 1.0;
+    }
+}
+static void r_hess(void* ud, const double* x, double objf, const double* y, double* Hm) {
+    resto_ud* R = (resto_ud*)ud;
+    int n = R->n, N = n + 2 * R->m;
+    R->P->hess(R->P->ud, x, 0.0, y, R->Hb);
+    memset(Hm, 0, (size_t)N * N * sizeof(double));
+    for (int i = 0; i < n; ++i) {
+        memcpy(Hm + (size_t)i * N, R->Hb + (size_t)i * n, n * sizeof(double));
+        Hm[(size_t)i * N + i] += objf * R->zeta * R->DR2[i];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+static double dot(int n, const double* a, const double* b) {
+    double s = 0;
+    for (int i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+static double nrm1(int n, const double* a) {
+    double s = 0;
+    for (int i = 0; i < n; ++i) s += fabs(a[i]);
+    return s;
+}
+static double nrmi(int n, const double* a) {
+    double s = 0;
+    for (int i = 0; i < n; ++i) if (fabs(a[i]) > s) s = fabs(a[i]);
+    return s;
+}
+
+/* barrier objective phi_mu (eq. (3)) restricted to the finite bounds; NaN outside the interior */
+static double barrier_obj(const nlp_t* P, const double* x, double f, double mu) {
+    double b = 0;
+    for (int i = 0; i < P->n; ++i) {
+        if (isfinite(P->xl[i])) { double s = x[i] - P->xl[i]; if (!(s > 0)) return NAN; b += log(s); }
+        if (isfinite(P->xu[i])) { double s = P->xu[i] - x[i]; if (!(s > 0)) return NAN; b += log(s); }
+    }
+    return f - mu * b;
+}
+
+/* scaled KKT error E_mu of the perturbed optimality conditions (eq. (5)) with the IPOPT
+ * scaling s_d, s_c (s_max = 100).  g = grad f, c, J at T->x. */
+static double kkt_error(const nlp_t* P, const sub_t* T, const double* g, const double* c, const double* J,
+                        double mu, const ipmo_opts* o, double* wk) {
+    int n = P->n, m = P->m;
+    int nL = 0, nU = 0;
+    double s1 = nrm1(m, T->y), z1 = 0, comp = 0;
+    for (int i = 0; i < n; ++i) wk[i] = g[i] - T->zl[i] + T->zu[i];
+    for (int r = 0; r < m; ++r) {
+        double yr = T->y[r];
+        if (yr == 0.0) continue;
+        const double* Jr = J + (size_t)r * n;
+        for (int i = 0; i < n; ++i) wk[i] += Jr[i] * yr;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (isfinite(P->xl[i])) {
+            nL++; z1 += fabs(T->zl[i]);
+            double e = fabs((T->x[i] - P->xl[i]) * T->zl[i] - mu);
+            if (e > comp) comp = e;
+        }
+        if (isfinite(P->xu[i])) {
+            nU++; z1 += fabs(T->zu[i]);
+            double e = fabs((P->xu[i] - T->x[i]) * T->zu[i] - mu);
+            if (e > comp) comp = e;
+        }
+    }
+    double sd = 1.0, sc = 1.0;
+    if (m + nL + nU > 0) sd = fmax(o->s_max, (s1 + z1) / (double)(m + nL + nU)) / o->s_max;
+    if (nL + nU > 0) sc = fmax(o->s_max, z1 / (double)(nL + nU)) / o->s_max;
+    double e = nrmi(n, wk) / sd;
+    double pr = nrmi(m, c);
+    if (pr > e) e = pr;
+    if (comp / sc > e) e = comp / sc;
+    return e;
+}
+
+/* fraction-to-the-boundary rule on the bounded primal components */
+static double ftb_primal(const nlp_t* P, const double* x, const double* dx, double tau) {
+    double a = 1.0;
+    for (int i = 0; i < P->n; ++i) {
+        if (isfinite(P->xl[i]) && dx[i] < 0) { double t = -tau * (x[i] - P->xl[i]) / dx[i]; if (t < a) a = t; }
+        if (isfinite(P->xu[i]) && dx[i] > 0) { double t = tau * (P->xu[i] - x[i]) / dx[i]; if (t < a) a = t; }
+    }
+    return a;
+}
+static double ftb_dual(const nlp_t* P, const double* zl, const double* zu, const double* dzl,
+                       const double* dzu, double tau) {
+    double a = 1.0;
+    for (int i = 0; i < P->n; ++i) {
+        if (isfinite(P->xl[i]) && dzl[i] < 0) { double t = -tau * zl[i] / dzl[i]; if (t < a) a = t; }
+        if (isfinite(P->xu[i]) && dzu[i] < 0) { double t = -tau * zu[i] / dzu[i]; if (t < a) a = t; }
+    }
+    return a;
+}
+
+/* bound-multiplier steps eliminated from eq. (6) (Sec. IV):
+ *   dz_L = S_L^{-1}(mu e - S_L z_L - Z_L dx),  dz_U = S_U^{-1}(mu e - S_U z_U + Z_U dx) */
+static void dz_recover(const nlp_t* P, const sub_t* T, const double* dx, double* dzl, double* dzu) {
+    for (int i = 0; i < P->n; ++i) {
+        dzl[i] = dzu[i] = 0.0;
+        if (isfinite(P->xl[i])) { double s = T->x[i] - P->xl[i]; dzl[i] = (T->mu - s * T->zl[i] - T->zl[i] * dx[i]) / s; }
+        if (isfinite(P->xu[i])) { double s = P->xu[i] - T->x[i]; dzu[i] = (T->mu - s * T->zu[i] + T->zu[i] * dx[i]) / s; }
+    }
+}
+
+/* assemble the lower triangle of K(delta_x, delta_c) = [[W + Sigma + dx I, A^T], [A, -dc I]] (eq. (7)) */
+static void assemble_K(const nlp_t* P, const sub_t* T, const double* Hm, const double* J, double dxp, double dcp,
+                       double* K) {
+    int n = P->n, m = P->m, N = n + m;
+    for (int i = 0; i < n; ++i) {
+        double* Ki = K + (size_t)i * N;
+        memcpy(Ki, Hm + (size_t)i * n, (i + 1) * sizeof(double));
+        double sig = 0;
+        if (isfinite(P->xl[i])) sig += T->zl[i] / (T->x[i] - P->xl[i]);
+        if (isfinite(P->xu[i])) sig += T->zu[i] / (P->xu[i] - T->x[i]);
+        Ki[i] += sig + dxp;
+    }
+    for (int r = 0; r < m; ++r) {
+        double* Ki = K + (size_t)(n + r) * N;
+        memcpy(Ki, J + (size_t)r * n, n * sizeof(double));
+        memset(Ki + n, 0, (r + 1) * sizeof(double));
+        Ki[n + r] = -dcp;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+enum { R_ACCEPT = 0, R_CONVERGED, R_MAXITER, R_LSFAIL, R_ICFAIL, R_NUMERICAL };
+
+static void eval_point(solver_t* S, const nlp_t* P, const sub_t* T) {
+    P->f(P->ud, T->x, &S->f);
+    P->grad(P->ud, T->x, S->g);
+    P->c(P->ud, T->x, S->c);
+    P->jac(P->ud, T->x, S->J);
+}
+
+static void set_zeta(solver_t* S, const sub_t* T, int is_resto) {
+    if (is_resto) S->RU.zeta = sqrt(T->mu);
+}
+
+/* evaluate c, f, theta = |c|_1 and phi_mu at a trial point; returns 1 if all finite */
+static int trial_eval(const nlp_t* P, const sub_t* T, const double* xt, double* ct, double* th, double* ph) {
+    double f;
+    P->c(P->ud, xt, ct);
+    P->f(P->ud, xt, &f);
+    *th = nrm1(P->m, ct);
+    *ph = barrier_obj(P, xt, f, T->mu);
+    return isfinite(*th) && isfinite(*ph);
+}
+
+/* filter acceptance of a trial (theta_t, phi_t) for step size alpha (Table I row 1). */
+static int acceptable(const sub_t* T, const ipmo_opts* o, double thk, double phk, double gphi, double alpha,
+                      double tht, double pht, int* sw_out, int* arm_out) {
+    if (!(isfinite(tht) && isfinite(pht))) return 0;
+    if (tht > T->theta_max) return 0;
+    int sw = gphi < 0 && alpha * pow(-gphi, o->s_phi) > o->delta_sw * pow(thk, o->s_theta);
+    double slack = 10.0 * EPS * fabs(phk);
+    int arm = (pht - (phk + o->eta_phi * alpha * gphi)) <= slack;
+    int ok;
+    if (sw && thk <= T->theta_min) ok = arm;
+    else ok = (tht <= (1.0 - o->gamma_theta) * thk) || ((pht - (phk - o->gamma_phi * thk)) <= slack);
+    if (!ok) return 0;
+    if (!filter_ok(T, tht, pht)) return 0;
+    *sw_out = sw;
+    *arm_out = arm;
+    return 1;
+}
+
+/* monotone barrier update (Table I row 7): decrease mu while the barrier problem is solved to
+ * kappa_eps * mu, or once after a tiny step; reset the filter on every decrease. */
+static void mu_update(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
+    const ipmo_opts* o = &S->o;
+    double mu_min = o->tol / 10.0;
+    for (;;) {
+        double Emu = kkt_error(P, T, S->g, S->c, S->J, T->mu, o, S->wk);
+        if (!(Emu <= o->kappa_eps * T->mu || T->tiny)) break;
+        T->tiny = 0;
+        double nm = fmax(mu_min, fmin(o->kappa_mu * T->mu, pow(T->mu, o->theta_mu)));
+        if (!(nm < T->mu)) break;
+        T->mu = nm;
+        T->tau = fmax(o->tau_min, 1.0 - T->mu);
+        T->nf = 0;
+        if (is_resto) {                 /* the restoration objective depends on mu through zeta */
+            set_zeta(S, T, 1);
+            P->f(P->ud, T->x, &S->f);
+            P->grad(P->ud, T->x, S->g);
+        }
+    }
+}
+
+/* factor K with the delta_x / delta_c inertia correction; returns 0 on success */
+static int factor_ic(solver_t* S, const nlp_t* P, sub_t* T) {
+    const ipmo_opts* o = &S->o;
+    int n = P->n, m = P->m, N = n + m, in[3];
+    double dxp = 0.0, dcp = 0.0;
+    assemble_K(P, T, S->Hm, S->J, 0.0, 0.0, S->K);
+    bk_factor(N, S->K, S->perm, S->blk, in);
+    S->st_fact++;
+    if (in[0] == n && in[1] == m && in[2] == 0) { S->last_dx = 0; S->last_dc = 0; return 0; }
+    if (in[2] > 0) dcp = o->delta_c_bar * pow(T->mu, o->kappa_c);
+    dxp = (T->dx_last == 0.0) ? o->delta_0 : fmax(o->delta_min, o->kappa_minus * T->dx_last);
+    for (;;) {
+        assemble_K(P, T, S->Hm, S->J, dxp, dcp, S->K);
+        bk_factor(N, S->K, S->perm, S->blk, in);
+        S->st_fact++;
+        if (in[0] == n && in[1] == m && in[2] == 0) {
+            T->dx_last = dxp;
+            S->last_dx = dxp; S->last_dc = dcp;
+            return 0;
+        }
+        if (in[2] > 0 && dcp == 0.0) dcp = o->delta_c_bar * pow(T->mu, o->kappa_c);
+        dxp *= (T->dx_last == 0.0) ? o->kappa_plus_bar : o->kappa_plus;
+        if (dxp > o->delta_max) return 1;
+    }
+}
+
+static void kkt_solve(solver_t* S, int N, double* d) { bk_solve(N, S->K, S->perm, S->blk, d, S->wk); }
+
+/* one iteration of the barrier method on problem P with iterate T */
+static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
+    const ipmo_opts* o = &S->o;
+    int n = P->n, m = P->m, N = n + m;
+    set_zeta(S, T, is_resto);
+    eval_point(S, P, T);
+    double E0 = kkt_error(P, T, S->g, S->c, S->J, 0.0, o, S->wk);
+    if (!isfinite(E0)) return R_NUMERICAL;
+    if (E0 <= o->tol) return R_CONVERGED;
+    if (S->iter >= o->max_iter) return R_MAXITER;
+    mu_update(S, P, T, is_resto);
+    P->hess(P->ud, T->x, 1.0, T->y, S->Hm);
+
+    /* gradient of the barrier objective and the right-hand side of eq. (7) */
+    for (int i = 0; i < n; ++i) {
+        double gp = S->g[i];
+        if (isfinite(P->xl[i])) gp -= T->mu / (T->x[i] - P->xl[i]);
+        if (isfinite(P->xu[i])) gp += T->mu / (P->xu[i] - T->x[i]);
+        S->gphi[i] = gp;
+        S->rx[i] = gp;
+    }
+    for (int r = 0; r < m; ++r) {
+        const double* Jr = S->J + (size_t)r * n;
+        for (int i = 0; i < n; ++i) S->rx[i] += Jr[i] * T->y[r];
+    }
+    if (factor_ic(S, P, T)) return R_ICFAIL;
+    for (int i = 0; i < n; ++i) S->rhs[i] = -S->rx[i];
+    for (int r = 0; r < m; ++r) S->rhs[n + r] = -S->c[r];
+    kkt_solve(S, N, S->rhs);
+    memcpy(S->dx, S->rhs, n * sizeof(double));
+    memcpy(S->dy, S->rhs + n, m * sizeof(double));
+    dz_recover(P, T, S->dx, S->dzl, S->dzu);
+
+    double amax = ftb_primal(P, T->x, S->dx, T->tau);
+    double thk = nrm1(m, S->c);
+    double phk = barrier_obj(P, T->x, S->f, T->mu);
+    double gphi = dot(n, S->gphi, S->dx);
+
+    /* tiny step (Table I row 4): at a nearly feasible point (|c|_inf <= 1e-4), a step that changes
+     * no component by more than 10 eps (relative) is accepted without the line search */
+    double tmax = 0;
+    for (int i = 0; i < n; ++i) { double t = fabs(S->dx[i]) / (1.0 + fabs(T->x[i])); if (t > tmax) tmax = t; }
+    const double *ady = S->dy, *adzl = S->dzl, *adzu = S->dzu;
+    double ap = amax;
+    int augment = 0, accepted = 0;
+    S->last_soc = 0;
+    if (tmax < 10.0 * EPS && nrmi(m, S->c) <= 1e-4) {
+        for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + ap * S->dx[i];
+        T->tiny = 1;
+        S->st_tiny++;
+        accepted = 1;
+    } else {
+        /* backtracking filter line search (Table I rows 1-2) */
+        double amin;
+        if (gphi < 0) {
+            double t = fmin(o->gamma_theta, o->gamma_phi * thk / (-gphi));
+            if (thk <= T->theta_min) t = fmin(t, o->delta_sw * pow(thk, o->s_theta) / pow(-gphi, o->s_phi));
+            amin = o->gamma_alpha * t;
+        } else {
+            amin = o->gamma_alpha * o->gamma_theta;
+        }
+        double alpha = amax;
+        for (int l = 0;; ++l) {
+            if (alpha < amin) return R_LSFAIL;
+            for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + alpha * S->dx[i];
+            double tht, pht;
+            int fin = trial_eval(P, T, S->xt, S->ct, &tht, &pht);
+            int sw = 0, arm = 0;
+            if (acceptable(T, o, thk, phk, gphi, alpha, tht, pht, &sw, &arm)) {
+                ap = alpha;
+                augment = !(sw && arm);
+                accepted = 1;
+                break;
+            }
+            if (l == 0 && fin && o->max_soc > 0 && tht >= thk) {
+                /* second-order correction: c_soc <- a_soc c_soc + c(x_trial), same factor */
+                double asoc = alpha, th_old = 0;
+                memcpy(S->csoc, S->c, m * sizeof(double));
+                for (int p = 0; p < o->max_soc; ++p) {
+                    if (p > 0 && !(tht <= o->kappa_soc * th_old)) break;
+                    th_old = tht;
+                    for (int r = 0; r < m; ++r) S->csoc[r] = asoc * S->csoc[r] + S->ct[r];
+                    for (int i = 0; i < n; ++i) S->rhs[i] = -S->rx[i];
+                    for (int r = 0; r < m; ++r) S->rhs[n + r] = -S->csoc[r];
+                    kkt_solve(S, N, S->rhs);
+                    S->st_soc_try++;
+                    memcpy(S->dxs, S->rhs, n * sizeof(double));
+                    memcpy(S->dys, S->rhs + n, m * sizeof(double));
+                    asoc = ftb_primal(P, T->x, S->dxs, T->tau);
+                    for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + asoc * S->dxs[i];
+                    fin = trial_eval(P, T, S->xt, S->ct, &tht, &pht);
+                    /* acceptance uses the original step size and direction derivative */
+                    if (acceptable(T, o, thk, phk, gphi, alpha, tht, pht, &sw, &arm)) {
+                        dz_recover(P, T, S->dxs, S->dzls, S->dzus);
+                        ady = S->dys; adzl = S->dzls; adzu = S->dzus;
+                        ap = asoc;
+                        augment = !(sw && arm);
+                        accepted = 1;
+                        S->st_soc_acc++;
+                        S->last_soc = 1;
+                        break;
+                    }
+                    if (!fin) break;
+                }
+                if (accepted) break;
+            }
+            alpha *= 0.5;
+        }
+    }
+    (void)accepted;
+    /* accept: primal and equality multipliers with the primal step, bound multipliers with the
+     * dual fraction-to-boundary step, then the kappa_sigma safeguard */
+    double az = ftb_dual(P, T->zl, T->zu, adzl, adzu, T->tau);
+    S->last_alpha = ap;
+    S->last_alpha_z = az;
+    if (augment) filter_add(T, (1.0 - o->gamma_theta) * thk, phk - o->gamma_phi * thk);
+    for (int r = 0; r < m; ++r) T->y[r] += ap * ady[r];
+    for (int i = 0; i < n; ++i) T->x[i] = S->xt[i];
+    for (int i = 0; i < n; ++i) {
+        if (isfinite(P->xl[i])) {
+            double z = T->zl[i] + az * adzl[i], s = T->x[i] - P->xl[i];
+            T->zl[i] = fmax(fmin(z, o->kappa_sigma * T->mu / s), T->mu / (o->kappa_sigma * s));
+        }
+        if (isfinite(P->xu[i])) {
+            double z = T->zu[i] + az * adzu[i], s = P->xu[i] - T->x[i];
+            T->zu[i] = fmax(fmin(z, o->kappa_sigma * T->mu / s), T->mu / (o->kappa_sigma * s));
+        }
+    }
+    S->iter++;
+    if (is_resto) S->st_resto_iter++;
+    return R_ACCEPT;
+}
+
+/* ------------------------------------------------------------------ */
+/* least-squares equality multipliers: [[I, A^T], [A, 0]] [d; y] = -[grad f - z_L + z_U; 0] */
+static void init_y(solver_t* S) {
+    nlp_t* P = S->P;
+    sub_t* T = &S->main;
+    int n = P->n, m = P->m, N = n + m, in[3];
+    eval_point(S, P, T);
+    memset(S->K, 0, (size_t)N * N * sizeof(double));
+    for (int i = 0; i < n; ++i) S->K[(size_t)i * N + i] = 1.0;
+    for (int r = 0; r < m; ++r) memcpy(S->K + (size_t)(n + r) * N, S->J + (size_t)r * n, n * sizeof(double));
+    for (int i = 0; i < n; ++i) S->rhs[i] = -(S->g[i] - T->zl[i] + T->zu[i]);
+    for (int r = 0; r < m; ++r) S->rhs[n + r] = 0.0;
+    bk_factor(N, S->K, S->perm, S->blk, in);
+    kkt_solve(S, N, S->rhs);
+    double ym = nrmi(m, S->rhs + n);
+    if (!(ym <= S->o.lam_max)) memset(T->y, 0, m * sizeof(double));
+    else memcpy(T->y, S->rhs + n, m * sizeof(double));
+    if (S->init_filter) {
+        double th0 = nrm1(m, S->c);
+        T->theta_max = 1e4 * fmax(1.0, th0);
+        T->theta_min = 1e-4 * fmax(1.0, th0);
+        T->nf = 0;
+        S->init_filter = 0;
+    }
+}
+
+/* push a starting point into the bounds and set z = 1, mu = mu_0 */
+static void init_point(const nlp_t* P, const ipmo_opts* o, sub_t* T, const double* x0) {
+    for (int i = 0; i < P->n; ++i) {
+        double x = x0[i], l = P->xl[i], u = P->xu[i];
+        if (isfinite(l) && isfinite(u)) {
+            double pl = fmin(o->kappa1 * fmax(1.0, fabs(l)), o->kappa2 * (u - l));
+            double pu = fmin(o->kappa1 * fmax(1.0, fabs(u)), o->kappa2 * (u - l));
+            x = fmax(x, l + pl);
+            x = fmin(x, u - pu);
+        } else if (isfinite(l)) {
+            x = fmax(x, l + o->kappa1 * fmax(1.0, fabs(l)));
+        } else if (isfinite(u)) {
+            x = fmin(x, u - o->kappa1 * fmax(1.0, fabs(u)));
+        }
+        T->x[i] = x;
+        T->zl[i] = isfinite(l) ? 1.0 : 0.0;
+        T->zu[i] = isfinite(u) ? 1.0 : 0.0;
+    }
+    memset(T->y, 0, (P->m > 0 ? P->m : 1) * sizeof(double));
+    T->mu = o->mu_init;
+    T->tau = fmax(o->tau_min, 1.0 - T->mu);
+    T->dx_last = 0.0;
+    T->tiny = 0;
+    T->nf = 0;
+    T->theta_max = T->theta_min = 0.0;
+}
+
+/* enter feasibility restoration (Table I row 6) from the main iterate */
+static int resto_enter(solver_t* S) {
+    const ipmo_opts* o = &S->o;
+    nlp_t* P = S->P;
+    sub_t* T = &S->main;
+    sub_t* R = &S->rs;
+    int n = P->n, m = P->m;
+    grow_buffers(S, n + 2 * m);
+    eval_point(S, P, T);
+    double thk = nrm1(m, S->c);
+    double phk = barrier_obj(P, T->x, S->f, T->mu);
+    if (thk <= o->tol) return 1;           /* no infeasibility to remove */
+    filter_add(T, (1.0 - o->gamma_theta) * thk, phk - o->gamma_phi * thk);
+    S->theta_R = thk;
+    double muR = fmax(T->mu, nrmi(m, S->c));
+    double rho = o->rho_resto;
+    memcpy(S->RU.xR, T->x, n * sizeof(double));
+    for (int i = 0; i < n; ++i) {
+        double d = fmin(1.0, 1.0 / fabs(T->x[i]));
+        S->RU.DR2[i] = d * d;
+    }
+    memcpy(R->x, T->x, n * sizeof(double));
+    for (int r = 0; r < m; ++r) {
+        double c = S->c[r];
+        double a = (muR - rho * c) / (2.0 * rho);
+        double nn = a + sqrt(a * a + muR * c / (2.0 * rho));
+        double pp = c + nn;
+        R->x[n + r] = pp;
+        R->x[n + m + r] = nn;
+        R->zl[n + r] = muR / pp;
+        R->zl[n + m + r] = muR / nn;
+        R->zu[n + r] = R->zu[n + m + r] = 0.0;
+    }
+    for (int i = 0; i < n; ++i) {
+        R->zl[i] = isfinite(P->xl[i]) ? fmin(rho, T->zl[i]) : 0.0;
+        R->zu[i] = isfinite(P->xu[i]) ? fmin(rho, T->zu[i]) : 0.0;
+    }
+    memset(R->y, 0, (m > 0 ? m : 1) * sizeof(double));
+    R->mu = muR;
+    R->tau = fmax(o->tau_min, 1.0 - muR);
+    R->dx_last = 0.0;
+    R->tiny = 0;
+    R->nf = 0;
+    R->overflow = 0;
+    S->RP.c(S->RP.ud, R->x, S->ct);
+    double th0 = nrm1(m, S->ct);
+    R->theta_max = 1e4 * fmax(1.0, th0);
+    R->theta_min = 1e-4 * fmax(1.0, th0);
+    S->st_resto_entries++;
+    return 0;
+}
+
+/* after an accepted restoration step: return to the original problem when the point is
+ * acceptable to the original filter and theta <= kappa_resto theta(x_R) */
+static int resto_try_exit(solver_t* S) {
+    const ipmo_opts* o = &S->o;
+    nlp_t* P = S->P;
+    sub_t* T = &S->main;
+    sub_t* R = &S->rs;
+    int n = P->n, m = P->m;
+    double f;
+    P->c(P->ud, R->x, S->ct);
+    P->f(P->ud, R->x, &f);
+    double th = nrm1(m, S->ct);
+    double ph = barrier_obj(P, R->x, f, T->mu);
+    if (!(isfinite(th) && isfinite(ph))) return 0;
+    if (!(th <= o->kappa_resto * S->theta_R)) return 0;
+    if (!filter_ok(T, th, ph)) return 0;
+    memcpy(T->x, R->x, n * sizeof(double));
+    double zmax = 0;
+    for (int i = 0; i < n; ++i) {
+        T->zl[i] = R->zl[i];
+        T->zu[i] = R->zu[i];
+        if (T->zl[i] > zmax) zmax = T->zl[i];
+        if (T->zu[i] > zmax) zmax = T->zu[i];
+    }
+    if (zmax > o->bound_mult_reset)
+        for (int i = 0; i < n; ++i) {
+            T->zl[i] = isfinite(P->xl[i]) ? 1.0 : 0.0;
+            T->zu[i] = isfinite(P->xu[i]) ? 1.0 : 0.0;
+        }
+    T->tiny = 0;
+    return 1;
+}
+
+/* one pass of the phase machine */
+static void solver_pass(solver_t* S) {
+    S->st_passes++;
+    if (S->phase == PH_DONE) return;
+    if (S->phase == PH_INIT_Y) {
+        init_y(S);
+        S->phase = PH_REGULAR;
+        return;
+    }
+    if (S->phase == PH_REGULAR) {
+        int r = core_iter(S, S->P, &S->main, 0);
+        if (S->main.overflow) { S->status = ST_FILTER_OVERFLOW; S->phase = PH_DONE; return; }
+        switch (r) {
+        case R_ACCEPT: return;
+        case R_CONVERGED: S->status = ST_CONVERGED; S->phase = PH_DONE; return;
+        case R_MAXITER: S->status = ST_MAX_ITER; S->phase = PH_DONE; return;
+        case R_NUMERICAL: S->status = ST_NUMERICAL; S->phase = PH_DONE; return;
+        default:
+            if (resto_enter(S)) { S->status = ST_RESTO_FAILED; S->phase = PH_DONE; return; }
+            S->phase = PH_RESTO;
+            return;
+        }
+    }
+    if (S->phase == PH_RESTO) {
+        int r = core_iter(S, &S->RP, &S->rs, 1);
+        if (S->rs.overflow || S->main.overflow) { S->status = ST_FILTER_OVERFLOW; S->phase = PH_DONE; return; }
+        switch (r) {
+        case R_ACCEPT:
+            if (resto_try_exit(S)) S->phase = PH_INIT_Y;
+            return;
+        case R_CONVERGED: S->status = ST_INFEASIBLE; S->phase = PH_DONE; return;
+        case R_MAXITER: S->status = ST_MAX_ITER; S->phase = PH_DONE; return;
+        case R_NUMERICAL: S->status = ST_NUMERICAL; S->phase = PH_DONE; return;
+        default: S->status = ST_RESTO_FAILED; S->phase = PH_DONE; return;
+        }
+    }
+}
+
+
+/* evaluation and KKT buffers for a problem with nv variables and m constraints */
+static void grow_buffers(solver_t* S, int nv) {
+    if (nv <= S->cap_n) return;
+    int m = S->P->m, NK = nv + m;
+    free(S->g); free(S->J); free(S->Hm); free(S->K); free(S->rhs); free(S->wk); free(S->dx);
+    free(S->dzl); free(S->dzu); free(S->dxs); free(S->dzls); free(S->dzus); free(S->xt); free(S->gphi);
+    free(S->rx); free(S->perm); free(S->blk);
+    free(S->c); free(S->dy); free(S->dys); free(S->ct); free(S->csoc);
+    S->g = (double*)calloc(nv, sizeof(double));
+    S->J = (double*)calloc((size_t)(m + 1) * nv, sizeof(double));
+    S->Hm = (double*)calloc((size_t)nv * nv, sizeof(double));
+    S->K = (double*)calloc((size_t)NK * NK, sizeof(double));
+    S->rhs = (double*)calloc(NK, sizeof(double));
+    S->wk = (double*)calloc(NK, sizeof(double));
+    S->dx = (double*)calloc(nv, sizeof(double));
+    S->dzl = (double*)calloc(nv, sizeof(double));
+    S->dzu = (double*)calloc(nv, sizeof(double));
+    S->dxs = (double*)calloc(nv, sizeof(double));
+    S->dzls = (double*)calloc(nv, sizeof(double));
+    S->dzus = (double*)calloc(nv, sizeof(double));
+    S->xt = (double*)calloc(nv, sizeof(double));
+    S->gphi = (double*)calloc(nv, sizeof(double));
+    S->rx = (double*)calloc(nv, sizeof(double));
+    S->perm = (int*)calloc(NK, sizeof(int));
+    S->blk = (int*)calloc(NK, sizeof(int));
+    S->c = (double*)calloc(m + 1, sizeof(double));
+    S->dy = (double*)calloc(m + 1, sizeof(double));
+    S->dys = (double*)calloc(m + 1, sizeof(double));
+    S->ct = (double*)calloc(m + 1, sizeof(double));
+    S->csoc = (double*)calloc(m + 1, sizeof(double));
+    S->cap_n = nv;
+}
+
+/* ------------------------------------------------------------------ */
+static solver_t* solver_new(nlp_t* P, const ipmo_opts* o, const double* x0) {
+    solver_t* S = (solver_t*)calloc(1, sizeof(solver_t));
+    S->P = P;
+    S->o = *o;
+    int n = P->n, m = P->m;
+    int NR = n + 2 * m;                 /* restoration variables */
+    sub_alloc(&S->main, n, m, o->filter_cap);
+    sub_alloc(&S->rs, NR, m, o->filter_cap);
+    S->cap_n = 0;
+    grow_buffers(S, n);                 /* grown to the restoration size on first entry */
+    /* restoration NLP */
+    resto_ud* U = &S->RU;
+    U->P = P; U->n = n; U->m = m; U->rho = o->rho_resto;
+    U->xR = (double*)calloc(n, sizeof(double));
+    U->DR2 = (double*)calloc(n, sizeof(double));
+    U->xl = (double*)calloc(NR, sizeof(double));
+    U->xu = (double*)calloc(NR, sizeof(double));
+    U->Jb = (double*)calloc((size_t)(m + 1) * n, sizeof(double));
+    U->Hb = (double*)calloc((size_t)n * n, sizeof(double));
+    for (int i = 0; i < n; ++i) { U->xl[i] = P->xl[i]; U->xu[i] = P->xu[i]; }
+    for (int i = n; i < NR; ++i) { U->xl[i] = 0.0; U->xu[i] = INFINITY; }
+    S->RP.n = NR; S->RP.m = m; S->RP.xl = U->xl; S->RP.xu = U->xu; S->RP.ud = U;
+    S->RP.f = r_f; S->RP.grad = r_grad; S->RP.c = r_c; S->RP.jac = r_jac; S->RP.hess = r_hess;
+    init_point(P, o, &S->main, x0);
+    S->phase = PH_INIT_Y;
+    S->status = ST_RUNNING;
+    S->init_filter = 1;
+    return S;
+}
+
+static void solver_free(solver_t* S) {
+    if (!S) return;
+    sub_free(&S->main); sub_free(&S->rs);
+    free(S->g); free(S->c); free(S->J); free(S->Hm); free(S->K); free(S->rhs); free(S->wk);
+    free(S->dx); free(S->dy); free(S->dzl); free(S->dzu); free(S->dxs); free(S->dys); free(S->dzls);
+    free(S->dzus); free(S->xt); free(S->ct); free(S->csoc); free(S->gphi); free(S->rx);
+    free(S->perm); free(S->blk);
+    free(S->RU.xR); free(S->RU.DR2); free(S->RU.xl); free(S->RU.xu); free(S->RU.Jb); free(S->RU.Hb);
+    free(S);
+}
+
+static void solver_run(solver_t* S) {
+    while (S->phase != PH_DONE) solver_pass(S);
+}
+
+/* =================================================================== */
+/* exported C ABI (host pointers only)                                  */
+/* =================================================================== */
+void ipmo_default_opts(ipmo_opts* o) {
+    o->tol = 1e-8; o->max_iter = 1000; o->mu_init = 0.1; o->kappa_eps = 10.0; o->kappa_mu = 0.2;
+    o->theta_mu = 1.5; o->tau_min = 0.99; o->kappa1 = 1e-2; o->kappa2 = 1e-2; o->lam_max = 1e3;
+    o->s_max = 100.0; o->delta_min = 1e-20; o->delta_0 = 1e-4; o->delta_max = 1e40;
+    o->delta_c_bar = 1e-8; o->kappa_c = 0.25; o->kappa_minus = 1.0 / 3.0; o->kappa_plus = 8.0;
+    o->kappa_plus_bar = 100.0; o->gamma_theta = 1e-5; o->gamma_phi = 1e-8; o->delta_sw = 1.0;
+    o->s_theta = 1.1; o->s_phi = 2.3; o->eta_phi = 1e-8; o->gamma_alpha = 0.05; o->max_soc = 4;
+    o->kappa_soc = 0.99; o->kappa_sigma = 1e10; o->rho_resto = 1000.0; o->kappa_resto = 0.9;
+    o->bound_mult_reset = 1e3; o->filter_cap = 128;
+}
+
+int ipmo_sizeof_opts(void) { return (int)sizeof(ipmo_opts); }
+int ipmo_sizeof_desc(void) { return (int)sizeof(ipmo_quad_desc); }
+
+int ipmo_bk_factor(int n, double* A, int* perm, int* blk, int* inertia) { return bk_factor(n, A, perm, blk, inertia); }
+void ipmo_bk_solve(int n, const double* F, const int* perm, const int* blk, double* b) {
+    double* w = (double*)malloc((n > 0 ? n : 1) * sizeof(double));
+    bk_solve(n, F, perm, blk, b, w);
+    free(w);
+}
+
+/* outputs of one solve */
+typedef struct {
+    double* x; double* y; double* zl; double* zu; double* obj; double* kkt; int32_t* status; int32_t* iters;
+    int32_t* stats; /* 8 ints per instance */
+} outs_t;
+
+static void write_outputs(solver_t* S, int idx, const outs_t* O) {
+    nlp_t* P = S->P;
+    int n = P->n, m = P->m;
+    sub_t* T = &S->main;
+    if (O->x) memcpy(O->x + (size_t)idx * n, T->x, n * sizeof(double));
+    if (O->y) memcpy(O->y + (size_t)idx * m, T->y, m * sizeof(double));
+    if (O->zl) memcpy(O->zl + (size_t)idx * n, T->zl, n * sizeof(double));
+    if (O->zu) memcpy(O->zu + (size_t)idx * n, T->zu, n * sizeof(double));
+    if (O->obj || O->kkt) {
+        eval_point(S, P, T);
+        if (O->obj) O->obj[idx] = S->f;
+        if (O->kkt) O->kkt[idx] = kkt_error(P, T, S->g, S->c, S->J, 0.0, &S->o, S->wk);
+    }
+    if (O->status) O->status[idx] = S->status;
+    if (O->iters) O->iters[idx] = S->iter;
+    if (O->stats) {
+        int32_t* s = O->stats + (size_t)idx * 8;
+        s[0] = S->iter; s[1] = S->st_resto_iter; s[2] = S->st_soc_try; s[3] = S->st_soc_acc;
+        s[4] = S->st_fact; s[5] = S->st_resto_entries; s[6] = S->st_tiny; s[7] = S->st_passes;
+    }
+}
+
+typedef struct {
+    const ipmo_quad_desc* d;
+    const ipmo_opts* o;
+    int n_inst, n_theta, n;
+    const double* theta;
+    const double* warm_x;
+    const double* warm_y;
+    outs_t O;
+    int next;
+    pthread_mutex_t lock;
+} batch_t;
+
+static void solve_one_quad(batch_t* B, int i) {
+    nlp_t P;
+    const double* th = B->theta + (size_t)i * B->n_theta;
+    void* Q = quad_nlp_new(B->d, th, &P);
+    double* x0 = (double*)malloc(P.n * sizeof(double));
+    if (B->warm_x) memcpy(x0, B->warm_x + (size_t)i * P.n, P.n * sizeof(double));
+    else quad_cold_start(B->d, th, x0);
+    solver_t* S = solver_new(&P, B->o, x0);
+    solver_run(S);
+    write_outputs(S, i, &B->O);
+    solver_free(S);
+    free(x0);
+    quad_nlp_free(Q);
+}
+
+static void* batch_worker(void* arg) {
+    batch_t* B = (batch_t*)arg;
+    for (;;) {
+        pthread_mutex_lock(&B->lock);
+        int i = B->next++;
+        pthread_mutex_unlock(&B->lock);
+        if (i >= B->n_inst) break;
+        solve_one_quad(B, i);
+    }
+    return NULL;
+}
+
+static int desc_n_theta(const ipmo_quad_desc* d) {
+    if (d->family == 0) return 16 + 4 * d->n_obs;
+    if (d->family == 1) return 15 + 4 * d->n_obs;
+    return 16 * d->n_agents;
+}
+
+/* Solve n_inst quadrotor NMPC instances (cold start unless warm_x is given), threads workers. */
+int ipmo_solve_quad(const ipmo_quad_desc* d, const ipmo_opts* o, int n_inst, const double* theta,
+                    const double* warm_x, int threads, double* x, double* y, double* zl, double* zu,
+                    double* obj, double* kkt, int32_t* status, int32_t* iters, int32_t* stats) {
+    batch_t B;
+    memset(&B, 0, sizeof(B));
+    B.d = d; B.o = o; B.n_inst = n_inst; B.n_theta = desc_n_theta(d); B.theta = theta;
+    B.warm_x = warm_x;
+    B.O.x = x; B.O.y = y; B.O.zl = zl; B.O.zu = zu; B.O.obj = obj; B.O.kkt = kkt;
+    B.O.status = status; B.O.iters = iters; B.O.stats = stats;
+    pthread_mutex_init(&B.lock, NULL);
+    if (threads < 1) threads = 1;
+    if (threads > n_inst) threads = n_inst;
+    pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (threads > 0 ? threads : 1));
+    for (int t = 0; t < threads; ++t) pthread_create(&th[t], NULL, batch_worker, &B);
+    for (int t = 0; t < threads; ++t) pthread_join(th[t], NULL);
+    free(th);
+    pthread_mutex_destroy(&B.lock);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* handle API: pass-by-pass stepping and flat state export/import for the
+ * one-step replay test (Sec. VI "Correctness") */
+typedef struct {
+    nlp_t P;
+    void* Q;          /* quad user data, or NULL for a generic problem */
+    solver_t* S;
+} handle_t;
+
+void* ipmo_create_quad(const ipmo_quad_desc* d, const ipmo_opts* o, const double* theta, const double* x0_or_null) {
+    handle_t* Hd = (handle_t*)calloc(1, sizeof(handle_t));
+    Hd->Q = quad_nlp_new(d, theta, &Hd->P);
+    double* x0 = (double*)malloc(Hd->P.n * sizeof(double));
+    if (x0_or_null) memcpy(x0, x0_or_null, Hd->P.n * sizeof(double));
+    else quad_cold_start(d, theta, x0);
+    Hd->S = solver_new(&Hd->P, o, x0);
+    free(x0);
+    return Hd;
+}
+
+/* generic problem from callbacks; xl/xu are copied */
+void* ipmo_create_generic(int n, int m, const double* xl, const double* xu,
+                          void (*f)(void*, const double*, double*), void (*grad)(void*, const double*, double*),
+                          void (*c)(void*, const double*, double*), void (*jac)(void*, const double*, double*),
+                          void (*hess)(void*, const double*, double, const double*, double*),
+                          const ipmo_opts* o, const double* x0) {
+    handle_t* Hd = (handle_t*)calloc(1, sizeof(handle_t));
+    double* l = (double*)malloc((n > 0 ? n : 1) * sizeof(double));
+    double* u = (double*)malloc((n > 0 ? n : 1) * sizeof(double));
+    memcpy(l, xl, n * sizeof(double));
+    memcpy(u, xu, n * sizeof(double));
+    Hd->P.n = n; Hd->P.m = m; Hd->P.xl = l; Hd->P.xu = u; Hd->P.ud = NULL;
+    Hd->P.f = f; Hd->P.grad = grad; Hd->P.c = c; Hd->P.jac = jac; Hd->P.hess = hess;
+    Hd->S = solver_new(&Hd->P, o, x0);
+    return Hd;
+}
+
+void ipmo_destroy(void* h) {
+    handle_t* Hd = (handle_t*)h;
+    if (!Hd) return;
+    solver_free(Hd->S);
+    if (Hd->Q) quad_nlp_free(Hd->Q);
+    else { free((void*)Hd->P.xl); free((void*)Hd->P.xu); }
+    free(Hd);
+}
+
+int ipmo_pass(void* h) { handle_t* Hd = (handle_t*)h; solver_pass(Hd->S); return Hd->S->phase; }
+int ipmo_run(void* h) { handle_t* Hd = (handle_t*)h; solver_run(Hd->S); return Hd->S->status; }
+int ipmo_phase(void* h) { return ((handle_t*)h)->S->phase; }
+int ipmo_status(void* h) { return ((handle_t*)h)->S->status; }
+int ipmo_iter(void* h) { return ((handle_t*)h)->S->iter; }
+
+void ipmo_outputs(void* h, double* x, double* y, double* zl, double* zu, double* obj, double* kkt,
+                  int32_t* status, int32_t* iters, int32_t* stats) {
+    handle_t* Hd = (handle_t*)h;
+    outs_t O = {x, y, zl, zu, obj, kkt, status, iters, stats};
+    write_outputs(Hd->S, 0, &O);
+}
+
+/* last pass diagnostics: [delta_x, delta_c, alpha_primal, alpha_dual, soc_accepted, mu, tau, nf] */
+void ipmo_last_info(void* h, double* out) {
+    solver_t* S = ((handle_t*)h)->S;
+    sub_t* T = S->phase == PH_RESTO ? &S->rs : &S->main;
+    out[0] = S->last_dx; out[1] = S->last_dc; out[2] = S->last_alpha; out[3] = S->last_alpha_z;
+    out[4] = S->last_soc; out[5] = T->mu; out[6] = T->tau; out[7] = T->nf;
+}
+
+/* Flat state (FP64), field order:
+ *   header[16] = phase, iter, status, init_filter, theta_R, 0...
+ *   main sub-state  : mu, tau, dx_last, theta_max, theta_min, tiny, nf, 0 | x[n] y[m] zl[n] zu[n] | fth[cap] fph[cap]
+ *   resto sub-state : same with n_R = n + 2m variables
+ *   x_R[n], DR2[n]                                                              */
+static int sub_len(const sub_t* T) { return 8 + 3 * T->n + T->m + 2 * T->fcap; }
+
+int ipmo_state_len(void* h) {
+    solver_t* S = ((handle_t*)h)->S;
+    return 16 + sub_len(&S->main) + sub_len(&S->rs) + 2 * S->P->n;
+}
+
+static double* sub_put(const sub_t* T, double* p) {
+    p[0] = T->mu; p[1] = T->tau; p[2] = T->dx_last; p[3] = T->theta_max; p[4] = T->theta_min;
+    p[5] = T->tiny; p[6] = T->nf; p[7] = 0; p += 8;
+    memcpy(p, T->x, T->n * sizeof(double)); p += T->n;
+    memcpy(p, T->y, T->m * sizeof(double)); p += T->m;
+    memcpy(p, T->zl, T->n * sizeof(double)); p += T->n;
+    memcpy(p, T->zu, T->n * sizeof(double)); p += T->n;
+    for (int i = 0; i < T->fcap; ++i) p[i] = i < T->nf ? T->fth[i] : 0.0;
+    p += T->fcap;
+    for (int i = 0; i < T->fcap; ++i) p[i] = i < T->nf ? T->fph[i] : 0.0;
+    return p + T->fcap;
+}
+static const double* sub_get(sub_t* T, const double* p) {
+    T->mu = p[0]; T->tau = p[1]; T->dx_last = p[2]; T->theta_max = p[3]; T->theta_min = p[4];
+    T->tiny = (int)p[5]; T->nf = (int)p[6]; p += 8;
+    memcpy(T->x, p, T->n * sizeof(double)); p += T->n;
+    memcpy(T->y, p, T->m * sizeof(double)); p += T->m;
+    memcpy(T->zl, p, T->n * sizeof(double)); p += T->n;
+    memcpy(T->zu, p, T->n * sizeof(double)); p += T->n;
+    memcpy(T->fth, p, T->fcap * sizeof(double)); p += T->fcap;
+    memcpy(T->fph, p, T->fcap * sizeof(double));
+    return p + T->fcap;
+}
+
+void ipmo_state_get(void* h, double* out) {
+    solver_t* S = ((handle_t*)h)->S;
+    memset(out, 0, 16 * sizeof(double));
+    out[0] = S->phase; out[1] = S->iter; out[2] = S->status; out[3] = S->init_filter; out[4] = S->theta_R;
+    double* p = sub_put(&S->main, out + 16);
+    p = sub_put(&S->rs, p);
+    memcpy(p, S->RU.xR, S->P->n * sizeof(double)); p += S->P->n;
+    memcpy(p, S->RU.DR2, S->P->n * sizeof(double));
+}
+
+void ipmo_state_set(void* h, const double* in) {
+    solver_t* S = ((handle_t*)h)->S;
+    S->phase = (int)in[0]; S->iter = (int)in[1]; S->status = (int)in[2]; S->init_filter = (int)in[3];
+    S->theta_R = in[4];
+    const double* p = sub_get(&S->main, in + 16);
+    p = sub_get(&S->rs, p);
+    memcpy(S->RU.xR, p, S->P->n * sizeof(double)); p += S->P->n;
+    memcpy(S->RU.DR2, p, S->P->n * sizeof(double));
+}
+
+/* E_mu of the original problem at an arbitrary primal-dual point (used to re-check GPU results) */
+double ipmo_quad_kkt_error(const ipmo_quad_desc* d, const ipmo_opts* o, const double* theta, const double* x,
+                           const double* y, const double* zl, const double* zu, double mu) {
+    nlp_t P;
+    void* Q = quad_nlp_new(d, theta, &P);
+    sub_t T;
+    T.n = P.n; T.m = P.m;
+    T.x = (double*)x; T.y = (double*)y; T.zl = (double*)zl; T.zu = (double*)zu;
+    double* g = (double*)malloc(P.n * sizeof(double));
+    double* c = (double*)malloc((P.m + 1) * sizeof(double));
+    double* J = (double*)malloc((size_t)(P.m + 1) * P.n * sizeof(double));
+    double* wk = (double*)malloc(P.n * sizeof(double));
+    P.grad(P.ud, x, g);
+    P.c(P.ud, x, c);
+    P.jac(P.ud, x, J);
+    double e = kkt_error(&P, &T, g, c, J, mu, o, wk);
+    free(g); free(c); free(J); free(wk);
+    quad_nlp_free(Q);
+    return e;
+}
+
+/* Newton direction of the last regular pass (dx[n], dy[m], dzl[n], dzu[n]) and the gradient of
+ * the barrier objective used for it (for the eq. (6) == eq. (7) + elimination invariant test) */
+void ipmo_last_step(void* h, double* dx, double* dy, double* dzl, double* dzu) {
+    solver_t* S = ((handle_t*)h)->S;
+    int n = S->P->n, m = S->P->m;
+    memcpy(dx, S->dx, n * sizeof(double));
+    memcpy(dy, S->dy, m * sizeof(double));
+    memcpy(dzl, S->dzl, n * sizeof(double));
+    memcpy(dzu, S->dzu, n * sizeof(double));
+}
+
+/* f, grad f, c, dense Jacobian (m x n) and dense Hessian of objf f + y^T c at v (any may be NULL) */
+void ipmo_quad_eval(const ipmo_quad_desc* d, const double* theta, const double* v, const double* y, double objf,
+                    double* f, double* g, double* c, double* J, double* Hm) {
+    nlp_t P;
+    void* Q = quad_nlp_new(d, theta, &P);
+    if (f) P.f(P.ud, v, f);
+    if (g) P.grad(P.ud, v, g);
+    if (c) P.c(P.ud, v, c);
+    if (J) P.jac(P.ud, v, J);
+    if (Hm) P.hess(P.ud, v, objf, y, Hm);
+    quad_nlp_free(Q);
+}
