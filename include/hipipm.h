@@ -1,0 +1,180 @@
+/*
+ * hipipm -- batched primal-dual interior-point NLP solver for one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libhipipm.so.  The library solves batches of the parametric NLP
+ *     min_x f(x, theta)  s.t.  c(x, theta) = 0,  x_L <= x <= x_U           (Sec. III, eq. (1))
+ * whose instances share f, c and the bounds and differ only in theta (eq. (2)), with the
+ * IPOPT-style barrier method of Sec. IV: log-barrier subproblems (eq. (3)), Newton steps on
+ * the augmented KKT system (eq. (7)) with inertia correction, fraction-to-the-boundary, a
+ * backtracking filter line search with second-order correction, the tiny-step rule, hard
+ * feasibility restoration and the monotone barrier update (Table I rows 1, 2, 4, 6, 7).
+ * Finished instances are replaced by new ones at iteration boundaries (iteration-level
+ * batching, Sec. V and Fig. 2); every instance takes its own branch inside the same launches.
+ *
+ * f, c and the bounds are compiled problem families (quadrotor multiple-shooting NMPC); the
+ * caller supplies theta.  Decision vector layout (FP64), per instance:
+ *     v = (x_0, u_0, x_1, u_1, ..., x_{N-1}, u_{N-1}, x_N, s)
+ * with 13 states and 4 rotor thrusts per stage and s the inequality slacks ordered
+ * (k = 1..N) x (row j).  Constraint / multiplier order:
+ *     y = (x_0 - xbar0 [13], x_{k+1} - F(x_k, u_k) [13 each, k = 0..N-1], g_kj - s_kj).
+ * Bounds: 0 <= u <= 2 u_hover, s >= 0; every other component is free.
+ *
+ * Conventions for every call:
+ *   - return 0 on success, a negative HIPIPM_ERR_* code otherwise; no call aborts.
+ *     hipipm_last_error() describes the last failure of a context.
+ *   - "device pointer" arguments point to memory on the context's device that the caller
+ *     owns and keeps alive for the duration of the call (and, for the workspace, until it
+ *     is unbound or the context is destroyed).  The library never frees caller memory.
+ *   - work is enqueued on the HIP stream passed as `stream` (a hipStream_t; NULL = the
+ *     default stream) and the call returns when it has finished (hipipm_solve synchronizes
+ *     the stream to poll its completion counter).
+ *   - per-instance numerical failures are statuses (HIPIPM_STATUS_*), not call errors.
+ */
+#ifndef HIPIPM_H
+#define HIPIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define HIPIPM_OK 0
+#define HIPIPM_ERR_INVALID_ARG (-1)
+#define HIPIPM_ERR_HIP (-2)
+#define HIPIPM_ERR_UNSUPPORTED (-3)
+#define HIPIPM_ERR_WORKSPACE (-4)
+
+/* ---- per-instance status ---- */
+#define HIPIPM_STATUS_RUNNING 0
+#define HIPIPM_STATUS_CONVERGED 1       /* scaled KKT error E_0 <= tol */
+#define HIPIPM_STATUS_MAX_ITER 2
+#define HIPIPM_STATUS_RESTO_FAILED 3    /* restoration could not start or its line search failed */
+#define HIPIPM_STATUS_INFEASIBLE 4      /* restoration converged to a point that is not feasible */
+#define HIPIPM_STATUS_NUMERICAL 5       /* non-finite values in the iterate */
+#define HIPIPM_STATUS_FILTER_OVERFLOW 6 /* more non-dominated filter pairs than filter_cap */
+
+/* ---- problem families ---- */
+#define HIPIPM_FAMILY_QUAD_OBS 0   /* point-to-point with spherical obstacles;
+                                      theta = [xbar0 (13), target (3), n_obs x (cx, cy, cz, r)] */
+#define HIPIPM_FAMILY_QUAD_TRACK 1 /* figure-eight tracking with spherical obstacles;
+                                      theta = [xbar0 (13), A, omega, n_obs x (cx, cy, cz, r)] */
+
+/* Problem descriptor (Sec. VI quadrotor NMPC; constants are inputs, not baked in). */
+typedef struct {
+    int32_t family;   /* HIPIPM_FAMILY_* */
+    int32_t N;        /* shooting intervals, 1..64 */
+    int32_t n_agents; /* must be 1 */
+    int32_t n_obs;    /* spheres, 0..64 */
+    double dt, mass, jxx, jyy, jzz, arm, ctau, grav;
+    double q_weight, r_weight, d_min;
+} hipipm_problem_desc;
+
+/* Algorithm options.  hipipm_default_options() fills the published IPOPT defaults. */
+typedef struct {
+    double tol;
+    int32_t max_iter;
+    double mu_init, kappa_eps, kappa_mu, theta_mu, tau_min;
+    double kappa1, kappa2, lam_max, s_max;
+    double delta_min, delta_0, delta_max, delta_c_bar, kappa_c;
+    double kappa_minus, kappa_plus, kappa_plus_bar;
+    double gamma_theta, gamma_phi, delta_sw, s_theta, s_phi, eta_phi, gamma_alpha;
+    int32_t max_soc;
+    double kappa_soc, kappa_sigma, rho_resto, kappa_resto, bound_mult_reset;
+    int32_t filter_cap;   /* <= 128 */
+    int32_t poll_every;   /* iterations between completion polls (>= 1) */
+    int32_t timing;       /* 1: time every kernel launch with HIP events (hipipm_kernel_times) */
+} hipipm_options;
+
+typedef struct {
+    int32_t n, m, n_w, n_s, n_theta, n_lower, n_upper, N, nx, nu, n_ineq;
+} hipipm_dims;
+
+typedef struct {
+    int64_t iterations, resto_iterations, soc_tried, soc_accepted, factorizations, resto_entries,
+        tiny_steps, passes, instances_done;
+} hipipm_stats;
+
+typedef struct hipipm_ctx hipipm_ctx;
+
+/* Fill *o with the default options (tol 1e-8, max_iter 1000, mu_init 0.1, ...). */
+int hipipm_default_options(hipipm_options* o);
+
+/* Create a context for `slots` concurrently iterating instances on the current HIP device.
+ * Validates the descriptor; performs no device allocation (see hipipm_bind_workspace).
+ * *out receives the context; destroy it with hipipm_destroy. */
+int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t slots, hipipm_ctx** out);
+
+/* Sizes of one instance (n variables incl. slacks, m constraints, theta length, ...). */
+int hipipm_get_dims(const hipipm_ctx* ctx, hipipm_dims* out);
+
+/* Device workspace needed for the context's slot count, in bytes (256-byte aligned base). */
+int hipipm_workspace_bytes(const hipipm_ctx* ctx, size_t* bytes);
+
+/* Bind caller-owned device memory of at least hipipm_workspace_bytes() bytes, 256-byte
+ * aligned.  The library uses it for all slot state and scratch; the caller frees it after
+ * hipipm_destroy (or after binding another buffer). */
+int hipipm_bind_workspace(hipipm_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Solve n_inst instances with iteration-level batching over the context's slots.
+ *   theta   : device, [n_inst][n_theta] FP64, read only
+ *   warm_x  : device, [n_inst][n] FP64 starting points, or NULL for the cold start
+ *             (x_k = xbar0, u_k = hover thrust, s = g(x)); pushed into the bounds either way
+ *   x_out   : device, [n_inst][n];  y_out: [n_inst][m];  zl_out, zu_out: [n_inst][n]
+ *             (bound multipliers, zero on unbounded components)
+ *   obj_out, kkt_out : device, [n_inst] objective and scaled KKT error E_0 at the result
+ *   status_out, iters_out : device, [n_inst] int32
+ * Output pointers may be NULL to skip that output (theta may not). */
+int hipipm_solve(hipipm_ctx* ctx, int32_t n_inst, const double* theta, const double* warm_x, double* x_out,
+                 double* y_out, double* zl_out, double* zu_out, double* obj_out, double* kkt_out,
+                 int32_t* status_out, int32_t* iters_out, void* stream);
+
+/* Counters accumulated over all solves since creation (or the last hipipm_reset_stats). */
+int hipipm_stats_get(const hipipm_ctx* ctx, hipipm_stats* out);
+int hipipm_reset_stats(hipipm_ctx* ctx);
+
+/* Kernel timing (options.timing = 1): total milliseconds and launch counts per kernel since the
+ * last reset; names[i] are "eval", "factor", "linesearch", "setup".  n_kernels in/out. */
+int hipipm_kernel_times(const hipipm_ctx* ctx, int32_t* n_kernels, double* total_ms, int64_t* launches);
+
+/* ---- test hooks (one-step replay, Sec. VI "Correctness") ----
+ * A flat FP64 state per slot in the oracle's field order:
+ *   header[16]: phase, iter, status, init_filter, theta_R
+ *   main : mu, tau, dx_last, theta_max, theta_min, tiny, nf, 0 | x[n] y[m] zl[n] zu[n] | fth[128] fph[128]
+ *   resto: same with n + 2m variables (x, p, n)
+ *   x_R[n], DR2[n]
+ * hipipm_state_len gives its length.  hipipm_state_import loads `count` states (host pointer,
+ * [count][len]) into slots 0..count-1 (theta from the device pointer, [count][n_theta]);
+ * hipipm_step runs `passes` passes of the iteration pipeline on those slots without refill;
+ * hipipm_state_export copies the slot states back (host pointer). */
+int hipipm_state_len(const hipipm_ctx* ctx, int32_t* len);
+int hipipm_state_import(hipipm_ctx* ctx, int32_t count, const double* states_host, const double* theta_dev,
+                        void* stream);
+int hipipm_step(hipipm_ctx* ctx, int32_t count, int32_t passes, void* stream);
+int hipipm_state_export(hipipm_ctx* ctx, int32_t count, double* states_host, void* stream);
+
+/* Raw structured KKT factor + solve for kernel parity: for `count` instances (device pointers)
+ * at primal-dual points v [count][n], y [count][m], zl/zu [count][n] with barrier mu, factor
+ * the augmented matrix of eq. (7) with perturbations delta_x, delta_c, solve it for the
+ * right-hand side rhs [count][n + m] (v rows then y rows) into sol [count][n + m], and write
+ * inertia_ok [count] (1 when every pivot block had the required sign, i.e. inertia (n, m, 0)).
+ * theta: [count][n_theta]. */
+int hipipm_kkt_factor_solve(hipipm_ctx* ctx, int32_t count, const double* theta, const double* v,
+                            const double* y, const double* zl, const double* zu, double mu, double delta_x,
+                            double delta_c, const double* rhs, double* sol, int32_t* inertia_ok, void* stream);
+
+/* Stage derivatives for kernel parity: for `count` stages, F (13), G = dF/d(x,u) (13 x 17, row
+ * major) and H = sum_r lam_r d2F_r/d(x,u)^2 (17 x 17) of the RK4 step; x [count][13],
+ * u [count][4], lam [count][13] device pointers. */
+int hipipm_stage_derivs(hipipm_ctx* ctx, int32_t count, const double* x, const double* u, const double* lam,
+                        double* F, double* G, double* H, void* stream);
+
+const char* hipipm_last_error(const hipipm_ctx* ctx);
+void hipipm_destroy(hipipm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -428,7 +428,8 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
         }
         double alpha = amax;
         for (int l = 0;; ++l) {
-            if (alpha < amin) return R_LSFAIL;
+            /* alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point) */
+            if (alpha < amin || l >= 60) return R_LSFAIL;
             for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + alpha * S->dx[i];
             double tht, pht;
             int fin = trial_eval(P, T, S->xt, S->ct, &tht, &pht);

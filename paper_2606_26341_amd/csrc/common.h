@@ -1,0 +1,74 @@
+// Internal layout and configuration shared by the host driver and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hipipm {
+
+constexpr int NX = 13;   // states per quadrotor
+constexpr int NU = 4;    // rotor thrusts
+constexpr int NZ = NX + NU;
+constexpr int WAVE = 64;
+constexpr int FCAP = 128;
+constexpr int MAX_N = 64;
+constexpr int MAX_OBS = 64;
+
+// slot phases
+enum : int { PH_INIT_Y = 0, PH_REGULAR = 1, PH_RESTO = 2, PH_FINISH = 3, PH_EMPTY = 4 };
+// instance statuses (same values as the public HIPIPM_STATUS_*)
+enum : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAX_ITER = 2, ST_RESTO_FAILED = 3, ST_INFEASIBLE = 4,
+             ST_NUMERICAL = 5, ST_FILTER_OVERFLOW = 6 };
+// step flags handed from the factor kernel to the line-search kernel
+enum : int { STEP_NONE = 0, STEP_READY = 1, STEP_ICFAIL = 2 };
+
+// scalar block of a slot record (doubles)
+enum : int {
+  SC_MU = 0, SC_TAU, SC_DXL, SC_THMAX, SC_THMIN, SC_TINY, SC_NF,           // main sub-problem
+  SC_RMU = 8, SC_RTAU, SC_RDXL, SC_RTHMAX, SC_RTHMIN, SC_RTINY, SC_RNF,  // restoration sub-problem
+  SC_PHASE = 16, SC_STATUS, SC_ITER, SC_INST, SC_INITF, SC_THR, SC_OVERFLOW,
+  SC_STEP = 24, SC_AMAX, SC_THK, SC_PHK, SC_GPHI, SC_FK, SC_STEPMU,
+  SC_ST_RESTO = 32, SC_ST_SOCT, SC_ST_SOCA, SC_ST_FACT, SC_ST_RENT, SC_ST_TINY, SC_ST_PASS,
+  SC_LDX = 40, SC_LDC, SC_LALPHA, SC_LALPHAZ, SC_LSOC,
+  SC_LEN = 64
+};
+
+// per-stage factor record (doubles)
+enum : int { FR_LR = 0, FR_Y = 16, FR_P = 16 + NU * NX, FR_LC = FR_P + NX * NX, FR_DH = FR_LC + NX * NX,
+             FR_FLAG = FR_DH + NX, FR_LEN = ((FR_FLAG + 1 + 7) / 8) * 8 };
+// per-stage condensed right-hand side (lambda 13, x 13, u 4) padded
+constexpr int RB_LEN = 32;
+
+struct Cfg {
+  // problem
+  int family, N, NI, n_theta, n, m, n_w, n_s, n_lower, n_upper;
+  double dt, mass, jxx, jyy, jzz, arm, ctau, grav, qw, rw, uh, umax;
+  // options
+  double tol; int max_iter;
+  double mu_init, kappa_eps, kappa_mu, theta_mu, tau_min, kappa1, kappa2, lam_max, s_max;
+  double delta_min, delta_0, delta_max, delta_c_bar, kappa_c, kappa_minus, kappa_plus, kappa_plus_bar;
+  double gamma_theta, gamma_phi, delta_sw, s_theta, s_phi, eta_phi, gamma_alpha;
+  int max_soc; double kappa_soc, kappa_sigma, rho_resto, kappa_resto, bound_mult_reset;
+  int fcap;
+  // slot record layout, offsets in doubles
+  long long stride;
+  int o_v, o_y, o_zlu, o_zuu, o_zls, o_th, o_sc, o_fm, o_fr;
+  int o_yr, o_rzlu, o_rzuu, o_rzls, o_xr, o_p, o_nn, o_zp, o_zn;
+  int o_F, o_G, o_HW, o_fac, o_rb;
+  int o_dv, o_dy, o_dzlu, o_dzuu, o_dzls, o_dp, o_dn, o_dzp, o_dzn;
+  int o_rv, o_rc, o_rp, o_rn, o_vt, o_ct, o_pt, o_nt, o_csoc, o_dvs, o_dys, o_dps, o_dns;
+  int o_g;
+};
+
+// caller-owned output arrays of a solve
+struct Outs {
+  double *x, *y, *zl, *zu, *obj, *kkt;
+  int32_t *status, *iters;
+};
+
+// global counters (device): queue head, finished count, stats
+struct Counters {
+  int32_t head, done, n_inst, pad;
+  unsigned long long st[10];
+};
+
+}  // namespace hipipm

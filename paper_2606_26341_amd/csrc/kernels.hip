@@ -1,0 +1,1033 @@
+// gfx950 kernels of one fused batched interior-point iteration (Sec. V): every slot runs its
+// own branch of Table I inside the same launches, one 64-lane wavefront per slot.
+//
+//   k_eval       RK4 dynamics, Jacobian and Lagrangian-Hessian contraction per (slot, stage,
+//                direction) -- eq. (4) W and A = grad c
+//   k_factor     convergence test (E_0), monotone barrier update (Table I row 7), KKT assembly
+//                with slack condensation, inertia-correcting structured LDL^T (eq. (7)), step,
+//                bound-multiplier steps, fraction to the boundary; also least-squares
+//                multipliers (INIT_Y) and result write-out + slot refill (iteration-level
+//                batching, Sec. V)
+//   k_ls         tiny step (row 4), backtracking filter line search (row 1) with second-order
+//                correction (row 2), acceptance, restoration entry/exit (row 6)
+#include "common.h"
+#include "model.h"
+#include "kkt.h"
+
+namespace hipipm {
+
+// ============================================================================ derivatives
+__global__ __launch_bounds__(256) void k_eval(Cfg c, double* ws, int slots) {
+  const long long per = (long long)c.N * NZ;
+  const long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= (long long)slots * per) return;
+  const int slot = (int)(item / per);
+  const int rem = (int)(item % per);
+  const int k = rem / NZ, j = rem % NZ;
+  Slot s = make_slot(c, ws, slot);
+  const int ph = (int)s.sc[SC_PHASE];
+  if (ph == PH_EMPTY) return;
+  const double* yv = (ph == PH_RESTO) ? s.yr : s.y;
+  double x[NX], u[NU], lam[NX], Fv[NX], Gc[NX], Hc[NZ];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) x[i] = s.v[xo(k) + i];
+#pragma unroll
+  for (int i = 0; i < NU; ++i) u[i] = s.v[uo(k) + i];
+  // the rows x_{k+1} - F(x_k, u_k) contribute -sum_r y_r Hess F_r to W
+#pragma unroll
+  for (int i = 0; i < NX; ++i) lam[i] = -yv[(k + 1) * NX + i];
+  rk4_deriv_dir(c, x, u, lam, j, j == 0 ? Fv : nullptr, Gc, Hc);
+  double* G = s.G + (long long)k * NX * NZ;
+  double* H = s.HW + (long long)k * NZ * NZ;
+#pragma unroll
+  for (int i = 0; i < NX; ++i) G[i * NZ + j] = Gc[i];
+#pragma unroll
+  for (int i = 0; i < NZ; ++i) H[i * NZ + j] = Hc[i];
+  if (j == 0) {
+#pragma unroll
+    for (int i = 0; i < NX; ++i) s.F[k * NX + i] = Fv[i];
+  }
+}
+
+// ============================================================================ per-slot helpers
+__device__ __forceinline__ double fdiv_safe(double a, double b) { return a / b; }
+
+// -c at the current point into rc (restoration: -(c - p + n))
+__device__ void eval_c(const Cfg& c, const Slot& s, bool resto, int lane) {
+  const int N = c.N, NI = c.NI;
+  for (int r = lane; r < (N + 1) * NX; r += WAVE) {
+    int k = r / NX, i = r % NX;
+    double cv = (k == 0) ? s.v[i] - s.th[i] : s.v[xo(k) + i] - s.F[(k - 1) * NX + i];
+    s.rc[r] = -cv;
+  }
+  for (int q = lane; q < N * NI; q += WAVE) {
+    int k = 1 + q / NI, j = q % NI;
+    const double* o = obs_ptr(c, s.th) + 4 * j;
+    double g = 0.0;
+    for (int t = 0; t < 3; ++t) { double e = s.v[xo(k) + t] - o[t]; g += e * e; }
+    s.rc[go(c, k, j)] = -(g - o[3] * o[3] - s.v[so(c, k, j)]);
+  }
+  __syncthreads();
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE) s.rc[r] += s.p[r] - s.nn[r];
+  __syncthreads();
+}
+
+// objective gradient g = grad f (regular) or grad f_R (restoration, v part) and A^T y into aty
+__device__ void eval_grad(const Cfg& c, const Slot& s, const double* yv, bool resto, double zeta, double* aty,
+                          int lane) {
+  const int N = c.N, NI = c.NI;
+  for (int i = lane; i < c.n; i += WAVE) {
+    double gi = 0.0;
+    if (resto) {
+      double d = fmin(1.0, 1.0 / fabs(s.xr[i]));
+      gi = zeta * d * d * (s.v[i] - s.xr[i]);
+    } else if (i < c.n_w) {
+      int k = i / NZ, r = i % NZ;
+      if (r < NX) {
+        double xr[NX];
+        ref_state(c, s.th, k, xr);
+        gi = 2.0 * c.qw * (s.v[i] - xr[r]);
+      } else {
+        gi = 2.0 * c.rw * (s.v[i] - c.uh);
+      }
+    }
+    s.g[i] = gi;
+  }
+  // A^T y
+  for (int i = lane; i < c.n; i += WAVE) {
+    double a = 0.0;
+    if (i < c.n_w) {
+      int k = i / NZ, r = i % NZ;
+      if (r < NX) a += yv[k * NX + r];        // +I of the rows defining x_k
+      if (k < N) {
+        const double* Gk = s.G + (long long)k * NX * NZ;
+        for (int l = 0; l < NX; ++l) a -= Gk[l * NZ + r] * yv[(k + 1) * NX + l];
+      }
+      if (r < 3 && k >= 1) {
+        for (int j = 0; j < NI; ++j) {
+          const double* o = obs_ptr(c, s.th) + 4 * j;
+          a += 2.0 * (s.v[i] - o[r]) * yv[go(c, k, j)];
+        }
+      }
+    } else {
+      int q = i - c.n_w;
+      int k = 1 + q / NI, j = q % NI;
+      a = -yv[go(c, k, j)];
+    }
+    aty[i] = a;
+  }
+  __syncthreads();
+}
+
+// z_L / z_U of v component i (0 if unbounded)
+__device__ __forceinline__ void z_of(const Cfg& c, const Iter& it, int i, double& zl, double& zu) {
+  zl = zu = 0.0;
+  if (i < c.n_w) {
+    int k = i / NZ, r = i % NZ;
+    if (r >= NX && k < c.N) { zl = it.zlu[k * NU + r - NX]; zu = it.zuu[k * NU + r - NX]; }
+  } else {
+    zl = it.zls[i - c.n_w];
+  }
+}
+
+struct ErrParts {
+  double dual, prim, y1, z1;
+  int nL, nU;
+};
+
+__device__ ErrParts err_parts(const Cfg& c, const Slot& s, const Iter& it, const double* aty, int lane) {
+  double dual = 0.0, nanf = 0.0, z1 = 0.0, y1 = 0.0, prim = 0.0;
+  for (int i = lane; i < c.n; i += WAVE) {
+    double zl, zu;
+    z_of(c, it, i, zl, zu);
+    double d = s.g[i] + aty[i] - zl + zu;
+    if (!isfinite(d)) nanf = 1.0;
+    dual = fmax(dual, fabs(d));
+    z1 += fabs(zl) + fabs(zu);
+  }
+  for (int r = lane; r < c.m; r += WAVE) {
+    y1 += fabs(it.y[r]);
+    double pr = fabs(s.rc[r]);
+    if (!isfinite(pr)) nanf = 1.0;
+    prim = fmax(prim, pr);
+    if (it.resto) {
+      double dp = c.rho_resto - it.y[r] - s.zp[r];
+      double dn = c.rho_resto + it.y[r] - s.zn[r];
+      dual = fmax(dual, fmax(fabs(dp), fabs(dn)));
+      z1 += fabs(s.zp[r]) + fabs(s.zn[r]);
+    }
+  }
+  ErrParts e;
+  e.dual = wmax(dual);
+  e.prim = wmax(prim);
+  e.y1 = wsum(y1);
+  e.z1 = wsum(z1);
+  if (wmax(nanf) > 0.0) e.dual = NAN;
+  e.nL = c.N * NU + c.N * c.NI + (it.resto ? 2 * c.m : 0);
+  e.nU = c.N * NU;
+  return e;
+}
+
+// max |s z - mu| over the bounded components
+__device__ double compl_max(const Cfg& c, const Slot& s, const Iter& it, double mu, int lane) {
+  double cm = 0.0;
+  for (int b = lane; b < c.N * NU; b += WAVE) {
+    int k = b / NU, i = b % NU;
+    double u = s.v[uo(k) + i];
+    cm = fmax(cm, fabs(u * it.zlu[b] - mu));
+    cm = fmax(cm, fabs((c.umax - u) * it.zuu[b] - mu));
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) cm = fmax(cm, fabs(s.v[c.n_w + q] * it.zls[q] - mu));
+  if (it.resto)
+    for (int r = lane; r < c.m; r += WAVE) {
+      cm = fmax(cm, fabs(s.p[r] * s.zp[r] - mu));
+      cm = fmax(cm, fabs(s.nn[r] * s.zn[r] - mu));
+    }
+  return wmax(cm);
+}
+
+__device__ double kkt_err(const Cfg& c, const ErrParts& e, double cm, int m) {
+  double sd = 1.0, sc = 1.0;
+  if (m + e.nL + e.nU > 0) sd = fmax(c.s_max, (e.y1 + e.z1) / (double)(m + e.nL + e.nU)) / c.s_max;
+  if (e.nL + e.nU > 0) sc = fmax(c.s_max, e.z1 / (double)(e.nL + e.nU)) / c.s_max;
+  double r = e.dual / sd;
+  if (isnan(e.dual)) return NAN;
+  r = fmax(r, e.prim);
+  r = fmax(r, cm / sc);
+  return r;
+}
+
+// objective value at v (regular) -- wave sum
+__device__ double obj_regular(const Cfg& c, const Slot& s, const double* v, int lane) {
+  double f = 0.0;
+  for (int i = lane; i < c.n_w; i += WAVE) {
+    int k = i / NZ, r = i % NZ;
+    if (r < NX) {
+      double xr[NX];
+      ref_state(c, s.th, k, xr);
+      double e = v[i] - xr[r];
+      f += c.qw * e * e;
+    } else {
+      double e = v[i] - c.uh;
+      f += c.rw * e * e;
+    }
+  }
+  return wsum(f);
+}
+
+// restoration objective rho sum(p + n) + zeta/2 |D_R (v - x_R)|^2
+__device__ double obj_resto(const Cfg& c, const Slot& s, const double* v, const double* p, const double* nn,
+                            double zeta, int lane) {
+  double a = 0.0, q = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) a += p[r] + nn[r];
+  for (int i = lane; i < c.n; i += WAVE) {
+    double d = fmin(1.0, 1.0 / fabs(s.xr[i]));
+    double e = v[i] - s.xr[i];
+    q += d * d * e * e;
+  }
+  return c.rho_resto * wsum(a) + 0.5 * zeta * wsum(q);
+}
+
+// sum of log-slacks of the bounded components; NaN if one is not positive
+__device__ double log_barrier(const Cfg& c, const double* v, const double* p, const double* nn, bool resto,
+                              int lane) {
+  double b = 0.0, bad = 0.0;
+  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
+    int k = bb / NU, i = bb % NU;
+    double u = v[uo(k) + i];
+    double sl = u, su = c.umax - u;
+    if (!(sl > 0.0) || !(su > 0.0)) bad = 1.0;
+    else b += log(sl) + log(su);
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) {
+    double sv = v[c.n_w + q];
+    if (!(sv > 0.0)) bad = 1.0;
+    else b += log(sv);
+  }
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE) {
+      if (!(p[r] > 0.0) || !(nn[r] > 0.0)) bad = 1.0;
+      else b += log(p[r]) + log(nn[r]);
+    }
+  if (wmax(bad) > 0.0) return NAN;
+  return wsum(b);
+}
+
+// primal fraction to the boundary over the bounded components of (dv, dp, dn)
+__device__ double ftb_primal(const Cfg& c, const Slot& s, const double* dv, const double* dp, const double* dn,
+                             bool resto, double tau, int lane) {
+  double a = 1.0;
+  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
+    int k = bb / NU, i = bb % NU;
+    double u = s.v[uo(k) + i], d = dv[uo(k) + i];
+    if (d < 0) a = fmin(a, -tau * u / d);
+    if (d > 0) a = fmin(a, tau * (c.umax - u) / d);
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) {
+    double d = dv[c.n_w + q];
+    if (d < 0) a = fmin(a, -tau * s.v[c.n_w + q] / d);
+  }
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE) {
+      if (dp[r] < 0) a = fmin(a, -tau * s.p[r] / dp[r]);
+      if (dn[r] < 0) a = fmin(a, -tau * s.nn[r] / dn[r]);
+    }
+  return wmin(a);
+}
+
+// bound-multiplier steps (eq. (6) rows 3-4 eliminated): into dzlu, dzuu, dzls, dzp, dzn
+__device__ void dz_recover(const Cfg& c, const Slot& s, const Iter& it, double mu, const double* dv,
+                           const double* dp, const double* dn, int lane) {
+  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
+    int k = bb / NU, i = bb % NU;
+    double u = s.v[uo(k) + i], d = dv[uo(k) + i];
+    double sl = u, su = c.umax - u;
+    s.dzlu[bb] = (mu - sl * it.zlu[bb] - it.zlu[bb] * d) / sl;
+    s.dzuu[bb] = (mu - su * it.zuu[bb] + it.zuu[bb] * d) / su;
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) {
+    double sv = s.v[c.n_w + q], d = dv[c.n_w + q];
+    s.dzls[q] = (mu - sv * it.zls[q] - it.zls[q] * d) / sv;
+  }
+  if (it.resto)
+    for (int r = lane; r < c.m; r += WAVE) {
+      s.dzp[r] = (mu - s.p[r] * s.zp[r] - s.zp[r] * dp[r]) / s.p[r];
+      s.dzn[r] = (mu - s.nn[r] * s.zn[r] - s.zn[r] * dn[r]) / s.nn[r];
+    }
+  __syncthreads();
+}
+
+__device__ double ftb_dual(const Cfg& c, const Slot& s, const Iter& it, double tau, int lane) {
+  double a = 1.0;
+  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
+    if (s.dzlu[bb] < 0) a = fmin(a, -tau * it.zlu[bb] / s.dzlu[bb]);
+    if (s.dzuu[bb] < 0) a = fmin(a, -tau * it.zuu[bb] / s.dzuu[bb]);
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE)
+    if (s.dzls[q] < 0) a = fmin(a, -tau * it.zls[q] / s.dzls[q]);
+  if (it.resto)
+    for (int r = lane; r < c.m; r += WAVE) {
+      if (s.dzp[r] < 0) a = fmin(a, -tau * s.zp[r] / s.dzp[r]);
+      if (s.dzn[r] < 0) a = fmin(a, -tau * s.zn[r] / s.dzn[r]);
+    }
+  return wmin(a);
+}
+
+// filter: reject if theta >= theta_F and phi >= phi_F for some entry
+__device__ bool filter_ok(const double* filt, int nf, double th, double ph, int lane) {
+  int bad = 0;
+  for (int i = lane; i < nf; i += WAVE)
+    if (th >= filt[i] && ph >= filt[FCAP + i]) bad = 1;
+  return wor(bad) == 0;
+}
+
+// add an entry, dropping the entries it dominates; returns the new count (-1 on overflow)
+__device__ int filter_add(double* filt, int nf, int cap, double th, double ph, int lane) {
+  __shared__ int res;
+  if (lane == 0) {
+    int w = 0;
+    for (int i = 0; i < nf; ++i)
+      if (!(filt[i] >= th && filt[FCAP + i] >= ph)) {
+        filt[w] = filt[i];
+        filt[FCAP + w] = filt[FCAP + i];
+        ++w;
+      }
+    if (w >= cap) {
+      res = -1 - w;
+    } else {
+      filt[w] = th;
+      filt[FCAP + w] = ph;
+      res = w + 1;
+    }
+  }
+  __syncthreads();
+  int r = res;
+  __syncthreads();
+  return r;
+}
+
+// ============================================================================ slot initialisation
+__device__ void init_instance(const Cfg& c, const Slot& s, int inst, const double* theta, const double* warm_x,
+                              int lane) {
+  const double* th = theta + (long long)inst * c.n_theta;
+  for (int i = lane; i < c.n_theta; i += WAVE) s.th[i] = th[i];
+  __syncthreads();
+  for (int i = lane; i < c.n; i += WAVE) {
+    double x;
+    if (warm_x) {
+      x = warm_x[(long long)inst * c.n + i];
+    } else if (i < c.n_w) {
+      int r = i % NZ;
+      x = (r < NX) ? s.th[r] : c.uh;
+    } else {
+      int q = i - c.n_w, j = q % c.NI;
+      const double* o = obs_ptr(c, s.th) + 4 * j;
+      double g = 0.0;
+      for (int t = 0; t < 3; ++t) { double e = s.th[t] - o[t]; g += e * e; }
+      x = g - o[3] * o[3];
+    }
+    // push into the bounds (kappa_1, kappa_2)
+    if (i < c.n_w) {
+      int k = i / NZ, r = i % NZ;
+      if (r >= NX && k < c.N) {
+        double l = 0.0, u = c.umax;
+        double pl = fmin(c.kappa1 * fmax(1.0, fabs(l)), c.kappa2 * (u - l));
+        double pu = fmin(c.kappa1 * fmax(1.0, fabs(u)), c.kappa2 * (u - l));
+        x = fmax(x, l + pl);
+        x = fmin(x, u - pu);
+      }
+    } else {
+      x = fmax(x, 0.0 + c.kappa1 * 1.0);
+    }
+    s.v[i] = x;
+  }
+  for (int r = lane; r < c.m; r += WAVE) s.y[r] = 0.0;
+  for (int b = lane; b < c.N * NU; b += WAVE) { s.zlu[b] = 1.0; s.zuu[b] = 1.0; }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) s.zls[q] = 1.0;
+  for (int q = lane; q < SC_LEN; q += WAVE) s.sc[q] = 0.0;
+  __syncthreads();
+  if (lane == 0) {
+    s.sc[SC_MU] = c.mu_init;
+    s.sc[SC_TAU] = fmax(c.tau_min, 1.0 - c.mu_init);
+    s.sc[SC_PHASE] = PH_INIT_Y;
+    s.sc[SC_STATUS] = ST_RUNNING;
+    s.sc[SC_INST] = inst;
+    s.sc[SC_INITF] = 1.0;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_setup(Cfg c, double* ws, int slots, int n_active, const double* theta,
+                                              const double* warm_x) {
+  const int slot = blockIdx.x, lane = threadIdx.x;
+  Slot s = make_slot(c, ws, slot);
+  if (slot < n_active) {
+    init_instance(c, s, slot, theta, warm_x, lane);
+  } else {
+    for (int q = lane; q < SC_LEN; q += WAVE) s.sc[q] = 0.0;
+    __syncthreads();
+    if (lane == 0) s.sc[SC_PHASE] = PH_EMPTY;
+  }
+}
+
+// ============================================================================ factor kernel
+// finished instance: write the results (main problem, E_0 at the point), pop the next one
+__device__ void finish_slot(const Cfg& c, const Slot& s, const double* theta, const double* warm_x, Outs out,
+                            Counters* cnt, bool refill, int lane) {
+  Iter it = cur_iter(s, false);
+  eval_c(c, s, false, lane);
+  eval_grad(c, s, s.y, false, 0.0, s.vt, lane);
+  ErrParts ep = err_parts(c, s, it, s.vt, lane);
+  double E0 = kkt_err(c, ep, compl_max(c, s, it, 0.0, lane), c.m);
+  double f = obj_regular(c, s, s.v, lane);
+  const int inst = (int)s.sc[SC_INST];
+  const long long b = (long long)inst;
+  for (int i = lane; i < c.n; i += WAVE) {
+    double zl, zu;
+    z_of(c, it, i, zl, zu);
+    if (out.x) out.x[b * c.n + i] = s.v[i];
+    if (out.zl) out.zl[b * c.n + i] = zl;
+    if (out.zu) out.zu[b * c.n + i] = zu;
+  }
+  if (out.y)
+    for (int r = lane; r < c.m; r += WAVE) out.y[b * c.m + r] = s.y[r];
+  __shared__ int next;
+  if (lane == 0) {
+    if (out.obj) out.obj[inst] = f;
+    if (out.kkt) out.kkt[inst] = E0;
+    if (out.status) out.status[inst] = (int)s.sc[SC_STATUS];
+    if (out.iters) out.iters[inst] = (int)s.sc[SC_ITER];
+    if (cnt) {
+      atomicAdd(&cnt->st[0], (unsigned long long)s.sc[SC_ITER]);
+      atomicAdd(&cnt->st[1], (unsigned long long)s.sc[SC_ST_RESTO]);
+      atomicAdd(&cnt->st[2], (unsigned long long)s.sc[SC_ST_SOCT]);
+      atomicAdd(&cnt->st[3], (unsigned long long)s.sc[SC_ST_SOCA]);
+      atomicAdd(&cnt->st[4], (unsigned long long)s.sc[SC_ST_FACT]);
+      atomicAdd(&cnt->st[5], (unsigned long long)s.sc[SC_ST_RENT]);
+      atomicAdd(&cnt->st[6], (unsigned long long)s.sc[SC_ST_TINY]);
+      atomicAdd(&cnt->st[7], (unsigned long long)s.sc[SC_ST_PASS]);
+      atomicAdd(&cnt->st[8], 1ull);
+      atomicAdd(&cnt->done, 1);
+      next = refill ? atomicAdd(&cnt->head, 1) : INT_MAX;
+    } else {
+      next = INT_MAX;
+    }
+  }
+  __syncthreads();
+  const int nx = next;
+  if (cnt && nx < cnt->n_inst) {
+    init_instance(c, s, nx, theta, warm_x, lane);
+  } else {
+    __syncthreads();
+    if (lane == 0) s.sc[SC_PHASE] = PH_EMPTY;
+  }
+  __syncthreads();
+}
+
+// least-squares equality multipliers: [[I, A^T], [A, 0]] [d; y] = -[grad f - z_L + z_U; 0]
+__device__ void init_y(const Cfg& c, const Slot& s, KktLds& L, int lane) {
+  Iter it = cur_iter(s, false);
+  eval_c(c, s, false, lane);
+  eval_grad(c, s, s.y, false, 0.0, s.vt, lane);
+  for (int i = lane; i < c.n; i += WAVE) {
+    double zl, zu;
+    z_of(c, it, i, zl, zu);
+    s.rv[i] = -(s.g[i] - zl + zu);
+  }
+  for (int r = lane; r < c.m; r += WAVE) s.dvs[r] = 0.0;   // zero constraint right-hand side
+  __syncthreads();
+  Elim e{true, false, 0.0, 0.0, 0.0};
+  kkt_factor(c, s, it, e, 0.0, L, lane);
+  kkt_solve(c, s, it, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, L, lane);
+  double ym = 0.0, bad = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) {
+    ym = fmax(ym, fabs(s.dy[r]));
+    if (!isfinite(s.dy[r])) bad = 1.0;
+  }
+  ym = wmax(ym);
+  const bool keep = wmax(bad) == 0.0 && ym <= c.lam_max;
+  for (int r = lane; r < c.m; r += WAVE) s.y[r] = keep ? s.dy[r] : 0.0;
+  double th0 = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) th0 += fabs(s.rc[r]);
+  th0 = wsum(th0);
+  __syncthreads();
+  if (lane == 0) {
+    if (s.sc[SC_INITF] != 0.0) {
+      s.sc[SC_THMAX] = 1e4 * fmax(1.0, th0);
+      s.sc[SC_THMIN] = 1e-4 * fmax(1.0, th0);
+      s.sc[SC_NF] = 0.0;
+      s.sc[SC_INITF] = 0.0;
+    }
+    s.sc[SC_PHASE] = PH_REGULAR;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_factor(Cfg c, double* ws, const double* theta, const double* warm_x,
+                                               Outs out, Counters* cnt, int refill) {
+  __shared__ KktLds L;
+  const int slot = blockIdx.x, lane = threadIdx.x;
+  Slot s = make_slot(c, ws, slot);
+  const int ph = (int)s.sc[SC_PHASE];
+  if (ph == PH_EMPTY) return;
+  __syncthreads();
+  if (lane == 0) s.sc[SC_ST_PASS] += 1.0;
+  if (ph == PH_FINISH) { finish_slot(c, s, theta, warm_x, out, cnt, refill != 0, lane); return; }
+  if (ph == PH_INIT_Y) { init_y(c, s, L, lane); return; }
+
+  const bool resto = (ph == PH_RESTO);
+  Iter it = cur_iter(s, resto);
+  double* sub = it.sub;   // mu, tau, dx_last, theta_max, theta_min, tiny, nf
+  double mu = sub[0];
+  double zeta = resto ? sqrt(mu) : 0.0;
+  eval_c(c, s, resto, lane);
+  eval_grad(c, s, it.y, resto, zeta, s.vt, lane);
+  ErrParts ep = err_parts(c, s, it, s.vt, lane);
+  const double E0 = kkt_err(c, ep, compl_max(c, s, it, 0.0, lane), c.m);
+  __syncthreads();
+  if (!isfinite(E0)) {
+    if (lane == 0) { s.sc[SC_STATUS] = ST_NUMERICAL; s.sc[SC_PHASE] = PH_FINISH; }
+    if (resto) for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
+    return;
+  }
+  if (E0 <= c.tol) {
+    if (!resto) {
+      if (lane == 0) s.sc[SC_STATUS] = ST_CONVERGED;
+      __syncthreads();
+      finish_slot(c, s, theta, warm_x, out, cnt, refill != 0, lane);
+    } else {
+      for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
+      if (lane == 0) { s.sc[SC_STATUS] = ST_INFEASIBLE; s.sc[SC_PHASE] = PH_FINISH; }
+    }
+    return;
+  }
+  if (s.sc[SC_ITER] >= c.max_iter) {
+    if (!resto) {
+      if (lane == 0) s.sc[SC_STATUS] = ST_MAX_ITER;
+      __syncthreads();
+      finish_slot(c, s, theta, warm_x, out, cnt, refill != 0, lane);
+    } else {
+      for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
+      if (lane == 0) { s.sc[SC_STATUS] = ST_MAX_ITER; s.sc[SC_PHASE] = PH_FINISH; }
+    }
+    return;
+  }
+  // ---- monotone barrier update (Table I row 7) ----
+  {
+    const double mu_min = c.tol / 10.0;
+    double tau = sub[1];
+    double nf = sub[6];
+    bool tiny = sub[5] != 0.0;
+    for (;;) {
+      double Emu = kkt_err(c, ep, compl_max(c, s, it, mu, lane), c.m);
+      if (!(Emu <= c.kappa_eps * mu || tiny)) break;
+      tiny = false;
+      double nm = fmax(mu_min, fmin(c.kappa_mu * mu, pow(mu, c.theta_mu)));
+      if (!(nm < mu)) break;
+      mu = nm;
+      tau = fmax(c.tau_min, 1.0 - mu);
+      nf = 0.0;
+      if (resto) {
+        zeta = sqrt(mu);
+        eval_grad(c, s, it.y, resto, zeta, s.vt, lane);
+        ep = err_parts(c, s, it, s.vt, lane);
+      }
+    }
+    __syncthreads();
+    if (lane == 0) { sub[0] = mu; sub[1] = tau; sub[5] = tiny ? 1.0 : 0.0; sub[6] = nf; }
+    __syncthreads();
+  }
+  const double tau = sub[1];
+  // ---- barrier gradient, right-hand side of eq. (7), theta_k, phi_k ----
+  for (int i = lane; i < c.n; i += WAVE) {
+    double gp = s.g[i];
+    if (i < c.n_w) {
+      int k = i / NZ, r = i % NZ;
+      if (r >= NX && k < c.N) {
+        double u = s.v[i];
+        gp += -mu / u + mu / (c.umax - u);
+      }
+    } else {
+      gp -= mu / s.v[i];
+    }
+    s.g[i] = gp;                       // now grad phi_mu
+    s.rv[i] = -(gp + s.vt[i]);
+  }
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE) {
+      s.rp[r] = -(c.rho_resto - mu / s.p[r] - it.y[r]);
+      s.rn[r] = -(c.rho_resto - mu / s.nn[r] + it.y[r]);
+    }
+  double thk = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) thk += fabs(s.rc[r]);
+  thk = wsum(thk);
+  double fk = resto ? obj_resto(c, s, s.v, s.p, s.nn, zeta, lane) : obj_regular(c, s, s.v, lane);
+  double phk = fk - mu * log_barrier(c, s.v, s.p, s.nn, resto, lane);
+  __syncthreads();
+  if (lane == 0) { s.sc[SC_THK] = thk; s.sc[SC_PHK] = phk; s.sc[SC_FK] = fk; s.sc[SC_STEPMU] = mu; }
+  // ---- inertia-correcting factorization ----
+  Elim e{false, resto, 0.0, 0.0, zeta};
+  const double dxl = sub[2];
+  int st = kkt_factor(c, s, it, e, zeta, L, lane);
+  int nfact = 1;
+  bool ok = (st == 0);
+  if (!ok) {
+    if (st == 2) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
+    e.dxp = (dxl == 0.0) ? c.delta_0 : fmax(c.delta_min, c.kappa_minus * dxl);
+    for (;;) {
+      st = kkt_factor(c, s, it, e, zeta, L, lane);
+      ++nfact;
+      if (st == 0) { ok = true; break; }
+      if (st == 2 && e.dcp == 0.0) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
+      e.dxp *= (dxl == 0.0) ? c.kappa_plus_bar : c.kappa_plus;
+      if (e.dxp > c.delta_max) break;
+    }
+  }
+  __syncthreads();
+  if (lane == 0) {
+    s.sc[SC_ST_FACT] += nfact;
+    if (ok && (e.dxp != 0.0)) sub[2] = e.dxp;
+    s.sc[SC_LDX] = e.dxp;
+    s.sc[SC_LDC] = e.dcp;
+    s.sc[SC_STEP] = ok ? STEP_READY : STEP_ICFAIL;
+  }
+  if (!ok) return;
+  // ---- step ----
+  kkt_solve(c, s, it, e, s.rv, s.rc, s.rp, s.rn, s.dv, s.dy, s.dp, s.dn, L, lane);
+  dz_recover(c, s, it, mu, s.dv, s.dp, s.dn, lane);
+  double amax = ftb_primal(c, s, s.dv, s.dp, s.dn, resto, tau, lane);
+  double gphi = 0.0;
+  for (int i = lane; i < c.n; i += WAVE) gphi += s.g[i] * s.dv[i];
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE)
+      gphi += (c.rho_resto - mu / s.p[r]) * s.dp[r] + (c.rho_resto - mu / s.nn[r]) * s.dn[r];
+  gphi = wsum(gphi);
+  __syncthreads();
+  if (lane == 0) { s.sc[SC_AMAX] = amax; s.sc[SC_GPHI] = gphi; }
+}
+
+// ============================================================================ line search kernel
+struct Trial {
+  double th, ph;
+  bool fin;
+};
+
+// evaluate the trial point vt (pt, nt): constraints into ct, theta = |ct|_1, phi_mu
+__device__ Trial eval_trial(const Cfg& c, const Slot& s, bool resto, double mu, double zeta, int lane) {
+  const int N = c.N, NI = c.NI;
+  if (lane < N) {
+    double x[NX], u[NU], F[NX];
+    for (int i = 0; i < NX; ++i) x[i] = s.vt[xo(lane) + i];
+    for (int i = 0; i < NU; ++i) u[i] = s.vt[uo(lane) + i];
+    rk4(c, x, u, F);
+    for (int i = 0; i < NX; ++i) s.ct[(lane + 1) * NX + i] = s.vt[xo(lane + 1) + i] - F[i];
+  }
+  for (int i = lane; i < NX; i += WAVE) s.ct[i] = s.vt[i] - s.th[i];
+  for (int q = lane; q < N * NI; q += WAVE) {
+    int k = 1 + q / NI, j = q % NI;
+    const double* o = obs_ptr(c, s.th) + 4 * j;
+    double g = 0.0;
+    for (int t = 0; t < 3; ++t) { double e = s.vt[xo(k) + t] - o[t]; g += e * e; }
+    s.ct[go(c, k, j)] = g - o[3] * o[3] - s.vt[so(c, k, j)];
+  }
+  __syncthreads();
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE) s.ct[r] += -s.pt[r] + s.nt[r];
+  __syncthreads();
+  double th = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) th += fabs(s.ct[r]);
+  th = wsum(th);
+  double f = resto ? obj_resto(c, s, s.vt, s.pt, s.nt, zeta, lane) : obj_regular(c, s, s.vt, lane);
+  double ph = f - mu * log_barrier(c, s.vt, s.pt, s.nt, resto, lane);
+  Trial t;
+  t.th = th;
+  t.ph = ph;
+  t.fin = isfinite(th) && isfinite(ph);
+  return t;
+}
+
+__device__ __forceinline__ void make_trial(const Cfg& c, const Slot& s, bool resto, double a, const double* dv,
+                                           const double* dp, const double* dn, int lane) {
+  for (int i = lane; i < c.n; i += WAVE) s.vt[i] = s.v[i] + a * dv[i];
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE) { s.pt[r] = s.p[r] + a * dp[r]; s.nt[r] = s.nn[r] + a * dn[r]; }
+  __syncthreads();
+}
+
+struct Acc {
+  bool ok, sw, arm;
+};
+
+__device__ Acc acceptable(const Cfg& c, const double* sub, const double* filt, double thk, double phk, double gphi,
+                          double alpha, const Trial& t, int lane) {
+  Acc r{false, false, false};
+  if (!t.fin) return r;
+  if (t.th > sub[3]) return r;
+  bool sw = gphi < 0 && alpha * pow(-gphi, c.s_phi) > c.delta_sw * pow(thk, c.s_theta);
+  double slack = 10.0 * 2.220446049250313e-16 * fabs(phk);
+  bool arm = (t.ph - (phk + c.eta_phi * alpha * gphi)) <= slack;
+  bool ok;
+  if (sw && thk <= sub[4]) ok = arm;
+  else ok = (t.th <= (1.0 - c.gamma_theta) * thk) || ((t.ph - (phk - c.gamma_phi * thk)) <= slack);
+  if (!ok) return r;
+  if (!filter_ok(filt, (int)sub[6], t.th, t.ph, lane)) return r;
+  r.ok = true;
+  r.sw = sw;
+  r.arm = arm;
+  return r;
+}
+
+// enter feasibility restoration from the main iterate; false if it cannot start
+__device__ bool resto_enter(const Cfg& c, const Slot& s, int lane) {
+  const double thk = s.sc[SC_THK], phk = s.sc[SC_PHK];
+  if (thk <= c.tol) return false;
+  int nf = filter_add(s.fm, (int)s.sc[SC_NF], c.fcap, (1.0 - c.gamma_theta) * thk, phk - c.gamma_phi * thk, lane);
+  if (nf < 0) {
+    if (lane == 0) { s.sc[SC_OVERFLOW] = 1.0; s.sc[SC_NF] = -1 - nf; }
+    return true;
+  }
+  double cmax = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) cmax = fmax(cmax, fabs(s.rc[r]));
+  cmax = wmax(cmax);
+  const double mu = s.sc[SC_MU];
+  const double muR = fmax(mu, cmax);
+  const double rho = c.rho_resto;
+  for (int i = lane; i < c.n; i += WAVE) s.xr[i] = s.v[i];
+  double th0 = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) {
+    double cv = -s.rc[r];
+    double a = (muR - rho * cv) / (2.0 * rho);
+    double nn = a + sqrt(a * a + muR * cv / (2.0 * rho));
+    double pp = cv + nn;
+    s.p[r] = pp;
+    s.nn[r] = nn;
+    s.zp[r] = muR / pp;
+    s.zn[r] = muR / nn;
+    s.yr[r] = 0.0;
+    th0 += fabs(cv - pp + nn);
+  }
+  th0 = wsum(th0);
+  for (int b = lane; b < c.N * NU; b += WAVE) { s.rzlu[b] = fmin(rho, s.zlu[b]); s.rzuu[b] = fmin(rho, s.zuu[b]); }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) s.rzls[q] = fmin(rho, s.zls[q]);
+  __syncthreads();
+  if (lane == 0) {
+    s.sc[SC_NF] = nf;
+    s.sc[SC_THR] = thk;
+    s.sc[SC_RMU] = muR;
+    s.sc[SC_RTAU] = fmax(c.tau_min, 1.0 - muR);
+    s.sc[SC_RDXL] = 0.0;
+    s.sc[SC_RTINY] = 0.0;
+    s.sc[SC_RNF] = 0.0;
+    s.sc[SC_RTHMAX] = 1e4 * fmax(1.0, th0);
+    s.sc[SC_RTHMIN] = 1e-4 * fmax(1.0, th0);
+    s.sc[SC_ST_RENT] += 1.0;
+    s.sc[SC_PHASE] = PH_RESTO;
+  }
+  __syncthreads();
+  return true;
+}
+
+// after an accepted restoration step: return to the original problem if possible
+__device__ void resto_try_exit(const Cfg& c, const Slot& s, int lane) {
+  // original constraints and barrier objective at v (main mu)
+  for (int i = lane; i < c.n; i += WAVE) s.vt[i] = s.v[i];
+  __syncthreads();
+  const double mu = s.sc[SC_MU];
+  Trial t = eval_trial(c, s, false, mu, 0.0, lane);
+  if (!t.fin) return;
+  if (!(t.th <= c.kappa_resto * s.sc[SC_THR])) return;
+  if (!filter_ok(s.fm, (int)s.sc[SC_NF], t.th, t.ph, lane)) return;
+  double zmax = 0.0;
+  for (int b = lane; b < c.N * NU; b += WAVE) zmax = fmax(zmax, fmax(s.rzlu[b], s.rzuu[b]));
+  for (int q = lane; q < c.N * c.NI; q += WAVE) zmax = fmax(zmax, s.rzls[q]);
+  zmax = wmax(zmax);
+  const bool reset = zmax > c.bound_mult_reset;
+  for (int b = lane; b < c.N * NU; b += WAVE) {
+    s.zlu[b] = reset ? 1.0 : s.rzlu[b];
+    s.zuu[b] = reset ? 1.0 : s.rzuu[b];
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) s.zls[q] = reset ? 1.0 : s.rzls[q];
+  __syncthreads();
+  if (lane == 0) {
+    s.sc[SC_TINY] = 0.0;
+    s.sc[SC_PHASE] = PH_INIT_Y;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
+  __shared__ KktLds L;
+  const int slot = blockIdx.x, lane = threadIdx.x;
+  Slot s = make_slot(c, ws, slot);
+  const int ph = (int)s.sc[SC_PHASE];
+  if (ph != PH_REGULAR && ph != PH_RESTO) return;
+  const int step = (int)s.sc[SC_STEP];
+  if (step == STEP_NONE) return;
+  __syncthreads();
+  if (lane == 0) s.sc[SC_STEP] = STEP_NONE;
+  const bool resto = (ph == PH_RESTO);
+  Iter it = cur_iter(s, resto);
+  double* sub = it.sub;
+  const double mu = sub[0], tau = sub[1];
+  const double zeta = resto ? sqrt(mu) : 0.0;
+  const double thk = s.sc[SC_THK], phk = s.sc[SC_PHK], gphi = s.sc[SC_GPHI], amax = s.sc[SC_AMAX];
+  bool accepted = false, augment = false, soc_dir = false, tiny = false;
+  double ap = amax;
+  if (step == STEP_READY) {
+    // tiny step (Table I row 4) at a nearly feasible point
+    double tmax = 0.0, cmax = 0.0;
+    for (int i = lane; i < c.n; i += WAVE) tmax = fmax(tmax, fabs(s.dv[i]) / (1.0 + fabs(s.v[i])));
+    if (resto)
+      for (int r = lane; r < c.m; r += WAVE) {
+        tmax = fmax(tmax, fabs(s.dp[r]) / (1.0 + fabs(s.p[r])));
+        tmax = fmax(tmax, fabs(s.dn[r]) / (1.0 + fabs(s.nn[r])));
+      }
+    for (int r = lane; r < c.m; r += WAVE) cmax = fmax(cmax, fabs(s.rc[r]));
+    tmax = wmax(tmax);
+    cmax = wmax(cmax);
+    if (tmax < 10.0 * 2.220446049250313e-16 && cmax <= 1e-4) {
+      make_trial(c, s, resto, amax, s.dv, s.dp, s.dn, lane);
+      tiny = true;
+      accepted = true;
+    } else {
+      double amin;
+      if (gphi < 0) {
+        double t = fmin(c.gamma_theta, c.gamma_phi * thk / (-gphi));
+        if (thk <= sub[4]) t = fmin(t, c.delta_sw * pow(thk, c.s_theta) / pow(-gphi, c.s_phi));
+        amin = c.gamma_alpha * t;
+      } else {
+        amin = c.gamma_alpha * c.gamma_theta;
+      }
+      double alpha = amax;
+      for (int l = 0;; ++l) {
+        // alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point)
+        if (alpha < amin || l >= 60) break;
+        make_trial(c, s, resto, alpha, s.dv, s.dp, s.dn, lane);
+        Trial t = eval_trial(c, s, resto, mu, zeta, lane);
+        Acc a = acceptable(c, sub, it.filt, thk, phk, gphi, alpha, t, lane);
+        if (a.ok) {
+          ap = alpha;
+          augment = !(a.sw && a.arm);
+          accepted = true;
+          break;
+        }
+        if (l == 0 && t.fin && c.max_soc > 0 && t.th >= thk) {
+          // second-order correction with the stored factor (Table I row 2)
+          double asoc = alpha, th_old = 0.0, tht = t.th;
+          bool fin = true;
+          for (int r = lane; r < c.m; r += WAVE) s.csoc[r] = -s.rc[r];
+          __syncthreads();
+          Elim e{false, resto, s.sc[SC_LDX], s.sc[SC_LDC], zeta};
+          for (int p = 0; p < c.max_soc; ++p) {
+            if (p > 0 && !(tht <= c.kappa_soc * th_old)) break;
+            th_old = tht;
+            for (int r = lane; r < c.m; r += WAVE) {
+              s.csoc[r] = asoc * s.csoc[r] + s.ct[r];
+              s.ct[r] = -s.csoc[r];      // right-hand side rows of the constraints
+            }
+            __syncthreads();
+            kkt_solve(c, s, it, e, s.rv, s.ct, s.rp, s.rn, s.dvs, s.dys, s.dps, s.dns, L, lane);
+            if (lane == 0) s.sc[SC_ST_SOCT] += 1.0;
+            asoc = ftb_primal(c, s, s.dvs, s.dps, s.dns, resto, tau, lane);
+            make_trial(c, s, resto, asoc, s.dvs, s.dps, s.dns, lane);
+            Trial ts = eval_trial(c, s, resto, mu, zeta, lane);
+            tht = ts.th;
+            fin = ts.fin;
+            Acc as = acceptable(c, sub, it.filt, thk, phk, gphi, alpha, ts, lane);
+            if (as.ok) {
+              ap = asoc;
+              augment = !(as.sw && as.arm);
+              accepted = true;
+              soc_dir = true;
+              if (lane == 0) s.sc[SC_ST_SOCA] += 1.0;
+              break;
+            }
+            if (!fin) break;
+          }
+          if (accepted) break;
+        }
+        alpha *= 0.5;
+      }
+    }
+  }
+  __syncthreads();
+  if (!accepted) {
+    // line search or inertia correction failed
+    if (!resto) {
+      if (!resto_enter(c, s, lane)) {
+        if (lane == 0) { s.sc[SC_STATUS] = ST_RESTO_FAILED; s.sc[SC_PHASE] = PH_FINISH; }
+      } else if (s.sc[SC_OVERFLOW] != 0.0) {
+        if (lane == 0) { s.sc[SC_STATUS] = ST_FILTER_OVERFLOW; s.sc[SC_PHASE] = PH_FINISH; }
+      }
+    } else {
+      for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
+      if (lane == 0) { s.sc[SC_STATUS] = ST_RESTO_FAILED; s.sc[SC_PHASE] = PH_FINISH; }
+    }
+    __syncthreads();
+    return;
+  }
+  // ---- accept: (Table I) primal and y with the primal step, z with the dual fraction to the boundary
+  if (soc_dir) dz_recover(c, s, it, mu, s.dvs, s.dps, s.dns, lane);
+  const double az = ftb_dual(c, s, it, tau, lane);
+  const double* ady = soc_dir ? s.dys : s.dy;
+  if (augment) {
+    int nf = filter_add(it.filt, (int)sub[6], c.fcap, (1.0 - c.gamma_theta) * thk, phk - c.gamma_phi * thk, lane);
+    if (lane == 0) {
+      if (nf < 0) { s.sc[SC_OVERFLOW] = 1.0; sub[6] = -1 - nf; }
+      else sub[6] = nf;
+    }
+  }
+  for (int r = lane; r < c.m; r += WAVE) it.y[r] += ap * ady[r];
+  for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.vt[i];
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE) { s.p[r] = s.pt[r]; s.nn[r] = s.nt[r]; }
+  __syncthreads();
+  const double ks = c.kappa_sigma;
+  for (int b = lane; b < c.N * NU; b += WAVE) {
+    int k = b / NU, i = b % NU;
+    double u = s.v[uo(k) + i];
+    double z = it.zlu[b] + az * s.dzlu[b];
+    it.zlu[b] = fmax(fmin(z, ks * mu / u), mu / (ks * u));
+    double su = c.umax - u;
+    z = it.zuu[b] + az * s.dzuu[b];
+    it.zuu[b] = fmax(fmin(z, ks * mu / su), mu / (ks * su));
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) {
+    double sv = s.v[c.n_w + q];
+    double z = it.zls[q] + az * s.dzls[q];
+    it.zls[q] = fmax(fmin(z, ks * mu / sv), mu / (ks * sv));
+  }
+  if (resto)
+    for (int r = lane; r < c.m; r += WAVE) {
+      double z = s.zp[r] + az * s.dzp[r];
+      s.zp[r] = fmax(fmin(z, ks * mu / s.p[r]), mu / (ks * s.p[r]));
+      z = s.zn[r] + az * s.dzn[r];
+      s.zn[r] = fmax(fmin(z, ks * mu / s.nn[r]), mu / (ks * s.nn[r]));
+    }
+  __syncthreads();
+  if (lane == 0) {
+    if (tiny) { sub[5] = 1.0; s.sc[SC_ST_TINY] += 1.0; }
+    s.sc[SC_ITER] += 1.0;
+    if (resto) s.sc[SC_ST_RESTO] += 1.0;
+    s.sc[SC_LALPHA] = ap;
+    s.sc[SC_LALPHAZ] = az;
+    s.sc[SC_LSOC] = soc_dir ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (s.sc[SC_OVERFLOW] != 0.0) {
+    if (lane == 0) { s.sc[SC_STATUS] = ST_FILTER_OVERFLOW; s.sc[SC_PHASE] = PH_FINISH; }
+    if (resto) for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
+    return;
+  }
+  if (resto) resto_try_exit(c, s, lane);
+}
+
+// ============================================================================ parity hooks
+__global__ __launch_bounds__(64) void k_stage_derivs(Cfg c, int count, const double* x, const double* u,
+                                                     const double* lam, double* F, double* G, double* H) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= count * NZ) return;
+  const int k = item / NZ, j = item % NZ;
+  double xx[NX], uu[NU], ll[NX], Fv[NX], Gc[NX], Hc[NZ];
+  for (int i = 0; i < NX; ++i) { xx[i] = x[k * NX + i]; ll[i] = lam[k * NX + i]; }
+  for (int i = 0; i < NU; ++i) uu[i] = u[k * NU + i];
+  rk4_deriv_dir(c, xx, uu, ll, j, j == 0 ? Fv : nullptr, Gc, Hc);
+  for (int i = 0; i < NX; ++i) G[(long long)k * NX * NZ + i * NZ + j] = Gc[i];
+  for (int i = 0; i < NZ; ++i) H[(long long)k * NZ * NZ + i * NZ + j] = Hc[i];
+  if (j == 0)
+    for (int i = 0; i < NX; ++i) F[k * NX + i] = Fv[i];
+}
+
+// factor + solve the regular-phase system of slot `blockIdx.x` (derivatives already evaluated)
+__global__ __launch_bounds__(64) void k_kkt_test(Cfg c, double* ws, double mu, double dxp, double dcp,
+                                                 const double* rhs, double* sol, int* inertia_ok) {
+  __shared__ KktLds L;
+  const int slot = blockIdx.x, lane = threadIdx.x;
+  Slot s = make_slot(c, ws, slot);
+  Iter it = cur_iter(s, false);
+  (void)mu;
+  Elim e{false, false, dxp, dcp, 0.0};
+  int st = kkt_factor(c, s, it, e, 0.0, L, lane);
+  if (lane == 0) inertia_ok[slot] = (st == 0) ? 1 : 0;
+  if (st != 0) return;
+  const double* b = rhs + (long long)slot * (c.n + c.m);
+  for (int i = lane; i < c.n; i += WAVE) s.rv[i] = b[i];
+  for (int r = lane; r < c.m; r += WAVE) s.rc[r] = b[c.n + r];
+  __syncthreads();
+  kkt_solve(c, s, it, e, s.rv, s.rc, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, L, lane);
+  double* o = sol + (long long)slot * (c.n + c.m);
+  for (int i = lane; i < c.n; i += WAVE) o[i] = s.dv[i];
+  for (int r = lane; r < c.m; r += WAVE) o[c.n + r] = s.dy[r];
+}
+
+}  // namespace hipipm
+
+// ============================================================================ launch wrappers
+namespace hipipm {
+void launch_eval(const Cfg& c, double* ws, int slots, hipStream_t st) {
+  long long items = (long long)slots * c.N * NZ;
+  int blocks = (int)((items + 255) / 256);
+  if (blocks > 0) hipLaunchKernelGGL(k_eval, dim3(blocks), dim3(256), 0, st, c, ws, slots);
+}
+void launch_factor(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+                   Counters* cnt, int refill, hipStream_t st) {
+  hipLaunchKernelGGL(k_factor, dim3(slots), dim3(WAVE), 0, st, c, ws, theta, warm_x, out, cnt, refill);
+}
+void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st) {
+  hipLaunchKernelGGL(k_ls, dim3(slots), dim3(WAVE), 0, st, c, ws);
+}
+void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm_x,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_setup, dim3(slots), dim3(WAVE), 0, st, c, ws, slots, n_active, theta, warm_x);
+}
+void launch_stage_derivs(const Cfg& c, int count, const double* x, const double* u, const double* lam, double* F,
+                         double* G, double* H, hipStream_t st) {
+  int blocks = (count * NZ + 63) / 64;
+  if (blocks > 0) hipLaunchKernelGGL(k_stage_derivs, dim3(blocks), dim3(64), 0, st, c, count, x, u, lam, F, G, H);
+}
+void launch_kkt_test(const Cfg& c, double* ws, int count, double mu, double dxp, double dcp, const double* rhs,
+                     double* sol, int* inertia_ok, hipStream_t st) {
+  hipLaunchKernelGGL(k_kkt_test, dim3(count), dim3(WAVE), 0, st, c, ws, mu, dxp, dcp, rhs, sol, inertia_ok);
+}
+}  // namespace hipipm
