@@ -25,6 +25,7 @@ void launch_stage_derivs(const Cfg& c, int count, const double* x, const double*
                          double* G, double* H, hipStream_t st);
 void launch_kkt_test(const Cfg& c, double* ws, int count, double mu, double dxp, double dcp, const double* rhs,
                      double* sol, int* inertia_ok, hipStream_t st);
+void launch_prepare(const Cfg& c, double* ws, int count, hipStream_t st);
 }  // namespace hipipm
 
 using namespace hipipm;
@@ -78,6 +79,7 @@ static void layout(Cfg& c) {
   c.o_rv = take(n); c.o_rc = take(m); c.o_rp = take(m); c.o_rn = take(m);
   c.o_vt = take(n); c.o_ct = take(m); c.o_pt = take(m); c.o_nt = take(m); c.o_csoc = take(m);
   c.o_dvs = take(n); c.o_dys = take(m); c.o_dps = take(m); c.o_dns = take(m); c.o_g = take(n);
+  c.o_ref = take((N + 1) * NX);
   c.stride = rup(o, 64);
 }
 
@@ -425,6 +427,9 @@ int hipipm_state_import(hipipm_ctx* c, int32_t count, const double* in, const do
                              hipMemcpyHostToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
   }
+  launch_prepare(g, c->ws, count, st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(st));
   return HIPIPM_OK;
 }
 
@@ -473,6 +478,7 @@ int hipipm_kkt_factor_solve(hipipm_ctx* c, int32_t count, const double* theta, c
     HIPCHK(c, hipMemcpyAsync(c->ws + (size_t)s * g.stride, rec.data(), g.stride * 8, hipMemcpyHostToDevice, st));
     HIPCHK(c, hipStreamSynchronize(st));
   }
+  launch_prepare(g, c->ws, count, st);
   launch_eval(g, c->ws, count, st);
   launch_kkt_test(g, c->ws, count, mu, delta_x, delta_c, rhs, sol, inertia_ok, st);
   HIPCHK(c, hipGetLastError());

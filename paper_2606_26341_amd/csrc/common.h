@@ -56,7 +56,7 @@ struct Cfg {
   int o_F, o_G, o_HW, o_fac, o_rb;
   int o_dv, o_dy, o_dzlu, o_dzuu, o_dzls, o_dp, o_dn, o_dzp, o_dzn;
   int o_rv, o_rc, o_rp, o_rn, o_vt, o_ct, o_pt, o_nt, o_csoc, o_dvs, o_dys, o_dps, o_dns;
-  int o_g;
+  int o_g, o_ref;
 };
 
 // caller-owned output arrays of a solve

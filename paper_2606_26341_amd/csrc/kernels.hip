@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_eval(Cfg c, double* ws, int slots) {
 __device__ __forceinline__ double fdiv_safe(double a, double b) { return a / b; }
 
 // -c at the current point into rc (restoration: -(c - p + n))
-__device__ void eval_c(const Cfg& c, const Slot& s, bool resto, int lane) {
+__device__ __forceinline__ void eval_c(const Cfg& c, const Slot& s, bool resto, int lane) {
   const int N = c.N, NI = c.NI;
   for (int r = lane; r < (N + 1) * NX; r += WAVE) {
     int k = r / NX, i = r % NX;
@@ -74,7 +74,7 @@ __device__ void eval_c(const Cfg& c, const Slot& s, bool resto, int lane) {
 }
 
 // objective gradient g = grad f (regular) or grad f_R (restoration, v part) and A^T y into aty
-__device__ void eval_grad(const Cfg& c, const Slot& s, const double* yv, bool resto, double zeta, double* aty,
+__device__ __forceinline__ void eval_grad(const Cfg& c, const Slot& s, const double* yv, bool resto, double zeta, double* aty,
                           int lane) {
   const int N = c.N, NI = c.NI;
   for (int i = lane; i < c.n; i += WAVE) {
@@ -85,9 +85,7 @@ __device__ void eval_grad(const Cfg& c, const Slot& s, const double* yv, bool re
     } else if (i < c.n_w) {
       int k = i / NZ, r = i % NZ;
       if (r < NX) {
-        double xr[NX];
-        ref_state(c, s.th, k, xr);
-        gi = 2.0 * c.qw * (s.v[i] - xr[r]);
+        gi = 2.0 * c.qw * (s.v[i] - s.ref[k * NX + r]);
       } else {
         gi = 2.0 * c.rw * (s.v[i] - c.uh);
       }
@@ -136,7 +134,7 @@ struct ErrParts {
   int nL, nU;
 };
 
-__device__ ErrParts err_parts(const Cfg& c, const Slot& s, const Iter& it, const double* aty, int lane) {
+__device__ __forceinline__ ErrParts err_parts(const Cfg& c, const Slot& s, const Iter& it, const double* aty, int lane) {
   double dual = 0.0, nanf = 0.0, z1 = 0.0, y1 = 0.0, prim = 0.0;
   for (int i = lane; i < c.n; i += WAVE) {
     double zl, zu;
@@ -170,7 +168,7 @@ __device__ ErrParts err_parts(const Cfg& c, const Slot& s, const Iter& it, const
 }
 
 // max |s z - mu| over the bounded components
-__device__ double compl_max(const Cfg& c, const Slot& s, const Iter& it, double mu, int lane) {
+__device__ __forceinline__ double compl_max(const Cfg& c, const Slot& s, const Iter& it, double mu, int lane) {
   double cm = 0.0;
   for (int b = lane; b < c.N * NU; b += WAVE) {
     int k = b / NU, i = b % NU;
@@ -187,7 +185,7 @@ __device__ double compl_max(const Cfg& c, const Slot& s, const Iter& it, double 
   return wmax(cm);
 }
 
-__device__ double kkt_err(const Cfg& c, const ErrParts& e, double cm, int m) {
+__device__ __forceinline__ double kkt_err(const Cfg& c, const ErrParts& e, double cm, int m) {
   double sd = 1.0, sc = 1.0;
   if (m + e.nL + e.nU > 0) sd = fmax(c.s_max, (e.y1 + e.z1) / (double)(m + e.nL + e.nU)) / c.s_max;
   if (e.nL + e.nU > 0) sc = fmax(c.s_max, e.z1 / (double)(e.nL + e.nU)) / c.s_max;
@@ -199,14 +197,12 @@ __device__ double kkt_err(const Cfg& c, const ErrParts& e, double cm, int m) {
 }
 
 // objective value at v (regular) -- wave sum
-__device__ double obj_regular(const Cfg& c, const Slot& s, const double* v, int lane) {
+__device__ __forceinline__ double obj_regular(const Cfg& c, const Slot& s, const double* v, int lane) {
   double f = 0.0;
   for (int i = lane; i < c.n_w; i += WAVE) {
     int k = i / NZ, r = i % NZ;
     if (r < NX) {
-      double xr[NX];
-      ref_state(c, s.th, k, xr);
-      double e = v[i] - xr[r];
+      double e = v[i] - s.ref[k * NX + r];
       f += c.qw * e * e;
     } else {
       double e = v[i] - c.uh;
@@ -217,7 +213,7 @@ __device__ double obj_regular(const Cfg& c, const Slot& s, const double* v, int 
 }
 
 // restoration objective rho sum(p + n) + zeta/2 |D_R (v - x_R)|^2
-__device__ double obj_resto(const Cfg& c, const Slot& s, const double* v, const double* p, const double* nn,
+__device__ __forceinline__ double obj_resto(const Cfg& c, const Slot& s, const double* v, const double* p, const double* nn,
                             double zeta, int lane) {
   double a = 0.0, q = 0.0;
   for (int r = lane; r < c.m; r += WAVE) a += p[r] + nn[r];
@@ -230,7 +226,7 @@ __device__ double obj_resto(const Cfg& c, const Slot& s, const double* v, const 
 }
 
 // sum of log-slacks of the bounded components; NaN if one is not positive
-__device__ double log_barrier(const Cfg& c, const double* v, const double* p, const double* nn, bool resto,
+__device__ __forceinline__ double log_barrier(const Cfg& c, const double* v, const double* p, const double* nn, bool resto,
                               int lane) {
   double b = 0.0, bad = 0.0;
   for (int bb = lane; bb < c.N * NU; bb += WAVE) {
@@ -255,7 +251,7 @@ __device__ double log_barrier(const Cfg& c, const double* v, const double* p, co
 }
 
 // primal fraction to the boundary over the bounded components of (dv, dp, dn)
-__device__ double ftb_primal(const Cfg& c, const Slot& s, const double* dv, const double* dp, const double* dn,
+__device__ __forceinline__ double ftb_primal(const Cfg& c, const Slot& s, const double* dv, const double* dp, const double* dn,
                              bool resto, double tau, int lane) {
   double a = 1.0;
   for (int bb = lane; bb < c.N * NU; bb += WAVE) {
@@ -277,7 +273,7 @@ __device__ double ftb_primal(const Cfg& c, const Slot& s, const double* dv, cons
 }
 
 // bound-multiplier steps (eq. (6) rows 3-4 eliminated): into dzlu, dzuu, dzls, dzp, dzn
-__device__ void dz_recover(const Cfg& c, const Slot& s, const Iter& it, double mu, const double* dv,
+__device__ __forceinline__ void dz_recover(const Cfg& c, const Slot& s, const Iter& it, double mu, const double* dv,
                            const double* dp, const double* dn, int lane) {
   for (int bb = lane; bb < c.N * NU; bb += WAVE) {
     int k = bb / NU, i = bb % NU;
@@ -298,7 +294,7 @@ __device__ void dz_recover(const Cfg& c, const Slot& s, const Iter& it, double m
   __syncthreads();
 }
 
-__device__ double ftb_dual(const Cfg& c, const Slot& s, const Iter& it, double tau, int lane) {
+__device__ __forceinline__ double ftb_dual(const Cfg& c, const Slot& s, const Iter& it, double tau, int lane) {
   double a = 1.0;
   for (int bb = lane; bb < c.N * NU; bb += WAVE) {
     if (s.dzlu[bb] < 0) a = fmin(a, -tau * it.zlu[bb] / s.dzlu[bb]);
@@ -315,7 +311,7 @@ __device__ double ftb_dual(const Cfg& c, const Slot& s, const Iter& it, double t
 }
 
 // filter: reject if theta >= theta_F and phi >= phi_F for some entry
-__device__ bool filter_ok(const double* filt, int nf, double th, double ph, int lane) {
+__device__ __forceinline__ bool filter_ok(const double* filt, int nf, double th, double ph, int lane) {
   int bad = 0;
   for (int i = lane; i < nf; i += WAVE)
     if (th >= filt[i] && ph >= filt[FCAP + i]) bad = 1;
@@ -323,7 +319,7 @@ __device__ bool filter_ok(const double* filt, int nf, double th, double ph, int 
 }
 
 // add an entry, dropping the entries it dominates; returns the new count (-1 on overflow)
-__device__ int filter_add(double* filt, int nf, int cap, double th, double ph, int lane) {
+__device__ __forceinline__ int filter_add(double* filt, int nf, int cap, double th, double ph, int lane) {
   __shared__ int res;
   if (lane == 0) {
     int w = 0;
@@ -348,11 +344,28 @@ __device__ int filter_add(double* filt, int nf, int cap, double th, double ph, i
 }
 
 // ============================================================================ slot initialisation
-__device__ void init_instance(const Cfg& c, const Slot& s, int inst, const double* theta, const double* warm_x,
+// reference states x_ref,k (k = 0..N) of the cost, tabulated once per instance
+__device__ __forceinline__ void fill_ref(const Cfg& c, const Slot& s, int lane) {
+  for (int k = lane; k <= c.N; k += WAVE) {
+    double xr[NX];
+    ref_state(c, s.th, k, xr);
+#pragma unroll
+    for (int r = 0; r < NX; ++r) s.ref[k * NX + r] = xr[r];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_prepare(Cfg c, double* ws) {
+  Slot s = make_slot(c, ws, blockIdx.x);
+  fill_ref(c, s, threadIdx.x);
+}
+
+__device__ __forceinline__ void init_instance(const Cfg& c, const Slot& s, int inst, const double* theta, const double* warm_x,
                               int lane) {
   const double* th = theta + (long long)inst * c.n_theta;
   for (int i = lane; i < c.n_theta; i += WAVE) s.th[i] = th[i];
   __syncthreads();
+  fill_ref(c, s, lane);
   for (int i = lane; i < c.n; i += WAVE) {
     double x;
     if (warm_x) {
@@ -413,7 +426,7 @@ __global__ __launch_bounds__(64) void k_setup(Cfg c, double* ws, int slots, int 
 
 // ============================================================================ factor kernel
 // finished instance: write the results (main problem, E_0 at the point), pop the next one
-__device__ void finish_slot(const Cfg& c, const Slot& s, const double* theta, const double* warm_x, Outs out,
+__device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const double* theta, const double* warm_x, Outs out,
                             Counters* cnt, bool refill, int lane) {
   Iter it = cur_iter(s, false);
   eval_c(c, s, false, lane);
@@ -466,7 +479,7 @@ __device__ void finish_slot(const Cfg& c, const Slot& s, const double* theta, co
 }
 
 // least-squares equality multipliers: [[I, A^T], [A, 0]] [d; y] = -[grad f - z_L + z_U; 0]
-__device__ void init_y(const Cfg& c, const Slot& s, KktLds& L, int lane) {
+__device__ __forceinline__ void init_y(const Cfg& c, const Slot& s, KktLds& L, int lane) {
   Iter it = cur_iter(s, false);
   eval_c(c, s, false, lane);
   eval_grad(c, s, s.y, false, 0.0, s.vt, lane);
@@ -654,7 +667,7 @@ struct Trial {
 };
 
 // evaluate the trial point vt (pt, nt): constraints into ct, theta = |ct|_1, phi_mu
-__device__ Trial eval_trial(const Cfg& c, const Slot& s, bool resto, double mu, double zeta, int lane) {
+__device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool resto, double mu, double zeta, int lane) {
   const int N = c.N, NI = c.NI;
   if (lane < N) {
     double x[NX], u[NU], F[NX];
@@ -699,7 +712,7 @@ struct Acc {
   bool ok, sw, arm;
 };
 
-__device__ Acc acceptable(const Cfg& c, const double* sub, const double* filt, double thk, double phk, double gphi,
+__device__ __forceinline__ Acc acceptable(const Cfg& c, const double* sub, const double* filt, double thk, double phk, double gphi,
                           double alpha, const Trial& t, int lane) {
   Acc r{false, false, false};
   if (!t.fin) return r;
@@ -719,7 +732,7 @@ __device__ Acc acceptable(const Cfg& c, const double* sub, const double* filt, d
 }
 
 // enter feasibility restoration from the main iterate; false if it cannot start
-__device__ bool resto_enter(const Cfg& c, const Slot& s, int lane) {
+__device__ __forceinline__ bool resto_enter(const Cfg& c, const Slot& s, int lane) {
   const double thk = s.sc[SC_THK], phk = s.sc[SC_PHK];
   if (thk <= c.tol) return false;
   int nf = filter_add(s.fm, (int)s.sc[SC_NF], c.fcap, (1.0 - c.gamma_theta) * thk, phk - c.gamma_phi * thk, lane);
@@ -769,7 +782,7 @@ __device__ bool resto_enter(const Cfg& c, const Slot& s, int lane) {
 }
 
 // after an accepted restoration step: return to the original problem if possible
-__device__ void resto_try_exit(const Cfg& c, const Slot& s, int lane) {
+__device__ __forceinline__ void resto_try_exit(const Cfg& c, const Slot& s, int lane) {
   // original constraints and barrier objective at v (main mu)
   for (int i = lane; i < c.n; i += WAVE) s.vt[i] = s.v[i];
   __syncthreads();
@@ -1025,6 +1038,9 @@ void launch_stage_derivs(const Cfg& c, int count, const double* x, const double*
                          double* G, double* H, hipStream_t st) {
   int blocks = (count * NZ + 63) / 64;
   if (blocks > 0) hipLaunchKernelGGL(k_stage_derivs, dim3(blocks), dim3(64), 0, st, c, count, x, u, lam, F, G, H);
+}
+void launch_prepare(const Cfg& c, double* ws, int count, hipStream_t st) {
+  if (count > 0) hipLaunchKernelGGL(k_prepare, dim3(count), dim3(WAVE), 0, st, c, ws);
 }
 void launch_kkt_test(const Cfg& c, double* ws, int count, double mu, double dxp, double dcp, const double* rhs,
                      double* sol, int* inertia_ok, hipStream_t st) {

@@ -25,7 +25,7 @@ struct Slot {
   double *yr, *rzlu, *rzuu, *rzls, *xr, *p, *nn, *zp, *zn;
   double *F, *G, *HW, *fac, *rb;
   double *dv, *dy, *dzlu, *dzuu, *dzls, *dp, *dn, *dzp, *dzn;
-  double *rv, *rc, *rp, *rn, *vt, *ct, *pt, *nt, *csoc, *dvs, *dys, *dps, *dns, *g;
+  double *rv, *rc, *rp, *rn, *vt, *ct, *pt, *nt, *csoc, *dvs, *dys, *dps, *dns, *g, *ref;
 };
 
 __device__ __forceinline__ Slot make_slot(const Cfg& c, double* ws, int slot) {
@@ -42,6 +42,7 @@ __device__ __forceinline__ Slot make_slot(const Cfg& c, double* ws, int slot) {
   s.rv = R + c.o_rv; s.rc = R + c.o_rc; s.rp = R + c.o_rp; s.rn = R + c.o_rn;
   s.vt = R + c.o_vt; s.ct = R + c.o_ct; s.pt = R + c.o_pt; s.nt = R + c.o_nt; s.csoc = R + c.o_csoc;
   s.dvs = R + c.o_dvs; s.dys = R + c.o_dys; s.dps = R + c.o_dps; s.dns = R + c.o_dns; s.g = R + c.o_g;
+  s.ref = R + c.o_ref;
   return s;
 }
 
@@ -100,7 +101,8 @@ struct KktLds {
   double dh[NX];
   double jg[MAX_OBS * 3];
   double Dg[MAX_OBS];
-  double vec[4][32];
+  double vec[8][32];
+  double fr[FR_LEN];
   int bad;
 };
 
@@ -165,7 +167,7 @@ __device__ __forceinline__ int chol_lds(double* A, int n, int ld, int lane) {
 // ----------------------------------------------------------------------------- factorization
 // Assemble and factor all stage blocks; returns 0 (inertia correct), 1 (wrong), 2 (singular).
 // Per-stage factor records are written to s.fac.
-__device__ int kkt_factor(const Cfg& c, const Slot& s, const Iter& it, const Elim& e, double zeta, KktLds& L,
+__device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Iter& it, const Elim& e, double zeta, KktLds& L,
                           int lane) {
   const int N = c.N, NI = c.NI;
   for (int i = lane; i < NX * NX; i += WAVE) L.S[i] = 0.0;
@@ -325,40 +327,45 @@ __device__ int kkt_factor(const Cfg& c, const Slot& s, const Iter& it, const Eli
 }
 
 // ----------------------------------------------------------------------------- solve
-// Apply M_k^{-1} to (ra, rx, ru) of stage k with the stored factor: writes lambda (a), x (b)
-// and, for k < N, u (cu) into L.vec rows 0..2.  ra, rx, ru live in L.vec rows 1..3 on entry
-// (vec[1] = ra, vec[2] = rx, vec[3][0..3] = ru).  One lane computes (the blocks are tiny).
+// Apply M_k^{-1} to (ra, rx, ru) of stage k with its factor record: on entry L.vec[1] = ra,
+// L.vec[2] = rx, L.vec[3][0..3] = ru; on exit L.vec[0] = lambda part a and, if `full`,
+// L.vec[2] = x part b and L.vec[3] = u part.  The record is first staged into LDS with
+// coalesced loads; the small products are spread over lanes.
 __device__ __forceinline__ void stage_apply(const Cfg& c, const double* fr, bool has_u, KktLds& L, bool full,
                                             int lane) {
-  if (lane == 0) {
-    double wu[NU], rbp[NX], t[NX], a[NX];
-    const double* LR = fr + FR_LR;
-    const double* Y = fr + FR_Y;
-    const double* P = fr + FR_P;
-    const double* LC = fr + FR_LC;
-    const double* dh = fr + FR_DH;
-    const bool reg = fr[FR_FLAG] != 0.0;
-    for (int i = 0; i < NX; ++i) rbp[i] = L.vec[2][i];
-    if (has_u) {
-      for (int a2 = 0; a2 < NU; ++a2) {
-        double acc = L.vec[3][a2];
-        for (int l = 0; l < a2; ++l) acc -= LR[a2 * NU + l] * wu[l];
-        wu[a2] = acc / LR[a2 * NU + a2];
-      }
-      for (int i = 0; i < NX; ++i) {
-        double acc = rbp[i];
-        for (int a2 = 0; a2 < NU; ++a2) acc -= Y[a2 * NX + i] * wu[a2];
-        rbp[i] = acc;
-      }
+  double* F = L.fr;
+  for (int q = lane; q < FR_LEN; q += WAVE) F[q] = fr[q];
+  __syncthreads();
+  const double* LR = F + FR_LR;
+  const double* Y = F + FR_Y;
+  const double* P = F + FR_P;
+  const double* LC = F + FR_LC;
+  const double* dh = F + FR_DH;
+  const bool reg = F[FR_FLAG] != 0.0;
+  double* wu = L.vec[4];
+  double* t = L.vec[5];
+  // wu = L_R^{-1} ru
+  if (has_u && lane == 0) {
+    for (int a2 = 0; a2 < NU; ++a2) {
+      double acc = L.vec[3][a2];
+      for (int l = 0; l < a2; ++l) acc -= LR[a2 * NU + l] * wu[l];
+      wu[a2] = acc / LR[a2 * NU + a2];
     }
-    for (int i = 0; i < NX; ++i) {
-      double acc = rbp[i];
-      for (int l = 0; l < NX; ++l) acc -= P[i * NX + l] * L.vec[1][l];
-      t[i] = acc;
-    }
-    if (reg) {
-      // a = Delta^{-1/2} C^{-1} Delta^{1/2} t
-      double z[NX];
+  }
+  __syncthreads();
+  // t = rx - Y^T wu - P ra
+  if (lane < NX) {
+    double acc = L.vec[2][lane];
+    if (has_u)
+      for (int a2 = 0; a2 < NU; ++a2) acc -= Y[a2 * NX + lane] * wu[a2];
+    for (int l = 0; l < NX; ++l) acc -= P[lane * NX + l] * L.vec[1][l];
+    t[lane] = acc;
+  }
+  __syncthreads();
+  if (reg) {
+    // a = Delta^{-1/2} C^{-1} Delta^{1/2} t  with C = L_C L_C^T
+    if (lane == 0) {
+      double* z = L.vec[6];
       for (int i = 0; i < NX; ++i) {
         double acc = dh[i] * t[i];
         for (int l = 0; l < i; ++l) acc -= LC[i * NX + l] * z[l];
@@ -369,79 +376,83 @@ __device__ __forceinline__ void stage_apply(const Cfg& c, const double* fr, bool
         for (int l = i + 1; l < NX; ++l) acc -= LC[l * NX + i] * z[l];
         z[i] = acc / LC[i * NX + i];
       }
-      for (int i = 0; i < NX; ++i) a[i] = z[i] / dh[i];
-    } else {
-      for (int i = 0; i < NX; ++i) a[i] = t[i];
+      for (int i = 0; i < NX; ++i) L.vec[0][i] = z[i] / dh[i];
     }
-    for (int i = 0; i < NX; ++i) L.vec[0][i] = a[i];
-    if (full) {
-      double b[NX];
-      for (int i = 0; i < NX; ++i) b[i] = L.vec[1][i] + (reg ? dh[i] * dh[i] * a[i] : 0.0);
-      for (int i = 0; i < NX; ++i) L.vec[2][i] = b[i];
-      if (has_u) {
-        double cu[NU];
-        for (int a2 = 0; a2 < NU; ++a2) {
-          double acc = wu[a2];
-          for (int i = 0; i < NX; ++i) acc -= Y[a2 * NX + i] * b[i];
-          cu[a2] = acc;
-        }
-        for (int a2 = NU - 1; a2 >= 0; --a2) {
-          double acc = cu[a2];
-          for (int l = a2 + 1; l < NU; ++l) acc -= LR[l * NU + a2] * cu[l];
-          cu[a2] = acc / LR[a2 * NU + a2];
-        }
-        for (int a2 = 0; a2 < NU; ++a2) L.vec[3][a2] = cu[a2];
-      }
-    }
+  } else {
+    if (lane < NX) L.vec[0][lane] = t[lane];
   }
   __syncthreads();
+  if (!full) return;
+  // b = ra + Delta a
+  if (lane < NX) L.vec[2][lane] = L.vec[1][lane] + (reg ? dh[lane] * dh[lane] * L.vec[0][lane] : 0.0);
+  __syncthreads();
+  if (has_u) {
+    // u = L_R^{-T} (wu - Y b)
+    if (lane < NU) {
+      double acc = wu[lane];
+      for (int i = 0; i < NX; ++i) acc -= Y[lane * NX + i] * L.vec[2][i];
+      L.vec[6][lane] = acc;
+    }
+    __syncthreads();
+    if (lane == 0) {
+      double* cu = L.vec[6];
+      for (int a2 = NU - 1; a2 >= 0; --a2) {
+        double acc = cu[a2];
+        for (int l = a2 + 1; l < NU; ++l) acc -= LR[l * NU + a2] * cu[l];
+        cu[a2] = acc / LR[a2 * NU + a2];
+      }
+      for (int a2 = 0; a2 < NU; ++a2) L.vec[3][a2] = cu[a2];
+    }
+    __syncthreads();
+  }
 }
 
 // Solve K [dv; dy] = [bv; bc] (and the eliminated p/n rows bp, bn in restoration) with the
 // factor in s.fac.  Outputs xv (n), xc (m), xp, xn (m; restoration only).
-__device__ void kkt_solve(const Cfg& c, const Slot& s, const Iter& it, const Elim& e, const double* bv,
+__device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Iter& it, const Elim& e, const double* bv,
                           const double* bc, const double* bp, const double* bn, double* xv, double* xc, double* xp,
                           double* xn, KktLds& L, int lane) {
   const int N = c.N, NI = c.NI;
-  // 1. condensed stage right-hand sides into s.rb
-  for (int k = 0; k <= N; ++k) {
-    double* rb = s.rb + (long long)k * RB_LEN;
-    for (int i = lane; i < NX; i += WAVE) {
+  // 1. condensed stage right-hand sides into s.rb (lambda 13, x 13, u 4 per knot)
+  for (int q = lane; q < (N + 1) * RB_LEN; q += WAVE) {
+    int k = q / RB_LEN, i = q % RB_LEN;
+    double val = 0.0;
+    if (i < NX) {
       int r = k * NX + i;
-      double b = bc[r];
+      val = bc[r];
       if (e.resto) {
         double sp, sn;
         row_elastic(s, e, r, sp, sn);
-        b += bp[r] / sp - bn[r] / sn;
+        val += bp[r] / sp - bn[r] / sn;
       }
-      rb[i] = b;
-      rb[NX + i] = bv[xo(k) + i];
+    } else if (i < 2 * NX) {
+      val = bv[xo(k) + i - NX];
+    } else if (i < 2 * NX + NU && k < N) {
+      val = bv[uo(k) + i - 2 * NX];
     }
-    if (k < N)
-      for (int i = lane; i < NU; i += WAVE) rb[2 * NX + i] = bv[uo(k) + i];
+    s.rb[q] = val;
   }
   __syncthreads();
-  for (int k = 1; k <= N; ++k) {
-    // position rows of x_k gather the slack rows of stage k (3 lanes)
-    if (lane < 3) {
-      double acc = 0.0;
-      for (int j = 0; j < NI; ++j) {
-        const double* o = obs_ptr(c, s.th) + 4 * j;
-        int r = go(c, k, j);
-        double sig = slack_sigma(c, s, it, e, k, j);
-        double d = row_d(s, e, r);
-        double D = sig / (1.0 + sig * d);
-        double bg = bc[r];
-        if (e.resto) {
-          double sp, sn;
-          row_elastic(s, e, r, sp, sn);
-          bg += bp[r] / sp - bn[r] / sn;
-        }
-        double jg = 2.0 * (s.v[xo(k) + lane] - o[lane]);
-        acc += jg * D * (bv[so(c, k, j)] / sig + bg);
+  // position rows of x_k gather the slack rows of stage k
+  for (int q = lane; q < N * 3; q += WAVE) {
+    int k = 1 + q / 3, t = q % 3;
+    double acc = 0.0;
+    for (int j = 0; j < NI; ++j) {
+      const double* o = obs_ptr(c, s.th) + 4 * j;
+      int r = go(c, k, j);
+      double sig = slack_sigma(c, s, it, e, k, j);
+      double d = row_d(s, e, r);
+      double D = sig / (1.0 + sig * d);
+      double bg = bc[r];
+      if (e.resto) {
+        double sp, sn;
+        row_elastic(s, e, r, sp, sn);
+        bg += bp[r] / sp - bn[r] / sn;
       }
-      s.rb[(long long)k * RB_LEN + NX + lane] += acc;
+      double jg = 2.0 * (s.v[xo(k) + t] - o[t]);
+      acc += jg * D * (bv[so(c, k, j)] / sig + bg);
     }
+    s.rb[(long long)k * RB_LEN + NX + t] += acc;
   }
   __syncthreads();
   // 2. backward sweep: rbar_k = r_k + G_k^T a_{k+1}
