@@ -30,41 +30,47 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_roofline(w, st, kt, slots_launched):
-    """Roofline of the dominant kernel from the live HIP-event timings.
+# per-knot factor record actually produced: L_R (4x4), Y (4x13), P (13x13), Delta^1/2 (13), flag
+FR_WORDS = 16 + 52 + 169 + 13 + 1
 
-    The factor kernel's algorithmic traffic per slot and factorization attempt is the stage
-    data it must read (dynamics Jacobian G_k, 13x17, and Lagrangian-Hessian block W_k, 17x17,
-    per interval) plus the stage factor it writes (L_R 4x4, Y 4x13, P 13x13 per knot), all FP64.
-    The derivative kernel is bound by FP64 arithmetic: its algorithmic work is counted from the
-    implemented forward-over-adjoint RK4 sweep (flops per stage and direction).
+
+def sd_words(n_obs: int) -> int:
+    """Perturbation-free stage data per knot: Hessian diagonal (17), elastic ratios (2 x 13) and
+    7 words per inequality row, padded to 8 words."""
+    return ((17 + 26 + 7 * n_obs + 7) // 8) * 8
+
+
+def kernel_roofline(w, st, kt, slots_launched):
+    """Roofline of the dominant kernel from the live HIP-event timings (algorithmic FP64 bytes).
+
+    k_fac, per slot and factorization attempt: reads the stage inputs (G_k 13x17 and W_k 17x17 per
+    interval, the stage data per knot) and writes the factor record per knot.
+    k_sol, per solve: reads the factor record and stage data per knot, G_k per interval and the
+    right-hand side (n + m), writes the step (n + m).
     """
     N = w.N
-    names = ("eval", "factor", "linesearch")
-    tot = {k: kt[k][0] for k in names}
+    names = ("eval", "pre", "factor", "solve", "linesearch")
+    tot = {k: kt[k][0] for k in names if k in kt}
     dom = max(tot, key=tot.get)
     ms, launches = kt[dom]
     avg_ms = ms / max(1, launches)
+    sdw = sd_words(w.n_obs)
     if dom == "factor":
-        per_attempt = 8.0 * (N * (13 * 17 + 17 * 17) + (N + 1) * (16 + 52 + 169))
-        attempts = st["factorizations"]
-        bytes_total = per_attempt * attempts
-        per_launch = bytes_total / max(1, launches)
-        achieved = per_launch / (avg_ms * 1e-3) / 1e9
-        return dict(kernel="k_factor", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, avg_ms=avg_ms, launches=launches)
-    if dom == "eval":
-        flops_stage_dir = EVAL_FLOPS_PER_STAGE_DIR
-        per_launch = flops_stage_dir * 17 * N * slots_launched
-        achieved = per_launch / (avg_ms * 1e-3) / 1e12
-        return dict(kernel="k_eval", bound="alu", achieved=achieved, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / FP64_PEAK_TFLOPS, traffic=None, avg_ms=avg_ms, launches=launches)
-    return dict(kernel="k_ls", bound="latency", achieved=None, peak=None, unit=None, frac=None, traffic=None,
-                avg_ms=avg_ms, launches=launches)
-
-
-# flops of one (stage, direction) work item of k_eval, counted from the implemented sweep
-EVAL_FLOPS_PER_STAGE_DIR = 3000.0
+        per_unit = 8.0 * (N * (13 * 17 + 17 * 17) + (N + 1) * (sdw + FR_WORDS))
+        units = st["factorizations"]
+        kernel = "k_fac"
+    elif dom == "solve":
+        per_unit = 8.0 * ((N + 1) * (FR_WORDS + sdw) + N * 13 * 17 + 2 * (w.n + w.m))
+        units = st["iterations"] + st["instances_done"]
+        kernel = "k_sol"
+    else:
+        return dict(kernel="k_" + dom, bound="latency", achieved=None, peak=None, unit=None, frac=None,
+                    traffic=None, avg_ms=avg_ms, launches=launches)
+    per_launch = per_unit * units / max(1, launches)
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    return dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=achieved / HBM_PEAK_GBS, traffic=None, avg_ms=avg_ms, launches=launches,
+                bytes_per_unit=per_unit, units=units)
 
 
 def cpu_baseline(w, sample: int):

@@ -136,7 +136,9 @@ int hipipm_stats_get(const hipipm_ctx* ctx, hipipm_stats* out);
 int hipipm_reset_stats(hipipm_ctx* ctx);
 
 /* Kernel timing (options.timing = 1): total milliseconds and launch counts per kernel since the
- * last reset; names[i] are "eval", "factor", "linesearch", "setup".  n_kernels in/out. */
+ * last reset, in the order "eval", "pre", "factor", "solve", "linesearch", "setup" (the five
+ * kernels of one pass, then the per-solve setup).  *n_kernels: capacity of the arrays on input,
+ * number of timed kernels (6) on output. */
 int hipipm_kernel_times(const hipipm_ctx* ctx, int32_t* n_kernels, double* total_ms, int64_t* launches);
 
 /* ---- test hooks (one-step replay, Sec. VI "Correctness") ----

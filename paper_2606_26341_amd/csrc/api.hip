@@ -1,8 +1,8 @@
 // Host side of libhipipm.so: the C ABI of include/hipipm.h, the slot-record layout and the
-// iteration-level batching driver (Sec. V, Fig. 2): each pass launches the derivative, factor
-// and line-search kernels over all slots; finished slots are refilled from a device-side
-// instance counter inside the factor kernel, and the host polls the completion counter every
-// `poll_every` passes.
+// iteration-level batching driver (Sec. V, Fig. 2): each pass launches the derivative,
+// preparation, factor, solve and line-search kernels over all slots; finished slots are
+// refilled from a device-side instance counter inside the preparation kernel, and the host
+// polls the completion counter every `poll_every` passes.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -16,19 +16,26 @@
 
 namespace hipipm {
 void launch_eval(const Cfg& c, double* ws, int slots, hipStream_t st);
-void launch_factor(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
-                   Counters* cnt, int refill, hipStream_t st);
+void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+                Counters* cnt, int refill, hipStream_t st);
+void launch_fac(const Cfg& c, double* ws, int slots, hipStream_t st);
+void launch_sol(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm_x,
                   hipStream_t st);
 void launch_stage_derivs(const Cfg& c, int count, const double* x, const double* u, const double* lam, double* F,
                          double* G, double* H, hipStream_t st);
-void launch_kkt_test(const Cfg& c, double* ws, int count, double mu, double dxp, double dcp, const double* rhs,
-                     double* sol, int* inertia_ok, hipStream_t st);
+void launch_kkt_test(const Cfg& c, double* ws, int count, double dxp, double dcp, const double* rhs, double* sol,
+                     int* inertia_ok, hipStream_t st);
 void launch_prepare(const Cfg& c, double* ws, int count, hipStream_t st);
+int sd_len_host(int NI);
 }  // namespace hipipm
 
 using namespace hipipm;
+
+// timed kernels: eval, pre, factor, solve, linesearch (one launch each per pass), setup
+static constexpr int NKT = 6;
+static constexpr int NPK = 5;
 
 struct hipipm_ctx {
   hipipm_problem_desc desc;
@@ -42,8 +49,8 @@ struct hipipm_ctx {
   size_t cnt_off;
   std::string err;
   hipipm_stats stats;
-  double t_ms[4];
-  long long t_n[4];
+  double t_ms[NKT];
+  long long t_n[NKT];
 };
 
 static int fail(hipipm_ctx* c, int code, const std::string& msg) {
@@ -80,6 +87,7 @@ static void layout(Cfg& c) {
   c.o_vt = take(n); c.o_ct = take(m); c.o_pt = take(m); c.o_nt = take(m); c.o_csoc = take(m);
   c.o_dvs = take(n); c.o_dys = take(m); c.o_dps = take(m); c.o_dns = take(m); c.o_g = take(n);
   c.o_ref = take((N + 1) * NX);
+  c.o_sd = take((N + 1) * sd_len_host(NI));
   c.stride = rup(o, 64);
 }
 
@@ -196,7 +204,7 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   const bool timing = c->opts.timing != 0;
   std::vector<hipEvent_t> ev;
   if (timing) {
-    ev.resize(4 * poll + 2);
+    ev.resize((NPK + 1) * poll + 2);
     for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
     HIPCHK(c, hipEventRecord(ev[0], st));
   }
@@ -206,8 +214,8 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
     HIPCHK(c, hipEventSynchronize(ev[1]));
     float ms = 0;
     HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
-    c->t_ms[3] += ms;
-    c->t_n[3] += 1;
+    c->t_ms[NKT - 1] += ms;
+    c->t_n[NKT - 1] += 1;
   }
   HIPCHK(c, hipGetLastError());
   // every pass advances each running slot by at most one pipeline step; bound the loop
@@ -215,13 +223,18 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   long long passes = 0;
   for (;;) {
     for (int p = 0; p < poll; ++p) {
-      if (timing) HIPCHK(c, hipEventRecord(ev[4 * p], st));
+      hipEvent_t* e = timing ? &ev[(NPK + 1) * p] : nullptr;
+      if (timing) HIPCHK(c, hipEventRecord(e[0], st));
       launch_eval(c->cfg, c->ws, active, st);
-      if (timing) HIPCHK(c, hipEventRecord(ev[4 * p + 1], st));
-      launch_factor(c->cfg, c->ws, active, theta, warm_x, out, dcnt, 1, st);
-      if (timing) HIPCHK(c, hipEventRecord(ev[4 * p + 2], st));
+      if (timing) HIPCHK(c, hipEventRecord(e[1], st));
+      launch_pre(c->cfg, c->ws, active, theta, warm_x, out, dcnt, 1, st);
+      if (timing) HIPCHK(c, hipEventRecord(e[2], st));
+      launch_fac(c->cfg, c->ws, active, st);
+      if (timing) HIPCHK(c, hipEventRecord(e[3], st));
+      launch_sol(c->cfg, c->ws, active, st);
+      if (timing) HIPCHK(c, hipEventRecord(e[4], st));
       launch_ls(c->cfg, c->ws, active, st);
-      if (timing) HIPCHK(c, hipEventRecord(ev[4 * p + 3], st));
+      if (timing) HIPCHK(c, hipEventRecord(e[5], st));
     }
     HIPCHK(c, hipGetLastError());
     passes += poll;
@@ -229,12 +242,13 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
     HIPCHK(c, hipStreamSynchronize(st));
     if (timing) {
       for (int p = 0; p < poll; ++p) {
-        float a = 0, b = 0, d = 0;
-        HIPCHK(c, hipEventElapsedTime(&a, ev[4 * p], ev[4 * p + 1]));
-        HIPCHK(c, hipEventElapsedTime(&b, ev[4 * p + 1], ev[4 * p + 2]));
-        HIPCHK(c, hipEventElapsedTime(&d, ev[4 * p + 2], ev[4 * p + 3]));
-        c->t_ms[0] += a; c->t_ms[1] += b; c->t_ms[2] += d;
-        c->t_n[0] += 1; c->t_n[1] += 1; c->t_n[2] += 1;
+        const hipEvent_t* e = &ev[(NPK + 1) * p];
+        for (int q = 0; q < NPK; ++q) {
+          float ms = 0;
+          HIPCHK(c, hipEventElapsedTime(&ms, e[q], e[q + 1]));
+          c->t_ms[q] += ms;
+          c->t_n[q] += 1;
+        }
       }
     }
     if (h.done >= n_inst) break;
@@ -272,12 +286,12 @@ int hipipm_reset_stats(hipipm_ctx* c) {
 
 int hipipm_kernel_times(const hipipm_ctx* c, int32_t* n_kernels, double* total_ms, int64_t* launches) {
   if (!c || !n_kernels) return HIPIPM_ERR_INVALID_ARG;
-  int n = *n_kernels < 4 ? *n_kernels : 4;
+  int n = *n_kernels < NKT ? *n_kernels : NKT;
   for (int i = 0; i < n; ++i) {
     if (total_ms) total_ms[i] = c->t_ms[i];
     if (launches) launches[i] = c->t_n[i];
   }
-  *n_kernels = 4;
+  *n_kernels = NKT;
   return HIPIPM_OK;
 }
 
@@ -441,7 +455,9 @@ int hipipm_step(hipipm_ctx* c, int32_t count, int32_t passes, void* stream) {
   Outs none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   for (int p = 0; p < passes; ++p) {
     launch_eval(c->cfg, c->ws, count, st);
-    launch_factor(c->cfg, c->ws, count, nullptr, nullptr, none, nullptr, 0, st);
+    launch_pre(c->cfg, c->ws, count, nullptr, nullptr, none, nullptr, 0, st);
+    launch_fac(c->cfg, c->ws, count, st);
+    launch_sol(c->cfg, c->ws, count, st);
     launch_ls(c->cfg, c->ws, count, st);
   }
   HIPCHK(c, hipGetLastError());
@@ -480,7 +496,7 @@ int hipipm_kkt_factor_solve(hipipm_ctx* c, int32_t count, const double* theta, c
   }
   launch_prepare(g, c->ws, count, st);
   launch_eval(g, c->ws, count, st);
-  launch_kkt_test(g, c->ws, count, mu, delta_x, delta_c, rhs, sol, inertia_ok, st);
+  launch_kkt_test(g, c->ws, count, delta_x, delta_c, rhs, sol, inertia_ok, st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(st));
   return HIPIPM_OK;

@@ -20,6 +20,8 @@ enum : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAX_ITER = 2, ST_RESTO_FAILED 
              ST_NUMERICAL = 5, ST_FILTER_OVERFLOW = 6 };
 // step flags handed from the factor kernel to the line-search kernel
 enum : int { STEP_NONE = 0, STEP_READY = 1, STEP_ICFAIL = 2 };
+// factorization request of the current pass (k_pre -> k_fac -> k_sol)
+enum : int { W_NONE = 0, W_STEP = 1, W_LSQ = 2 };
 
 // scalar block of a slot record (doubles)
 enum : int {
@@ -28,13 +30,15 @@ enum : int {
   SC_PHASE = 16, SC_STATUS, SC_ITER, SC_INST, SC_INITF, SC_THR, SC_OVERFLOW,
   SC_STEP = 24, SC_AMAX, SC_THK, SC_PHK, SC_GPHI, SC_FK, SC_STEPMU,
   SC_ST_RESTO = 32, SC_ST_SOCT, SC_ST_SOCA, SC_ST_FACT, SC_ST_RENT, SC_ST_TINY, SC_ST_PASS,
-  SC_LDX = 40, SC_LDC, SC_LALPHA, SC_LALPHAZ, SC_LSOC,
+  SC_LDX = 40, SC_LDC, SC_LALPHA, SC_LALPHAZ, SC_LSOC, SC_WORK, SC_FSTAT,
   SC_LEN = 64
 };
 
 // per-stage factor record (doubles)
+//   L_R (4x4 lower), Y = L_R^{-1} Hbar^ux, P, L_C (lower, only when Delta > 0), Delta^1/2,
+//   1 / diag(L_C), 1 / diag(L_R), flag (Delta > 0)
 enum : int { FR_LR = 0, FR_Y = 16, FR_P = 16 + NU * NX, FR_LC = FR_P + NX * NX, FR_DH = FR_LC + NX * NX,
-             FR_FLAG = FR_DH + NX, FR_LEN = ((FR_FLAG + 1 + 7) / 8) * 8 };
+             FR_RI = FR_DH + NX, FR_RR = FR_RI + NX, FR_FLAG = FR_RR + NU, FR_LEN = ((FR_FLAG + 1 + 7) / 8) * 8 };
 // per-stage condensed right-hand side (lambda 13, x 13, u 4) padded
 constexpr int RB_LEN = 32;
 
@@ -56,7 +60,7 @@ struct Cfg {
   int o_F, o_G, o_HW, o_fac, o_rb;
   int o_dv, o_dy, o_dzlu, o_dzuu, o_dzls, o_dp, o_dn, o_dzp, o_dzn;
   int o_rv, o_rc, o_rp, o_rn, o_vt, o_ct, o_pt, o_nt, o_csoc, o_dvs, o_dys, o_dps, o_dns;
-  int o_g, o_ref;
+  int o_g, o_ref, o_sd;
 };
 
 // caller-owned output arrays of a solve

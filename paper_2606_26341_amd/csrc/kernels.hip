@@ -1,15 +1,18 @@
 // gfx950 kernels of one fused batched interior-point iteration (Sec. V): every slot runs its
-// own branch of Table I inside the same launches, one 64-lane wavefront per slot.
+// own branch of Table I inside the same launches, one 64-lane wavefront per slot.  One pass is
 //
-//   k_eval       RK4 dynamics, Jacobian and Lagrangian-Hessian contraction per (slot, stage,
-//                direction) -- eq. (4) W and A = grad c
-//   k_factor     convergence test (E_0), monotone barrier update (Table I row 7), KKT assembly
-//                with slack condensation, inertia-correcting structured LDL^T (eq. (7)), step,
-//                bound-multiplier steps, fraction to the boundary; also least-squares
-//                multipliers (INIT_Y) and result write-out + slot refill (iteration-level
-//                batching, Sec. V)
-//   k_ls         tiny step (row 4), backtracking filter line search (row 1) with second-order
-//                correction (row 2), acceptance, restoration entry/exit (row 6)
+//   k_eval   RK4 dynamics, Jacobian and Lagrangian-Hessian contraction per (slot, stage,
+//            direction) -- eq. (4) W and A = grad c
+//   k_pre    phase dispatch, result write-out + slot refill (iteration-level batching, Sec. V),
+//            convergence test (E_0), monotone barrier update (Table I row 7), right-hand side
+//            of eq. (7), perturbation-free stage data of the KKT matrix
+//   k_fac    inertia-correcting structured LDL^T of eq. (7) with slack condensation
+//   k_sol    step, bound-multiplier steps, fraction to the boundary; least-squares multipliers
+//   k_ls     tiny step (row 4), backtracking filter line search (row 1) with second-order
+//            correction (row 2), acceptance, restoration entry/exit (row 6)
+//
+// The factor and solve live in kernels of their own so that each gets the register budget of
+// its own working set.
 #include "common.h"
 #include "model.h"
 #include "kkt.h"
@@ -478,8 +481,12 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
   __syncthreads();
 }
 
-// least-squares equality multipliers: [[I, A^T], [A, 0]] [d; y] = -[grad f - z_L + z_U; 0]
-__device__ __forceinline__ void init_y(const Cfg& c, const Slot& s, KktLds& L, int lane) {
+// ---------------------------------------------------------------------------- k_pre
+// Phase dispatch of one slot: result write-out and refill (FINISH), convergence and iteration
+// limit tests (E_0), the monotone barrier update (Table I row 7), grad phi_mu, the right-hand
+// side of eq. (7), theta_k and phi_k, and the perturbation-free stage data for the factorization.
+// INIT_Y slots set up the least-squares multiplier system [[I, A^T], [A, 0]] instead.
+__device__ __forceinline__ void pre_init_y(const Cfg& c, const Slot& s, int lane) {
   Iter it = cur_iter(s, false);
   eval_c(c, s, false, lane);
   eval_grad(c, s, s.y, false, 0.0, s.vt, lane);
@@ -489,45 +496,21 @@ __device__ __forceinline__ void init_y(const Cfg& c, const Slot& s, KktLds& L, i
     s.rv[i] = -(s.g[i] - zl + zu);
   }
   for (int r = lane; r < c.m; r += WAVE) s.dvs[r] = 0.0;   // zero constraint right-hand side
-  __syncthreads();
   Elim e{true, false, 0.0, 0.0, 0.0};
-  kkt_factor(c, s, it, e, 0.0, L, lane);
-  kkt_solve(c, s, it, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, L, lane);
-  double ym = 0.0, bad = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) {
-    ym = fmax(ym, fabs(s.dy[r]));
-    if (!isfinite(s.dy[r])) bad = 1.0;
-  }
-  ym = wmax(ym);
-  const bool keep = wmax(bad) == 0.0 && ym <= c.lam_max;
-  for (int r = lane; r < c.m; r += WAVE) s.y[r] = keep ? s.dy[r] : 0.0;
-  double th0 = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) th0 += fabs(s.rc[r]);
-  th0 = wsum(th0);
-  __syncthreads();
-  if (lane == 0) {
-    if (s.sc[SC_INITF] != 0.0) {
-      s.sc[SC_THMAX] = 1e4 * fmax(1.0, th0);
-      s.sc[SC_THMIN] = 1e-4 * fmax(1.0, th0);
-      s.sc[SC_NF] = 0.0;
-      s.sc[SC_INITF] = 0.0;
-    }
-    s.sc[SC_PHASE] = PH_REGULAR;
-  }
-  __syncthreads();
+  kkt_stage_data(c, s, it, e, lane);
+  if (lane == 0) s.sc[SC_WORK] = W_LSQ;
 }
 
-__global__ __launch_bounds__(64) void k_factor(Cfg c, double* ws, const double* theta, const double* warm_x,
-                                               Outs out, Counters* cnt, int refill) {
-  __shared__ KktLds L;
+__global__ __launch_bounds__(64) void k_pre(Cfg c, double* ws, const double* theta, const double* warm_x, Outs out,
+                                            Counters* cnt, int refill) {
   const int slot = blockIdx.x, lane = threadIdx.x;
   Slot s = make_slot(c, ws, slot);
   const int ph = (int)s.sc[SC_PHASE];
   if (ph == PH_EMPTY) return;
   __syncthreads();
-  if (lane == 0) s.sc[SC_ST_PASS] += 1.0;
+  if (lane == 0) { s.sc[SC_ST_PASS] += 1.0; s.sc[SC_WORK] = W_NONE; }
   if (ph == PH_FINISH) { finish_slot(c, s, theta, warm_x, out, cnt, refill != 0, lane); return; }
-  if (ph == PH_INIT_Y) { init_y(c, s, L, lane); return; }
+  if (ph == PH_INIT_Y) { pre_init_y(c, s, lane); return; }
 
   const bool resto = (ph == PH_RESTO);
   Iter it = cur_iter(s, resto);
@@ -591,7 +574,6 @@ __global__ __launch_bounds__(64) void k_factor(Cfg c, double* ws, const double* 
     if (lane == 0) { sub[0] = mu; sub[1] = tau; sub[5] = tiny ? 1.0 : 0.0; sub[6] = nf; }
     __syncthreads();
   }
-  const double tau = sub[1];
   // ---- barrier gradient, right-hand side of eq. (7), theta_k, phi_k ----
   for (int i = lane; i < c.n; i += WAVE) {
     double gp = s.g[i];
@@ -617,19 +599,44 @@ __global__ __launch_bounds__(64) void k_factor(Cfg c, double* ws, const double* 
   thk = wsum(thk);
   double fk = resto ? obj_resto(c, s, s.v, s.p, s.nn, zeta, lane) : obj_regular(c, s, s.v, lane);
   double phk = fk - mu * log_barrier(c, s.v, s.p, s.nn, resto, lane);
-  __syncthreads();
-  if (lane == 0) { s.sc[SC_THK] = thk; s.sc[SC_PHK] = phk; s.sc[SC_FK] = fk; s.sc[SC_STEPMU] = mu; }
-  // ---- inertia-correcting factorization ----
   Elim e{false, resto, 0.0, 0.0, zeta};
+  kkt_stage_data(c, s, it, e, lane);
+  if (lane == 0) {
+    s.sc[SC_THK] = thk; s.sc[SC_PHK] = phk; s.sc[SC_FK] = fk; s.sc[SC_STEPMU] = mu;
+    s.sc[SC_WORK] = W_STEP;
+  }
+}
+
+// ---------------------------------------------------------------------------- k_fac
+// Inertia-correcting factorization (Sec. IV "Inertia correction"): first without
+// perturbation; on a singular matrix add delta_c = delta_c_bar mu^kappa_c; then grow delta_x
+// from delta_0 (or kappa_minus times the last used value) by kappa_plus_bar / kappa_plus until
+// the inertia is (n, m, 0) or delta_x exceeds delta_max.
+__global__ __launch_bounds__(64) void k_fac(Cfg c, double* ws) {
+  __shared__ FacLds L;
+  const int slot = blockIdx.x, lane = threadIdx.x;
+  Slot s = make_slot(c, ws, slot);
+  const int work = (int)s.sc[SC_WORK];
+  if (work == W_NONE) return;
+  if (work == W_LSQ) {
+    Elim e{true, false, 0.0, 0.0, 0.0};
+    const int st = kkt_factor(c, s, e, L, lane);
+    if (lane == 0) s.sc[SC_FSTAT] = st;
+    return;
+  }
+  const bool resto = (int)s.sc[SC_PHASE] == PH_RESTO;
+  double* sub = s.sc + (resto ? SC_RMU : SC_MU);
+  const double mu = sub[0];
   const double dxl = sub[2];
-  int st = kkt_factor(c, s, it, e, zeta, L, lane);
+  Elim e{false, resto, 0.0, 0.0, resto ? sqrt(mu) : 0.0};
+  int st = kkt_factor(c, s, e, L, lane);
   int nfact = 1;
   bool ok = (st == 0);
   if (!ok) {
     if (st == 2) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
     e.dxp = (dxl == 0.0) ? c.delta_0 : fmax(c.delta_min, c.kappa_minus * dxl);
     for (;;) {
-      st = kkt_factor(c, s, it, e, zeta, L, lane);
+      st = kkt_factor(c, s, e, L, lane);
       ++nfact;
       if (st == 0) { ok = true; break; }
       if (st == 2 && e.dcp == 0.0) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
@@ -643,11 +650,64 @@ __global__ __launch_bounds__(64) void k_factor(Cfg c, double* ws, const double* 
     if (ok && (e.dxp != 0.0)) sub[2] = e.dxp;
     s.sc[SC_LDX] = e.dxp;
     s.sc[SC_LDC] = e.dcp;
+    s.sc[SC_FSTAT] = ok ? 0.0 : 1.0;
     s.sc[SC_STEP] = ok ? STEP_READY : STEP_ICFAIL;
   }
-  if (!ok) return;
-  // ---- step ----
-  kkt_solve(c, s, it, e, s.rv, s.rc, s.rp, s.rn, s.dv, s.dy, s.dp, s.dn, L, lane);
+}
+
+// ---------------------------------------------------------------------------- k_sol
+// least-squares multipliers: keep y if finite and |y|_inf <= lambda_max, else y = 0; the first
+// one also initialises the filter bounds theta_max, theta_min
+__device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, SolLds& V, int lane) {
+  const bool fok = s.sc[SC_FSTAT] == 0.0;
+  Elim e{true, false, 0.0, 0.0, 0.0};
+  if (fok) kkt_solve(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, V, lane);
+  double ym = 0.0, bad = fok ? 0.0 : 1.0;
+  if (fok)
+    for (int r = lane; r < c.m; r += WAVE) {
+      ym = fmax(ym, fabs(s.dy[r]));
+      if (!isfinite(s.dy[r])) bad = 1.0;
+    }
+  ym = wmax(ym);
+  const bool keep = wmax(bad) == 0.0 && ym <= c.lam_max;
+  for (int r = lane; r < c.m; r += WAVE) s.y[r] = keep ? s.dy[r] : 0.0;
+  double th0 = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) th0 += fabs(s.rc[r]);
+  th0 = wsum(th0);
+  __syncthreads();
+  if (lane == 0) {
+    if (s.sc[SC_INITF] != 0.0) {
+      s.sc[SC_THMAX] = 1e4 * fmax(1.0, th0);
+      s.sc[SC_THMIN] = 1e-4 * fmax(1.0, th0);
+      s.sc[SC_NF] = 0.0;
+      s.sc[SC_INITF] = 0.0;
+    }
+    s.sc[SC_PHASE] = PH_REGULAR;
+    s.sc[SC_WORK] = W_NONE;
+  }
+  __syncthreads();
+}
+
+// Step of eq. (7) from the stored factor, bound-multiplier steps, fraction to the boundary
+// (primal) and the directional derivative of phi_mu.
+__global__ __launch_bounds__(64) void k_sol(Cfg c, double* ws) {
+  HIP_DYNAMIC_SHARED(double, sol_dyn)
+  const int slot = blockIdx.x, lane = threadIdx.x;
+  Slot s = make_slot(c, ws, slot);
+  const int work = (int)s.sc[SC_WORK];
+  if (work == W_NONE) return;
+  SolLds V = sol_lds(c, sol_dyn);
+  if (work == W_LSQ) { sol_init_y(c, s, V, lane); return; }
+  if ((int)s.sc[SC_STEP] != STEP_READY) {
+    __syncthreads();
+    if (lane == 0) s.sc[SC_WORK] = W_NONE;
+    return;
+  }
+  const bool resto = (int)s.sc[SC_PHASE] == PH_RESTO;
+  Iter it = cur_iter(s, resto);
+  const double mu = it.sub[0], tau = it.sub[1];
+  Elim e{false, resto, s.sc[SC_LDX], s.sc[SC_LDC], resto ? sqrt(mu) : 0.0};
+  kkt_solve(c, s, e, s.rv, s.rc, s.rp, s.rn, s.dv, s.dy, s.dp, s.dn, V, lane);
   dz_recover(c, s, it, mu, s.dv, s.dp, s.dn, lane);
   double amax = ftb_primal(c, s, s.dv, s.dp, s.dn, resto, tau, lane);
   double gphi = 0.0;
@@ -657,7 +717,7 @@ __global__ __launch_bounds__(64) void k_factor(Cfg c, double* ws, const double* 
       gphi += (c.rho_resto - mu / s.p[r]) * s.dp[r] + (c.rho_resto - mu / s.nn[r]) * s.dn[r];
   gphi = wsum(gphi);
   __syncthreads();
-  if (lane == 0) { s.sc[SC_AMAX] = amax; s.sc[SC_GPHI] = gphi; }
+  if (lane == 0) { s.sc[SC_AMAX] = amax; s.sc[SC_GPHI] = gphi; s.sc[SC_WORK] = W_NONE; }
 }
 
 // ============================================================================ line search kernel
@@ -810,13 +870,14 @@ __device__ __forceinline__ void resto_try_exit(const Cfg& c, const Slot& s, int 
 }
 
 __global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
-  __shared__ KktLds L;
+  HIP_DYNAMIC_SHARED(double, sol_dyn)
   const int slot = blockIdx.x, lane = threadIdx.x;
   Slot s = make_slot(c, ws, slot);
   const int ph = (int)s.sc[SC_PHASE];
   if (ph != PH_REGULAR && ph != PH_RESTO) return;
   const int step = (int)s.sc[SC_STEP];
   if (step == STEP_NONE) return;
+  SolLds V = sol_lds(c, sol_dyn);
   __syncthreads();
   if (lane == 0) s.sc[SC_STEP] = STEP_NONE;
   const bool resto = (ph == PH_RESTO);
@@ -880,7 +941,7 @@ __global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
               s.ct[r] = -s.csoc[r];      // right-hand side rows of the constraints
             }
             __syncthreads();
-            kkt_solve(c, s, it, e, s.rv, s.ct, s.rp, s.rn, s.dvs, s.dys, s.dps, s.dns, L, lane);
+            kkt_solve(c, s, e, s.rv, s.ct, s.rp, s.rn, s.dvs, s.dys, s.dps, s.dns, V, lane);
             if (lane == 0) s.sc[SC_ST_SOCT] += 1.0;
             asoc = ftb_primal(c, s, s.dvs, s.dps, s.dns, resto, tau, lane);
             make_trial(c, s, resto, asoc, s.dvs, s.dps, s.dns, lane);
@@ -993,22 +1054,26 @@ __global__ __launch_bounds__(64) void k_stage_derivs(Cfg c, int count, const dou
 }
 
 // factor + solve the regular-phase system of slot `blockIdx.x` (derivatives already evaluated)
-__global__ __launch_bounds__(64) void k_kkt_test(Cfg c, double* ws, double mu, double dxp, double dcp,
-                                                 const double* rhs, double* sol, int* inertia_ok) {
-  __shared__ KktLds L;
+__global__ __launch_bounds__(64) void k_kkt_test(Cfg c, double* ws, double dxp, double dcp, const double* rhs,
+                                                 double* sol, int* inertia_ok) {
+  __shared__ FacLds L;
+  HIP_DYNAMIC_SHARED(double, sol_dyn)
   const int slot = blockIdx.x, lane = threadIdx.x;
   Slot s = make_slot(c, ws, slot);
   Iter it = cur_iter(s, false);
-  (void)mu;
-  Elim e{false, false, dxp, dcp, 0.0};
-  int st = kkt_factor(c, s, it, e, 0.0, L, lane);
+  Elim e{false, false, 0.0, 0.0, 0.0};
+  kkt_stage_data(c, s, it, e, lane);
+  e.dxp = dxp;
+  e.dcp = dcp;
+  const int st = kkt_factor(c, s, e, L, lane);
   if (lane == 0) inertia_ok[slot] = (st == 0) ? 1 : 0;
   if (st != 0) return;
   const double* b = rhs + (long long)slot * (c.n + c.m);
   for (int i = lane; i < c.n; i += WAVE) s.rv[i] = b[i];
   for (int r = lane; r < c.m; r += WAVE) s.rc[r] = b[c.n + r];
   __syncthreads();
-  kkt_solve(c, s, it, e, s.rv, s.rc, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, L, lane);
+  SolLds V = sol_lds(c, sol_dyn);
+  kkt_solve(c, s, e, s.rv, s.rc, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, V, lane);
   double* o = sol + (long long)slot * (c.n + c.m);
   for (int i = lane; i < c.n; i += WAVE) o[i] = s.dv[i];
   for (int r = lane; r < c.m; r += WAVE) o[c.n + r] = s.dy[r];
@@ -1023,12 +1088,20 @@ void launch_eval(const Cfg& c, double* ws, int slots, hipStream_t st) {
   int blocks = (int)((items + 255) / 256);
   if (blocks > 0) hipLaunchKernelGGL(k_eval, dim3(blocks), dim3(256), 0, st, c, ws, slots);
 }
-void launch_factor(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
-                   Counters* cnt, int refill, hipStream_t st) {
-  hipLaunchKernelGGL(k_factor, dim3(slots), dim3(WAVE), 0, st, c, ws, theta, warm_x, out, cnt, refill);
+int sd_len_host(int NI) { return sd_len_of(NI); }
+static size_t sol_bytes(const Cfg& c) { return (size_t)sol_lds_doubles(c.N) * sizeof(double); }
+void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+                Counters* cnt, int refill, hipStream_t st) {
+  hipLaunchKernelGGL(k_pre, dim3(slots), dim3(WAVE), 0, st, c, ws, theta, warm_x, out, cnt, refill);
+}
+void launch_fac(const Cfg& c, double* ws, int slots, hipStream_t st) {
+  hipLaunchKernelGGL(k_fac, dim3(slots), dim3(WAVE), 0, st, c, ws);
+}
+void launch_sol(const Cfg& c, double* ws, int slots, hipStream_t st) {
+  hipLaunchKernelGGL(k_sol, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws);
 }
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st) {
-  hipLaunchKernelGGL(k_ls, dim3(slots), dim3(WAVE), 0, st, c, ws);
+  hipLaunchKernelGGL(k_ls, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws);
 }
 void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm_x,
                   hipStream_t st) {
@@ -1042,8 +1115,8 @@ void launch_stage_derivs(const Cfg& c, int count, const double* x, const double*
 void launch_prepare(const Cfg& c, double* ws, int count, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_prepare, dim3(count), dim3(WAVE), 0, st, c, ws);
 }
-void launch_kkt_test(const Cfg& c, double* ws, int count, double mu, double dxp, double dcp, const double* rhs,
-                     double* sol, int* inertia_ok, hipStream_t st) {
-  hipLaunchKernelGGL(k_kkt_test, dim3(count), dim3(WAVE), 0, st, c, ws, mu, dxp, dcp, rhs, sol, inertia_ok);
+void launch_kkt_test(const Cfg& c, double* ws, int count, double dxp, double dcp, const double* rhs, double* sol,
+                     int* inertia_ok, hipStream_t st) {
+  hipLaunchKernelGGL(k_kkt_test, dim3(count), dim3(WAVE), sol_bytes(c), st, c, ws, dxp, dcp, rhs, sol, inertia_ok);
 }
 }  // namespace hipipm

@@ -14,6 +14,12 @@
 //   S_k = P - V^T V, V = L_C^{-1} Delta^1/2 P.
 // The inertia is (n, m, 0) iff every Cholesky succeeds; a pivot that is exactly zero marks the
 // matrix singular (Sec. IV "Step direction": inertia-controlled LDL^T).
+//
+// Memory schedule: the per-stage inputs (derivative blocks G_k, W_k and the perturbation-free
+// diagonal data) are read from HBM one stage ahead into registers while the current stage is
+// computed, then parked in an LDS double buffer; the wave synchronises on LDS only, so those
+// loads stay in flight across the stage's barriers.  The solve keeps all stage right-hand sides
+// and the running step in LDS.
 #pragma once
 #include "common.h"
 
@@ -25,7 +31,7 @@ struct Slot {
   double *yr, *rzlu, *rzuu, *rzls, *xr, *p, *nn, *zp, *zn;
   double *F, *G, *HW, *fac, *rb;
   double *dv, *dy, *dzlu, *dzuu, *dzls, *dp, *dn, *dzp, *dzn;
-  double *rv, *rc, *rp, *rn, *vt, *ct, *pt, *nt, *csoc, *dvs, *dys, *dps, *dns, *g, *ref;
+  double *rv, *rc, *rp, *rn, *vt, *ct, *pt, *nt, *csoc, *dvs, *dys, *dps, *dns, *g, *ref, *sd;
 };
 
 __device__ __forceinline__ Slot make_slot(const Cfg& c, double* ws, int slot) {
@@ -43,6 +49,7 @@ __device__ __forceinline__ Slot make_slot(const Cfg& c, double* ws, int slot) {
   s.vt = R + c.o_vt; s.ct = R + c.o_ct; s.pt = R + c.o_pt; s.nt = R + c.o_nt; s.csoc = R + c.o_csoc;
   s.dvs = R + c.o_dvs; s.dys = R + c.o_dys; s.dps = R + c.o_dps; s.dns = R + c.o_dns; s.g = R + c.o_g;
   s.ref = R + c.o_ref;
+  s.sd = R + c.o_sd;
   return s;
 }
 
@@ -87,196 +94,283 @@ __device__ __forceinline__ int wor(int v) {
   return v;
 }
 
-// ----------------------------------------------------------------------------- LDS workspace
-struct KktLds {
-  double S[NX * NX];
-  double H[NZ * NZ];
-  double T[NX * NZ];
-  double Gs[NX * NZ];
-  double LR[NU * NU];
-  double Y[NU * NX];
-  double P[NX * NX];
-  double C[NX * NX];
-  double V[NX * NX];
-  double dh[NX];
-  double jg[MAX_OBS * 3];
-  double Dg[MAX_OBS];
-  double vec[8][32];
-  double fr[FR_LEN];
-  int bad;
-};
+// Workgroup barrier whose fences cover LDS only, so outstanding global loads (prefetches) stay in
+// flight across it.  Used only where no lane reads global memory written by another lane since
+// the last full __syncthreads.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
-enum : int { MODE_STEP = 0, MODE_LSQ = 1 };
+// ----------------------------------------------------------------------------- stage data
+// Perturbation-free diagonal data of knot k (written once per factorization request):
+//   [0, NZ)            objective Hessian diagonal + bound Sigma of (x_k, u_k) (identity in LSQ mode)
+//   [NZ, NZ+NX)        z_p/p of the rows defining x_k   (restoration only)
+//   [NZ+NX, NZ+2NX)    z_n/n of those rows              (restoration only)
+//   then per inequality row j of the knot: sigma0 (z_s/s [+ zeta D_R^2]), z_p/p, z_n/n, J_g (3),
+//   2 y_g (Hessian of the row).
+constexpr int SD_HEAD = NZ + 2 * NX;
+constexpr int SD_OBS = 7;
+__device__ __host__ __forceinline__ int sd_len_of(int NI) { return ((SD_HEAD + SD_OBS * NI + 7) / 8) * 8; }
+__device__ __forceinline__ int sd_len(const Cfg& c) { return sd_len_of(c.NI); }
 
-// diagonal data of the eliminated variables
 struct Elim {
   bool lsq, resto;
   double dxp, dcp, zeta;
 };
 
-// sigma of slack (k, j) and the row regularisation d of constraint row r
-__device__ __forceinline__ double slack_sigma(const Cfg& c, const Slot& s, const Iter& it, const Elim& e, int k,
-                                              int j) {
-  if (e.lsq) return 1.0;
-  const int si = so(c, k, j);
-  double sv = s.v[si];
-  double sig = it.zls[(k - 1) * c.NI + j] / sv + e.dxp;
-  if (e.resto) {
-    double d = fmin(1.0, 1.0 / fabs(s.xr[si]));
-    sig += e.zeta * d * d;
-  }
-  return sig;
-}
-__device__ __forceinline__ void row_elastic(const Slot& s, const Elim& e, int r, double& sp, double& sn) {
-  sp = s.zp[r] / s.p[r] + e.dxp;
-  sn = s.zn[r] / s.nn[r] + e.dxp;
-}
-__device__ __forceinline__ double row_d(const Slot& s, const Elim& e, int r) {
+// row regularisation d = delta_c + 1/(z_p/p + delta_x) + 1/(z_n/n + delta_x) (elastic part in restoration)
+__device__ __forceinline__ double row_dreg(const Elim& e, double sp0, double sn0) {
   if (e.lsq) return 0.0;
   double d = e.dcp;
-  if (e.resto) {
-    double sp, sn;
-    row_elastic(s, e, r, sp, sn);
-    d += 1.0 / sp + 1.0 / sn;
-  }
+  if (e.resto) d += 1.0 / (sp0 + e.dxp) + 1.0 / (sn0 + e.dxp);
   return d;
 }
 
-// Cholesky of an n x n matrix in LDS (in place, lower), executed cooperatively; returns 0 ok,
-// 1 non-positive pivot, 2 exactly-zero pivot.
-__device__ __forceinline__ int chol_lds(double* A, int n, int ld, int lane) {
-  for (int j = 0; j < n; ++j) {
-    __syncthreads();
-    double d = A[j * ld + j];
-    if (!(d > 0.0)) return d == 0.0 ? 2 : 1;
-    double r = sqrt(d);
-    __syncthreads();
-    if (lane == 0) A[j * ld + j] = r;
-    for (int i = j + 1 + lane; i < n; i += WAVE) A[i * ld + j] /= r;
-    __syncthreads();
-    const int m = n - j - 1;
-    for (int e = lane; e < m * m; e += WAVE) {
-      int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (l <= i) A[i * ld + l] -= A[i * ld + j] * A[l * ld + j];
-    }
-  }
-  __syncthreads();
-  return 0;
-}
-
-// ----------------------------------------------------------------------------- factorization
-// Assemble and factor all stage blocks; returns 0 (inertia correct), 1 (wrong), 2 (singular).
-// Per-stage factor records are written to s.fac.
-__device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Iter& it, const Elim& e, double zeta, KktLds& L,
-                          int lane) {
-  const int N = c.N, NI = c.NI;
-  for (int i = lane; i < NX * NX; i += WAVE) L.S[i] = 0.0;
-  int status = 0;
-  for (int k = N; k >= 0; --k) {
-    const int nz = (k < N) ? NZ : NX;
-    __syncthreads();
-    // ---- stage Hessian H_k = W_k + Sigma + delta_x I (+ condensed slacks) ----
-    for (int q = lane; q < nz * nz; q += WAVE) {
-      int i = q / nz, j = q % nz;
-      double h = 0.0;
-      if (!e.lsq && k < N) h = s.HW[(long long)k * NZ * NZ + i * NZ + j];
-      if (i == j) {
+__device__ __forceinline__ void kkt_stage_data(const Cfg& c, const Slot& s, const Iter& it, const Elim& e,
+                                               int lane) {
+  const int N = c.N, NI = c.NI, L = sd_len(c);
+  for (int q = lane; q < (N + 1) * SD_HEAD; q += WAVE) {
+    const int k = q / SD_HEAD, i = q % SD_HEAD;
+    double* sd = s.sd + (long long)k * L;
+    double val = 0.0;
+    if (i < NZ) {
+      if (k < N || i < NX) {
         if (e.lsq) {
-          h += 1.0;
+          val = 1.0;
         } else {
-          int vi = (i < NX) ? xo(k) + i : uo(k) + (i - NX);
+          const int vi = (i < NX) ? xo(k) + i : uo(k) + (i - NX);
           if (e.resto) {
             double d = fmin(1.0, 1.0 / fabs(s.xr[vi]));
-            h += zeta * d * d;
+            val = e.zeta * d * d;
           } else {
-            h += (i < NX) ? 2.0 * c.qw : 2.0 * c.rw;
+            val = (i < NX) ? 2.0 * c.qw : 2.0 * c.rw;
           }
           if (i >= NX) {
             double u = s.v[vi];
             int b = k * NU + (i - NX);
-            h += it.zlu[b] / u + it.zuu[b] / (c.umax - u);
+            val += it.zlu[b] / u + it.zuu[b] / (c.umax - u);
           }
-          h += e.dxp;
         }
       }
-      L.H[i * nz + j] = h;
+    } else if (e.resto) {
+      const int r = k * NX + (i - NZ) % NX;
+      val = (i < NZ + NX) ? s.zp[r] / s.p[r] : s.zn[r] / s.nn[r];
     }
-    // slack condensation data of stage k (k >= 1)
-    if (k >= 1) {
-      for (int j = lane; j < NI; j += WAVE) {
-        const double* o = obs_ptr(c, s.th) + 4 * j;
-        double sig = slack_sigma(c, s, it, e, k, j);
-        double d = row_d(s, e, go(c, k, j));
-        L.Dg[j] = sig / (1.0 + sig * d);
-        for (int t = 0; t < 3; ++t) L.jg[3 * j + t] = 2.0 * (s.v[xo(k) + t] - o[t]);
+    sd[i] = val;
+  }
+  for (int q = lane; q < N * NI; q += WAVE) {
+    const int k = 1 + q / NI, j = q % NI;
+    double* o7 = s.sd + (long long)k * L + SD_HEAD + SD_OBS * j;
+    const double* o = obs_ptr(c, s.th) + 4 * j;
+    const int si = so(c, k, j), r = go(c, k, j);
+    double sig0 = 1.0;
+    if (!e.lsq) {
+      sig0 = it.zls[q] / s.v[si];
+      if (e.resto) {
+        double d = fmin(1.0, 1.0 / fabs(s.xr[si]));
+        sig0 += e.zeta * d * d;
       }
     }
-    __syncthreads();
+    o7[0] = sig0;
+    o7[1] = e.resto ? s.zp[r] / s.p[r] : 0.0;
+    o7[2] = e.resto ? s.zn[r] / s.nn[r] : 0.0;
+    for (int t = 0; t < 3; ++t) o7[3 + t] = 2.0 * (s.v[xo(k) + t] - o[t]);
+    o7[6] = e.lsq ? 0.0 : 2.0 * it.y[r];
+  }
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------------------- LDS workspaces
+constexpr int PF = 16;   // prefetch registers per lane (one stage of inputs)
+static_assert(NZ * NZ + NX * NZ + SD_HEAD + SD_OBS * MAX_OBS + 8 <= PF * WAVE, "stage inputs exceed the prefetch");
+
+struct FacLds {
+  double S[NX * NX];
+  double H[NZ * NZ];
+  double Y[NU * NX];
+  double P[NX * NX];
+  double CV[2 * NX * NX];     // T = S G (NX x NZ) during the Schur update, then C | V
+  double dh[NX];
+  double buf[PF * WAVE];      // stage inputs: W (NZ*NZ) | G (NX*NZ) | stage data
+};
+
+constexpr int SPF = (FR_LEN + NX * NZ + WAVE - 1) / WAVE;
+static_assert(FR_LEN + NX * NZ <= SPF * WAVE, "solve stage inputs exceed the prefetch");
+
+// solve workspace, carved from dynamic LDS (its size depends on the horizon)
+struct SolLds {
+  double* rb;                        // condensed stage right-hand sides, (N+1) x RB_LEN
+  double* buf;                       // factor record of the knot | G of the coupling interval
+  double* tmp;                       // 32 words: x part of the current stage
+};
+__device__ __host__ __forceinline__ int sol_lds_doubles(int N) { return (N + 1) * RB_LEN + SPF * WAVE + 32; }
+__device__ __forceinline__ SolLds sol_lds(const Cfg& c, double* dyn) {
+  SolLds V;
+  V.rb = dyn;
+  V.buf = dyn + (c.N + 1) * RB_LEN;
+  V.tmp = V.buf + SPF * WAVE;
+  return V;
+}
+
+// value of v on lane src (src uniform), delivered to every lane through the scalar unit
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// In-register Cholesky of an NX x NX SPD candidate held one row per lane (lane i < NX holds
+// c[l] = A_il; the lower part is used).  Right-looking, column j broadcast from lane j.  On
+// success row `lane` of L is in c (lower part) and rinv[j] = 1 / L_jj on every lane.  Returns 0,
+// 1 (a non-positive pivot) or 2 (an exactly-zero pivot); the result is wave-uniform.
+__device__ __forceinline__ int chol_rows(double (&c)[NX], double (&rinv)[NX], int lane) {
+#pragma unroll
+  for (int j = 0; j < NX; ++j) {
+    const double d = lane_bcast(c[j], j);
+    if (!(d > 0.0)) return d == 0.0 ? 2 : 1;
+    const double r = sqrt(d);
+    rinv[j] = 1.0 / r;
+    c[j] = (lane == j) ? r : c[j] * rinv[j];
+#pragma unroll
+    for (int l = j + 1; l < NX; ++l) {
+      const double ljl = lane_bcast(c[j], l);     // L_lj
+      if (lane >= l) c[l] -= c[j] * ljl;
+    }
+  }
+  return 0;
+}
+
+// stage k inputs as one flat range: [W_k (k < N) | G_k (k < N) | stage data].  Every lane loads
+// from a valid address (lanes past the end re-read the last word) so that no load sits behind a
+// branch: the registers are consumed only by stage_park, where the wait for the loads lands.
+__device__ __forceinline__ void stage_prefetch(const Cfg& c, const Slot& s, int k, int lane, double* reg) {
+  const int nW = (k < c.N) ? NZ * NZ : 0, nG = (k < c.N) ? NX * NZ : 0, nS = sd_len(c);
+  const double* W = s.HW + (long long)(k < c.N ? k : 0) * NZ * NZ;
+  const double* G = s.G + (long long)(k < c.N ? k : 0) * NX * NZ;
+  const double* D = s.sd + (long long)k * nS;
+#pragma unroll
+  for (int t = 0; t < PF; ++t) {
+    const int q = lane + WAVE * t;
+    const double* a = (q < nW) ? W + q : (q < nW + nG) ? G + (q - nW) : D + min(q - nW - nG, nS - 1);
+    reg[t] = *a;
+  }
+}
+__device__ __forceinline__ void stage_park(double* buf, int lane, const double* reg) {
+#pragma unroll
+  for (int t = 0; t < PF; ++t) buf[lane + WAVE * t] = reg[t];
+}
+
+// ----------------------------------------------------------------------------- factorization
+// Factor all stage blocks with perturbations (e.dxp, e.dcp); stage data from kkt_stage_data.
+// Returns 0 (inertia correct), 1 (wrong), 2 (singular).  Writes the per-knot factor records.
+__device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Elim& e, FacLds& L, int lane) {
+  const int N = c.N, NI = c.NI;
+  double reg[PF];
+  for (int i = lane; i < NX * NX; i += WAVE) L.S[i] = 0.0;
+  stage_prefetch(c, s, N, lane, reg);
+  stage_park(L.buf, lane, reg);
+  lds_barrier();
+  int status = 0;
+  for (int k = N; k >= 0; --k) {
+    const int nz = (k < N) ? NZ : NX;
+    const double* B = L.buf;      // dead after the barrier that follows the dh read
+    const double* Wk = B;
+    const double* Gk = B + ((k < N) ? NZ * NZ : 0);
+    const double* SD = B + ((k < N) ? NZ * NZ + NX * NZ : 0);
+    double* fr = s.fac + (long long)k * FR_LEN;
+    if (k > 0) stage_prefetch(c, s, k - 1, lane, reg);   // in flight during this stage
+    // ---- stage Hessian H_k = W_k + diag + delta_x I (+ condensed slacks) ----
+    for (int q = lane; q < nz * nz; q += WAVE) {
+      const int i = q / nz, j = q % nz;
+      double h = (!e.lsq && k < N) ? Wk[i * NZ + j] : 0.0;
+      if (i == j) h += SD[i] + (e.lsq ? 0.0 : e.dxp);
+      L.H[i * nz + j] = h;
+    }
+    lds_barrier();
     if (k >= 1) {
       for (int q = lane; q < 9; q += WAVE) {
-        int a = q / 3, b = q % 3;
+        const int a = q / 3, b = q % 3;
         double acc = 0.0;
         for (int j = 0; j < NI; ++j) {
-          acc += L.Dg[j] * L.jg[3 * j + a] * L.jg[3 * j + b];
-          if (a == b && !e.lsq) acc += 2.0 * it.y[go(c, k, j)];
+          const double* o7 = SD + SD_HEAD + SD_OBS * j;
+          const double sig = o7[0] + (e.lsq ? 0.0 : e.dxp);
+          const double d = row_dreg(e, o7[1], o7[2]);
+          const double D = sig / (1.0 + sig * d);
+          acc += D * o7[3 + a] * o7[3 + b];
+          if (a == b) acc += o7[6];
         }
         L.H[a * nz + b] += acc;
       }
+      lds_barrier();
     }
     // ---- Schur update H += G^T S_{k+1} G ----
     if (k < N) {
-      const double* Gk = s.G + (long long)k * NX * NZ;
-      for (int q = lane; q < NX * NZ; q += WAVE) L.Gs[q] = Gk[q];
-      __syncthreads();
       for (int q = lane; q < NX * NZ; q += WAVE) {
-        int i = q / NZ, j = q % NZ;
+        const int i = q / NZ, j = q % NZ;
         double acc = 0.0;
-#pragma unroll
-        for (int l = 0; l < NX; ++l) acc += L.S[i * NX + l] * L.Gs[l * NZ + j];
-        L.T[q] = acc;
+        for (int l = 0; l < NX; ++l) acc += L.S[i * NX + l] * Gk[l * NZ + j];
+        L.CV[q] = acc;
       }
-      __syncthreads();
+      lds_barrier();
       for (int q = lane; q < NZ * NZ; q += WAVE) {
-        int i = q / NZ, j = q % NZ;
+        const int i = q / NZ, j = q % NZ;
         double acc = 0.0;
-#pragma unroll
-        for (int l = 0; l < NX; ++l) acc += L.Gs[l * NZ + i] * L.T[l * NZ + j];
+        for (int l = 0; l < NX; ++l) acc += Gk[l * NZ + i] * L.CV[l * NZ + j];
         L.H[q] += acc;
       }
+      lds_barrier();
     }
-    __syncthreads();
-    double* fr = s.fac + (long long)k * FR_LEN;
-    // ---- control block: Cholesky of Hbar^uu, Y, P ----
+    // ---- control block: Cholesky of Hbar^uu (on every lane, in registers), Y, P ----
+    const int li = lane < NX ? lane : NX - 1;
     if (k < N) {
-      if (lane == 0) {
-        int bad = 0;
-        for (int j = 0; j < NU && !bad; ++j) {
-          double d = L.H[(NX + j) * NZ + NX + j];
-          for (int l = 0; l < j; ++l) d -= L.LR[j * NU + l] * L.LR[j * NU + l];
-          if (!(d > 0.0)) { bad = (d == 0.0) ? 2 : 1; break; }
-          double r = sqrt(d);
-          L.LR[j * NU + j] = r;
-          for (int i = j + 1; i < NU; ++i) {
-            double a = L.H[(NX + i) * NZ + NX + j];
-            for (int l = 0; l < j; ++l) a -= L.LR[i * NU + l] * L.LR[j * NU + l];
-            L.LR[i * NU + j] = a / r;
-          }
-          for (int i = 0; i < j; ++i) L.LR[i * NU + j] = 0.0;
+      double lr[NU * NU], rr[NU];
+      int bad = 0;
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+        double d = L.H[(NX + j) * NZ + NX + j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) d -= lr[j * NU + l] * lr[j * NU + l];
+        if (bad == 0 && !(d > 0.0)) bad = (d == 0.0) ? 2 : 1;
+        const double r = sqrt(d);
+        rr[j] = 1.0 / r;
+        lr[j * NU + j] = r;
+#pragma unroll
+        for (int i = 0; i < NU; ++i) {
+          if (i < j) lr[i * NU + j] = 0.0;
+          if (i <= j) continue;
+          double a = L.H[(NX + i) * NZ + NX + j];
+#pragma unroll
+          for (int l = 0; l < j; ++l) a -= lr[i * NU + l] * lr[j * NU + l];
+          lr[i * NU + j] = a * rr[j];
         }
-        L.bad = bad;
       }
-      __syncthreads();
-      if (L.bad) { status = L.bad; break; }
-      for (int b = lane; b < NX; b += WAVE) {
+      if (bad) { status = bad; break; }
+      {
+        double v = 0.0, w = 0.0;
+#pragma unroll
+        for (int t = 0; t < NU * NU; ++t) v = (lane == t) ? lr[t] : v;
+#pragma unroll
+        for (int t = 0; t < NU; ++t) w = (lane == t) ? rr[t] : w;
+        if (lane < NU * NU) fr[FR_LR + lane] = v;
+        if (lane < NU) fr[FR_RR + lane] = w;
+      }
+      if (lane < NX) {
+        double y[NU];
+#pragma unroll
         for (int a = 0; a < NU; ++a) {
-          double acc = L.H[(NX + a) * NZ + b];
-          for (int l = 0; l < a; ++l) acc -= L.LR[a * NU + l] * L.Y[l * NX + b];
-          L.Y[a * NX + b] = acc / L.LR[a * NU + a];
+          double acc = L.H[(NX + a) * NZ + lane];
+#pragma unroll
+          for (int l = 0; l < a; ++l) acc -= lr[a * NU + l] * y[l];
+          y[a] = acc * rr[a];
+          L.Y[a * NX + lane] = y[a];
         }
       }
-      __syncthreads();
+      lds_barrier();
       for (int q = lane; q < NX * NX; q += WAVE) {
-        int i = q / NX, j = q % NX;
+        const int i = q / NX, j = q % NX;
         double acc = L.H[i * NZ + j];
 #pragma unroll
         for (int a = 0; a < NU; ++a) acc -= L.Y[a * NX + i] * L.Y[a * NX + j];
@@ -286,250 +380,301 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Ite
       for (int q = lane; q < NX * NX; q += WAVE) L.P[q] = L.H[q];
     }
     // ---- pair pivot with the dual regularisation Delta_k of the rows defining x_k ----
-    for (int i = lane; i < NX; i += WAVE) L.dh[i] = sqrt(row_d(s, e, k * NX + i));
-    __syncthreads();
+    const double dhl = sqrt(row_dreg(e, SD[NZ + li], SD[NZ + NX + li]));
+    if (lane < NX) L.dh[lane] = dhl;
+    lds_barrier();
     double dmax = 0.0;
+#pragma unroll
     for (int i = 0; i < NX; ++i) dmax = fmax(dmax, L.dh[i]);
+    double* LC = L.CV;
+    double* VV = L.CV + NX * NX;
     if (dmax > 0.0) {
-      for (int q = lane; q < NX * NX; q += WAVE) {
-        int i = q / NX, j = q % NX;
-        L.C[q] = L.dh[i] * L.P[q] * L.dh[j] + (i == j ? 1.0 : 0.0);
-      }
-      int r = chol_lds(L.C, NX, NX, lane);
+      // C = I + Delta^1/2 P Delta^1/2, one row per lane, factored in registers
+      double cr[NX], ri[NX];
+#pragma unroll
+      for (int l = 0; l < NX; ++l) cr[l] = dhl * L.P[li * NX + l] * L.dh[l] + (lane == l ? 1.0 : 0.0);
+      const int r = chol_rows(cr, ri, lane);
       if (r) { status = r; break; }
-      for (int col = lane; col < NX; col += WAVE) {
+      if (lane < NX) {
+#pragma unroll
+        for (int l = 0; l < NX; ++l) {
+          const double v = (l <= lane) ? cr[l] : 0.0;
+          LC[lane * NX + l] = v;
+          fr[FR_LC + lane * NX + l] = v;
+        }
+        double rl = 0.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) rl = (l == lane) ? ri[l] : rl;
+        fr[FR_RI + lane] = rl;
+      }
+      lds_barrier();
+      // V = L_C^{-1} Delta^1/2 P, one column per lane, forward substitution in registers
+      if (lane < NX) {
+        double v[NX];
+#pragma unroll
         for (int i = 0; i < NX; ++i) {
-          double acc = L.dh[i] * L.P[i * NX + col];
-          for (int l = 0; l < i; ++l) acc -= L.C[i * NX + l] * L.V[l * NX + col];
-          L.V[i * NX + col] = acc / L.C[i * NX + i];
+          double acc = L.dh[i] * L.P[i * NX + lane];
+#pragma unroll
+          for (int l = 0; l < i; ++l) acc -= LC[i * NX + l] * v[l];
+          v[i] = acc * ri[i];
+          VV[i * NX + lane] = v[i];
         }
       }
-      __syncthreads();
+      lds_barrier();
       for (int q = lane; q < NX * NX; q += WAVE) {
-        int i = q / NX, j = q % NX;
+        const int i = q / NX, j = q % NX;
         double acc = L.P[q];
-        for (int l = 0; l < NX; ++l) acc -= L.V[l * NX + i] * L.V[l * NX + j];
+#pragma unroll
+        for (int l = 0; l < NX; ++l) acc -= VV[l * NX + i] * VV[l * NX + j];
         L.S[q] = acc;
       }
-      for (int q = lane; q < NX * NX; q += WAVE) fr[FR_LC + q] = L.C[q];
     } else {
       for (int q = lane; q < NX * NX; q += WAVE) L.S[q] = L.P[q];
     }
     // ---- store the stage factor ----
-    for (int q = lane; q < NU * NU; q += WAVE) fr[FR_LR + q] = L.LR[q];
     for (int q = lane; q < NU * NX; q += WAVE) fr[FR_Y + q] = L.Y[q];
     for (int q = lane; q < NX * NX; q += WAVE) fr[FR_P + q] = L.P[q];
-    for (int q = lane; q < NX; q += WAVE) fr[FR_DH + q] = L.dh[q];
+    if (lane < NX) fr[FR_DH + lane] = dhl;
     if (lane == 0) fr[FR_FLAG] = dmax > 0.0 ? 1.0 : 0.0;
+    if (k > 0) stage_park(L.buf, lane, reg);
+    lds_barrier();
   }
   __syncthreads();
   return status;
 }
 
 // ----------------------------------------------------------------------------- solve
-// Apply M_k^{-1} to (ra, rx, ru) of stage k with its factor record: on entry L.vec[1] = ra,
-// L.vec[2] = rx, L.vec[3][0..3] = ru; on exit L.vec[0] = lambda part a and, if `full`,
-// L.vec[2] = x part b and L.vec[3] = u part.  The record is first staged into LDS with
-// coalesced loads; the small products are spread over lanes.
-__device__ __forceinline__ void stage_apply(const Cfg& c, const double* fr, bool has_u, KktLds& L, bool full,
-                                            int lane) {
-  double* F = L.fr;
-  for (int q = lane; q < FR_LEN; q += WAVE) F[q] = fr[q];
-  __syncthreads();
-  const double* LR = F + FR_LR;
-  const double* Y = F + FR_Y;
-  const double* P = F + FR_P;
-  const double* LC = F + FR_LC;
-  const double* dh = F + FR_DH;
+// Apply M_k^{-1} of stage k (factor record F in LDS) to the stage right-hand side
+// (ra, rx, ru): ra[] holds the lambda part on every lane, rx the x component of row `lane`,
+// ru[] the control part on every lane.  Returns the lambda component a of row `lane`; with
+// `full` also the x component b of row `lane` and the control part cu[] on every lane.
+// Lanes >= NX compute throw-away values.  Ends with an LDS barrier after the last read of F.
+//   w_u = L_R^{-1} r_u,  t = r_x - Y^T w_u - P r_a,
+//   a = t (Delta = 0)  or  a = Delta^{-1/2} C^{-1} Delta^{1/2} t  with C = L_C L_C^T,
+//   b = r_a + Delta a,  c_u = L_R^{-T} (w_u - Y b)
+__device__ __forceinline__ double stage_apply(const double* F, bool has_u, const double (&ra)[NX], double rx,
+                                              const double (&ru)[NU], bool full, int lane, double& b,
+                                              double (&cu)[NU], SolLds& V) {
+  const int li = lane < NX ? lane : NX - 1;
   const bool reg = F[FR_FLAG] != 0.0;
-  double* wu = L.vec[4];
-  double* t = L.vec[5];
-  // wu = L_R^{-1} ru
-  if (has_u && lane == 0) {
-    for (int a2 = 0; a2 < NU; ++a2) {
-      double acc = L.vec[3][a2];
-      for (int l = 0; l < a2; ++l) acc -= LR[a2 * NU + l] * wu[l];
-      wu[a2] = acc / LR[a2 * NU + a2];
-    }
+  double wu[NU];
+#pragma unroll
+  for (int a2 = 0; a2 < NU; ++a2) {
+    double acc = ru[a2];
+#pragma unroll
+    for (int l = 0; l < a2; ++l) acc -= F[FR_LR + a2 * NU + l] * wu[l];
+    wu[a2] = has_u ? acc * F[FR_RR + a2] : 0.0;
   }
-  __syncthreads();
-  // t = rx - Y^T wu - P ra
-  if (lane < NX) {
-    double acc = L.vec[2][lane];
-    if (has_u)
-      for (int a2 = 0; a2 < NU; ++a2) acc -= Y[a2 * NX + lane] * wu[a2];
-    for (int l = 0; l < NX; ++l) acc -= P[lane * NX + l] * L.vec[1][l];
-    t[lane] = acc;
-  }
-  __syncthreads();
+  double t = rx;
+  if (has_u)
+#pragma unroll
+    for (int a2 = 0; a2 < NU; ++a2) t -= F[FR_Y + a2 * NX + li] * wu[a2];
+#pragma unroll
+  for (int l = 0; l < NX; ++l) t -= F[FR_P + li * NX + l] * ra[l];
+  double av = t;
+  const double dh = F[FR_DH + li];
   if (reg) {
-    // a = Delta^{-1/2} C^{-1} Delta^{1/2} t  with C = L_C L_C^T
-    if (lane == 0) {
-      double* z = L.vec[6];
-      for (int i = 0; i < NX; ++i) {
-        double acc = dh[i] * t[i];
-        for (int l = 0; l < i; ++l) acc -= LC[i * NX + l] * z[l];
-        z[i] = acc / LC[i * NX + i];
-      }
-      for (int i = NX - 1; i >= 0; --i) {
-        double acc = z[i];
-        for (int l = i + 1; l < NX; ++l) acc -= LC[l * NX + i] * z[l];
-        z[i] = acc / LC[i * NX + i];
-      }
-      for (int i = 0; i < NX; ++i) L.vec[0][i] = z[i] / dh[i];
+    // L_C z = Delta^1/2 t (row `lane` of L_C), then L_C^T w = z (column `lane`)
+    double acc = dh * t, z = 0.0;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const double zj = lane_bcast(acc, j) * F[FR_RI + j];
+      if (lane == j) z = zj;
+      if (lane > j) acc -= F[FR_LC + li * NX + j] * zj;
     }
-  } else {
-    if (lane < NX) L.vec[0][lane] = t[lane];
+    double acc2 = z, w = 0.0;
+#pragma unroll
+    for (int j = NX - 1; j >= 0; --j) {
+      const double wj = lane_bcast(acc2, j) * F[FR_RI + j];
+      if (lane == j) w = wj;
+      if (lane < j) acc2 -= F[FR_LC + j * NX + li] * wj;
+    }
+    av = w / dh;
   }
-  __syncthreads();
-  if (!full) return;
-  // b = ra + Delta a
-  if (lane < NX) L.vec[2][lane] = L.vec[1][lane] + (reg ? dh[lane] * dh[lane] * L.vec[0][lane] : 0.0);
-  __syncthreads();
-  if (has_u) {
-    // u = L_R^{-T} (wu - Y b)
-    if (lane < NU) {
-      double acc = wu[lane];
-      for (int i = 0; i < NX; ++i) acc -= Y[lane * NX + i] * L.vec[2][i];
-      L.vec[6][lane] = acc;
-    }
-    __syncthreads();
-    if (lane == 0) {
-      double* cu = L.vec[6];
+  if (full) {
+    b = ra[li] + (reg ? dh * dh * av : 0.0);
+    if (has_u) {
+      if (lane < NX) V.tmp[lane] = b;
+      lds_barrier();
+      double c2[NU];
+#pragma unroll
+      for (int a2 = 0; a2 < NU; ++a2) {
+        double acc = wu[a2];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) acc -= F[FR_Y + a2 * NX + i] * V.tmp[i];
+        c2[a2] = acc;
+      }
+#pragma unroll
       for (int a2 = NU - 1; a2 >= 0; --a2) {
-        double acc = cu[a2];
-        for (int l = a2 + 1; l < NU; ++l) acc -= LR[l * NU + a2] * cu[l];
-        cu[a2] = acc / LR[a2 * NU + a2];
+        double acc = c2[a2];
+#pragma unroll
+        for (int l = a2 + 1; l < NU; ++l) acc -= F[FR_LR + l * NU + a2] * cu[l];
+        cu[a2] = acc * F[FR_RR + a2];
       }
-      for (int a2 = 0; a2 < NU; ++a2) L.vec[3][a2] = cu[a2];
+    } else {
+#pragma unroll
+      for (int a2 = 0; a2 < NU; ++a2) cu[a2] = 0.0;
     }
-    __syncthreads();
   }
+  lds_barrier();
+  return av;
 }
 
-// Solve K [dv; dy] = [bv; bc] (and the eliminated p/n rows bp, bn in restoration) with the
-// factor in s.fac.  Outputs xv (n), xc (m), xp, xn (m; restoration only).
-__device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Iter& it, const Elim& e, const double* bv,
-                          const double* bc, const double* bp, const double* bn, double* xv, double* xc, double* xp,
-                          double* xn, KktLds& L, int lane) {
-  const int N = c.N, NI = c.NI;
-  // 1. condensed stage right-hand sides into s.rb (lambda 13, x 13, u 4 per knot)
+// flat prefetch of [factor record of knot kf | G of interval kg]; out-of-range kf / kg load a
+// valid record whose words the sweeps never read (branch-free loads, see stage_prefetch)
+__device__ __forceinline__ void sol_prefetch(const Cfg& c, const Slot& s, int kf, int kg, int lane, double* reg) {
+  const bool hf = kf >= 0 && kf <= c.N, hg = kg >= 0 && kg < c.N;
+  const double* Fp = s.fac + (long long)(hf ? kf : 0) * FR_LEN;
+  const double* Gp = s.G + (long long)(hg ? kg : 0) * NX * NZ;
+#pragma unroll
+  for (int t = 0; t < SPF; ++t) {
+    const int q = lane + WAVE * t;
+    const double* a = (q < FR_LEN) ? Fp + q : Gp + min(q - FR_LEN, NX * NZ - 1);
+    reg[t] = *a;
+  }
+}
+__device__ __forceinline__ void sol_park(double* buf, int lane, const double* reg) {
+#pragma unroll
+  for (int t = 0; t < SPF; ++t) buf[lane + WAVE * t] = reg[t];
+}
+
+// Solve K [dv; dy] = [bv; bc] (and the eliminated p/n rows bp, bn in restoration) with the factor
+// in s.fac and the stage data in s.sd.  Outputs xv (n), xc (m), xp, xn (m; restoration only).
+__device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Elim& e, const double* bv,
+                                          const double* bc, const double* bp, const double* bn, double* xv,
+                                          double* xc, double* xp, double* xn, SolLds& V, int lane) {
+  const int N = c.N, NI = c.NI, SL = sd_len(c);
+  double reg[SPF];
+  sol_prefetch(c, s, N, N - 1, lane, reg);      // first backward stage
+  // 1. condensed stage right-hand sides (lambda 13, x 13, u 4 per knot) into LDS
   for (int q = lane; q < (N + 1) * RB_LEN; q += WAVE) {
-    int k = q / RB_LEN, i = q % RB_LEN;
+    const int k = q / RB_LEN, i = q % RB_LEN;
     double val = 0.0;
     if (i < NX) {
-      int r = k * NX + i;
+      const int r = k * NX + i;
       val = bc[r];
       if (e.resto) {
-        double sp, sn;
-        row_elastic(s, e, r, sp, sn);
-        val += bp[r] / sp - bn[r] / sn;
+        const double* sdk = s.sd + (long long)k * SL;
+        val += bp[r] / (sdk[NZ + i] + e.dxp) - bn[r] / (sdk[NZ + NX + i] + e.dxp);
       }
     } else if (i < 2 * NX) {
       val = bv[xo(k) + i - NX];
     } else if (i < 2 * NX + NU && k < N) {
       val = bv[uo(k) + i - 2 * NX];
     }
-    s.rb[q] = val;
+    V.rb[q] = val;
   }
-  __syncthreads();
-  // position rows of x_k gather the slack rows of stage k
+  lds_barrier();
+  // position rows of x_k gather the slack rows of knot k
   for (int q = lane; q < N * 3; q += WAVE) {
-    int k = 1 + q / 3, t = q % 3;
+    const int k = 1 + q / 3, t = q % 3;
+    const double* sdk = s.sd + (long long)k * SL;
     double acc = 0.0;
     for (int j = 0; j < NI; ++j) {
-      const double* o = obs_ptr(c, s.th) + 4 * j;
-      int r = go(c, k, j);
-      double sig = slack_sigma(c, s, it, e, k, j);
-      double d = row_d(s, e, r);
-      double D = sig / (1.0 + sig * d);
+      const double* o7 = sdk + SD_HEAD + SD_OBS * j;
+      const int r = go(c, k, j);
+      const double sig = o7[0] + (e.lsq ? 0.0 : e.dxp);
+      const double d = row_dreg(e, o7[1], o7[2]);
+      const double D = sig / (1.0 + sig * d);
       double bg = bc[r];
-      if (e.resto) {
-        double sp, sn;
-        row_elastic(s, e, r, sp, sn);
-        bg += bp[r] / sp - bn[r] / sn;
-      }
-      double jg = 2.0 * (s.v[xo(k) + t] - o[t]);
-      acc += jg * D * (bv[so(c, k, j)] / sig + bg);
+      if (e.resto) bg += bp[r] / (o7[1] + e.dxp) - bn[r] / (o7[2] + e.dxp);
+      acc += o7[3 + t] * D * (bv[so(c, k, j)] / sig + bg);
     }
-    s.rb[(long long)k * RB_LEN + NX + t] += acc;
+    V.rb[k * RB_LEN + NX + t] += acc;
   }
-  __syncthreads();
+  sol_park(V.buf, lane, reg);
+  lds_barrier();
   // 2. backward sweep: rbar_k = r_k + G_k^T a_{k+1}
+  const int li = lane < NX ? lane : NX - 1;
   for (int k = N; k >= 0; --k) {
-    double* rb = s.rb + (long long)k * RB_LEN;
-    const double* fr = s.fac + (long long)k * FR_LEN;
-    for (int i = lane; i < NX; i += WAVE) {
-      L.vec[1][i] = rb[i];
-      L.vec[2][i] = rb[NX + i];
-    }
-    if (k < N)
-      for (int i = lane; i < NU; i += WAVE) L.vec[3][i] = rb[2 * NX + i];
-    __syncthreads();
-    stage_apply(c, fr, k < N, L, false, lane);
+    const double* B = V.buf;                  // factor of knot k | G_{k-1}
+    if (k > 0) sol_prefetch(c, s, k - 1, k - 2, lane, reg);
+    const double* rbk = V.rb + k * RB_LEN;
+    double ra[NX], ru[NU], cu[NU], bx;
+#pragma unroll
+    for (int l = 0; l < NX; ++l) ra[l] = rbk[l];
+#pragma unroll
+    for (int a2 = 0; a2 < NU; ++a2) ru[a2] = (k < N) ? rbk[2 * NX + a2] : 0.0;
+    const double av = stage_apply(B, k < N, ra, rbk[NX + li], ru, false, lane, bx, cu, V);
     if (k > 0) {
-      const double* Gp = s.G + (long long)(k - 1) * NX * NZ;
-      double* rbp = s.rb + (long long)(k - 1) * RB_LEN;
-      for (int j = lane; j < NZ; j += WAVE) {
+      double al[NX];
+#pragma unroll
+      for (int l = 0; l < NX; ++l) al[l] = lane_bcast(av, l);
+      if (lane < NZ) {
+        const double* Gp = B + FR_LEN;         // G_{k-1}
         double acc = 0.0;
-        for (int l = 0; l < NX; ++l) acc += Gp[l * NZ + j] * L.vec[0][l];
-        rbp[NX + j] += acc;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) acc += Gp[l * NZ + lane] * al[l];
+        V.rb[(k - 1) * RB_LEN + NX + lane] += acc;
       }
+      lds_barrier();
+      sol_park(V.buf, lane, reg);
     }
-    __syncthreads();
+    lds_barrier();
   }
-  // 3. forward sweep
+  // 3. forward sweep with the lambda rows fed by G_{k-1} (dx_{k-1}, du_{k-1}); the buffer still
+  //    holds the record of knot 0 from the last backward stage
+  double dz[NZ];
+#pragma unroll
+  for (int l = 0; l < NZ; ++l) dz[l] = 0.0;
   for (int k = 0; k <= N; ++k) {
-    const double* rb = s.rb + (long long)k * RB_LEN;
-    const double* fr = s.fac + (long long)k * FR_LEN;
-    for (int i = lane; i < NX; i += WAVE) {
+    const double* B = V.buf;                  // factor of knot k | G_{k-1}
+    if (k < N) sol_prefetch(c, s, k + 1, k, lane, reg);
+    const double* rbk = V.rb + k * RB_LEN;
+    double rai = rbk[li];
+    if (k > 0) {
+      const double* Gp = B + FR_LEN;
       double w = 0.0;
-      if (k > 0) {
-        const double* Gp = s.G + (long long)(k - 1) * NX * NZ;
-        for (int l = 0; l < NZ; ++l) w += Gp[i * NZ + l] * xv[(k - 1) * NZ + l];
-      }
-      L.vec[1][i] = rb[i] + w;
-      L.vec[2][i] = rb[NX + i];
+#pragma unroll
+      for (int l = 0; l < NZ; ++l) w += Gp[li * NZ + l] * dz[l];
+      rai += w;
     }
-    if (k < N)
-      for (int i = lane; i < NU; i += WAVE) L.vec[3][i] = rb[2 * NX + i];
-    __syncthreads();
-    stage_apply(c, fr, k < N, L, true, lane);
-    for (int i = lane; i < NX; i += WAVE) {
-      xc[k * NX + i] = L.vec[0][i];
-      xv[xo(k) + i] = L.vec[2][i];
+    double ra[NX], ru[NU], cu[NU], bx = 0.0;
+#pragma unroll
+    for (int l = 0; l < NX; ++l) ra[l] = lane_bcast(rai, l);
+#pragma unroll
+    for (int a2 = 0; a2 < NU; ++a2) ru[a2] = (k < N) ? rbk[2 * NX + a2] : 0.0;
+    const double av = stage_apply(B, k < N, ra, rbk[NX + li], ru, true, lane, bx, cu, V);
+    if (lane < NX) {
+      xc[k * NX + lane] = av;
+      xv[xo(k) + lane] = bx;
     }
-    if (k < N)
-      for (int i = lane; i < NU; i += WAVE) xv[uo(k) + i] = L.vec[3][i];
-    __syncthreads();
+    if (k < N) {
+      double u = 0.0;
+#pragma unroll
+      for (int a2 = 0; a2 < NU; ++a2) u = (lane == a2) ? cu[a2] : u;
+      if (lane < NU) xv[uo(k) + lane] = u;
+    }
+#pragma unroll
+    for (int l = 0; l < NX; ++l) dz[l] = lane_bcast(bx, l);
+#pragma unroll
+    for (int a2 = 0; a2 < NU; ++a2) dz[NX + a2] = cu[a2];
+    if (k < N) sol_park(V.buf, lane, reg);    // stage_apply ended with a barrier after its last read
+    lds_barrier();
   }
+  __syncthreads();   // xv is read back by other lanes below
   // 4. recover slack steps, inequality multiplier steps and elastic steps
   for (int q = lane; q < N * NI; q += WAVE) {
-    int k = 1 + q / NI, j = q % NI;
-    const double* o = obs_ptr(c, s.th) + 4 * j;
-    int r = go(c, k, j);
-    double sig = slack_sigma(c, s, it, e, k, j);
-    double d = row_d(s, e, r);
-    double D = sig / (1.0 + sig * d);
+    const int k = 1 + q / NI, j = q % NI;
+    const double* o7 = s.sd + (long long)k * SL + SD_HEAD + SD_OBS * j;
+    const int r = go(c, k, j);
+    const double sig = o7[0] + (e.lsq ? 0.0 : e.dxp);
+    const double d = row_dreg(e, o7[1], o7[2]);
+    const double D = sig / (1.0 + sig * d);
     double bg = bc[r];
-    if (e.resto) {
-      double sp, sn;
-      row_elastic(s, e, r, sp, sn);
-      bg += bp[r] / sp - bn[r] / sn;
-    }
+    if (e.resto) bg += bp[r] / (o7[1] + e.dxp) - bn[r] / (o7[2] + e.dxp);
     double jdx = 0.0;
-    for (int t = 0; t < 3; ++t) jdx += 2.0 * (s.v[xo(k) + t] - o[t]) * xv[xo(k) + t];
-    int si = so(c, k, j);
-    double bs = bv[si];
-    double dyg = D * (jdx - bs / sig - bg);
+    for (int t = 0; t < 3; ++t) jdx += o7[3 + t] * xv[xo(k) + t];
+    const int si = so(c, k, j);
+    const double bs = bv[si];
+    const double dyg = D * (jdx - bs / sig - bg);
     xc[r] = dyg;
     xv[si] = (bs + dyg) / sig;
   }
   __syncthreads();
   if (e.resto) {
     for (int r = lane; r < c.m; r += WAVE) {
-      double sp, sn;
-      row_elastic(s, e, r, sp, sn);
+      const double sp = s.zp[r] / s.p[r] + e.dxp, sn = s.zn[r] / s.nn[r] + e.dxp;
       xp[r] = (bp[r] + xc[r]) / sp;
       xn[r] = (bn[r] - xc[r]) / sn;
     }

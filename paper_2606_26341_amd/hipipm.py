@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhipipm.so")
 STATUS = {0: "RUNNING", 1: "CONVERGED", 2: "MAX_ITER", 3: "RESTO_FAILED", 4: "INFEASIBLE", 5: "NUMERICAL",
           6: "FILTER_OVERFLOW"}
 ST_CONVERGED = 1
-KERNELS = ("eval", "factor", "linesearch", "setup")
+KERNELS = ("eval", "pre", "factor", "solve", "linesearch", "setup")
 
 
 class ProblemDesc(C.Structure):
@@ -197,11 +197,12 @@ class Solver:
         self._check(self.L.hipipm_reset_stats(self.h))
 
     def kernel_times(self) -> dict:
-        n = C.c_int32(4)
-        ms = (C.c_double * 4)()
-        cnt = (C.c_int64 * 4)()
+        k = len(KERNELS)
+        n = C.c_int32(k)
+        ms = (C.c_double * k)()
+        cnt = (C.c_int64 * k)()
         self._check(self.L.hipipm_kernel_times(self.h, C.byref(n), ms, cnt))
-        return {KERNELS[i]: (float(ms[i]), int(cnt[i])) for i in range(4)}
+        return {KERNELS[i]: (float(ms[i]), int(cnt[i])) for i in range(min(k, n.value))}
 
     # ------------------------------------------------------------------ test hooks
     def state_len(self) -> int:
