@@ -30,14 +30,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# per-knot factor record actually produced: L_R (4x4), Y (4x13), P (13x13), Delta^1/2 (13), flag
-FR_WORDS = 16 + 52 + 169 + 13 + 1
+# per-knot factor record produced on the regular path: L_R (4x4), Y (4x13), P (13x13),
+# Delta^1/2 (13), 1/diag(L_R) (4), flag
+FR_WORDS = 16 + 52 + 169 + 13 + 4 + 1
 
 
 def sd_words(n_obs: int) -> int:
-    """Perturbation-free stage data per knot: Hessian diagonal (17), elastic ratios (2 x 13) and
-    7 words per inequality row, padded to 8 words."""
-    return ((17 + 26 + 7 * n_obs + 7) // 8) * 8
+    """Stage data per knot: Hessian diagonal (17), elastic ratios (2 x 13), condensed inequality
+    block (9) and 7 words per inequality row, padded to 8 words."""
+    return ((17 + 26 + 9 + 7 * n_obs + 7) // 8) * 8
 
 
 def kernel_roofline(w, st, kt, slots_launched):

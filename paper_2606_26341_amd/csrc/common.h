@@ -35,10 +35,10 @@ enum : int {
 };
 
 // per-stage factor record (doubles)
-//   L_R (4x4 lower), Y = L_R^{-1} Hbar^ux, P, L_C (lower, only when Delta > 0), Delta^1/2,
-//   1 / diag(L_C), 1 / diag(L_R), flag (Delta > 0)
-enum : int { FR_LR = 0, FR_Y = 16, FR_P = 16 + NU * NX, FR_LC = FR_P + NX * NX, FR_DH = FR_LC + NX * NX,
-             FR_RI = FR_DH + NX, FR_RR = FR_RI + NX, FR_FLAG = FR_RR + NU, FR_LEN = ((FR_FLAG + 1 + 7) / 8) * 8 };
+//   L_R (4x4 lower), Y = L_R^{-1} Hbar^ux, P, M = Delta^{-1/2} C^{-1} Delta^{1/2} (only when
+//   Delta > 0), Delta^1/2, 1 / diag(L_R), flag (Delta > 0)
+enum : int { FR_LR = 0, FR_Y = 16, FR_P = 16 + NU * NX, FR_M = FR_P + NX * NX, FR_DH = FR_M + NX * NX,
+             FR_RR = FR_DH + NX, FR_FLAG = FR_RR + NU, FR_LEN = ((FR_FLAG + 1 + 7) / 8) * 8 };
 // per-stage condensed right-hand side (lambda 13, x 13, u 4) padded
 constexpr int RB_LEN = 32;
 

@@ -108,9 +108,11 @@ __device__ __forceinline__ void lds_barrier() {
 //   [0, NZ)            objective Hessian diagonal + bound Sigma of (x_k, u_k) (identity in LSQ mode)
 //   [NZ, NZ+NX)        z_p/p of the rows defining x_k   (restoration only)
 //   [NZ+NX, NZ+2NX)    z_n/n of those rows              (restoration only)
+//   [NZ+2NX, NZ+2NX+9) condensed inequality block Hc of the position rows (3x3), see kkt_condense
 //   then per inequality row j of the knot: sigma0 (z_s/s [+ zeta D_R^2]), z_p/p, z_n/n, J_g (3),
 //   2 y_g (Hessian of the row).
-constexpr int SD_HEAD = NZ + 2 * NX;
+constexpr int SD_HC = NZ + 2 * NX;
+constexpr int SD_HEAD = SD_HC + 9;
 constexpr int SD_OBS = 7;
 __device__ __host__ __forceinline__ int sd_len_of(int NI) { return ((SD_HEAD + SD_OBS * NI + 7) / 8) * 8; }
 __device__ __forceinline__ int sd_len(const Cfg& c) { return sd_len_of(c.NI); }
@@ -128,11 +130,38 @@ __device__ __forceinline__ double row_dreg(const Elim& e, double sp0, double sn0
   return d;
 }
 
+// Condensed inequality block of every knot k >= 1 for the perturbations in e:
+//   Hc_k = sum_j D_kj J_kj^T J_kj + diag(sum_j 2 y_kj) (position rows),
+//   D_kj = sigma / (1 + sigma d),  sigma = sigma0 + delta_x,  d = delta_c + elastic part,
+// which is what eliminating the slack s_kj and its row (and the elastic p/n) leaves on x_k.
+// One (knot, upper-triangle entry) per lane; reads and rewrites the stage data.
+__device__ __forceinline__ void kkt_condense(const Cfg& c, const Slot& s, const Elim& e, int lane) {
+  const int N = c.N, NI = c.NI, SL = sd_len(c);
+  for (int q = lane; q < N * 6; q += WAVE) {
+    const int k = 1 + q / 6, p = q % 6;
+    const int a = p < 3 ? 0 : (p < 5 ? 1 : 2), b = p < 3 ? p : (p < 5 ? p - 2 : 2);
+    double* sdk = s.sd + (long long)k * SL;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < NI; ++j) {
+      const double* o7 = sdk + SD_HEAD + SD_OBS * j;
+      const double sig = o7[0] + (e.lsq ? 0.0 : e.dxp);
+      const double d = row_dreg(e, o7[1], o7[2]);
+      const double D = sig / (1.0 + sig * d);
+      acc += D * o7[3 + a] * o7[3 + b];
+      if (a == b) acc += o7[6];
+    }
+    sdk[SD_HC + a * 3 + b] = acc;
+    if (a != b) sdk[SD_HC + b * 3 + a] = acc;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void kkt_stage_data(const Cfg& c, const Slot& s, const Iter& it, const Elim& e,
                                                int lane) {
   const int N = c.N, NI = c.NI, L = sd_len(c);
-  for (int q = lane; q < (N + 1) * SD_HEAD; q += WAVE) {
-    const int k = q / SD_HEAD, i = q % SD_HEAD;
+  for (int q = lane; q < (N + 1) * SD_HC; q += WAVE) {
+    const int k = q / SD_HC, i = q % SD_HC;
     double* sd = s.sd + (long long)k * L;
     double val = 0.0;
     if (i < NZ) {
@@ -180,19 +209,29 @@ __device__ __forceinline__ void kkt_stage_data(const Cfg& c, const Slot& s, cons
     o7[6] = e.lsq ? 0.0 : 2.0 * it.y[r];
   }
   __syncthreads();
+  kkt_condense(c, s, e, lane);
 }
 
 // ----------------------------------------------------------------------------- LDS workspaces
 constexpr int PF = 16;   // prefetch registers per lane (one stage of inputs)
 static_assert(NZ * NZ + NX * NZ + SD_HEAD + SD_OBS * MAX_OBS + 8 <= PF * WAVE, "stage inputs exceed the prefetch");
 
+// The unrolled loops below give every lane the same number of entries and no per-entry
+// branch, so that the entries' dependency chains overlap; the arrays are padded so that the
+// surplus lanes read and write harmless words.
+constexpr int TILE_T = (NX * NZ + WAVE - 1) / WAVE;    // 4 entries of T = S G per lane
+constexpr int TILE_H = (NZ * NZ + WAVE - 1) / WAVE;    // 5 entries of H per lane
+constexpr int TILE_P = (NX * NX + WAVE - 1) / WAVE;    // 3 entries of P, S per lane
+
 struct FacLds {
-  double S[NX * NX];
-  double H[NZ * NZ];
-  double Y[NU * NX];
-  double P[NX * NX];
-  double CV[2 * NX * NX];     // T = S G (NX x NZ) during the Schur update, then C | V
+  double S[16 * NX];          // rows read up to (TILE_T * WAVE - 1) / NZ
+  double H[TILE_H * WAVE];
+  double Y[WAVE];
+  double P[TILE_P * WAVE];
+  double CV[TILE_T * WAVE + 96];   // T = S G during the Schur update, then L_C | V (+ read-only pad)
+  double LI[NX * NX];              // L_C^{-1}
   double dh[NX];
+  double rdh[NX];
   double buf[PF * WAVE];      // stage inputs: W (NZ*NZ) | G (NX*NZ) | stage data
 };
 
@@ -214,6 +253,22 @@ __device__ __forceinline__ SolLds sol_lds(const Cfg& c, double* dyn) {
   return V;
 }
 
+// 1/sqrt(d) for finite d > 0: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  const double h = 0.5 * d;
+  double y = __builtin_amdgcn_rsq(d);
+  y = y * fma(-h * y, y, 1.5);
+  y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+// 1/x for finite nonzero x: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return y;
+}
+
 // value of v on lane src (src uniform), delivered to every lane through the scalar unit
 __device__ __forceinline__ double lane_bcast(double v, int src) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
@@ -231,9 +286,8 @@ __device__ __forceinline__ int chol_rows(double (&c)[NX], double (&rinv)[NX], in
   for (int j = 0; j < NX; ++j) {
     const double d = lane_bcast(c[j], j);
     if (!(d > 0.0)) return d == 0.0 ? 2 : 1;
-    const double r = sqrt(d);
-    rinv[j] = 1.0 / r;
-    c[j] = (lane == j) ? r : c[j] * rinv[j];
+    rinv[j] = rsqrt_nr(d);
+    c[j] = (lane == j) ? d * rinv[j] : c[j] * rinv[j];
 #pragma unroll
     for (int l = j + 1; l < NX; ++l) {
       const double ljl = lane_bcast(c[j], l);     // L_lj
@@ -267,62 +321,50 @@ __device__ __forceinline__ void stage_park(double* buf, int lane, const double* 
 // Factor all stage blocks with perturbations (e.dxp, e.dcp); stage data from kkt_stage_data.
 // Returns 0 (inertia correct), 1 (wrong), 2 (singular).  Writes the per-knot factor records.
 __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Elim& e, FacLds& L, int lane) {
-  const int N = c.N, NI = c.NI;
+  const int N = c.N;
   double reg[PF];
-  for (int i = lane; i < NX * NX; i += WAVE) L.S[i] = 0.0;
+  if (!e.lsq && (e.dxp != 0.0 || e.dcp != 0.0)) kkt_condense(c, s, e, lane);
+  for (int i = lane; i < 16 * NX; i += WAVE) L.S[i] = 0.0;
   stage_prefetch(c, s, N, lane, reg);
   stage_park(L.buf, lane, reg);
   lds_barrier();
+  const double dx = e.lsq ? 0.0 : e.dxp;
   int status = 0;
   for (int k = N; k >= 0; --k) {
-    const int nz = (k < N) ? NZ : NX;
     const double* B = L.buf;      // dead after the barrier that follows the dh read
     const double* Wk = B;
     const double* Gk = B + ((k < N) ? NZ * NZ : 0);
     const double* SD = B + ((k < N) ? NZ * NZ + NX * NZ : 0);
     double* fr = s.fac + (long long)k * FR_LEN;
     if (k > 0) stage_prefetch(c, s, k - 1, lane, reg);   // in flight during this stage
-    // ---- stage Hessian H_k = W_k + diag + delta_x I (+ condensed slacks) ----
-    for (int q = lane; q < nz * nz; q += WAVE) {
-      const int i = q / nz, j = q % nz;
-      double h = (!e.lsq && k < N) ? Wk[i * NZ + j] : 0.0;
-      if (i == j) h += SD[i] + (e.lsq ? 0.0 : e.dxp);
-      L.H[i * nz + j] = h;
-    }
-    lds_barrier();
-    if (k >= 1) {
-      for (int q = lane; q < 9; q += WAVE) {
-        const int a = q / 3, b = q % 3;
-        double acc = 0.0;
-        for (int j = 0; j < NI; ++j) {
-          const double* o7 = SD + SD_HEAD + SD_OBS * j;
-          const double sig = o7[0] + (e.lsq ? 0.0 : e.dxp);
-          const double d = row_dreg(e, o7[1], o7[2]);
-          const double D = sig / (1.0 + sig * d);
-          acc += D * o7[3 + a] * o7[3 + b];
-          if (a == b) acc += o7[6];
-        }
-        L.H[a * nz + b] += acc;
-      }
-      lds_barrier();
-    }
-    // ---- Schur update H += G^T S_{k+1} G ----
+    // ---- Schur update, first half: T = S_{k+1} G_k (13 x 17) ----
     if (k < N) {
-      for (int q = lane; q < NX * NZ; q += WAVE) {
-        const int i = q / NZ, j = q % NZ;
+#pragma unroll
+      for (int t = 0; t < TILE_T; ++t) {
+        const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
         double acc = 0.0;
+#pragma unroll
         for (int l = 0; l < NX; ++l) acc += L.S[i * NX + l] * Gk[l * NZ + j];
         L.CV[q] = acc;
       }
       lds_barrier();
-      for (int q = lane; q < NZ * NZ; q += WAVE) {
-        const int i = q / NZ, j = q % NZ;
-        double acc = 0.0;
-        for (int l = 0; l < NX; ++l) acc += Gk[l * NZ + i] * L.CV[l * NZ + j];
-        L.H[q] += acc;
-      }
-      lds_barrier();
     }
+    // ---- stage Hessian (NZ stride): W_k + diag + delta_x I + Hc_k + G_k^T T ----
+#pragma unroll
+    for (int t = 0; t < TILE_H; ++t) {
+      const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
+      double h = (!e.lsq && k < N) ? Wk[q] : 0.0;
+      h += (i == j && (k < N || i < NX)) ? SD[j] + dx : 0.0;
+      h += (k >= 1 && i < 3 && j < 3) ? SD[SD_HC + 3 * (i < 3 ? i : 0) + j] : 0.0;
+      if (k < N) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) acc += Gk[l * NZ + i] * L.CV[l * NZ + j];
+        h += acc;
+      }
+      L.H[q] = h;
+    }
+    lds_barrier();
     // ---- control block: Cholesky of Hbar^uu (on every lane, in registers), Y, P ----
     const int li = lane < NX ? lane : NX - 1;
     if (k < N) {
@@ -334,9 +376,8 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
         for (int l = 0; l < j; ++l) d -= lr[j * NU + l] * lr[j * NU + l];
         if (bad == 0 && !(d > 0.0)) bad = (d == 0.0) ? 2 : 1;
-        const double r = sqrt(d);
-        rr[j] = 1.0 / r;
-        lr[j * NU + j] = r;
+        rr[j] = rsqrt_nr(d);
+        lr[j * NU + j] = d * rr[j];
 #pragma unroll
         for (int i = 0; i < NU; ++i) {
           if (i < j) lr[i * NU + j] = 0.0;
@@ -369,26 +410,30 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         }
       }
       lds_barrier();
-      for (int q = lane; q < NX * NX; q += WAVE) {
-        const int i = q / NX, j = q % NX;
+#pragma unroll
+      for (int t = 0; t < TILE_P; ++t) {
+        const int q = lane + WAVE * t, i = q / NX, j = q % NX;
         double acc = L.H[i * NZ + j];
 #pragma unroll
         for (int a = 0; a < NU; ++a) acc -= L.Y[a * NX + i] * L.Y[a * NX + j];
         L.P[q] = acc;
       }
     } else {
-      for (int q = lane; q < NX * NX; q += WAVE) L.P[q] = L.H[q];
+#pragma unroll
+      for (int t = 0; t < TILE_P; ++t) {
+        const int q = lane + WAVE * t;
+        L.P[q] = L.H[(q / NX) * NZ + q % NX];
+      }
     }
     // ---- pair pivot with the dual regularisation Delta_k of the rows defining x_k ----
-    const double dhl = sqrt(row_dreg(e, SD[NZ + li], SD[NZ + NX + li]));
+    // (Delta > 0 on every row exactly when delta_c > 0 or the elastic variables are eliminated)
+    const bool pair = !e.lsq && (e.resto || e.dcp > 0.0);
+    const double dhl = pair ? sqrt(row_dreg(e, SD[NZ + li], SD[NZ + NX + li])) : 0.0;
     if (lane < NX) L.dh[lane] = dhl;
     lds_barrier();
-    double dmax = 0.0;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) dmax = fmax(dmax, L.dh[i]);
     double* LC = L.CV;
     double* VV = L.CV + NX * NX;
-    if (dmax > 0.0) {
+    if (pair) {
       // C = I + Delta^1/2 P Delta^1/2, one row per lane, factored in registers
       double cr[NX], ri[NX];
 #pragma unroll
@@ -397,45 +442,57 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       if (r) { status = r; break; }
       if (lane < NX) {
 #pragma unroll
-        for (int l = 0; l < NX; ++l) {
-          const double v = (l <= lane) ? cr[l] : 0.0;
-          LC[lane * NX + l] = v;
-          fr[FR_LC + lane * NX + l] = v;
-        }
-        double rl = 0.0;
-#pragma unroll
-        for (int l = 0; l < NX; ++l) rl = (l == lane) ? ri[l] : rl;
-        fr[FR_RI + lane] = rl;
+        for (int l = 0; l < NX; ++l) LC[lane * NX + l] = (l <= lane) ? cr[l] : 0.0;
+        L.rdh[lane] = rcp_nr(dhl);
       }
       lds_barrier();
-      // V = L_C^{-1} Delta^1/2 P, one column per lane, forward substitution in registers
-      if (lane < NX) {
+      // lanes 0..12: column `lane` of V = L_C^{-1} Delta^1/2 P; lanes 32..44: column `lane - 32` of
+      // L_C^{-1}; forward substitutions in registers
+      if (lane < NX || (lane >= 32 && lane < 32 + NX)) {
+        const bool inv = lane >= 32;
+        const int col = inv ? lane - 32 : lane;
         double v[NX];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          double acc = L.dh[i] * L.P[i * NX + lane];
+          double acc = inv ? (i == col ? 1.0 : 0.0) : L.dh[i] * L.P[i * NX + col];
 #pragma unroll
           for (int l = 0; l < i; ++l) acc -= LC[i * NX + l] * v[l];
           v[i] = acc * ri[i];
-          VV[i * NX + lane] = v[i];
+          if (inv) L.LI[i * NX + col] = v[i];
+          else VV[i * NX + col] = v[i];
         }
       }
       lds_barrier();
-      for (int q = lane; q < NX * NX; q += WAVE) {
-        const int i = q / NX, j = q % NX;
+      // S = P - V^T V and M = Delta^{-1/2} C^{-1} Delta^{1/2}, C^{-1} = L_C^{-T} L_C^{-1}
+#pragma unroll
+      for (int t = 0; t < TILE_P; ++t) {
+        const int q = lane + WAVE * t, i = q / NX, j = q % NX;
         double acc = L.P[q];
 #pragma unroll
         for (int l = 0; l < NX; ++l) acc -= VV[l * NX + i] * VV[l * NX + j];
         L.S[q] = acc;
+        const int qi = q < NX * NX ? i : 0;
+        double ci = 0.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) ci += L.LI[l * NX + qi] * L.LI[l * NX + j];
+        if (q < NX * NX) fr[FR_M + q] = ci * L.dh[j] * L.rdh[qi];
       }
     } else {
-      for (int q = lane; q < NX * NX; q += WAVE) L.S[q] = L.P[q];
+#pragma unroll
+      for (int t = 0; t < TILE_P; ++t) {
+        const int q = lane + WAVE * t;
+        L.S[q] = L.P[q];
+      }
     }
     // ---- store the stage factor ----
-    for (int q = lane; q < NU * NX; q += WAVE) fr[FR_Y + q] = L.Y[q];
-    for (int q = lane; q < NX * NX; q += WAVE) fr[FR_P + q] = L.P[q];
+    if (lane < NU * NX) fr[FR_Y + lane] = L.Y[lane];
+#pragma unroll
+    for (int t = 0; t < TILE_P; ++t) {
+      const int q = lane + WAVE * t;
+      if (q < NX * NX) fr[FR_P + q] = L.P[q];
+    }
     if (lane < NX) fr[FR_DH + lane] = dhl;
-    if (lane == 0) fr[FR_FLAG] = dmax > 0.0 ? 1.0 : 0.0;
+    if (lane == 0) fr[FR_FLAG] = pair ? 1.0 : 0.0;
     if (k > 0) stage_park(L.buf, lane, reg);
     lds_barrier();
   }
@@ -450,7 +507,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 // `full` also the x component b of row `lane` and the control part cu[] on every lane.
 // Lanes >= NX compute throw-away values.  Ends with an LDS barrier after the last read of F.
 //   w_u = L_R^{-1} r_u,  t = r_x - Y^T w_u - P r_a,
-//   a = t (Delta = 0)  or  a = Delta^{-1/2} C^{-1} Delta^{1/2} t  with C = L_C L_C^T,
+//   a = t (Delta = 0)  or  a = M t,  M = Delta^{-1/2} C^{-1} Delta^{1/2} from the factor record,
 //   b = r_a + Delta a,  c_u = L_R^{-T} (w_u - Y b)
 __device__ __forceinline__ double stage_apply(const double* F, bool has_u, const double (&ra)[NX], double rx,
                                               const double (&ru)[NU], bool full, int lane, double& b,
@@ -474,22 +531,13 @@ __device__ __forceinline__ double stage_apply(const double* F, bool has_u, const
   double av = t;
   const double dh = F[FR_DH + li];
   if (reg) {
-    // L_C z = Delta^1/2 t (row `lane` of L_C), then L_C^T w = z (column `lane`)
-    double acc = dh * t, z = 0.0;
+    double tl[NX];
 #pragma unroll
-    for (int j = 0; j < NX; ++j) {
-      const double zj = lane_bcast(acc, j) * F[FR_RI + j];
-      if (lane == j) z = zj;
-      if (lane > j) acc -= F[FR_LC + li * NX + j] * zj;
-    }
-    double acc2 = z, w = 0.0;
+    for (int l = 0; l < NX; ++l) tl[l] = lane_bcast(t, l);
+    double acc = 0.0;
 #pragma unroll
-    for (int j = NX - 1; j >= 0; --j) {
-      const double wj = lane_bcast(acc2, j) * F[FR_RI + j];
-      if (lane == j) w = wj;
-      if (lane < j) acc2 -= F[FR_LC + j * NX + li] * wj;
-    }
-    av = w / dh;
+    for (int l = 0; l < NX; ++l) acc += F[FR_M + li * NX + l] * tl[l];
+    av = acc;
   }
   if (full) {
     b = ra[li] + (reg ? dh * dh * av : 0.0);
