@@ -44,34 +44,38 @@ def sd_words(n_obs: int) -> int:
 def kernel_roofline(w, st, kt, slots_launched):
     """Roofline of the dominant kernel from the live HIP-event timings (algorithmic FP64 bytes).
 
-    k_fac, per slot and factorization attempt: reads the stage inputs (G_k 13x17 and W_k 17x17 per
-    interval, the stage data per knot) and writes the factor record per knot.
-    k_sol, per solve: reads the factor record and stage data per knot, G_k per interval and the
-    right-hand side (n + m), writes the step (n + m).
+    One factorization attempt (per slot) reads the stage inputs (G_k 13x17 and W_k 17x17 per
+    interval, the stage data per knot) and writes the factor record per knot.  One solve reads
+    the factor record and stage data per knot, G_k per interval and the right-hand side (n + m),
+    and writes the step (n + m).  k_fac does factorizations only; the fused pass kernel (the
+    last instances of a batch) is charged only the bytes of the factorizations and solves it
+    runs, so its figure is a lower bound of its traffic.
     """
     N = w.N
-    names = ("eval", "pre", "factor", "solve", "linesearch")
+    names = ("eval", "pre", "factor", "solve", "linesearch", "fused")
     tot = {k: kt[k][0] for k in names if k in kt}
     dom = max(tot, key=tot.get)
     ms, launches = kt[dom]
     avg_ms = ms / max(1, launches)
     sdw = sd_words(w.n_obs)
+    fact_bytes = 8.0 * (N * (13 * 17 + 17 * 17) + (N + 1) * (sdw + FR_WORDS))
+    solve_bytes = 8.0 * ((N + 1) * (FR_WORDS + sdw) + N * 13 * 17 + 2 * (w.n + w.m))
     if dom == "factor":
-        per_unit = 8.0 * (N * (13 * 17 + 17 * 17) + (N + 1) * (sdw + FR_WORDS))
-        units = st["factorizations"]
-        kernel = "k_fac"
-    elif dom == "solve":
-        per_unit = 8.0 * ((N + 1) * (FR_WORDS + sdw) + N * 13 * 17 + 2 * (w.n + w.m))
-        units = st["iterations"] + st["instances_done"]
-        kernel = "k_sol"
+        units = st["factorizations"] - st["fused_factorizations"]
+        per_launch = fact_bytes * units / max(1, launches)
+        kernel, unit_desc = "k_fac", f"{units} factorizations x {fact_bytes:.0f} B"
+    elif dom == "fused":
+        per_launch = (fact_bytes * st["fused_factorizations"] + solve_bytes * st["fused_solves"]) / max(1, launches)
+        kernel = "k_iter"
+        unit_desc = (f"{st['fused_factorizations']} factorizations x {fact_bytes:.0f} B + "
+                     f"{st['fused_solves']} solves x {solve_bytes:.0f} B")
     else:
         return dict(kernel="k_" + dom, bound="latency", achieved=None, peak=None, unit=None, frac=None,
                     traffic=None, avg_ms=avg_ms, launches=launches)
-    per_launch = per_unit * units / max(1, launches)
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     return dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=achieved / HBM_PEAK_GBS, traffic=None, avg_ms=avg_ms, launches=launches,
-                bytes_per_unit=per_unit, units=units)
+                bytes_per_launch=per_launch, units=unit_desc)
 
 
 def cpu_baseline(w, sample: int):
@@ -96,8 +100,12 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--slots", type=int, default=0, help="concurrent slots (default: all instances)")
     ap.add_argument("--instances", type=int, default=0)
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (HBM counter calibration) and exit")
+    ap.add_argument("--fuse-below", type=int, default=None,
+                    help="unfinished-instance count below which passes use the fused kernel (default: library's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported (instances shard "
@@ -105,13 +113,25 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        n = 1 << 25                      # 2^25 doubles = 256 MiB read + 256 MiB written per copy
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 4}), flush=True)
+        return
     from paper_2606_26341_amd import hipipm, workloads as W
 
     w = W.get(args.workload)
     n_inst = args.instances or w.n_inst
     slots = args.slots or n_inst
     TH = torch.tensor(w.thetas(0, n_inst), dtype=torch.float64, device="cuda:0")
-    solver = hipipm.Solver(w, slots, hipipm.default_options(timing=1))
+    opts = dict(timing=1)
+    if args.fuse_below is not None:
+        opts["fuse_below"] = args.fuse_below
+    solver = hipipm.Solver(w, slots, hipipm.default_options(**opts))
     out = solver.alloc_outputs(n_inst)
     stream = torch.cuda.current_stream()
     log(f"[bench] workload {w.name}: {n_inst} instances, N={w.N}, n={w.n}, m={w.m}, slots={slots}")
@@ -154,6 +174,7 @@ def main():
         "max_kkt_converged": float(kkt[status == 1].max()) if (status == 1).any() else None,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "roofline_kernel": roof["kernel"],
+        "roofline_detail": {k: roof[k] for k in ("avg_ms", "launches", "bytes_per_launch", "units") if k in roof},
         "kernel_ms": {k: v[0] for k, v in kt.items()},
     }
     if not args.no_cpu:

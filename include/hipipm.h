@@ -86,6 +86,9 @@ typedef struct {
     int32_t filter_cap;   /* <= 128 */
     int32_t poll_every;   /* iterations between completion polls (>= 1) */
     int32_t timing;       /* 1: time every kernel launch with HIP events (hipipm_kernel_times) */
+    int32_t fuse_below;   /* once at most this many instances are unfinished, each pass runs the
+                             per-slot phases in one fused launch (0: never); default 2^30,
+                             i.e. always */
 } hipipm_options;
 
 typedef struct {
@@ -95,6 +98,9 @@ typedef struct {
 typedef struct {
     int64_t iterations, resto_iterations, soc_tried, soc_accepted, factorizations, resto_entries,
         tiny_steps, passes, instances_done;
+    int64_t solves;                  /* step solves with a stored factor (incl. least-squares y, not SOC) */
+    int64_t fused_factorizations;    /* factorizations done inside the fused pass kernel */
+    int64_t fused_solves;            /* solves (step and SOC) done inside the fused pass kernel */
 } hipipm_stats;
 
 typedef struct hipipm_ctx hipipm_ctx;
@@ -136,9 +142,10 @@ int hipipm_stats_get(const hipipm_ctx* ctx, hipipm_stats* out);
 int hipipm_reset_stats(hipipm_ctx* ctx);
 
 /* Kernel timing (options.timing = 1): total milliseconds and launch counts per kernel since the
- * last reset, in the order "eval", "pre", "factor", "solve", "linesearch", "setup" (the five
- * kernels of one pass, then the per-solve setup).  *n_kernels: capacity of the arrays on input,
- * number of timed kernels (6) on output. */
+ * last reset, in the order "eval", "pre", "factor", "solve", "linesearch", "fused", "setup" (the
+ * five kernels of a pass, the fused pass kernel used for the last options.fuse_below instances,
+ * then the per-solve setup).  *n_kernels: capacity of the arrays on input, number of timed
+ * kernels (7) on output. */
 int hipipm_kernel_times(const hipipm_ctx* ctx, int32_t* n_kernels, double* total_ms, int64_t* launches);
 
 /* ---- test hooks (one-step replay, Sec. VI "Correctness") ----

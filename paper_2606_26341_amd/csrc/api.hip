@@ -21,6 +21,8 @@ void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const 
 void launch_fac(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_sol(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st);
+void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+                 Counters* cnt, int refill, hipStream_t st);
 void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm_x,
                   hipStream_t st);
 void launch_stage_derivs(const Cfg& c, int count, const double* x, const double* u, const double* lam, double* F,
@@ -33,9 +35,11 @@ int sd_len_host(int NI);
 
 using namespace hipipm;
 
-// timed kernels: eval, pre, factor, solve, linesearch (one launch each per pass), setup
-static constexpr int NKT = 6;
+// timed kernels: eval, pre, factor, solve, linesearch (one launch each per pass), fused pass
+// kernel, setup
+static constexpr int NKT = 7;
 static constexpr int NPK = 5;
+static constexpr int KT_FUSED = 5;
 
 struct hipipm_ctx {
   hipipm_problem_desc desc;
@@ -102,7 +106,7 @@ int hipipm_default_options(hipipm_options* o) {
   o->gamma_theta = 1e-5; o->gamma_phi = 1e-8; o->delta_sw = 1.0; o->s_theta = 1.1; o->s_phi = 2.3;
   o->eta_phi = 1e-8; o->gamma_alpha = 0.05; o->max_soc = 4; o->kappa_soc = 0.99; o->kappa_sigma = 1e10;
   o->rho_resto = 1000.0; o->kappa_resto = 0.9; o->bound_mult_reset = 1e3; o->filter_cap = 128;
-  o->poll_every = 4; o->timing = 0;
+  o->poll_every = 4; o->timing = 0; o->fuse_below = 1 << 30;
   return HIPIPM_OK;
 }
 
@@ -113,7 +117,8 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   if (d->n_agents != 1) return HIPIPM_ERR_UNSUPPORTED;
   if (d->N < 1 || d->N > MAX_N || d->n_obs < 0 || d->n_obs > MAX_OBS) return HIPIPM_ERR_INVALID_ARG;
   if (!(d->dt > 0) || !(d->mass > 0) || !(d->jxx > 0) || !(d->jyy > 0) || !(d->jzz > 0)) return HIPIPM_ERR_INVALID_ARG;
-  if (o->filter_cap < 1 || o->filter_cap > FCAP || o->max_iter < 0 || o->poll_every < 1 || !(o->tol > 0))
+  if (o->filter_cap < 1 || o->filter_cap > FCAP || o->max_iter < 0 || o->poll_every < 1 || !(o->tol > 0) ||
+      o->fuse_below < 0)
     return HIPIPM_ERR_INVALID_ARG;
   hipipm_ctx* c = new hipipm_ctx();
   c->desc = *d;
@@ -222,19 +227,26 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   const long long max_passes = ((long long)c->opts.max_iter + 8) * 3 * ((n_inst + active - 1) / active) + 64;
   long long passes = 0;
   for (;;) {
+    // few unfinished instances left: fused pass kernel (every launch still covers all slots)
+    const bool fused = c->opts.fuse_below > 0 && n_inst - h.done <= c->opts.fuse_below;
     for (int p = 0; p < poll; ++p) {
       hipEvent_t* e = timing ? &ev[(NPK + 1) * p] : nullptr;
       if (timing) HIPCHK(c, hipEventRecord(e[0], st));
       launch_eval(c->cfg, c->ws, active, st);
       if (timing) HIPCHK(c, hipEventRecord(e[1], st));
-      launch_pre(c->cfg, c->ws, active, theta, warm_x, out, dcnt, 1, st);
-      if (timing) HIPCHK(c, hipEventRecord(e[2], st));
-      launch_fac(c->cfg, c->ws, active, st);
-      if (timing) HIPCHK(c, hipEventRecord(e[3], st));
-      launch_sol(c->cfg, c->ws, active, st);
-      if (timing) HIPCHK(c, hipEventRecord(e[4], st));
-      launch_ls(c->cfg, c->ws, active, st);
-      if (timing) HIPCHK(c, hipEventRecord(e[5], st));
+      if (fused) {
+        launch_iter(c->cfg, c->ws, active, theta, warm_x, out, dcnt, 1, st);
+        if (timing) HIPCHK(c, hipEventRecord(e[2], st));
+      } else {
+        launch_pre(c->cfg, c->ws, active, theta, warm_x, out, dcnt, 1, st);
+        if (timing) HIPCHK(c, hipEventRecord(e[2], st));
+        launch_fac(c->cfg, c->ws, active, st);
+        if (timing) HIPCHK(c, hipEventRecord(e[3], st));
+        launch_sol(c->cfg, c->ws, active, st);
+        if (timing) HIPCHK(c, hipEventRecord(e[4], st));
+        launch_ls(c->cfg, c->ws, active, st);
+        if (timing) HIPCHK(c, hipEventRecord(e[5], st));
+      }
     }
     HIPCHK(c, hipGetLastError());
     passes += poll;
@@ -243,11 +255,13 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
     if (timing) {
       for (int p = 0; p < poll; ++p) {
         const hipEvent_t* e = &ev[(NPK + 1) * p];
-        for (int q = 0; q < NPK; ++q) {
+        const int nk = fused ? 2 : NPK;
+        for (int q = 0; q < nk; ++q) {
           float ms = 0;
           HIPCHK(c, hipEventElapsedTime(&ms, e[q], e[q + 1]));
-          c->t_ms[q] += ms;
-          c->t_n[q] += 1;
+          const int bucket = (fused && q == 1) ? KT_FUSED : q;
+          c->t_ms[bucket] += ms;
+          c->t_n[bucket] += 1;
         }
       }
     }
@@ -267,6 +281,9 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   c->stats.tiny_steps += (int64_t)h.st[6];
   c->stats.passes += passes;
   c->stats.instances_done += (int64_t)h.st[8];
+  c->stats.solves += (int64_t)h.st[9];
+  c->stats.fused_factorizations += (int64_t)h.st[10];
+  c->stats.fused_solves += (int64_t)h.st[11];
   return HIPIPM_OK;
 }
 

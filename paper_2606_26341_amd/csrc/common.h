@@ -31,6 +31,7 @@ enum : int {
   SC_STEP = 24, SC_AMAX, SC_THK, SC_PHK, SC_GPHI, SC_FK, SC_STEPMU,
   SC_ST_RESTO = 32, SC_ST_SOCT, SC_ST_SOCA, SC_ST_FACT, SC_ST_RENT, SC_ST_TINY, SC_ST_PASS,
   SC_LDX = 40, SC_LDC, SC_LALPHA, SC_LALPHAZ, SC_LSOC, SC_WORK, SC_FSTAT,
+  SC_ST_SOLV, SC_ST_FFACT, SC_ST_FSOLV,
   SC_LEN = 64
 };
 
@@ -72,7 +73,7 @@ struct Outs {
 // global counters (device): queue head, finished count, stats
 struct Counters {
   int32_t head, done, n_inst, pad;
-  unsigned long long st[10];
+  unsigned long long st[12];
 };
 
 }  // namespace hipipm

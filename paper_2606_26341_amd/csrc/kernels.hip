@@ -12,7 +12,8 @@
 //            correction (row 2), acceptance, restoration entry/exit (row 6)
 //
 // The factor and solve live in kernels of their own so that each gets the register budget of
-// its own working set.
+// its own working set.  Once few instances remain, k_iter runs k_pre .. k_ls of a slot back to
+// back in one launch.
 #include "common.h"
 #include "model.h"
 #include "kkt.h"
@@ -139,7 +140,7 @@ struct ErrParts {
 
 __device__ __forceinline__ ErrParts err_parts(const Cfg& c, const Slot& s, const Iter& it, const double* aty, int lane) {
   double dual = 0.0, nanf = 0.0, z1 = 0.0, y1 = 0.0, prim = 0.0;
-  for (int i = lane; i < c.n; i += WAVE) {
+    for (int i = lane; i < c.n; i += WAVE) {
     double zl, zu;
     z_of(c, it, i, zl, zu);
     double d = s.g[i] + aty[i] - zl + zu;
@@ -147,7 +148,7 @@ __device__ __forceinline__ ErrParts err_parts(const Cfg& c, const Slot& s, const
     dual = fmax(dual, fabs(d));
     z1 += fabs(zl) + fabs(zu);
   }
-  for (int r = lane; r < c.m; r += WAVE) {
+    for (int r = lane; r < c.m; r += WAVE) {
     y1 += fabs(it.y[r]);
     double pr = fabs(s.rc[r]);
     if (!isfinite(pr)) nanf = 1.0;
@@ -173,15 +174,15 @@ __device__ __forceinline__ ErrParts err_parts(const Cfg& c, const Slot& s, const
 // max |s z - mu| over the bounded components
 __device__ __forceinline__ double compl_max(const Cfg& c, const Slot& s, const Iter& it, double mu, int lane) {
   double cm = 0.0;
-  for (int b = lane; b < c.N * NU; b += WAVE) {
+    for (int b = lane; b < c.N * NU; b += WAVE) {
     int k = b / NU, i = b % NU;
     double u = s.v[uo(k) + i];
     cm = fmax(cm, fabs(u * it.zlu[b] - mu));
     cm = fmax(cm, fabs((c.umax - u) * it.zuu[b] - mu));
   }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) cm = fmax(cm, fabs(s.v[c.n_w + q] * it.zls[q] - mu));
+    for (int q = lane; q < c.N * c.NI; q += WAVE) cm = fmax(cm, fabs(s.v[c.n_w + q] * it.zls[q] - mu));
   if (it.resto)
-    for (int r = lane; r < c.m; r += WAVE) {
+        for (int r = lane; r < c.m; r += WAVE) {
       cm = fmax(cm, fabs(s.p[r] * s.zp[r] - mu));
       cm = fmax(cm, fabs(s.nn[r] * s.zn[r] - mu));
     }
@@ -202,7 +203,7 @@ __device__ __forceinline__ double kkt_err(const Cfg& c, const ErrParts& e, doubl
 // objective value at v (regular) -- wave sum
 __device__ __forceinline__ double obj_regular(const Cfg& c, const Slot& s, const double* v, int lane) {
   double f = 0.0;
-  for (int i = lane; i < c.n_w; i += WAVE) {
+    for (int i = lane; i < c.n_w; i += WAVE) {
     int k = i / NZ, r = i % NZ;
     if (r < NX) {
       double e = v[i] - s.ref[k * NX + r];
@@ -219,8 +220,8 @@ __device__ __forceinline__ double obj_regular(const Cfg& c, const Slot& s, const
 __device__ __forceinline__ double obj_resto(const Cfg& c, const Slot& s, const double* v, const double* p, const double* nn,
                             double zeta, int lane) {
   double a = 0.0, q = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) a += p[r] + nn[r];
-  for (int i = lane; i < c.n; i += WAVE) {
+    for (int r = lane; r < c.m; r += WAVE) a += p[r] + nn[r];
+    for (int i = lane; i < c.n; i += WAVE) {
     double d = fmin(1.0, 1.0 / fabs(s.xr[i]));
     double e = v[i] - s.xr[i];
     q += d * d * e * e;
@@ -232,20 +233,20 @@ __device__ __forceinline__ double obj_resto(const Cfg& c, const Slot& s, const d
 __device__ __forceinline__ double log_barrier(const Cfg& c, const double* v, const double* p, const double* nn, bool resto,
                               int lane) {
   double b = 0.0, bad = 0.0;
-  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
+    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
     int k = bb / NU, i = bb % NU;
     double u = v[uo(k) + i];
     double sl = u, su = c.umax - u;
     if (!(sl > 0.0) || !(su > 0.0)) bad = 1.0;
     else b += log(sl) + log(su);
   }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) {
+    for (int q = lane; q < c.N * c.NI; q += WAVE) {
     double sv = v[c.n_w + q];
     if (!(sv > 0.0)) bad = 1.0;
     else b += log(sv);
   }
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE) {
+        for (int r = lane; r < c.m; r += WAVE) {
       if (!(p[r] > 0.0) || !(nn[r] > 0.0)) bad = 1.0;
       else b += log(p[r]) + log(nn[r]);
     }
@@ -257,18 +258,18 @@ __device__ __forceinline__ double log_barrier(const Cfg& c, const double* v, con
 __device__ __forceinline__ double ftb_primal(const Cfg& c, const Slot& s, const double* dv, const double* dp, const double* dn,
                              bool resto, double tau, int lane) {
   double a = 1.0;
-  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
+    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
     int k = bb / NU, i = bb % NU;
     double u = s.v[uo(k) + i], d = dv[uo(k) + i];
     if (d < 0) a = fmin(a, -tau * u / d);
     if (d > 0) a = fmin(a, tau * (c.umax - u) / d);
   }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) {
+    for (int q = lane; q < c.N * c.NI; q += WAVE) {
     double d = dv[c.n_w + q];
     if (d < 0) a = fmin(a, -tau * s.v[c.n_w + q] / d);
   }
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE) {
+        for (int r = lane; r < c.m; r += WAVE) {
       if (dp[r] < 0) a = fmin(a, -tau * s.p[r] / dp[r]);
       if (dn[r] < 0) a = fmin(a, -tau * s.nn[r] / dn[r]);
     }
@@ -299,14 +300,14 @@ __device__ __forceinline__ void dz_recover(const Cfg& c, const Slot& s, const It
 
 __device__ __forceinline__ double ftb_dual(const Cfg& c, const Slot& s, const Iter& it, double tau, int lane) {
   double a = 1.0;
-  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
+    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
     if (s.dzlu[bb] < 0) a = fmin(a, -tau * it.zlu[bb] / s.dzlu[bb]);
     if (s.dzuu[bb] < 0) a = fmin(a, -tau * it.zuu[bb] / s.dzuu[bb]);
   }
-  for (int q = lane; q < c.N * c.NI; q += WAVE)
+    for (int q = lane; q < c.N * c.NI; q += WAVE)
     if (s.dzls[q] < 0) a = fmin(a, -tau * it.zls[q] / s.dzls[q]);
   if (it.resto)
-    for (int r = lane; r < c.m; r += WAVE) {
+        for (int r = lane; r < c.m; r += WAVE) {
       if (s.dzp[r] < 0) a = fmin(a, -tau * s.zp[r] / s.dzp[r]);
       if (s.dzn[r] < 0) a = fmin(a, -tau * s.zn[r] / s.dzn[r]);
     }
@@ -316,7 +317,7 @@ __device__ __forceinline__ double ftb_dual(const Cfg& c, const Slot& s, const It
 // filter: reject if theta >= theta_F and phi >= phi_F for some entry
 __device__ __forceinline__ bool filter_ok(const double* filt, int nf, double th, double ph, int lane) {
   int bad = 0;
-  for (int i = lane; i < nf; i += WAVE)
+    for (int i = lane; i < nf; i += WAVE)
     if (th >= filt[i] && ph >= filt[FCAP + i]) bad = 1;
   return wor(bad) == 0;
 }
@@ -464,6 +465,9 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
       atomicAdd(&cnt->st[6], (unsigned long long)s.sc[SC_ST_TINY]);
       atomicAdd(&cnt->st[7], (unsigned long long)s.sc[SC_ST_PASS]);
       atomicAdd(&cnt->st[8], 1ull);
+      atomicAdd(&cnt->st[9], (unsigned long long)s.sc[SC_ST_SOLV]);
+      atomicAdd(&cnt->st[10], (unsigned long long)s.sc[SC_ST_FFACT]);
+      atomicAdd(&cnt->st[11], (unsigned long long)s.sc[SC_ST_FSOLV]);
       atomicAdd(&cnt->done, 1);
       next = refill ? atomicAdd(&cnt->head, 1) : INT_MAX;
     } else {
@@ -501,10 +505,8 @@ __device__ __forceinline__ void pre_init_y(const Cfg& c, const Slot& s, int lane
   if (lane == 0) s.sc[SC_WORK] = W_LSQ;
 }
 
-__global__ __launch_bounds__(64) void k_pre(Cfg c, double* ws, const double* theta, const double* warm_x, Outs out,
-                                            Counters* cnt, int refill) {
-  const int slot = blockIdx.x, lane = threadIdx.x;
-  Slot s = make_slot(c, ws, slot);
+__device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const double* theta, const double* warm_x,
+                                         Outs out, Counters* cnt, int refill, int lane) {
   const int ph = (int)s.sc[SC_PHASE];
   if (ph == PH_EMPTY) return;
   __syncthreads();
@@ -612,10 +614,7 @@ __global__ __launch_bounds__(64) void k_pre(Cfg c, double* ws, const double* the
 // perturbation; on a singular matrix add delta_c = delta_c_bar mu^kappa_c; then grow delta_x
 // from delta_0 (or kappa_minus times the last used value) by kappa_plus_bar / kappa_plus until
 // the inertia is (n, m, 0) or delta_x exceeds delta_max.
-__global__ __launch_bounds__(64) void k_fac(Cfg c, double* ws) {
-  __shared__ FacLds L;
-  const int slot = blockIdx.x, lane = threadIdx.x;
-  Slot s = make_slot(c, ws, slot);
+__device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L, bool fused, int lane) {
   const int work = (int)s.sc[SC_WORK];
   if (work == W_NONE) return;
   if (work == W_LSQ) {
@@ -647,6 +646,7 @@ __global__ __launch_bounds__(64) void k_fac(Cfg c, double* ws) {
   __syncthreads();
   if (lane == 0) {
     s.sc[SC_ST_FACT] += nfact;
+    if (fused) s.sc[SC_ST_FFACT] += nfact;
     if (ok && (e.dxp != 0.0)) sub[2] = e.dxp;
     s.sc[SC_LDX] = e.dxp;
     s.sc[SC_LDC] = e.dcp;
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(64) void k_fac(Cfg c, double* ws) {
 // ---------------------------------------------------------------------------- k_sol
 // least-squares multipliers: keep y if finite and |y|_inf <= lambda_max, else y = 0; the first
 // one also initialises the filter bounds theta_max, theta_min
-__device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, SolLds& V, int lane) {
+__device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, SolLds& V, bool fused, int lane) {
   const bool fok = s.sc[SC_FSTAT] == 0.0;
   Elim e{true, false, 0.0, 0.0, 0.0};
   if (fok) kkt_solve(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, V, lane);
@@ -684,20 +684,21 @@ __device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, SolLds& 
     }
     s.sc[SC_PHASE] = PH_REGULAR;
     s.sc[SC_WORK] = W_NONE;
+    if (fok) {
+      s.sc[SC_ST_SOLV] += 1.0;
+      if (fused) s.sc[SC_ST_FSOLV] += 1.0;
+    }
   }
   __syncthreads();
 }
 
 // Step of eq. (7) from the stored factor, bound-multiplier steps, fraction to the boundary
 // (primal) and the directional derivative of phi_mu.
-__global__ __launch_bounds__(64) void k_sol(Cfg c, double* ws) {
-  HIP_DYNAMIC_SHARED(double, sol_dyn)
-  const int slot = blockIdx.x, lane = threadIdx.x;
-  Slot s = make_slot(c, ws, slot);
+__device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, double* sol_dyn, bool fused, int lane) {
   const int work = (int)s.sc[SC_WORK];
   if (work == W_NONE) return;
   SolLds V = sol_lds(c, sol_dyn);
-  if (work == W_LSQ) { sol_init_y(c, s, V, lane); return; }
+  if (work == W_LSQ) { sol_init_y(c, s, V, fused, lane); return; }
   if ((int)s.sc[SC_STEP] != STEP_READY) {
     __syncthreads();
     if (lane == 0) s.sc[SC_WORK] = W_NONE;
@@ -717,7 +718,13 @@ __global__ __launch_bounds__(64) void k_sol(Cfg c, double* ws) {
       gphi += (c.rho_resto - mu / s.p[r]) * s.dp[r] + (c.rho_resto - mu / s.nn[r]) * s.dn[r];
   gphi = wsum(gphi);
   __syncthreads();
-  if (lane == 0) { s.sc[SC_AMAX] = amax; s.sc[SC_GPHI] = gphi; s.sc[SC_WORK] = W_NONE; }
+  if (lane == 0) {
+    s.sc[SC_AMAX] = amax;
+    s.sc[SC_GPHI] = gphi;
+    s.sc[SC_WORK] = W_NONE;
+    s.sc[SC_ST_SOLV] += 1.0;
+    if (fused) s.sc[SC_ST_FSOLV] += 1.0;
+  }
 }
 
 // ============================================================================ line search kernel
@@ -869,10 +876,7 @@ __device__ __forceinline__ void resto_try_exit(const Cfg& c, const Slot& s, int 
   __syncthreads();
 }
 
-__global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
-  HIP_DYNAMIC_SHARED(double, sol_dyn)
-  const int slot = blockIdx.x, lane = threadIdx.x;
-  Slot s = make_slot(c, ws, slot);
+__device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol_dyn, bool fused, int lane) {
   const int ph = (int)s.sc[SC_PHASE];
   if (ph != PH_REGULAR && ph != PH_RESTO) return;
   const int step = (int)s.sc[SC_STEP];
@@ -942,7 +946,10 @@ __global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
             }
             __syncthreads();
             kkt_solve(c, s, e, s.rv, s.ct, s.rp, s.rn, s.dvs, s.dys, s.dps, s.dns, V, lane);
-            if (lane == 0) s.sc[SC_ST_SOCT] += 1.0;
+            if (lane == 0) {
+              s.sc[SC_ST_SOCT] += 1.0;
+              if (fused) s.sc[SC_ST_FSOLV] += 1.0;
+            }
             asoc = ftb_primal(c, s, s.dvs, s.dps, s.dns, resto, tau, lane);
             make_trial(c, s, resto, asoc, s.dvs, s.dps, s.dns, lane);
             Trial ts = eval_trial(c, s, resto, mu, zeta, lane);
@@ -1037,6 +1044,42 @@ __global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
   if (resto) resto_try_exit(c, s, lane);
 }
 
+// ============================================================================ pass kernels
+__global__ __launch_bounds__(64) void k_pre(Cfg c, double* ws, const double* theta, const double* warm_x, Outs out,
+                                            Counters* cnt, int refill) {
+  pre_body(c, make_slot(c, ws, blockIdx.x), theta, warm_x, out, cnt, refill, threadIdx.x);
+}
+__global__ __launch_bounds__(64) void k_fac(Cfg c, double* ws) {
+  __shared__ FacLds L;
+  fac_body(c, make_slot(c, ws, blockIdx.x), L, false, threadIdx.x);
+}
+__global__ __launch_bounds__(64) void k_sol(Cfg c, double* ws) {
+  HIP_DYNAMIC_SHARED(double, sol_dyn)
+  sol_body(c, make_slot(c, ws, blockIdx.x), sol_dyn, false, threadIdx.x);
+}
+__global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
+  HIP_DYNAMIC_SHARED(double, sol_dyn)
+  ls_body(c, make_slot(c, ws, blockIdx.x), sol_dyn, false, threadIdx.x);
+}
+// The four per-slot phases of one iteration in a single launch.  Used once few instances remain:
+// each slot then runs its phases back to back, instead of every phase waiting for the slowest
+// slot of the previous one, and a pass costs two launches instead of five.
+__global__ __launch_bounds__(64) void k_iter(Cfg c, double* ws, const double* theta, const double* warm_x, Outs out,
+                                             Counters* cnt, int refill) {
+  __shared__ FacLds L;
+  HIP_DYNAMIC_SHARED(double, sol_dyn)
+  const int lane = threadIdx.x;
+  const Slot s = make_slot(c, ws, blockIdx.x);
+  if ((int)s.sc[SC_PHASE] == PH_EMPTY) return;
+  pre_body(c, s, theta, warm_x, out, cnt, refill, lane);
+  __syncthreads();
+  fac_body(c, s, L, true, lane);
+  __syncthreads();
+  sol_body(c, s, sol_dyn, true, lane);
+  __syncthreads();
+  ls_body(c, s, sol_dyn, true, lane);
+}
+
 // ============================================================================ parity hooks
 __global__ __launch_bounds__(64) void k_stage_derivs(Cfg c, int count, const double* x, const double* u,
                                                      const double* lam, double* F, double* G, double* H) {
@@ -1102,6 +1145,10 @@ void launch_sol(const Cfg& c, double* ws, int slots, hipStream_t st) {
 }
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st) {
   hipLaunchKernelGGL(k_ls, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws);
+}
+void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+                 Counters* cnt, int refill, hipStream_t st) {
+  hipLaunchKernelGGL(k_iter, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm_x, out, cnt, refill);
 }
 void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm_x,
                   hipStream_t st) {

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libhipipm.so")
 STATUS = {0: "RUNNING", 1: "CONVERGED", 2: "MAX_ITER", 3: "RESTO_FAILED", 4: "INFEASIBLE", 5: "NUMERICAL",
           6: "FILTER_OVERFLOW"}
 ST_CONVERGED = 1
-KERNELS = ("eval", "pre", "factor", "solve", "linesearch", "setup")
+KERNELS = ("eval", "pre", "factor", "solve", "linesearch", "fused", "setup")
 
 
 class ProblemDesc(C.Structure):
@@ -40,6 +40,7 @@ class Options(C.Structure):
         ("max_soc", C.c_int32), ("kappa_soc", C.c_double), ("kappa_sigma", C.c_double),
         ("rho_resto", C.c_double), ("kappa_resto", C.c_double), ("bound_mult_reset", C.c_double),
         ("filter_cap", C.c_int32), ("poll_every", C.c_int32), ("timing", C.c_int32),
+        ("fuse_below", C.c_int32),
     ]
 
 
@@ -51,7 +52,8 @@ class Dims(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("iterations", "resto_iterations", "soc_tried", "soc_accepted",
                                          "factorizations", "resto_entries", "tiny_steps", "passes",
-                                         "instances_done")]
+                                         "instances_done", "solves", "fused_factorizations",
+                                         "fused_solves")]
 
 
 _lib = None
