@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration) and exit")
+    ap.add_argument("--precision", type=int, default=None,
+                    help="KKT factor precision: 0 FP64, 1 FP32 + FP64 refinement (default: the workload's)")
     ap.add_argument("--fuse-below", type=int, default=None,
                     help="unfinished-instance count below which passes use the fused kernel (default: library's)")
     args = ap.parse_args()
@@ -145,6 +147,7 @@ def main():
     slots = args.slots or n_inst
     TH = torch.tensor(w.thetas(0, n_inst), dtype=torch.float64, device="cuda:0")
     opts = dict(timing=1)
+    opts["precision"] = args.precision if args.precision is not None else (1 if w.precision == "fp32ir" else 0)
     if args.fuse_below is not None:
         opts["fuse_below"] = args.fuse_below
     solver = hipipm.Solver(w, slots, hipipm.default_options(**opts))
@@ -184,7 +187,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if opts["precision"] == 0 else "f32 factor + f64 refinement",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: figure-eight tracking NMPC, FP64 cold start" if w.name == "C2" else w.name,
                    "instances": n_inst, "horizon_N": w.N, "n_obs": w.n_obs, "n": w.n, "m": w.m, "slots": slots},

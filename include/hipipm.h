@@ -89,6 +89,11 @@ typedef struct {
     int32_t fuse_below;   /* once at most this many instances are unfinished, each pass runs the
                              per-slot phases in one fused launch (0: never); default 2^30,
                              i.e. always */
+    int32_t precision;    /* KKT factor and solve: 0 FP64 (default); 1 FP32 with FP64 iterative
+                             refinement on the full system, FP64 refactorization when refinement
+                             fails (runs every pass fused) */
+    int32_t refine_max;   /* refinement sweeps per solve in precision 1 (default 3) */
+    double refine_tol;    /* refinement stops when |b - K x|_inf <= refine_tol |b|_inf (default 1e-10) */
 } hipipm_options;
 
 typedef struct {
@@ -101,6 +106,8 @@ typedef struct {
     int64_t solves;                  /* step solves with a stored factor (incl. least-squares y, not SOC) */
     int64_t fused_factorizations;    /* factorizations done inside the fused pass kernel */
     int64_t fused_solves;            /* solves (step and SOC) done inside the fused pass kernel */
+    int64_t refine_sweeps;           /* precision 1: refinement sweeps (each one FP32 solve) */
+    int64_t fp64_fallbacks;          /* precision 1: iterations refactored in FP64 after refinement failed */
 } hipipm_stats;
 
 typedef struct hipipm_ctx hipipm_ctx;

@@ -92,6 +92,8 @@ static void layout(Cfg& c) {
   c.o_dvs = take(n); c.o_dys = take(m); c.o_dps = take(m); c.o_dns = take(m); c.o_g = take(n);
   c.o_ref = take((N + 1) * NX);
   c.o_sd = take((N + 1) * sd_len_host(NI));
+  c.o_qv = take(n); c.o_qc = take(m); c.o_qp = take(m); c.o_qn = take(m);
+  c.o_ev = take(n); c.o_ec = take(m); c.o_ep = take(m); c.o_en = take(m);
   c.stride = rup(o, 64);
 }
 
@@ -107,6 +109,7 @@ int hipipm_default_options(hipipm_options* o) {
   o->eta_phi = 1e-8; o->gamma_alpha = 0.05; o->max_soc = 4; o->kappa_soc = 0.99; o->kappa_sigma = 1e10;
   o->rho_resto = 1000.0; o->kappa_resto = 0.9; o->bound_mult_reset = 1e3; o->filter_cap = 128;
   o->poll_every = 4; o->timing = 0; o->fuse_below = 1 << 30;
+  o->precision = 0; o->refine_max = 3; o->refine_tol = 1e-10;
   return HIPIPM_OK;
 }
 
@@ -118,7 +121,7 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   if (d->N < 1 || d->N > MAX_N || d->n_obs < 0 || d->n_obs > MAX_OBS) return HIPIPM_ERR_INVALID_ARG;
   if (!(d->dt > 0) || !(d->mass > 0) || !(d->jxx > 0) || !(d->jyy > 0) || !(d->jzz > 0)) return HIPIPM_ERR_INVALID_ARG;
   if (o->filter_cap < 1 || o->filter_cap > FCAP || o->max_iter < 0 || o->poll_every < 1 || !(o->tol > 0) ||
-      o->fuse_below < 0)
+      o->fuse_below < 0 || o->precision < 0 || o->precision > 1 || o->refine_max < 0 || !(o->refine_tol > 0))
     return HIPIPM_ERR_INVALID_ARG;
   hipipm_ctx* c = new hipipm_ctx();
   c->desc = *d;
@@ -150,6 +153,7 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   g.s_phi = o->s_phi; g.eta_phi = o->eta_phi; g.gamma_alpha = o->gamma_alpha; g.max_soc = o->max_soc;
   g.kappa_soc = o->kappa_soc; g.kappa_sigma = o->kappa_sigma; g.rho_resto = o->rho_resto;
   g.kappa_resto = o->kappa_resto; g.bound_mult_reset = o->bound_mult_reset; g.fcap = o->filter_cap;
+  g.prec = o->precision; g.refine_max = o->refine_max; g.refine_tol = o->refine_tol;
   layout(g);
   size_t rec = (size_t)g.stride * sizeof(double) * (size_t)slots;
   c->cnt_off = (rec + 255) / 256 * 256;
@@ -228,7 +232,7 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   long long passes = 0;
   for (;;) {
     // few unfinished instances left: fused pass kernel (every launch still covers all slots)
-    const bool fused = c->opts.fuse_below > 0 && n_inst - h.done <= c->opts.fuse_below;
+    const bool fused = c->opts.precision == 1 || (c->opts.fuse_below > 0 && n_inst - h.done <= c->opts.fuse_below);
     for (int p = 0; p < poll; ++p) {
       hipEvent_t* e = timing ? &ev[(NPK + 1) * p] : nullptr;
       if (timing) HIPCHK(c, hipEventRecord(e[0], st));
@@ -284,6 +288,8 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   c->stats.solves += (int64_t)h.st[9];
   c->stats.fused_factorizations += (int64_t)h.st[10];
   c->stats.fused_solves += (int64_t)h.st[11];
+  c->stats.refine_sweeps += (int64_t)h.st[12];
+  c->stats.fp64_fallbacks += (int64_t)h.st[13];
   return HIPIPM_OK;
 }
 

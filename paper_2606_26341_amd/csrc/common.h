@@ -31,7 +31,7 @@ enum : int {
   SC_STEP = 24, SC_AMAX, SC_THK, SC_PHK, SC_GPHI, SC_FK, SC_STEPMU,
   SC_ST_RESTO = 32, SC_ST_SOCT, SC_ST_SOCA, SC_ST_FACT, SC_ST_RENT, SC_ST_TINY, SC_ST_PASS,
   SC_LDX = 40, SC_LDC, SC_LALPHA, SC_LALPHAZ, SC_LSOC, SC_WORK, SC_FSTAT,
-  SC_ST_SOLV, SC_ST_FFACT, SC_ST_FSOLV,
+  SC_ST_SOLV, SC_ST_FFACT, SC_ST_FSOLV, SC_FPREC, SC_FORCE64, SC_ST_REF, SC_ST_FB, SC_DXLSAVE,
   SC_LEN = 64
 };
 
@@ -54,6 +54,7 @@ struct Cfg {
   double gamma_theta, gamma_phi, delta_sw, s_theta, s_phi, eta_phi, gamma_alpha;
   int max_soc; double kappa_soc, kappa_sigma, rho_resto, kappa_resto, bound_mult_reset;
   int fcap;
+  int prec, refine_max; double refine_tol;   // KKT factor precision (1: FP32 + FP64 refinement)
   // slot record layout, offsets in doubles
   long long stride;
   int o_v, o_y, o_zlu, o_zuu, o_zls, o_th, o_sc, o_fm, o_fr;
@@ -62,6 +63,7 @@ struct Cfg {
   int o_dv, o_dy, o_dzlu, o_dzuu, o_dzls, o_dp, o_dn, o_dzp, o_dzn;
   int o_rv, o_rc, o_rp, o_rn, o_vt, o_ct, o_pt, o_nt, o_csoc, o_dvs, o_dys, o_dps, o_dns;
   int o_g, o_ref, o_sd;
+  int o_qv, o_qc, o_qp, o_qn, o_ev, o_ec, o_ep, o_en;   // refinement residual and correction
 };
 
 // caller-owned output arrays of a solve
@@ -73,7 +75,7 @@ struct Outs {
 // global counters (device): queue head, finished count, stats
 struct Counters {
   int32_t head, done, n_inst, pad;
-  unsigned long long st[12];
+  unsigned long long st[14];
 };
 
 }  // namespace hipipm

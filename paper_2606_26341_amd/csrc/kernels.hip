@@ -468,6 +468,8 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
       atomicAdd(&cnt->st[9], (unsigned long long)s.sc[SC_ST_SOLV]);
       atomicAdd(&cnt->st[10], (unsigned long long)s.sc[SC_ST_FFACT]);
       atomicAdd(&cnt->st[11], (unsigned long long)s.sc[SC_ST_FSOLV]);
+      atomicAdd(&cnt->st[12], (unsigned long long)s.sc[SC_ST_REF]);
+      atomicAdd(&cnt->st[13], (unsigned long long)s.sc[SC_ST_FB]);
       atomicAdd(&cnt->done, 1);
       next = refill ? atomicAdd(&cnt->head, 1) : INT_MAX;
     } else {
@@ -483,6 +485,138 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
     if (lane == 0) s.sc[SC_PHASE] = PH_EMPTY;
   }
   __syncthreads();
+}
+
+// ---------------------------------------------------------------------------- mixed precision
+// y = K x for the system of eq. (7) with the perturbations of e, slacks (and, in restoration, the
+// elastic p, n) kept as variables of their own: the un-condensed system the condensed factor
+// solves, assembled on the fly from W_k, G_k and the stage data.
+__device__ __forceinline__ void kkt_matvec(const Cfg& c, const Slot& s, const Elim& e, const double* xv,
+                                           const double* xc, const double* xp, const double* xn, double* yv,
+                                           double* yc, double* yp, double* yn, int lane) {
+  const int N = c.N, NI = c.NI, SL = sd_len(c);
+  const double dx = e.lsq ? 0.0 : e.dxp, dc = e.lsq ? 0.0 : e.dcp;
+  // primal rows of the knots
+  for (int q = lane; q < (N + 1) * NZ; q += WAVE) {
+    const int k = q / NZ, i = q % NZ;
+    if (k == N && i >= NX) continue;
+    const double* sdk = s.sd + (long long)k * SL;
+    const int vi = k * NZ + i;
+    double acc = (sdk[i] + dx) * xv[vi];
+    if (k < N) {
+      if (!e.lsq) {
+        const double* W = s.HW + (long long)k * NZ * NZ + i * NZ;
+        for (int j = 0; j < NZ; ++j) acc += W[j] * xv[k * NZ + j];
+      }
+      const double* G = s.G + (long long)k * NX * NZ;
+      for (int l = 0; l < NX; ++l) acc -= G[l * NZ + i] * xc[(k + 1) * NX + l];
+    }
+    if (i < NX) acc += xc[k * NX + i];
+    if (k >= 1 && i < 3)
+      for (int j = 0; j < NI; ++j) {
+        const double* o7 = sdk + SD_HEAD + SD_OBS * j;
+        acc += o7[6] * xv[vi] + o7[3 + i] * xc[go(c, k, j)];
+      }
+    yv[vi] = acc;
+  }
+  // slack rows and inequality rows
+  for (int q = lane; q < N * NI; q += WAVE) {
+    const int k = 1 + q / NI, j = q % NI;
+    const double* o7 = s.sd + (long long)k * SL + SD_HEAD + SD_OBS * j;
+    const int si = so(c, k, j), r = go(c, k, j);
+    yv[si] = (o7[0] + dx) * xv[si] - xc[r];
+    double acc = -xv[si] - dc * xc[r];
+    for (int t = 0; t < 3; ++t) acc += o7[3 + t] * xv[xo(k) + t];
+    if (e.resto) {
+      acc += xn[r] - xp[r];
+      yp[r] = (o7[1] + dx) * xp[r] - xc[r];
+      yn[r] = (o7[2] + dx) * xn[r] + xc[r];
+    }
+    yc[r] = acc;
+  }
+  // rows defining the states
+  for (int r = lane; r < (N + 1) * NX; r += WAVE) {
+    const int k = r / NX, i = r % NX;
+    double acc = xv[xo(k) + i] - dc * xc[r];
+    if (k >= 1) {
+      const double* G = s.G + (long long)(k - 1) * NX * NZ + i * NZ;
+      for (int l = 0; l < NZ; ++l) acc -= G[l] * xv[(k - 1) * NZ + l];
+    }
+    if (e.resto) {
+      const double* sdk = s.sd + (long long)k * SL;
+      acc += xn[r] - xp[r];
+      yp[r] = (sdk[NZ + i] + dx) * xp[r] - xc[r];
+      yn[r] = (sdk[NZ + NX + i] + dx) * xn[r] + xc[r];
+    }
+    yc[r] = acc;
+  }
+  __syncthreads();
+}
+
+// Solve K x = b with the stored factor.  FP64 factor: one solve.  FP32 factor: one FP32 solve,
+// then sweeps of r = b - K x (FP64, full system) and x += K^{-1} r (FP32 solve) until
+// |r|_inf <= refine_tol |b|_inf, at most refine_max sweeps; false if that was not reached.
+__device__ __forceinline__ bool solve_refined(const Cfg& c, const Slot& s, const Elim& e, const double* bv,
+                                              const double* bc, const double* bp, const double* bn, double* xv,
+                                              double* xc, double* xp, double* xn, double* dyn, bool mixed, int lane) {
+  if (!mixed || s.sc[SC_FPREC] == 0.0) {
+    SolLdsT<double> V = sol_lds<double>(c, dyn);
+    kkt_solve(c, s, e, bv, bc, bp, bn, xv, xc, xp, xn, V, lane);
+    return true;
+  }
+  SolLdsT<float> V = sol_lds<float>(c, dyn);
+  kkt_solve(c, s, e, bv, bc, bp, bn, xv, xc, xp, xn, V, lane);
+  const int n = c.n, m = c.m;
+  double bmax = 0.0;
+  for (int i = lane; i < n; i += WAVE) bmax = fmax(bmax, fabs(bv[i]));
+  for (int r = lane; r < m; r += WAVE) {
+    bmax = fmax(bmax, fabs(bc[r]));
+    if (e.resto) bmax = fmax(bmax, fmax(fabs(bp[r]), fabs(bn[r])));
+  }
+  bmax = wmax(bmax);
+  int sweeps = 0;
+  bool ok = false;
+  for (;;) {
+    kkt_matvec(c, s, e, xv, xc, xp, xn, s.qv, s.qc, s.qp, s.qn, lane);
+    double rmax = 0.0;
+    for (int i = lane; i < n; i += WAVE) {
+      const double r = bv[i] - s.qv[i];
+      s.qv[i] = r;
+      rmax = fmax(rmax, fabs(r));
+    }
+    for (int r = lane; r < m; r += WAVE) {
+      const double rc = bc[r] - s.qc[r];
+      s.qc[r] = rc;
+      rmax = fmax(rmax, fabs(rc));
+      if (e.resto) {
+        const double rp = bp[r] - s.qp[r], rn = bn[r] - s.qn[r];
+        s.qp[r] = rp;
+        s.qn[r] = rn;
+        rmax = fmax(rmax, fmax(fabs(rp), fabs(rn)));
+      }
+    }
+    rmax = wmax(rmax);
+    __syncthreads();
+    if (rmax <= c.refine_tol * bmax) { ok = true; break; }
+    if (!isfinite(rmax) || sweeps >= c.refine_max) break;
+    kkt_solve(c, s, e, s.qv, s.qc, s.qp, s.qn, s.ev, s.ec, s.ep, s.en, V, lane);
+    for (int i = lane; i < n; i += WAVE) xv[i] += s.ev[i];
+    for (int r = lane; r < m; r += WAVE) {
+      xc[r] += s.ec[r];
+      if (e.resto) { xp[r] += s.ep[r]; xn[r] += s.en[r]; }
+    }
+    __syncthreads();
+    ++sweeps;
+  }
+  if (lane == 0) s.sc[SC_ST_REF] += sweeps;
+  __syncthreads();
+  return ok;
+}
+
+// the structured factorization in the precision of this iteration
+__device__ __forceinline__ int factor_any(const Cfg& c, const Slot& s, const Elim& e, FacLds& L, bool f32, int lane) {
+  if (f32) return kkt_factor(c, s, e, *reinterpret_cast<FacLdsT<float>*>(&L), lane);   // only mixed kernels
+  return kkt_factor(c, s, e, L, lane);
 }
 
 // ---------------------------------------------------------------------------- k_pre
@@ -510,7 +644,7 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
   const int ph = (int)s.sc[SC_PHASE];
   if (ph == PH_EMPTY) return;
   __syncthreads();
-  if (lane == 0) { s.sc[SC_ST_PASS] += 1.0; s.sc[SC_WORK] = W_NONE; }
+  if (lane == 0) { s.sc[SC_ST_PASS] += 1.0; s.sc[SC_WORK] = W_NONE; s.sc[SC_FORCE64] = 0.0; }
   if (ph == PH_FINISH) { finish_slot(c, s, theta, warm_x, out, cnt, refill != 0, lane); return; }
   if (ph == PH_INIT_Y) { pre_init_y(c, s, lane); return; }
 
@@ -614,28 +748,31 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
 // perturbation; on a singular matrix add delta_c = delta_c_bar mu^kappa_c; then grow delta_x
 // from delta_0 (or kappa_minus times the last used value) by kappa_plus_bar / kappa_plus until
 // the inertia is (n, m, 0) or delta_x exceeds delta_max.
-__device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L, bool fused, int lane) {
+__device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L, bool fused, bool mixed, int lane) {
   const int work = (int)s.sc[SC_WORK];
   if (work == W_NONE) return;
+  const bool f32 = mixed && c.prec == 1 && s.sc[SC_FORCE64] == 0.0;
   if (work == W_LSQ) {
     Elim e{true, false, 0.0, 0.0, 0.0};
-    const int st = kkt_factor(c, s, e, L, lane);
-    if (lane == 0) s.sc[SC_FSTAT] = st;
+    const int st = factor_any(c, s, e, L, f32, lane);
+    if (lane == 0) { s.sc[SC_FSTAT] = st; s.sc[SC_FPREC] = f32 ? 1.0 : 0.0; }
+    __syncthreads();
     return;
   }
   const bool resto = (int)s.sc[SC_PHASE] == PH_RESTO;
   double* sub = s.sc + (resto ? SC_RMU : SC_MU);
   const double mu = sub[0];
-  const double dxl = sub[2];
+  // an FP64 redo of this iteration's factorization starts from the same delta_x^last
+  const double dxl = (s.sc[SC_FORCE64] != 0.0) ? s.sc[SC_DXLSAVE] : sub[2];
   Elim e{false, resto, 0.0, 0.0, resto ? sqrt(mu) : 0.0};
-  int st = kkt_factor(c, s, e, L, lane);
+  int st = factor_any(c, s, e, L, f32, lane);
   int nfact = 1;
   bool ok = (st == 0);
   if (!ok) {
     if (st == 2) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
     e.dxp = (dxl == 0.0) ? c.delta_0 : fmax(c.delta_min, c.kappa_minus * dxl);
     for (;;) {
-      st = kkt_factor(c, s, e, L, lane);
+      st = factor_any(c, s, e, L, f32, lane);
       ++nfact;
       if (st == 0) { ok = true; break; }
       if (st == 2 && e.dcp == 0.0) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
@@ -647,7 +784,9 @@ __device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L,
   if (lane == 0) {
     s.sc[SC_ST_FACT] += nfact;
     if (fused) s.sc[SC_ST_FFACT] += nfact;
+    s.sc[SC_DXLSAVE] = dxl;
     if (ok && (e.dxp != 0.0)) sub[2] = e.dxp;
+    s.sc[SC_FPREC] = f32 ? 1.0 : 0.0;
     s.sc[SC_LDX] = e.dxp;
     s.sc[SC_LDC] = e.dcp;
     s.sc[SC_FSTAT] = ok ? 0.0 : 1.0;
@@ -658,10 +797,19 @@ __device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L,
 // ---------------------------------------------------------------------------- k_sol
 // least-squares multipliers: keep y if finite and |y|_inf <= lambda_max, else y = 0; the first
 // one also initialises the filter bounds theta_max, theta_min
-__device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, SolLds& V, bool fused, int lane) {
-  const bool fok = s.sc[SC_FSTAT] == 0.0;
+__device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, double* sol_dyn, FacLds* L, bool fused,
+                                           bool mixed, int lane) {
   Elim e{true, false, 0.0, 0.0, 0.0};
-  if (fok) kkt_solve(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, V, lane);
+  bool fok = s.sc[SC_FSTAT] == 0.0;
+  if (fok) fok = solve_refined(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, sol_dyn, mixed, lane);
+  if (!fok && L && s.sc[SC_FPREC] != 0.0) {
+    // FP32 refinement failed: the least-squares system again in FP64
+    if (lane == 0) { s.sc[SC_FORCE64] = 1.0; s.sc[SC_ST_FB] += 1.0; }
+    __syncthreads();
+    fac_body(c, s, *L, fused, mixed, lane);
+    fok = s.sc[SC_FSTAT] == 0.0;
+    if (fok) fok = solve_refined(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, sol_dyn, mixed, lane);
+  }
   double ym = 0.0, bad = fok ? 0.0 : 1.0;
   if (fok)
     for (int r = lane; r < c.m; r += WAVE) {
@@ -694,11 +842,11 @@ __device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, SolLds& 
 
 // Step of eq. (7) from the stored factor, bound-multiplier steps, fraction to the boundary
 // (primal) and the directional derivative of phi_mu.
-__device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, double* sol_dyn, bool fused, int lane) {
+__device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, double* sol_dyn, FacLds* L, bool fused,
+                                         bool mixed, int lane) {
   const int work = (int)s.sc[SC_WORK];
   if (work == W_NONE) return;
-  SolLds V = sol_lds(c, sol_dyn);
-  if (work == W_LSQ) { sol_init_y(c, s, V, fused, lane); return; }
+  if (work == W_LSQ) { sol_init_y(c, s, sol_dyn, L, fused, mixed, lane); return; }
   if ((int)s.sc[SC_STEP] != STEP_READY) {
     __syncthreads();
     if (lane == 0) s.sc[SC_WORK] = W_NONE;
@@ -708,7 +856,20 @@ __device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, double* so
   Iter it = cur_iter(s, resto);
   const double mu = it.sub[0], tau = it.sub[1];
   Elim e{false, resto, s.sc[SC_LDX], s.sc[SC_LDC], resto ? sqrt(mu) : 0.0};
-  kkt_solve(c, s, e, s.rv, s.rc, s.rp, s.rn, s.dv, s.dy, s.dp, s.dn, V, lane);
+  if (!solve_refined(c, s, e, s.rv, s.rc, s.rp, s.rn, s.dv, s.dy, s.dp, s.dn, sol_dyn, mixed, lane) && L) {
+    // FP32 refinement failed: factor this iteration again in FP64 (same inertia-correction start)
+    if (lane == 0) { s.sc[SC_FORCE64] = 1.0; s.sc[SC_ST_FB] += 1.0; }
+    __syncthreads();
+    fac_body(c, s, *L, fused, mixed, lane);
+    __syncthreads();
+    if ((int)s.sc[SC_STEP] != STEP_READY) {
+      if (lane == 0) s.sc[SC_WORK] = W_NONE;
+      return;
+    }
+    e.dxp = s.sc[SC_LDX];
+    e.dcp = s.sc[SC_LDC];
+    solve_refined(c, s, e, s.rv, s.rc, s.rp, s.rn, s.dv, s.dy, s.dp, s.dn, sol_dyn, mixed, lane);
+  }
   dz_recover(c, s, it, mu, s.dv, s.dp, s.dn, lane);
   double amax = ftb_primal(c, s, s.dv, s.dp, s.dn, resto, tau, lane);
   double gphi = 0.0;
@@ -876,12 +1037,12 @@ __device__ __forceinline__ void resto_try_exit(const Cfg& c, const Slot& s, int 
   __syncthreads();
 }
 
-__device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol_dyn, bool fused, int lane) {
+__device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol_dyn, bool fused, bool mixed,
+                                        int lane) {
   const int ph = (int)s.sc[SC_PHASE];
   if (ph != PH_REGULAR && ph != PH_RESTO) return;
   const int step = (int)s.sc[SC_STEP];
   if (step == STEP_NONE) return;
-  SolLds V = sol_lds(c, sol_dyn);
   __syncthreads();
   if (lane == 0) s.sc[SC_STEP] = STEP_NONE;
   const bool resto = (ph == PH_RESTO);
@@ -945,7 +1106,7 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
               s.ct[r] = -s.csoc[r];      // right-hand side rows of the constraints
             }
             __syncthreads();
-            kkt_solve(c, s, e, s.rv, s.ct, s.rp, s.rn, s.dvs, s.dys, s.dps, s.dns, V, lane);
+            if (!solve_refined(c, s, e, s.rv, s.ct, s.rp, s.rn, s.dvs, s.dys, s.dps, s.dns, sol_dyn, mixed, lane)) break;
             if (lane == 0) {
               s.sc[SC_ST_SOCT] += 1.0;
               if (fused) s.sc[SC_ST_FSOLV] += 1.0;
@@ -1051,19 +1212,20 @@ __global__ __launch_bounds__(64) void k_pre(Cfg c, double* ws, const double* the
 }
 __global__ __launch_bounds__(64) void k_fac(Cfg c, double* ws) {
   __shared__ FacLds L;
-  fac_body(c, make_slot(c, ws, blockIdx.x), L, false, threadIdx.x);
+  fac_body(c, make_slot(c, ws, blockIdx.x), L, false, false, threadIdx.x);
 }
 __global__ __launch_bounds__(64) void k_sol(Cfg c, double* ws) {
   HIP_DYNAMIC_SHARED(double, sol_dyn)
-  sol_body(c, make_slot(c, ws, blockIdx.x), sol_dyn, false, threadIdx.x);
+  sol_body(c, make_slot(c, ws, blockIdx.x), sol_dyn, nullptr, false, false, threadIdx.x);
 }
 __global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
   HIP_DYNAMIC_SHARED(double, sol_dyn)
-  ls_body(c, make_slot(c, ws, blockIdx.x), sol_dyn, false, threadIdx.x);
+  ls_body(c, make_slot(c, ws, blockIdx.x), sol_dyn, false, false, threadIdx.x);
 }
-// The four per-slot phases of one iteration in a single launch.  Used once few instances remain:
-// each slot then runs its phases back to back, instead of every phase waiting for the slowest
-// slot of the previous one, and a pass costs two launches instead of five.
+// The four per-slot phases of one iteration in a single launch: each slot runs its phases back
+// to back, instead of every phase waiting for the slowest slot of the previous one, and a pass
+// costs two launches instead of five.  MIXED: the FP32 factor / FP64 refinement variant.
+template <bool MIXED>
 __global__ __launch_bounds__(64) void k_iter(Cfg c, double* ws, const double* theta, const double* warm_x, Outs out,
                                              Counters* cnt, int refill) {
   __shared__ FacLds L;
@@ -1073,11 +1235,11 @@ __global__ __launch_bounds__(64) void k_iter(Cfg c, double* ws, const double* th
   if ((int)s.sc[SC_PHASE] == PH_EMPTY) return;
   pre_body(c, s, theta, warm_x, out, cnt, refill, lane);
   __syncthreads();
-  fac_body(c, s, L, true, lane);
+  fac_body(c, s, L, true, MIXED, lane);
   __syncthreads();
-  sol_body(c, s, sol_dyn, true, lane);
+  sol_body(c, s, sol_dyn, &L, true, MIXED, lane);
   __syncthreads();
-  ls_body(c, s, sol_dyn, true, lane);
+  ls_body(c, s, sol_dyn, true, MIXED, lane);
 }
 
 // ============================================================================ parity hooks
@@ -1108,15 +1270,18 @@ __global__ __launch_bounds__(64) void k_kkt_test(Cfg c, double* ws, double dxp, 
   kkt_stage_data(c, s, it, e, lane);
   e.dxp = dxp;
   e.dcp = dcp;
-  const int st = kkt_factor(c, s, e, L, lane);
-  if (lane == 0) inertia_ok[slot] = (st == 0) ? 1 : 0;
+  // precision 1: FP32 factor and FP32 solve with FP64 refinement (no FP64 fallback here: the
+  // caller sees the refined FP32 result); inertia_ok = 1 inertia correct, 2 also refinement converged
+  const bool f32 = c.prec == 1;
+  const int st = factor_any(c, s, e, L, f32, lane);
+  if (lane == 0) { inertia_ok[slot] = (st == 0) ? 1 : 0; s.sc[SC_FPREC] = f32 ? 1.0 : 0.0; }
   if (st != 0) return;
   const double* b = rhs + (long long)slot * (c.n + c.m);
   for (int i = lane; i < c.n; i += WAVE) s.rv[i] = b[i];
   for (int r = lane; r < c.m; r += WAVE) s.rc[r] = b[c.n + r];
   __syncthreads();
-  SolLds V = sol_lds(c, sol_dyn);
-  kkt_solve(c, s, e, s.rv, s.rc, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, V, lane);
+  const bool conv = solve_refined(c, s, e, s.rv, s.rc, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, sol_dyn, f32, lane);
+  if (lane == 0 && f32 && conv) inertia_ok[slot] = 2;
   double* o = sol + (long long)slot * (c.n + c.m);
   for (int i = lane; i < c.n; i += WAVE) o[i] = s.dv[i];
   for (int r = lane; r < c.m; r += WAVE) o[c.n + r] = s.dy[r];
@@ -1148,7 +1313,10 @@ void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st) {
 }
 void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
                  Counters* cnt, int refill, hipStream_t st) {
-  hipLaunchKernelGGL(k_iter, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm_x, out, cnt, refill);
+  if (c.prec == 1)
+    hipLaunchKernelGGL(k_iter<true>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm_x, out, cnt, refill);
+  else
+    hipLaunchKernelGGL(k_iter<false>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm_x, out, cnt, refill);
 }
 void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm_x,
                   hipStream_t st) {

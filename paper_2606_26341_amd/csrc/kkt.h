@@ -32,6 +32,7 @@ struct Slot {
   double *F, *G, *HW, *fac, *rb;
   double *dv, *dy, *dzlu, *dzuu, *dzls, *dp, *dn, *dzp, *dzn;
   double *rv, *rc, *rp, *rn, *vt, *ct, *pt, *nt, *csoc, *dvs, *dys, *dps, *dns, *g, *ref, *sd;
+  double *qv, *qc, *qp, *qn, *ev, *ec, *ep, *en;
 };
 
 __device__ __forceinline__ Slot make_slot(const Cfg& c, double* ws, int slot) {
@@ -50,6 +51,8 @@ __device__ __forceinline__ Slot make_slot(const Cfg& c, double* ws, int slot) {
   s.dvs = R + c.o_dvs; s.dys = R + c.o_dys; s.dps = R + c.o_dps; s.dns = R + c.o_dns; s.g = R + c.o_g;
   s.ref = R + c.o_ref;
   s.sd = R + c.o_sd;
+  s.qv = R + c.o_qv; s.qc = R + c.o_qc; s.qp = R + c.o_qp; s.qn = R + c.o_qn;
+  s.ev = R + c.o_ev; s.ec = R + c.o_ec; s.ep = R + c.o_ep; s.en = R + c.o_en;
   return s;
 }
 
@@ -223,32 +226,37 @@ constexpr int TILE_T = (NX * NZ + WAVE - 1) / WAVE;    // 4 entries of T = S G p
 constexpr int TILE_H = (NZ * NZ + WAVE - 1) / WAVE;    // 5 entries of H per lane
 constexpr int TILE_P = (NX * NX + WAVE - 1) / WAVE;    // 3 entries of P, S per lane
 
-struct FacLds {
-  double S[16 * NX];          // rows read up to (TILE_T * WAVE - 1) / NZ
-  double H[TILE_H * WAVE];
-  double Y[WAVE];
-  double P[TILE_P * WAVE];
-  double CV[TILE_T * WAVE + 96];   // T = S G during the Schur update, then L_C | V (+ read-only pad)
-  double LI[NX * NX];              // L_C^{-1}
-  double dh[NX];
-  double rdh[NX];
-  double buf[PF * WAVE];      // stage inputs: W (NZ*NZ) | G (NX*NZ) | stage data
+template <typename T>
+struct FacLdsT {
+  T S[16 * NX];          // rows read up to (TILE_T * WAVE - 1) / NZ
+  T H[TILE_H * WAVE];
+  T Y[WAVE];
+  T P[TILE_P * WAVE];
+  T CV[TILE_T * WAVE + 96];   // T = S G during the Schur update, then L_C | V (+ read-only pad)
+  T LI[NX * NX];              // L_C^{-1}
+  T dh[NX];
+  T rdh[NX];
+  T buf[PF * WAVE];      // stage inputs: W (NZ*NZ) | G (NX*NZ) | stage data
 };
+using FacLds = FacLdsT<double>;
 
 constexpr int SPF = (FR_LEN + NX * NZ + WAVE - 1) / WAVE;
 static_assert(FR_LEN + NX * NZ <= SPF * WAVE, "solve stage inputs exceed the prefetch");
 
-// solve workspace, carved from dynamic LDS (its size depends on the horizon)
-struct SolLds {
-  double* rb;                        // condensed stage right-hand sides, (N+1) x RB_LEN
-  double* buf;                       // factor record of the knot | G of the coupling interval
-  double* tmp;                       // 32 words: x part of the current stage
+// solve workspace, carved from dynamic LDS (its size depends on the horizon; sized in doubles)
+template <typename T>
+struct SolLdsT {
+  T* rb;                             // condensed stage right-hand sides, (N+1) x RB_LEN
+  T* buf;                            // factor record of the knot | G of the coupling interval
+  T* tmp;                            // 32 words: x part of the current stage
 };
+using SolLds = SolLdsT<double>;
 __device__ __host__ __forceinline__ int sol_lds_doubles(int N) { return (N + 1) * RB_LEN + SPF * WAVE + 32; }
-__device__ __forceinline__ SolLds sol_lds(const Cfg& c, double* dyn) {
-  SolLds V;
-  V.rb = dyn;
-  V.buf = dyn + (c.N + 1) * RB_LEN;
+template <typename T>
+__device__ __forceinline__ SolLdsT<T> sol_lds(const Cfg& c, double* dyn) {
+  SolLdsT<T> V;
+  V.rb = reinterpret_cast<T*>(dyn);
+  V.buf = V.rb + (c.N + 1) * RB_LEN;
   V.tmp = V.buf + SPF * WAVE;
   return V;
 }
@@ -269,6 +277,15 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return y;
 }
 
+__device__ __forceinline__ float rsqrt_nr(float d) {
+  const float y = __builtin_amdgcn_rsqf(d);
+  return y * fmaf(-0.5f * d * y, y, 1.5f);
+}
+__device__ __forceinline__ float rcp_nr(float x) {
+  const float y = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, y, 1.0f), y, y);
+}
+
 // value of v on lane src (src uniform), delivered to every lane through the scalar unit
 __device__ __forceinline__ double lane_bcast(double v, int src) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
@@ -276,21 +293,25 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
 
 // In-register Cholesky of an NX x NX SPD candidate held one row per lane (lane i < NX holds
 // c[l] = A_il; the lower part is used).  Right-looking, column j broadcast from lane j.  On
 // success row `lane` of L is in c (lower part) and rinv[j] = 1 / L_jj on every lane.  Returns 0,
 // 1 (a non-positive pivot) or 2 (an exactly-zero pivot); the result is wave-uniform.
-__device__ __forceinline__ int chol_rows(double (&c)[NX], double (&rinv)[NX], int lane) {
+template <typename T>
+__device__ __forceinline__ int chol_rows(T (&c)[NX], T (&rinv)[NX], int lane) {
 #pragma unroll
   for (int j = 0; j < NX; ++j) {
-    const double d = lane_bcast(c[j], j);
+    const T d = lane_bcast(c[j], j);
     if (!(d > 0.0)) return d == 0.0 ? 2 : 1;
     rinv[j] = rsqrt_nr(d);
     c[j] = (lane == j) ? d * rinv[j] : c[j] * rinv[j];
 #pragma unroll
     for (int l = j + 1; l < NX; ++l) {
-      const double ljl = lane_bcast(c[j], l);     // L_lj
+      const T ljl = lane_bcast(c[j], l);     // L_lj
       if (lane >= l) c[l] -= c[j] * ljl;
     }
   }
@@ -312,37 +333,39 @@ __device__ __forceinline__ void stage_prefetch(const Cfg& c, const Slot& s, int 
     reg[t] = *a;
   }
 }
-__device__ __forceinline__ void stage_park(double* buf, int lane, const double* reg) {
+template <typename T>
+__device__ __forceinline__ void stage_park(T* buf, int lane, const double* reg) {
 #pragma unroll
-  for (int t = 0; t < PF; ++t) buf[lane + WAVE * t] = reg[t];
+  for (int t = 0; t < PF; ++t) buf[lane + WAVE * t] = (T)reg[t];
 }
 
 // ----------------------------------------------------------------------------- factorization
 // Factor all stage blocks with perturbations (e.dxp, e.dcp); stage data from kkt_stage_data.
 // Returns 0 (inertia correct), 1 (wrong), 2 (singular).  Writes the per-knot factor records.
-__device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Elim& e, FacLds& L, int lane) {
+template <typename T>
+__device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Elim& e, FacLdsT<T>& L, int lane) {
   const int N = c.N;
-  double reg[PF];
+  double reg[PF];   // FP64 inputs, rounded to T when parked
   if (!e.lsq && (e.dxp != 0.0 || e.dcp != 0.0)) kkt_condense(c, s, e, lane);
   for (int i = lane; i < 16 * NX; i += WAVE) L.S[i] = 0.0;
   stage_prefetch(c, s, N, lane, reg);
   stage_park(L.buf, lane, reg);
   lds_barrier();
-  const double dx = e.lsq ? 0.0 : e.dxp;
+  const T dx = e.lsq ? T(0) : T(e.dxp);
   int status = 0;
   for (int k = N; k >= 0; --k) {
-    const double* B = L.buf;      // dead after the barrier that follows the dh read
-    const double* Wk = B;
-    const double* Gk = B + ((k < N) ? NZ * NZ : 0);
-    const double* SD = B + ((k < N) ? NZ * NZ + NX * NZ : 0);
-    double* fr = s.fac + (long long)k * FR_LEN;
+    const T* B = L.buf;      // dead after the barrier that follows the dh read
+    const T* Wk = B;
+    const T* Gk = B + ((k < N) ? NZ * NZ : 0);
+    const T* SD = B + ((k < N) ? NZ * NZ + NX * NZ : 0);
+    T* fr = reinterpret_cast<T*>(s.fac) + (long long)k * FR_LEN;
     if (k > 0) stage_prefetch(c, s, k - 1, lane, reg);   // in flight during this stage
     // ---- Schur update, first half: T = S_{k+1} G_k (13 x 17) ----
     if (k < N) {
 #pragma unroll
       for (int t = 0; t < TILE_T; ++t) {
         const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
-        double acc = 0.0;
+        T acc = 0.0;
 #pragma unroll
         for (int l = 0; l < NX; ++l) acc += L.S[i * NX + l] * Gk[l * NZ + j];
         L.CV[q] = acc;
@@ -353,11 +376,11 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
     for (int t = 0; t < TILE_H; ++t) {
       const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
-      double h = (!e.lsq && k < N) ? Wk[q] : 0.0;
+      T h = (!e.lsq && k < N) ? Wk[q] : 0.0;
       h += (i == j && (k < N || i < NX)) ? SD[j] + dx : 0.0;
       h += (k >= 1 && i < 3 && j < 3) ? SD[SD_HC + 3 * (i < 3 ? i : 0) + j] : 0.0;
       if (k < N) {
-        double acc = 0.0;
+        T acc = 0.0;
 #pragma unroll
         for (int l = 0; l < NX; ++l) acc += Gk[l * NZ + i] * L.CV[l * NZ + j];
         h += acc;
@@ -368,11 +391,11 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     // ---- control block: Cholesky of Hbar^uu (on every lane, in registers), Y, P ----
     const int li = lane < NX ? lane : NX - 1;
     if (k < N) {
-      double lr[NU * NU], rr[NU];
+      T lr[NU * NU], rr[NU];
       int bad = 0;
 #pragma unroll
       for (int j = 0; j < NU; ++j) {
-        double d = L.H[(NX + j) * NZ + NX + j];
+        T d = L.H[(NX + j) * NZ + NX + j];
 #pragma unroll
         for (int l = 0; l < j; ++l) d -= lr[j * NU + l] * lr[j * NU + l];
         if (bad == 0 && !(d > 0.0)) bad = (d == 0.0) ? 2 : 1;
@@ -382,7 +405,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         for (int i = 0; i < NU; ++i) {
           if (i < j) lr[i * NU + j] = 0.0;
           if (i <= j) continue;
-          double a = L.H[(NX + i) * NZ + NX + j];
+          T a = L.H[(NX + i) * NZ + NX + j];
 #pragma unroll
           for (int l = 0; l < j; ++l) a -= lr[i * NU + l] * lr[j * NU + l];
           lr[i * NU + j] = a * rr[j];
@@ -390,7 +413,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       }
       if (bad) { status = bad; break; }
       {
-        double v = 0.0, w = 0.0;
+        T v = 0.0, w = 0.0;
 #pragma unroll
         for (int t = 0; t < NU * NU; ++t) v = (lane == t) ? lr[t] : v;
 #pragma unroll
@@ -399,10 +422,10 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         if (lane < NU) fr[FR_RR + lane] = w;
       }
       if (lane < NX) {
-        double y[NU];
+        T y[NU];
 #pragma unroll
         for (int a = 0; a < NU; ++a) {
-          double acc = L.H[(NX + a) * NZ + lane];
+          T acc = L.H[(NX + a) * NZ + lane];
 #pragma unroll
           for (int l = 0; l < a; ++l) acc -= lr[a * NU + l] * y[l];
           y[a] = acc * rr[a];
@@ -413,7 +436,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
       for (int t = 0; t < TILE_P; ++t) {
         const int q = lane + WAVE * t, i = q / NX, j = q % NX;
-        double acc = L.H[i * NZ + j];
+        T acc = L.H[i * NZ + j];
 #pragma unroll
         for (int a = 0; a < NU; ++a) acc -= L.Y[a * NX + i] * L.Y[a * NX + j];
         L.P[q] = acc;
@@ -428,14 +451,14 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     // ---- pair pivot with the dual regularisation Delta_k of the rows defining x_k ----
     // (Delta > 0 on every row exactly when delta_c > 0 or the elastic variables are eliminated)
     const bool pair = !e.lsq && (e.resto || e.dcp > 0.0);
-    const double dhl = pair ? sqrt(row_dreg(e, SD[NZ + li], SD[NZ + NX + li])) : 0.0;
+    const T dhl = pair ? T(sqrt(row_dreg(e, SD[NZ + li], SD[NZ + NX + li]))) : T(0);
     if (lane < NX) L.dh[lane] = dhl;
     lds_barrier();
-    double* LC = L.CV;
-    double* VV = L.CV + NX * NX;
+    T* LC = L.CV;
+    T* VV = L.CV + NX * NX;
     if (pair) {
       // C = I + Delta^1/2 P Delta^1/2, one row per lane, factored in registers
-      double cr[NX], ri[NX];
+      T cr[NX], ri[NX];
 #pragma unroll
       for (int l = 0; l < NX; ++l) cr[l] = dhl * L.P[li * NX + l] * L.dh[l] + (lane == l ? 1.0 : 0.0);
       const int r = chol_rows(cr, ri, lane);
@@ -451,10 +474,10 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       if (lane < NX || (lane >= 32 && lane < 32 + NX)) {
         const bool inv = lane >= 32;
         const int col = inv ? lane - 32 : lane;
-        double v[NX];
+        T v[NX];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          double acc = inv ? (i == col ? 1.0 : 0.0) : L.dh[i] * L.P[i * NX + col];
+          T acc = inv ? (i == col ? 1.0 : 0.0) : L.dh[i] * L.P[i * NX + col];
 #pragma unroll
           for (int l = 0; l < i; ++l) acc -= LC[i * NX + l] * v[l];
           v[i] = acc * ri[i];
@@ -467,12 +490,12 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
       for (int t = 0; t < TILE_P; ++t) {
         const int q = lane + WAVE * t, i = q / NX, j = q % NX;
-        double acc = L.P[q];
+        T acc = L.P[q];
 #pragma unroll
         for (int l = 0; l < NX; ++l) acc -= VV[l * NX + i] * VV[l * NX + j];
         L.S[q] = acc;
         const int qi = q < NX * NX ? i : 0;
-        double ci = 0.0;
+        T ci = 0.0;
 #pragma unroll
         for (int l = 0; l < NX; ++l) ci += L.LI[l * NX + qi] * L.LI[l * NX + j];
         if (q < NX * NX) fr[FR_M + q] = ci * L.dh[j] * L.rdh[qi];
@@ -509,32 +532,32 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 //   w_u = L_R^{-1} r_u,  t = r_x - Y^T w_u - P r_a,
 //   a = t (Delta = 0)  or  a = M t,  M = Delta^{-1/2} C^{-1} Delta^{1/2} from the factor record,
 //   b = r_a + Delta a,  c_u = L_R^{-T} (w_u - Y b)
-__device__ __forceinline__ double stage_apply(const double* F, bool has_u, const double (&ra)[NX], double rx,
-                                              const double (&ru)[NU], bool full, int lane, double& b,
-                                              double (&cu)[NU], SolLds& V) {
+template <typename T>
+__device__ __forceinline__ T stage_apply(const T* F, bool has_u, const T (&ra)[NX], T rx, const T (&ru)[NU], bool full,
+                                         int lane, T& b, T (&cu)[NU], SolLdsT<T>& V) {
   const int li = lane < NX ? lane : NX - 1;
   const bool reg = F[FR_FLAG] != 0.0;
-  double wu[NU];
+  T wu[NU];
 #pragma unroll
   for (int a2 = 0; a2 < NU; ++a2) {
-    double acc = ru[a2];
+    T acc = ru[a2];
 #pragma unroll
     for (int l = 0; l < a2; ++l) acc -= F[FR_LR + a2 * NU + l] * wu[l];
     wu[a2] = has_u ? acc * F[FR_RR + a2] : 0.0;
   }
-  double t = rx;
+  T t = rx;
   if (has_u)
 #pragma unroll
     for (int a2 = 0; a2 < NU; ++a2) t -= F[FR_Y + a2 * NX + li] * wu[a2];
 #pragma unroll
   for (int l = 0; l < NX; ++l) t -= F[FR_P + li * NX + l] * ra[l];
-  double av = t;
-  const double dh = F[FR_DH + li];
+  T av = t;
+  const T dh = F[FR_DH + li];
   if (reg) {
-    double tl[NX];
+    T tl[NX];
 #pragma unroll
     for (int l = 0; l < NX; ++l) tl[l] = lane_bcast(t, l);
-    double acc = 0.0;
+    T acc = 0.0;
 #pragma unroll
     for (int l = 0; l < NX; ++l) acc += F[FR_M + li * NX + l] * tl[l];
     av = acc;
@@ -544,17 +567,17 @@ __device__ __forceinline__ double stage_apply(const double* F, bool has_u, const
     if (has_u) {
       if (lane < NX) V.tmp[lane] = b;
       lds_barrier();
-      double c2[NU];
+      T c2[NU];
 #pragma unroll
       for (int a2 = 0; a2 < NU; ++a2) {
-        double acc = wu[a2];
+        T acc = wu[a2];
 #pragma unroll
         for (int i = 0; i < NX; ++i) acc -= F[FR_Y + a2 * NX + i] * V.tmp[i];
         c2[a2] = acc;
       }
 #pragma unroll
       for (int a2 = NU - 1; a2 >= 0; --a2) {
-        double acc = c2[a2];
+        T acc = c2[a2];
 #pragma unroll
         for (int l = a2 + 1; l < NU; ++l) acc -= F[FR_LR + l * NU + a2] * cu[l];
         cu[a2] = acc * F[FR_RR + a2];
@@ -570,29 +593,38 @@ __device__ __forceinline__ double stage_apply(const double* F, bool has_u, const
 
 // flat prefetch of [factor record of knot kf | G of interval kg]; out-of-range kf / kg load a
 // valid record whose words the sweeps never read (branch-free loads, see stage_prefetch)
-__device__ __forceinline__ void sol_prefetch(const Cfg& c, const Slot& s, int kf, int kg, int lane, double* reg) {
+template <typename T>
+__device__ __forceinline__ void sol_prefetch(const Cfg& c, const Slot& s, int kf, int kg, int lane, T* reg) {
   const bool hf = kf >= 0 && kf <= c.N, hg = kg >= 0 && kg < c.N;
-  const double* Fp = s.fac + (long long)(hf ? kf : 0) * FR_LEN;
+  const T* Fp = reinterpret_cast<const T*>(s.fac) + (long long)(hf ? kf : 0) * FR_LEN;
   const double* Gp = s.G + (long long)(hg ? kg : 0) * NX * NZ;
 #pragma unroll
   for (int t = 0; t < SPF; ++t) {
     const int q = lane + WAVE * t;
-    const double* a = (q < FR_LEN) ? Fp + q : Gp + min(q - FR_LEN, NX * NZ - 1);
-    reg[t] = *a;
+    if constexpr (sizeof(T) == sizeof(double)) {
+      const double* a = (q < FR_LEN) ? reinterpret_cast<const double*>(Fp) + q : Gp + min(q - FR_LEN, NX * NZ - 1);
+      reg[t] = *a;
+    } else {
+      const T fv = Fp[q < FR_LEN ? q : FR_LEN - 1];
+      const double gv = Gp[q < FR_LEN ? 0 : min(q - FR_LEN, NX * NZ - 1)];
+      reg[t] = q < FR_LEN ? fv : T(gv);
+    }
   }
 }
-__device__ __forceinline__ void sol_park(double* buf, int lane, const double* reg) {
+template <typename T>
+__device__ __forceinline__ void sol_park(T* buf, int lane, const T* reg) {
 #pragma unroll
   for (int t = 0; t < SPF; ++t) buf[lane + WAVE * t] = reg[t];
 }
 
 // Solve K [dv; dy] = [bv; bc] (and the eliminated p/n rows bp, bn in restoration) with the factor
 // in s.fac and the stage data in s.sd.  Outputs xv (n), xc (m), xp, xn (m; restoration only).
+template <typename T>
 __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Elim& e, const double* bv,
                                           const double* bc, const double* bp, const double* bn, double* xv,
-                                          double* xc, double* xp, double* xn, SolLds& V, int lane) {
+                                          double* xc, double* xp, double* xn, SolLdsT<T>& V, int lane) {
   const int N = c.N, NI = c.NI, SL = sd_len(c);
-  double reg[SPF];
+  T reg[SPF];
   sol_prefetch(c, s, N, N - 1, lane, reg);      // first backward stage
   // 1. condensed stage right-hand sides (lambda 13, x 13, u 4 per knot) into LDS
   for (int q = lane; q < (N + 1) * RB_LEN; q += WAVE) {
@@ -610,7 +642,7 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
     } else if (i < 2 * NX + NU && k < N) {
       val = bv[uo(k) + i - 2 * NX];
     }
-    V.rb[q] = val;
+    V.rb[q] = T(val);
   }
   lds_barrier();
   // position rows of x_k gather the slack rows of knot k
@@ -628,29 +660,29 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
       if (e.resto) bg += bp[r] / (o7[1] + e.dxp) - bn[r] / (o7[2] + e.dxp);
       acc += o7[3 + t] * D * (bv[so(c, k, j)] / sig + bg);
     }
-    V.rb[k * RB_LEN + NX + t] += acc;
+    V.rb[k * RB_LEN + NX + t] += T(acc);
   }
   sol_park(V.buf, lane, reg);
   lds_barrier();
   // 2. backward sweep: rbar_k = r_k + G_k^T a_{k+1}
   const int li = lane < NX ? lane : NX - 1;
   for (int k = N; k >= 0; --k) {
-    const double* B = V.buf;                  // factor of knot k | G_{k-1}
+    const T* B = V.buf;                  // factor of knot k | G_{k-1}
     if (k > 0) sol_prefetch(c, s, k - 1, k - 2, lane, reg);
-    const double* rbk = V.rb + k * RB_LEN;
-    double ra[NX], ru[NU], cu[NU], bx;
+    const T* rbk = V.rb + k * RB_LEN;
+    T ra[NX], ru[NU], cu[NU], bx;
 #pragma unroll
     for (int l = 0; l < NX; ++l) ra[l] = rbk[l];
 #pragma unroll
     for (int a2 = 0; a2 < NU; ++a2) ru[a2] = (k < N) ? rbk[2 * NX + a2] : 0.0;
-    const double av = stage_apply(B, k < N, ra, rbk[NX + li], ru, false, lane, bx, cu, V);
+    const T av = stage_apply(B, k < N, ra, rbk[NX + li], ru, false, lane, bx, cu, V);
     if (k > 0) {
-      double al[NX];
+      T al[NX];
 #pragma unroll
       for (int l = 0; l < NX; ++l) al[l] = lane_bcast(av, l);
       if (lane < NZ) {
-        const double* Gp = B + FR_LEN;         // G_{k-1}
-        double acc = 0.0;
+        const T* Gp = B + FR_LEN;         // G_{k-1}
+        T acc = 0.0;
 #pragma unroll
         for (int l = 0; l < NX; ++l) acc += Gp[l * NZ + lane] * al[l];
         V.rb[(k - 1) * RB_LEN + NX + lane] += acc;
@@ -662,33 +694,33 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
   }
   // 3. forward sweep with the lambda rows fed by G_{k-1} (dx_{k-1}, du_{k-1}); the buffer still
   //    holds the record of knot 0 from the last backward stage
-  double dz[NZ];
+  T dz[NZ];
 #pragma unroll
   for (int l = 0; l < NZ; ++l) dz[l] = 0.0;
   for (int k = 0; k <= N; ++k) {
-    const double* B = V.buf;                  // factor of knot k | G_{k-1}
+    const T* B = V.buf;                  // factor of knot k | G_{k-1}
     if (k < N) sol_prefetch(c, s, k + 1, k, lane, reg);
-    const double* rbk = V.rb + k * RB_LEN;
-    double rai = rbk[li];
+    const T* rbk = V.rb + k * RB_LEN;
+    T rai = rbk[li];
     if (k > 0) {
-      const double* Gp = B + FR_LEN;
-      double w = 0.0;
+      const T* Gp = B + FR_LEN;
+      T w = 0.0;
 #pragma unroll
       for (int l = 0; l < NZ; ++l) w += Gp[li * NZ + l] * dz[l];
       rai += w;
     }
-    double ra[NX], ru[NU], cu[NU], bx = 0.0;
+    T ra[NX], ru[NU], cu[NU], bx = 0.0;
 #pragma unroll
     for (int l = 0; l < NX; ++l) ra[l] = lane_bcast(rai, l);
 #pragma unroll
     for (int a2 = 0; a2 < NU; ++a2) ru[a2] = (k < N) ? rbk[2 * NX + a2] : 0.0;
-    const double av = stage_apply(B, k < N, ra, rbk[NX + li], ru, true, lane, bx, cu, V);
+    const T av = stage_apply(B, k < N, ra, rbk[NX + li], ru, true, lane, bx, cu, V);
     if (lane < NX) {
       xc[k * NX + lane] = av;
       xv[xo(k) + lane] = bx;
     }
     if (k < N) {
-      double u = 0.0;
+      T u = 0.0;
 #pragma unroll
       for (int a2 = 0; a2 < NU; ++a2) u = (lane == a2) ? cu[a2] : u;
       if (lane < NU) xv[uo(k) + lane] = u;

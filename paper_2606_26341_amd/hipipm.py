@@ -40,7 +40,8 @@ class Options(C.Structure):
         ("max_soc", C.c_int32), ("kappa_soc", C.c_double), ("kappa_sigma", C.c_double),
         ("rho_resto", C.c_double), ("kappa_resto", C.c_double), ("bound_mult_reset", C.c_double),
         ("filter_cap", C.c_int32), ("poll_every", C.c_int32), ("timing", C.c_int32),
-        ("fuse_below", C.c_int32),
+        ("fuse_below", C.c_int32), ("precision", C.c_int32), ("refine_max", C.c_int32),
+        ("refine_tol", C.c_double),
     ]
 
 
@@ -53,7 +54,7 @@ class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("iterations", "resto_iterations", "soc_tried", "soc_accepted",
                                          "factorizations", "resto_entries", "tiny_steps", "passes",
                                          "instances_done", "solves", "fused_factorizations",
-                                         "fused_solves")]
+                                         "fused_solves", "refine_sweeps", "fp64_fallbacks")]
 
 
 _lib = None

@@ -213,6 +213,8 @@ WORKLOADS = {
     "C3": Workload("C3", FAMILY_MULTI_QUAD, 1024, N=20, n_agents=4, seed_tag=3),
     "C4": Workload("C4", FAMILY_QUAD_OBS, 8192, N=40, n_obs=32, precision="fp32ir", seed_tag=4),
     "C5": Workload("C5", FAMILY_QUAD_OBS, 16384, N=10, n_obs=3, precision="fp32ir", seed_tag=5),
+    # reduced cluttered case the oracle solves in seconds (parity of the FP32 + refinement path)
+    "C4s": Workload("C4s", FAMILY_QUAD_OBS, 32, N=12, n_obs=8, precision="fp32ir", seed_tag=41),
 }
 
 

@@ -77,9 +77,10 @@ def _dense_kkt(w, th, v, y, zl, zu, dx, dc):
     return K, L, U
 
 
+@pytest.mark.parametrize("precision", [0, 1])
 @pytest.mark.parametrize("name", ["C1", "C2"])
 @pytest.mark.parametrize("dx,dc", [(0.0, 0.0), (1e-2, 0.0), (10.0, 1e-6)])
-def test_kkt_factor_solve_matches_dense_oracle(torch_cuda, name, dx, dc):
+def test_kkt_factor_solve_matches_dense_oracle(torch_cuda, name, dx, dc, precision):
     torch = torch_cuda
     w = W.get(name)
     cnt = 6
@@ -101,7 +102,7 @@ def test_kkt_factor_solve_matches_dense_oracle(torch_cuda, name, dx, dc):
         V.append(v); Y.append(rng.normal(size=w.m)); ZL.append(zl); ZU.append(zu)
         RHS.append(rng.normal(size=w.n + w.m))
     V, Y, ZL, ZU, RHS = map(np.array, (V, Y, ZL, ZU, RHS))
-    s = solver_for(w, cnt)
+    s = solver_for(w, cnt, precision=precision)
     dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda").contiguous()
     sol, ok = s.kkt_factor_solve(dev(TH), dev(V), dev(Y), dev(ZL), dev(ZU), 0.1, dx, dc, dev(RHS))
     sol, ok = sol.cpu().numpy(), ok.cpu().numpy()
@@ -111,6 +112,8 @@ def test_kkt_factor_solve_matches_dense_oracle(torch_cuda, name, dx, dc):
         want_ok = fact[3] == (w.n, w.m, 0)
         say(name, i, "inertia", fact[3], "gpu ok", ok[i])
         assert bool(ok[i]) == want_ok
+        if want_ok and precision == 1:
+            assert ok[i] == 2          # FP32 factor + FP64 refinement reached 1e-10 |b|
         if want_ok:
             ref = oracle.bk_solve(fact, RHS[i])
             err = np.abs(sol[i] - ref).max() / max(1.0, np.abs(ref).max())
@@ -201,6 +204,20 @@ def test_c2_sample_matches_oracle(torch_cuda):
     n_match, n_diff = _compare_solves(w, TH, g, o)
     say("C2 match", n_match, "different local minimum", n_diff)
     assert n_match >= 30
+
+
+def test_mixed_precision_matches_oracle(torch_cuda):
+    # FP32 factor and solve with FP64 refinement on the reduced cluttered case: the same KKT
+    # points as the FP64 oracle, at E_0 <= 1e-8 checked by the oracle on the returned point
+    w = W.get("C4s")
+    TH = w.thetas(0, w.n_inst)
+    o = oracle.solve_quad(w, TH, threads=THREADS)
+    g, st = _gpu_solve(w, TH, slots=12, precision=1)
+    say("gpu stats", st)
+    assert st["refine_sweeps"] > 0 and st["fused_factorizations"] == st["factorizations"]
+    n_match, n_diff = _compare_solves(w, TH, g, o)
+    say("C4s mixed: match", n_match, "different local minimum", n_diff)
+    assert n_match >= w.n_inst - 2
 
 
 def test_fused_pass_kernel_is_bitwise_identical(torch_cuda):
