@@ -751,7 +751,7 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
 __device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L, bool fused, bool mixed, int lane) {
   const int work = (int)s.sc[SC_WORK];
   if (work == W_NONE) return;
-  const bool f32 = mixed && c.prec == 1 && s.sc[SC_FORCE64] == 0.0;
+  bool f32 = mixed && c.prec == 1 && s.sc[SC_FORCE64] == 0.0;
   if (work == W_LSQ) {
     Elim e{true, false, 0.0, 0.0, 0.0};
     const int st = factor_any(c, s, e, L, f32, lane);
@@ -767,6 +767,13 @@ __device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L,
   Elim e{false, resto, 0.0, 0.0, resto ? sqrt(mu) : 0.0};
   int st = factor_any(c, s, e, L, f32, lane);
   int nfact = 1;
+  if (f32 && st != 0) {
+    // the inertia-correction decisions are FP64 ones: an FP32 verdict of wrong inertia is
+    // re-taken in FP64, and the rest of this iteration's correction runs in FP64
+    f32 = false;
+    st = factor_any(c, s, e, L, false, lane);
+    ++nfact;
+  }
   bool ok = (st == 0);
   if (!ok) {
     if (st == 2) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);

@@ -220,6 +220,28 @@ def test_mixed_precision_matches_oracle(torch_cuda):
     assert n_match >= w.n_inst - 2
 
 
+@pytest.mark.slow
+def test_c4_mixed_precision_against_fp64(torch_cuda):
+    # the full cluttered batch (8192 instances, N = 40, 32 spheres) in FP32 + refinement and in
+    # FP64: same statuses and KKT points; E_0 of sampled mixed results re-checked by the oracle
+    w = W.get("C4")
+    TH = w.thetas(0, w.n_inst)
+    g1, st1 = _gpu_solve(w, TH, slots=w.n_inst, precision=1)
+    g0, st0 = _gpu_solve(w, TH, slots=w.n_inst, precision=0)
+    say("mixed stats", st1)
+    both = (g1["status"] == oracle.ST_CONVERGED) & (g0["status"] == oracle.ST_CONVERGED)
+    assert both.mean() >= 0.97
+    rel = np.abs(g1["obj"] - g0["obj"]) / np.maximum(1.0, np.abs(g0["obj"]))
+    dx = np.abs(g1["x"] - g0["x"]).max(axis=1)
+    same = both & (rel <= 1e-6) & (dx <= 1e-5)
+    say("converged both", int(both.sum()), "same point", int(same.sum()), "max rel obj (same)",
+        float(rel[same].max()), "max |dx| (same)", float(dx[same].max()))
+    assert same.sum() >= 0.97 * both.sum()
+    for i in np.flatnonzero(both)[:: max(1, int(both.sum()) // 24)]:
+        e0 = oracle.kkt_error(w, TH[i], g1["x"][i], g1["y"][i], g1["zl"][i], g1["zu"][i])
+        assert e0 <= 1e-8, (i, e0)
+
+
 def test_fused_pass_kernel_is_bitwise_identical(torch_cuda):
     # the fused pass kernel runs the same per-slot phases: results must not change by a bit,
     # whether it is used from the start, never, or from the middle of the solve on
