@@ -21,3 +21,10 @@ def _oracle_built():
         import oracle
         oracle.build()
     yield
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch

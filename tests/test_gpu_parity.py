@@ -23,13 +23,6 @@ def say(*a):
     print(*a, flush=True)
 
 
-@pytest.fixture(scope="module")
-def torch_cuda():
-    import torch
-    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
-    return torch
-
-
 def solver_for(w, slots, **opts):
     from paper_2606_26341_amd import hipipm
     return hipipm.Solver(w, slots, hipipm.default_options(**opts))
