@@ -94,6 +94,10 @@ typedef struct {
                              fails (runs every pass fused) */
     int32_t refine_max;   /* refinement sweeps per solve in precision 1 (default 3) */
     double refine_tol;    /* refinement stops when |b - K x|_inf <= refine_tol |b|_inf (default 1e-10) */
+    double warm_mu0;      /* barrier parameter of a warm start (default 1e-3) */
+    double warm_push;     /* bound push (kappa_1 = kappa_2) of a warm start (default 1e-3) */
+    int32_t warm_iter_cap; /* a warm-started instance still running after this many iterations, or
+                              entering restoration, restarts cold in its slot (0: only restoration) */
 } hipipm_options;
 
 typedef struct {
@@ -108,6 +112,9 @@ typedef struct {
     int64_t fused_solves;            /* solves (step and SOC) done inside the fused pass kernel */
     int64_t refine_sweeps;           /* precision 1: refinement sweeps (each one FP32 solve) */
     int64_t fp64_fallbacks;          /* precision 1: iterations refactored in FP64 after refinement failed */
+    int64_t warm_started;            /* instances started from a warm point */
+    int64_t warm_rejected;           /* warm points rejected at initialisation (non-finite) -> cold */
+    int64_t warm_restarts;           /* warm starts that diverged and restarted cold */
 } hipipm_stats;
 
 typedef struct hipipm_ctx hipipm_ctx;
@@ -133,14 +140,19 @@ int hipipm_bind_workspace(hipipm_ctx* ctx, void* dev_ptr, size_t bytes);
 
 /* Solve n_inst instances with iteration-level batching over the context's slots.
  *   theta   : device, [n_inst][n_theta] FP64, read only
- *   warm_x  : device, [n_inst][n] FP64 starting points, or NULL for the cold start
- *             (x_k = xbar0, u_k = hover thrust, s = g(x)); pushed into the bounds either way
+ *   warm    : device, [n_inst][n_w + m] FP64 warm points (the primal w = (x_0, u_0, ..., x_N)
+ *             without slacks, then the equality multipliers y), or NULL for the cold start
+ *             (x_k = xbar0, u_k = hover thrust, s = g(x), z = 1, least-squares y).  A warm
+ *             instance starts at w pushed into the bounds by options.warm_push, s = max(g(w),
+ *             warm_push), its y, bound multipliers from stationarity floored at mu0 / slack,
+ *             mu0 = options.warm_mu0; a warm point with a non-finite entry is rejected and the
+ *             instance starts cold (see also options.warm_iter_cap)
  *   x_out   : device, [n_inst][n];  y_out: [n_inst][m];  zl_out, zu_out: [n_inst][n]
  *             (bound multipliers, zero on unbounded components)
  *   obj_out, kkt_out : device, [n_inst] objective and scaled KKT error E_0 at the result
  *   status_out, iters_out : device, [n_inst] int32
  * Output pointers may be NULL to skip that output (theta may not). */
-int hipipm_solve(hipipm_ctx* ctx, int32_t n_inst, const double* theta, const double* warm_x, double* x_out,
+int hipipm_solve(hipipm_ctx* ctx, int32_t n_inst, const double* theta, const double* warm, double* x_out,
                  double* y_out, double* zl_out, double* zu_out, double* obj_out, double* kkt_out,
                  int32_t* status_out, int32_t* iters_out, void* stream);
 

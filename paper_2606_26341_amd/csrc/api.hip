@@ -16,14 +16,14 @@
 
 namespace hipipm {
 void launch_eval(const Cfg& c, double* ws, int slots, hipStream_t st);
-void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                 Counters* cnt, int refill, hipStream_t st);
 void launch_fac(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_sol(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st);
-void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                  Counters* cnt, int refill, hipStream_t st);
-void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm_x,
+void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm,
                   hipStream_t st);
 void launch_stage_derivs(const Cfg& c, int count, const double* x, const double* u, const double* lam, double* F,
                          double* G, double* H, hipStream_t st);
@@ -110,6 +110,7 @@ int hipipm_default_options(hipipm_options* o) {
   o->rho_resto = 1000.0; o->kappa_resto = 0.9; o->bound_mult_reset = 1e3; o->filter_cap = 128;
   o->poll_every = 4; o->timing = 0; o->fuse_below = 1 << 30;
   o->precision = 0; o->refine_max = 3; o->refine_tol = 1e-10;
+  o->warm_mu0 = 1e-3; o->warm_push = 1e-3; o->warm_iter_cap = 0;
   return HIPIPM_OK;
 }
 
@@ -121,7 +122,8 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   if (d->N < 1 || d->N > MAX_N || d->n_obs < 0 || d->n_obs > MAX_OBS) return HIPIPM_ERR_INVALID_ARG;
   if (!(d->dt > 0) || !(d->mass > 0) || !(d->jxx > 0) || !(d->jyy > 0) || !(d->jzz > 0)) return HIPIPM_ERR_INVALID_ARG;
   if (o->filter_cap < 1 || o->filter_cap > FCAP || o->max_iter < 0 || o->poll_every < 1 || !(o->tol > 0) ||
-      o->fuse_below < 0 || o->precision < 0 || o->precision > 1 || o->refine_max < 0 || !(o->refine_tol > 0))
+      o->fuse_below < 0 || o->precision < 0 || o->precision > 1 || o->refine_max < 0 || !(o->refine_tol > 0) ||
+      !(o->warm_mu0 > 0) || !(o->warm_push > 0) || o->warm_iter_cap < 0)
     return HIPIPM_ERR_INVALID_ARG;
   hipipm_ctx* c = new hipipm_ctx();
   c->desc = *d;
@@ -154,6 +156,7 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   g.kappa_soc = o->kappa_soc; g.kappa_sigma = o->kappa_sigma; g.rho_resto = o->rho_resto;
   g.kappa_resto = o->kappa_resto; g.bound_mult_reset = o->bound_mult_reset; g.fcap = o->filter_cap;
   g.prec = o->precision; g.refine_max = o->refine_max; g.refine_tol = o->refine_tol;
+  g.warm_mu0 = o->warm_mu0; g.warm_push = o->warm_push; g.warm_cap = o->warm_iter_cap;
   layout(g);
   size_t rec = (size_t)g.stride * sizeof(double) * (size_t)slots;
   c->cnt_off = (rec + 255) / 256 * 256;
@@ -190,7 +193,7 @@ int hipipm_bind_workspace(hipipm_ctx* c, void* p, size_t bytes) {
 
 static Counters* counters(hipipm_ctx* c) { return (Counters*)((char*)c->ws + c->cnt_off); }
 
-int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const double* warm_x, double* x_out,
+int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const double* warm, double* x_out,
                  double* y_out, double* zl_out, double* zu_out, double* obj_out, double* kkt_out,
                  int32_t* status_out, int32_t* iters_out, void* stream) {
   if (!c) return HIPIPM_ERR_INVALID_ARG;
@@ -217,7 +220,7 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
     for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
     HIPCHK(c, hipEventRecord(ev[0], st));
   }
-  launch_setup(c->cfg, c->ws, active, active, theta, warm_x, st);
+  launch_setup(c->cfg, c->ws, active, active, theta, warm, st);
   if (timing) {
     HIPCHK(c, hipEventRecord(ev[1], st));
     HIPCHK(c, hipEventSynchronize(ev[1]));
@@ -239,10 +242,10 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
       launch_eval(c->cfg, c->ws, active, st);
       if (timing) HIPCHK(c, hipEventRecord(e[1], st));
       if (fused) {
-        launch_iter(c->cfg, c->ws, active, theta, warm_x, out, dcnt, 1, st);
+        launch_iter(c->cfg, c->ws, active, theta, warm, out, dcnt, 1, st);
         if (timing) HIPCHK(c, hipEventRecord(e[2], st));
       } else {
-        launch_pre(c->cfg, c->ws, active, theta, warm_x, out, dcnt, 1, st);
+        launch_pre(c->cfg, c->ws, active, theta, warm, out, dcnt, 1, st);
         if (timing) HIPCHK(c, hipEventRecord(e[2], st));
         launch_fac(c->cfg, c->ws, active, st);
         if (timing) HIPCHK(c, hipEventRecord(e[3], st));
@@ -290,6 +293,9 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   c->stats.fused_solves += (int64_t)h.st[11];
   c->stats.refine_sweeps += (int64_t)h.st[12];
   c->stats.fp64_fallbacks += (int64_t)h.st[13];
+  c->stats.warm_started += (int64_t)h.st[14];
+  c->stats.warm_rejected += (int64_t)h.st[15];
+  c->stats.warm_restarts += (int64_t)h.st[16];
   return HIPIPM_OK;
 }
 

@@ -32,6 +32,7 @@ enum : int {
   SC_ST_RESTO = 32, SC_ST_SOCT, SC_ST_SOCA, SC_ST_FACT, SC_ST_RENT, SC_ST_TINY, SC_ST_PASS,
   SC_LDX = 40, SC_LDC, SC_LALPHA, SC_LALPHAZ, SC_LSOC, SC_WORK, SC_FSTAT,
   SC_ST_SOLV, SC_ST_FFACT, SC_ST_FSOLV, SC_FPREC, SC_FORCE64, SC_ST_REF, SC_ST_FB, SC_DXLSAVE,
+  SC_WARM, SC_ST_WSTART, SC_ST_WREJ, SC_ST_WRST,
   SC_LEN = 64
 };
 
@@ -55,6 +56,7 @@ struct Cfg {
   int max_soc; double kappa_soc, kappa_sigma, rho_resto, kappa_resto, bound_mult_reset;
   int fcap;
   int prec, refine_max; double refine_tol;   // KKT factor precision (1: FP32 + FP64 refinement)
+  double warm_mu0, warm_push; int warm_cap;  // warm start: barrier parameter, bound push, iteration cap
   // slot record layout, offsets in doubles
   long long stride;
   int o_v, o_y, o_zlu, o_zuu, o_zls, o_th, o_sc, o_fm, o_fr;
@@ -75,7 +77,7 @@ struct Outs {
 // global counters (device): queue head, finished count, stats
 struct Counters {
   int32_t head, done, n_inst, pad;
-  unsigned long long st[14];
+  unsigned long long st[17];
 };
 
 }  // namespace hipipm

@@ -364,63 +364,89 @@ __global__ __launch_bounds__(64) void k_prepare(Cfg c, double* ws) {
   fill_ref(c, s, threadIdx.x);
 }
 
-__device__ __forceinline__ void init_instance(const Cfg& c, const Slot& s, int inst, const double* theta, const double* warm_x,
-                              int lane) {
+// Start an instance in a slot: cold (x_k = xbar0, u_k = hover, s = g(xbar0), z = 1; y by least
+// squares in the INIT_Y phase) or warm from (w, y) (rows of `warm`: n_w primal then m multipliers;
+// slacks from g(w), bound multipliers from stationarity in the INIT_Y phase).  Every start is pushed
+// into the bounds (kappa_1, kappa_2; warm_push for a warm start).  `restart`: the cold restart of a
+// diverged warm start (warm is ignored, iterations and counters are kept).
+// the scalar-block words a cold restart of a diverged warm start keeps: iterations and counters
+__device__ __forceinline__ bool kept_on_restart(int q) {
+  return q == SC_ITER || (q >= SC_ST_RESTO && q <= SC_ST_PASS) || q == SC_ST_SOLV || q == SC_ST_FFACT ||
+         q == SC_ST_FSOLV || q == SC_ST_REF || q == SC_ST_FB || q == SC_ST_WSTART;
+}
+
+__device__ __forceinline__ void init_instance(const Cfg& c, const Slot& s, int inst, const double* theta, const double* warm,
+                              int lane, bool restart = false) {
   const double* th = theta + (long long)inst * c.n_theta;
   for (int i = lane; i < c.n_theta; i += WAVE) s.th[i] = th[i];
+  const double* wp = (warm && !restart) ? warm + (long long)inst * (c.n_w + c.m) : nullptr;
+  int bad = 0;
+  if (wp)
+    for (int i = lane; i < c.n_w + c.m; i += WAVE)
+      if (!isfinite(wp[i])) bad = 1;
+  const bool use_warm = wp && wor(bad) == 0;
+  // the cold and warm constants are loaded unconditionally and blended by value
+  const double kc1 = c.kappa1, kc2 = c.kappa2, kw = c.warm_push, mc = c.mu_init, mw = c.warm_mu0;
+  const double k1 = use_warm ? kw : kc1, k2 = use_warm ? kw : kc2;
   __syncthreads();
   fill_ref(c, s, lane);
   for (int i = lane; i < c.n; i += WAVE) {
     double x;
-    if (warm_x) {
-      x = warm_x[(long long)inst * c.n + i];
-    } else if (i < c.n_w) {
-      int r = i % NZ;
-      x = (r < NX) ? s.th[r] : c.uh;
+    if (i < c.n_w) {
+      const int r = i % NZ;
+      x = use_warm ? wp[i] : ((r < NX) ? s.th[r] : c.uh);
     } else {
-      int q = i - c.n_w, j = q % c.NI;
+      const int q = i - c.n_w, k = 1 + q / c.NI, j = q % c.NI;
       const double* o = obs_ptr(c, s.th) + 4 * j;
       double g = 0.0;
-      for (int t = 0; t < 3; ++t) { double e = s.th[t] - o[t]; g += e * e; }
+      for (int t = 0; t < 3; ++t) {
+        const double e = (use_warm ? wp[xo(k) + t] : s.th[t]) - o[t];
+        g += e * e;
+      }
       x = g - o[3] * o[3];
     }
-    // push into the bounds (kappa_1, kappa_2)
+    // push into the bounds
     if (i < c.n_w) {
       int k = i / NZ, r = i % NZ;
       if (r >= NX && k < c.N) {
         double l = 0.0, u = c.umax;
-        double pl = fmin(c.kappa1 * fmax(1.0, fabs(l)), c.kappa2 * (u - l));
-        double pu = fmin(c.kappa1 * fmax(1.0, fabs(u)), c.kappa2 * (u - l));
+        double pl = fmin(k1 * fmax(1.0, fabs(l)), k2 * (u - l));
+        double pu = fmin(k1 * fmax(1.0, fabs(u)), k2 * (u - l));
         x = fmax(x, l + pl);
         x = fmin(x, u - pu);
       }
     } else {
-      x = fmax(x, 0.0 + c.kappa1 * 1.0);
+      x = fmax(x, 0.0 + k1 * 1.0);
     }
     s.v[i] = x;
   }
-  for (int r = lane; r < c.m; r += WAVE) s.y[r] = 0.0;
+  for (int r = lane; r < c.m; r += WAVE) s.y[r] = use_warm ? wp[c.n_w + r] : 0.0;
   for (int b = lane; b < c.N * NU; b += WAVE) { s.zlu[b] = 1.0; s.zuu[b] = 1.0; }
   for (int q = lane; q < c.N * c.NI; q += WAVE) s.zls[q] = 1.0;
-  for (int q = lane; q < SC_LEN; q += WAVE) s.sc[q] = 0.0;
+  for (int q = lane; q < SC_LEN; q += WAVE)
+    if (!(restart && kept_on_restart(q))) s.sc[q] = 0.0;
   __syncthreads();
   if (lane == 0) {
-    s.sc[SC_MU] = c.mu_init;
-    s.sc[SC_TAU] = fmax(c.tau_min, 1.0 - c.mu_init);
+    const double mu0 = use_warm ? mw : mc;
+    s.sc[SC_MU] = mu0;
+    s.sc[SC_TAU] = fmax(c.tau_min, 1.0 - mu0);
     s.sc[SC_PHASE] = PH_INIT_Y;
     s.sc[SC_STATUS] = ST_RUNNING;
     s.sc[SC_INST] = inst;
     s.sc[SC_INITF] = 1.0;
+    s.sc[SC_WARM] = use_warm ? 1.0 : 0.0;
+    if (!restart) s.sc[SC_ST_WSTART] = use_warm ? 1.0 : 0.0;
+    s.sc[SC_ST_WREJ] = (wp && !use_warm) ? 1.0 : 0.0;
   }
   __syncthreads();
 }
 
 __global__ __launch_bounds__(64) void k_setup(Cfg c, double* ws, int slots, int n_active, const double* theta,
-                                              const double* warm_x) {
+                                              const double* warm) {
   const int slot = blockIdx.x, lane = threadIdx.x;
   Slot s = make_slot(c, ws, slot);
   if (slot < n_active) {
-    init_instance(c, s, slot, theta, warm_x, lane);
+    init_instance(c, s, slot, theta, warm, lane);
   } else {
     for (int q = lane; q < SC_LEN; q += WAVE) s.sc[q] = 0.0;
     __syncthreads();
@@ -430,7 +456,7 @@ __global__ __launch_bounds__(64) void k_setup(Cfg c, double* ws, int slots, int 
 
 // ============================================================================ factor kernel
 // finished instance: write the results (main problem, E_0 at the point), pop the next one
-__device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const double* theta, const double* warm_x, Outs out,
+__device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const double* theta, const double* warm, Outs out,
                             Counters* cnt, bool refill, int lane) {
   Iter it = cur_iter(s, false);
   eval_c(c, s, false, lane);
@@ -470,6 +496,9 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
       atomicAdd(&cnt->st[11], (unsigned long long)s.sc[SC_ST_FSOLV]);
       atomicAdd(&cnt->st[12], (unsigned long long)s.sc[SC_ST_REF]);
       atomicAdd(&cnt->st[13], (unsigned long long)s.sc[SC_ST_FB]);
+      atomicAdd(&cnt->st[14], (unsigned long long)s.sc[SC_ST_WSTART]);
+      atomicAdd(&cnt->st[15], (unsigned long long)s.sc[SC_ST_WREJ]);
+      atomicAdd(&cnt->st[16], (unsigned long long)s.sc[SC_ST_WRST]);
       atomicAdd(&cnt->done, 1);
       next = refill ? atomicAdd(&cnt->head, 1) : INT_MAX;
     } else {
@@ -479,7 +508,7 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
   __syncthreads();
   const int nx = next;
   if (cnt && nx < cnt->n_inst) {
-    init_instance(c, s, nx, theta, warm_x, lane);
+    init_instance(c, s, nx, theta, warm, lane);
   } else {
     __syncthreads();
     if (lane == 0) s.sc[SC_PHASE] = PH_EMPTY;
@@ -628,6 +657,34 @@ __device__ __forceinline__ void pre_init_y(const Cfg& c, const Slot& s, int lane
   Iter it = cur_iter(s, false);
   eval_c(c, s, false, lane);
   eval_grad(c, s, s.y, false, 0.0, s.vt, lane);
+  if (s.sc[SC_WARM] != 0.0) {
+    // warm start: keep y; bound multipliers from stationarity grad f + A^T y - z_L + z_U = 0,
+    // floored at mu0 / slack; filter bounds from theta_0; no least-squares system
+    const double mu0 = s.sc[SC_MU];
+    for (int b = lane; b < c.N * NU; b += WAVE) {
+      const int vi = uo(b / NU) + b % NU;
+      const double u = s.v[vi], r = s.g[vi] + s.vt[vi];
+      s.zlu[b] = fmax(r, mu0 / u);
+      s.zuu[b] = fmax(-r, mu0 / (c.umax - u));
+    }
+    for (int q = lane; q < c.N * c.NI; q += WAVE) {
+      const int si = c.n_w + q;
+      s.zls[q] = fmax(s.g[si] + s.vt[si], mu0 / s.v[si]);
+    }
+    double th0 = 0.0;
+    for (int r = lane; r < c.m; r += WAVE) th0 += fabs(s.rc[r]);
+    th0 = wsum(th0);
+    __syncthreads();
+    if (lane == 0) {
+      s.sc[SC_THMAX] = 1e4 * fmax(1.0, th0);
+      s.sc[SC_THMIN] = 1e-4 * fmax(1.0, th0);
+      s.sc[SC_NF] = 0.0;
+      s.sc[SC_INITF] = 0.0;
+      s.sc[SC_PHASE] = PH_REGULAR;
+    }
+    __syncthreads();
+    return;
+  }
   for (int i = lane; i < c.n; i += WAVE) {
     double zl, zu;
     z_of(c, it, i, zl, zu);
@@ -639,16 +696,25 @@ __device__ __forceinline__ void pre_init_y(const Cfg& c, const Slot& s, int lane
   if (lane == 0) s.sc[SC_WORK] = W_LSQ;
 }
 
-__device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const double* theta, const double* warm_x,
+__device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const double* theta, const double* warm,
                                          Outs out, Counters* cnt, int refill, int lane) {
   const int ph = (int)s.sc[SC_PHASE];
   if (ph == PH_EMPTY) return;
   __syncthreads();
   if (lane == 0) { s.sc[SC_ST_PASS] += 1.0; s.sc[SC_WORK] = W_NONE; s.sc[SC_FORCE64] = 0.0; }
-  if (ph == PH_FINISH) { finish_slot(c, s, theta, warm_x, out, cnt, refill != 0, lane); return; }
+  if (ph == PH_FINISH) { finish_slot(c, s, theta, warm, out, cnt, refill != 0, lane); return; }
   if (ph == PH_INIT_Y) { pre_init_y(c, s, lane); return; }
 
   const bool resto = (ph == PH_RESTO);
+  if (s.sc[SC_WARM] != 0.0 && (resto || (c.warm_cap > 0 && s.sc[SC_ITER] >= c.warm_cap))) {
+    // the warm start diverged (restoration, or too many iterations): restart cold in this slot,
+    // keeping the iterations and counters spent so far
+    __syncthreads();
+    init_instance(c, s, (int)s.sc[SC_INST], theta, warm, lane, true);
+    if (lane == 0) s.sc[SC_ST_WRST] = 1.0;
+    __syncthreads();
+    return;
+  }
   Iter it = cur_iter(s, resto);
   double* sub = it.sub;   // mu, tau, dx_last, theta_max, theta_min, tiny, nf
   double mu = sub[0];
@@ -667,7 +733,7 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
     if (!resto) {
       if (lane == 0) s.sc[SC_STATUS] = ST_CONVERGED;
       __syncthreads();
-      finish_slot(c, s, theta, warm_x, out, cnt, refill != 0, lane);
+      finish_slot(c, s, theta, warm, out, cnt, refill != 0, lane);
     } else {
       for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
       if (lane == 0) { s.sc[SC_STATUS] = ST_INFEASIBLE; s.sc[SC_PHASE] = PH_FINISH; }
@@ -678,7 +744,7 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
     if (!resto) {
       if (lane == 0) s.sc[SC_STATUS] = ST_MAX_ITER;
       __syncthreads();
-      finish_slot(c, s, theta, warm_x, out, cnt, refill != 0, lane);
+      finish_slot(c, s, theta, warm, out, cnt, refill != 0, lane);
     } else {
       for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
       if (lane == 0) { s.sc[SC_STATUS] = ST_MAX_ITER; s.sc[SC_PHASE] = PH_FINISH; }
@@ -1213,9 +1279,9 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
 }
 
 // ============================================================================ pass kernels
-__global__ __launch_bounds__(64) void k_pre(Cfg c, double* ws, const double* theta, const double* warm_x, Outs out,
+__global__ __launch_bounds__(64) void k_pre(Cfg c, double* ws, const double* theta, const double* warm, Outs out,
                                             Counters* cnt, int refill) {
-  pre_body(c, make_slot(c, ws, blockIdx.x), theta, warm_x, out, cnt, refill, threadIdx.x);
+  pre_body(c, make_slot(c, ws, blockIdx.x), theta, warm, out, cnt, refill, threadIdx.x);
 }
 __global__ __launch_bounds__(64) void k_fac(Cfg c, double* ws) {
   __shared__ FacLds L;
@@ -1233,14 +1299,14 @@ __global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
 // to back, instead of every phase waiting for the slowest slot of the previous one, and a pass
 // costs two launches instead of five.  MIXED: the FP32 factor / FP64 refinement variant.
 template <bool MIXED>
-__global__ __launch_bounds__(64) void k_iter(Cfg c, double* ws, const double* theta, const double* warm_x, Outs out,
+__global__ __launch_bounds__(64) void k_iter(Cfg c, double* ws, const double* theta, const double* warm, Outs out,
                                              Counters* cnt, int refill) {
   __shared__ FacLds L;
   HIP_DYNAMIC_SHARED(double, sol_dyn)
   const int lane = threadIdx.x;
   const Slot s = make_slot(c, ws, blockIdx.x);
   if ((int)s.sc[SC_PHASE] == PH_EMPTY) return;
-  pre_body(c, s, theta, warm_x, out, cnt, refill, lane);
+  pre_body(c, s, theta, warm, out, cnt, refill, lane);
   __syncthreads();
   fac_body(c, s, L, true, MIXED, lane);
   __syncthreads();
@@ -1305,9 +1371,9 @@ void launch_eval(const Cfg& c, double* ws, int slots, hipStream_t st) {
 }
 int sd_len_host(int NI) { return sd_len_of(NI); }
 static size_t sol_bytes(const Cfg& c) { return (size_t)sol_lds_doubles(c.N) * sizeof(double); }
-void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                 Counters* cnt, int refill, hipStream_t st) {
-  hipLaunchKernelGGL(k_pre, dim3(slots), dim3(WAVE), 0, st, c, ws, theta, warm_x, out, cnt, refill);
+  hipLaunchKernelGGL(k_pre, dim3(slots), dim3(WAVE), 0, st, c, ws, theta, warm, out, cnt, refill);
 }
 void launch_fac(const Cfg& c, double* ws, int slots, hipStream_t st) {
   hipLaunchKernelGGL(k_fac, dim3(slots), dim3(WAVE), 0, st, c, ws);
@@ -1318,16 +1384,16 @@ void launch_sol(const Cfg& c, double* ws, int slots, hipStream_t st) {
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st) {
   hipLaunchKernelGGL(k_ls, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws);
 }
-void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm_x, Outs out,
+void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                  Counters* cnt, int refill, hipStream_t st) {
   if (c.prec == 1)
-    hipLaunchKernelGGL(k_iter<true>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm_x, out, cnt, refill);
+    hipLaunchKernelGGL(k_iter<true>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm, out, cnt, refill);
   else
-    hipLaunchKernelGGL(k_iter<false>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm_x, out, cnt, refill);
+    hipLaunchKernelGGL(k_iter<false>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm, out, cnt, refill);
 }
-void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm_x,
+void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm,
                   hipStream_t st) {
-  hipLaunchKernelGGL(k_setup, dim3(slots), dim3(WAVE), 0, st, c, ws, slots, n_active, theta, warm_x);
+  hipLaunchKernelGGL(k_setup, dim3(slots), dim3(WAVE), 0, st, c, ws, slots, n_active, theta, warm);
 }
 void launch_stage_derivs(const Cfg& c, int count, const double* x, const double* u, const double* lam, double* F,
                          double* G, double* H, hipStream_t st) {

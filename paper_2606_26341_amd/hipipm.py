@@ -41,7 +41,8 @@ class Options(C.Structure):
         ("rho_resto", C.c_double), ("kappa_resto", C.c_double), ("bound_mult_reset", C.c_double),
         ("filter_cap", C.c_int32), ("poll_every", C.c_int32), ("timing", C.c_int32),
         ("fuse_below", C.c_int32), ("precision", C.c_int32), ("refine_max", C.c_int32),
-        ("refine_tol", C.c_double),
+        ("refine_tol", C.c_double), ("warm_mu0", C.c_double), ("warm_push", C.c_double),
+        ("warm_iter_cap", C.c_int32),
     ]
 
 
@@ -54,7 +55,8 @@ class Stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("iterations", "resto_iterations", "soc_tried", "soc_accepted",
                                          "factorizations", "resto_entries", "tiny_steps", "passes",
                                          "instances_done", "solves", "fused_factorizations",
-                                         "fused_solves", "refine_sweeps", "fp64_fallbacks")]
+                                         "fused_solves", "refine_sweeps", "fp64_fallbacks", "warm_started",
+                                         "warm_rejected", "warm_restarts")]
 
 
 _lib = None
@@ -177,16 +179,16 @@ class Solver:
                     status=torch.empty(n_inst, dtype=torch.int32, device=dev),
                     iters=torch.empty(n_inst, dtype=torch.int32, device=dev))
 
-    def solve(self, theta: torch.Tensor, warm_x: torch.Tensor | None = None, out: dict | None = None,
+    def solve(self, theta: torch.Tensor, warm: torch.Tensor | None = None, out: dict | None = None,
               stream=None) -> dict:
         assert theta.dtype == torch.float64 and theta.dim() == 2 and theta.shape[1] == self.dims.n_theta
         theta = theta.contiguous()
         n_inst = theta.shape[0]
-        if warm_x is not None:
-            assert warm_x.shape == (n_inst, self.dims.n) and warm_x.dtype == torch.float64
-            warm_x = warm_x.contiguous()
+        if warm is not None:
+            assert warm.shape == (n_inst, self.dims.n_w + self.dims.m) and warm.dtype == torch.float64
+            warm = warm.contiguous()
         o = out if out is not None else self.alloc_outputs(n_inst)
-        self._check(self.L.hipipm_solve(self.h, n_inst, _ptr(theta), _ptr(warm_x), _ptr(o["x"]), _ptr(o["y"]),
+        self._check(self.L.hipipm_solve(self.h, n_inst, _ptr(theta), _ptr(warm), _ptr(o["x"]), _ptr(o["y"]),
                                         _ptr(o["zl"]), _ptr(o["zu"]), _ptr(o["obj"]), _ptr(o["kkt"]),
                                         _ptr(o["status"]), _ptr(o["iters"]), _stream(stream)))
         return o

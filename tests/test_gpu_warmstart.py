@@ -1,0 +1,70 @@
+"""Learned warm start on the GPU: trained on the solver's own solutions, judged by the solver.
+The trained network must cut the iterations of held-out instances against the cold start while
+reaching the same KKT points; unusable warm points fall back to the cold start."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_26341_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def trained(torch_cuda):
+    from paper_2606_26341_amd import warmstart
+    w = W.get("C5")
+    ws, losses, n = warmstart.train_for(w, 16384, seed_tag=51, epochs=30, batch=1024)
+    say("trained on", n, "solutions; loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.2 * losses[0]
+    return w, ws
+
+
+def test_warm_start_cuts_iterations(torch_cuda, trained):
+    torch = torch_cuda
+    from paper_2606_26341_amd import hipipm
+    w, ws = trained
+    TH = torch.tensor(w.thetas(0, 2048), dtype=torch.float64, device="cuda")
+    s = hipipm.Solver(w, 2048, hipipm.default_options())
+    cold = {k: v.cpu().numpy() for k, v in s.solve(TH).items()}
+    warm_pts = ws.predict(TH)
+    s.reset_stats()
+    warm = {k: v.cpu().numpy() for k, v in s.solve(TH, warm=warm_pts).items()}
+    st = s.stats()
+    okc, okw = cold["status"] == 1, warm["status"] == 1
+    say("cold: converged", okc.mean(), "mean iters", cold["iters"].mean(),
+        "| warm: converged", okw.mean(), "mean iters", warm["iters"].mean(), "stats", st)
+    assert st["warm_started"] == 2048 and st["warm_rejected"] == 0
+    assert okw.mean() >= okc.mean() - 0.01
+    assert warm["iters"][okw].mean() < 0.8 * cold["iters"][okc].mean()
+    both = okc & okw
+    rel = np.abs(warm["obj"] - cold["obj"]) / np.maximum(1.0, np.abs(cold["obj"]))
+    same = both & (rel <= 1e-6) & (np.abs(warm["x"] - cold["x"]).max(axis=1) <= 1e-5)
+    say("same KKT point", same.sum(), "of", both.sum())
+    assert same.sum() >= 0.9 * both.sum()
+    for i in np.flatnonzero(okw)[:8]:
+        th = TH[i].cpu().numpy()
+        assert oracle.kkt_error(w, th, warm["x"][i], warm["y"][i], warm["zl"][i], warm["zu"][i]) <= 1e-8
+
+
+def test_unusable_warm_points_fall_back_to_cold(torch_cuda, trained):
+    torch = torch_cuda
+    from paper_2606_26341_amd import hipipm
+    w, ws = trained
+    TH = torch.tensor(w.thetas(5000, 64), dtype=torch.float64, device="cuda")
+    s = hipipm.Solver(w, 64, hipipm.default_options(warm_iter_cap=40))
+    cold = {k: v.cpu().numpy() for k, v in s.solve(TH).items()}
+    bad = ws.predict(TH)
+    bad[0:16, 5] = float("nan")                     # rejected at initialisation
+    bad[16:32] = bad[16:32] * 0.0 + 50.0            # far from anything: must restart cold or still converge
+    s.reset_stats()
+    out = {k: v.cpu().numpy() for k, v in s.solve(TH, warm=bad).items()}
+    st = s.stats()
+    say("stats", st, "statuses", np.bincount(out["status"]))
+    assert st["warm_rejected"] == 16
+    assert (out["status"][0:16] == cold["status"][0:16]).all()
+    assert (out["status"] == 1).mean() >= (cold["status"] == 1).mean() - 0.05
