@@ -55,6 +55,10 @@ struct hipipm_ctx {
   hipipm_stats stats;
   double t_ms[NKT];
   long long t_n[NKT];
+  // pinned copies of the device counter block, one per chunk of passes in flight, and the
+  // events that mark each copy complete (allocated at the first solve)
+  Counters* hcnt = nullptr;
+  hipEvent_t cev[2] = {nullptr, nullptr};
 };
 
 static int fail(hipipm_ctx* c, int code, const std::string& msg) {
@@ -212,11 +216,19 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   Counters* dcnt = counters(c);
   HIPCHK(c, hipMemcpyAsync(dcnt, &h, sizeof(h), hipMemcpyHostToDevice, st));
   Outs out{x_out, y_out, zl_out, zu_out, obj_out, kkt_out, status_out, iters_out};
+  if (!c->hcnt) {
+    void* p = nullptr;
+    HIPCHK(c, hipHostMalloc(&p, 2 * sizeof(Counters), hipHostMallocDefault));
+    c->hcnt = (Counters*)p;
+    for (auto& e : c->cev) HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   const int poll = c->opts.poll_every;
   const bool timing = c->opts.timing != 0;
+  // timing events: setup (2), then one set of (NPK + 1) per pass for each of the two chunks in flight
+  const int per_chunk = (NPK + 1) * poll;
   std::vector<hipEvent_t> ev;
   if (timing) {
-    ev.resize((NPK + 1) * poll + 2);
+    ev.resize(2 + 2 * per_chunk);
     for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
     HIPCHK(c, hipEventRecord(ev[0], st));
   }
@@ -233,11 +245,14 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   // every pass advances each running slot by at most one pipeline step; bound the loop
   const long long max_passes = ((long long)c->opts.max_iter + 8) * 3 * ((n_inst + active - 1) / active) + 64;
   long long passes = 0;
-  for (;;) {
-    // few unfinished instances left: fused pass kernel (every launch still covers all slots)
-    const bool fused = c->opts.precision == 1 || (c->opts.fuse_below > 0 && n_inst - h.done <= c->opts.fuse_below);
+  bool fused_of[2] = {false, false};
+  // Passes go out in chunks of `poll`; each chunk ends with an asynchronous copy of the counter
+  // block into pinned memory.  The next chunk is queued before the host waits for the previous
+  // chunk's copy, so the GPU never idles on the poll.  Passes queued after the last instance
+  // finished find every slot empty and return at once.
+  auto launch_chunk = [&](int par, bool fused) -> int {
     for (int p = 0; p < poll; ++p) {
-      hipEvent_t* e = timing ? &ev[(NPK + 1) * p] : nullptr;
+      hipEvent_t* e = timing ? &ev[2 + par * per_chunk + (NPK + 1) * p] : nullptr;
       if (timing) HIPCHK(c, hipEventRecord(e[0], st));
       launch_eval(c->cfg, c->ws, active, st);
       if (timing) HIPCHK(c, hipEventRecord(e[1], st));
@@ -256,27 +271,53 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
       }
     }
     HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&c->hcnt[par], dcnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipEventRecord(c->cev[par], st));
+    fused_of[par] = fused;
     passes += poll;
-    HIPCHK(c, hipMemcpyAsync(&h, dcnt, sizeof(h), hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    return HIPIPM_OK;
+  };
+  // wait for chunk `par`: its counters into h, its kernel times into the buckets
+  auto finish_chunk = [&](int par) -> int {
+    HIPCHK(c, hipEventSynchronize(c->cev[par]));
+    h = c->hcnt[par];
     if (timing) {
       for (int p = 0; p < poll; ++p) {
-        const hipEvent_t* e = &ev[(NPK + 1) * p];
-        const int nk = fused ? 2 : NPK;
+        const hipEvent_t* e = &ev[2 + par * per_chunk + (NPK + 1) * p];
+        const int nk = fused_of[par] ? 2 : NPK;
         for (int q = 0; q < nk; ++q) {
           float ms = 0;
           HIPCHK(c, hipEventElapsedTime(&ms, e[q], e[q + 1]));
-          const int bucket = (fused && q == 1) ? KT_FUSED : q;
+          const int bucket = (fused_of[par] && q == 1) ? KT_FUSED : q;
           c->t_ms[bucket] += ms;
           c->t_n[bucket] += 1;
         }
       }
     }
-    if (h.done >= n_inst) break;
-    if (passes > max_passes) {
-      if (timing) for (auto& e : ev) (void)hipEventDestroy(e);
-      return fail(c, HIPIPM_ERR_HIP, "solve did not finish within the pass bound");
+    return HIPIPM_OK;
+  };
+  // few unfinished instances left: fused pass kernel (every launch still covers all slots); the
+  // count seen is one chunk old
+  auto use_fused = [&]() {
+    return c->opts.precision == 1 || (c->opts.fuse_below > 0 && n_inst - h.done <= c->opts.fuse_below);
+  };
+  auto bail = [&](int rc) {
+    (void)hipStreamSynchronize(st);
+    if (timing) for (auto& e : ev) (void)hipEventDestroy(e);
+    return rc;
+  };
+  int rc = launch_chunk(0, use_fused());
+  if (rc) return bail(rc);
+  for (int cur = 0;; cur ^= 1) {
+    const int nxt = cur ^ 1;
+    const bool more = passes <= max_passes;
+    if (more && (rc = launch_chunk(nxt, use_fused()))) return bail(rc);
+    if ((rc = finish_chunk(cur))) return bail(rc);
+    if (h.done >= n_inst) {
+      if (more && (rc = finish_chunk(nxt))) return bail(rc);
+      break;
     }
+    if (!more) return bail(fail(c, HIPIPM_ERR_HIP, "solve did not finish within the pass bound"));
   }
   if (timing) for (auto& e : ev) (void)hipEventDestroy(e);
   c->stats.iterations += (int64_t)h.st[0];
@@ -544,6 +585,12 @@ int hipipm_stage_derivs(hipipm_ctx* c, int32_t count, const double* x, const dou
 
 const char* hipipm_last_error(const hipipm_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-void hipipm_destroy(hipipm_ctx* c) { delete c; }
+void hipipm_destroy(hipipm_ctx* c) {
+  if (!c) return;
+  if (c->hcnt) (void)hipHostFree(c->hcnt);
+  for (auto e : c->cev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+}
 
 }  // extern "C"

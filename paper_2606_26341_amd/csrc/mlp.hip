@@ -63,6 +63,10 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __builtin_bit_ca
 // a 32 x 32 quarter as 2 x 2 MFMA blocks of 16 x 16; K advances 16 at a time.  MFMA operand
 // layout (16x16x16): lane l holds A(i, k) and B(k, j) for i = j = l % 16 and k = 4 (l / 16) + 0..3,
 // and receives C(4 (l / 16) + 0..3, l % 16).
+// AK / BK: the operand is contiguous along k with rows aligned to 4 elements and K % 4 == 0, so a
+// lane's four k values are one 8-byte load (the network's forward products); otherwise four
+// 2-byte loads.
+template <bool AK, bool BK>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t* __restrict__ A, long long sam,
                                               long long sak, const uint16_t* __restrict__ B, long long sbk,
                                               long long sbn, float* __restrict__ C, long long ldc) {
@@ -79,19 +83,29 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int m = m0 + 16 * i + r16;
+      if constexpr (AK) {
+        const int k = k0 + kq;
+        a[i] = (m < M && k < K) ? *reinterpret_cast<const bf16x4*>(A + m * sam + k) : bf16x4{0, 0, 0, 0};
+      } else {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = k0 + kq + t;
-        a[i][t] = (m < M && k < K) ? (short)A[m * sam + k * sak] : (short)0;
+        for (int t = 0; t < 4; ++t) {
+          const int k = k0 + kq + t;
+          a[i][t] = (m < M && k < K) ? (short)A[m * sam + k * sak] : (short)0;
+        }
       }
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int n = n0 + 16 * j + r16;
+      if constexpr (BK) {
+        const int k = k0 + kq;
+        b[j] = (n < N && k < K) ? *reinterpret_cast<const bf16x4*>(B + n * sbn + k) : bf16x4{0, 0, 0, 0};
+      } else {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int k = k0 + kq + t;
-        b[j][t] = (n < N && k < K) ? (short)B[k * sbk + n * sbn] : (short)0;
+        for (int t = 0; t < 4; ++t) {
+          const int k = k0 + kq + t;
+          b[j][t] = (n < N && k < K) ? (short)B[k * sbk + n * sbn] : (short)0;
+        }
       }
     }
 #pragma unroll
@@ -110,11 +124,23 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
       }
 }
 
+static bool k_contig(const uint16_t* p, long long s_k, long long s_row, int K) {
+  return s_k == 1 && s_row % 4 == 0 && K % 4 == 0 && ((uintptr_t)p & 7) == 0;
+}
+
 static void gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, long long sam, long long sak,
                  const uint16_t* B, long long sbk, long long sbn, float* C, long long ldc) {
   if (M <= 0 || N <= 0) return;
   dim3 grid((N + 63) / 64, (M + 63) / 64);
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc);
+  const bool ak = k_contig(A, sak, sam, K), bk = k_contig(B, sbk, sbn, K);
+  if (ak && bk)
+    hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc);
+  else if (ak)
+    hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc);
+  else if (bk)
+    hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc);
+  else
+    hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc);
 }
 
 // ---------------------------------------------------------------------------- elementwise
@@ -186,13 +212,35 @@ __global__ void k_gelu_back(int B, int n, const float* __restrict__ da, const fl
   dz[q] = to_bf16(da[q] * gelu_d(z[q]));
 }
 
-// bias gradient: column sums of dz (one thread per column)
-__global__ void k_colsum(int B, int n, const uint16_t* __restrict__ dz, float* __restrict__ g) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= n) return;
+// bias gradient: column sums of dz.  A workgroup owns 64 columns (lane = column, so each row is
+// one coalesced read per wavefront); its CS_WAVES wavefronts take every CS_WAVES-th row and their
+// partial sums are added in wavefront order (deterministic).
+constexpr int CS_WAVES = 8;
+__global__ __launch_bounds__(CS_WAVES * 64) void k_colsum(int B, int n, const uint16_t* __restrict__ dz,
+                                                         float* __restrict__ g) {
+  __shared__ float part[CS_WAVES][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int r = 0; r < B; ++r) s += from_bf16(dz[(long long)r * n + col]);
-  g[col] = s;
+  if (col < n) {
+    // eight independent loads in flight per lane, summed in row order
+    int r = wv;
+    for (; r + 7 * CS_WAVES < B; r += 8 * CS_WAVES) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = from_bf16(dz[(long long)(r + u * CS_WAVES) * n + col]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; r < B; r += CS_WAVES) s += from_bf16(dz[(long long)r * n + col]);
+  }
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && col < n) {
+    float t = 0.f;
+    for (int w = 0; w < CS_WAVES; ++w) t += part[w][lane];
+    g[col] = t;
+  }
 }
 
 // Adam on the parameters (FP32 master), then the BF16 copy of the weights
@@ -212,21 +260,44 @@ __global__ void k_to_bf16(long long n, const float* __restrict__ src, uint16_t* 
   if (q < n) dst[q] = to_bf16(src[q]);
 }
 
-// column mean and standard deviation (floored at 1e-6) of an FP64 [rows][cols] array
-__global__ void k_colstats(long long rows, int cols, const double* __restrict__ x, float* __restrict__ mu,
-                           float* __restrict__ sd) {
-  const int col = blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= cols) return;
+// column mean and standard deviation (floored at 1e-6) of an FP64 [rows][cols] array; the same
+// column-tile layout as k_colsum with CT_WAVES wavefronts over the rows, FP64 sums
+constexpr int CT_WAVES = 16;
+__global__ __launch_bounds__(CT_WAVES * 64) void k_colstats(long long rows, int cols, const double* __restrict__ x,
+                                                           float* __restrict__ mu, float* __restrict__ sd) {
+  __shared__ double p1[CT_WAVES][64], p2[CT_WAVES][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
   double s = 0.0, s2 = 0.0;
-  for (long long r = 0; r < rows; ++r) {
-    const double v = x[r * cols + col];
-    s += v;
-    s2 += v * v;
+  if (col < cols) {
+    long long r = wv;
+    for (; r + 7 * CT_WAVES < rows; r += 8 * CT_WAVES) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = x[(r + u * CT_WAVES) * cols + col];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s += v[u];
+        s2 += v[u] * v[u];
+      }
+    }
+    for (; r < rows; r += CT_WAVES) {
+      const double v = x[r * cols + col];
+      s += v;
+      s2 += v * v;
+    }
   }
-  const double m = s / (double)rows;
-  const double var = s2 / (double)rows - m * m;
-  mu[col] = (float)m;
-  sd[col] = (float)fmax(sqrt(fmax(var, 0.0)), 1e-6);
+  p1[wv][lane] = s;
+  p2[wv][lane] = s2;
+  __syncthreads();
+  if (wv == 0 && col < cols) {
+    double t = 0.0, t2 = 0.0;
+    for (int w = 0; w < CT_WAVES; ++w) { t += p1[w][lane]; t2 += p2[w][lane]; }
+    const double m = t / (double)rows;
+    const double var = t2 / (double)rows - m * m;
+    mu[col] = (float)m;
+    sd[col] = (float)fmax(sqrt(fmax(var, 0.0)), 1e-6);
+  }
 }
 
 static inline unsigned blocks(long long n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -300,7 +371,7 @@ static void backward(hipStream_t st, const Dims& d, const float* model, const ui
     const uint16_t* ain = (l == 0) ? a.xb : a.a[l - 1];
     // dW_l[o][i] = sum_b dz[b][o] ain[b][i];  db_l = column sums of dz
     gemm(st, nout, nin, B, dz, 1, nout, ain, nin, 1, grad + d.w[l], nin);
-    hipLaunchKernelGGL(k_colsum, dim3(blocks(nout, 256)), dim3(256), 0, st, B, nout, dz, grad + d.b[l]);
+    hipLaunchKernelGGL(k_colsum, dim3(blocks(nout, 64)), dim3(CS_WAVES * 64), 0, st, B, nout, dz, grad + d.b[l]);
     if (l == 0) break;
     // da[b][i] = sum_o dz[b][o] W_l[o][i], then dz_{l-1} = da * GELU'(z_{l-1})
     gemm(st, B, nin, nout, dz, nout, 1, wb + d.wb[l], nin, 1, a.da, nin);
@@ -350,9 +421,9 @@ int hipipm_mlp_normalizer(int32_t d_in, int32_t hidden, int32_t d_out, int64_t r
   if (!dims_ok(d_in, hidden, d_out) || rows <= 0 || !inputs || !targets || !model) return -1;
   const Dims d = dims_of(d_in, hidden, d_out);
   hipStream_t st = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_colstats, dim3(blocks(d.din, 64)), dim3(64), 0, st, (long long)rows, d.din, inputs,
+  hipLaunchKernelGGL(k_colstats, dim3(blocks(d.din, 64)), dim3(CT_WAVES * 64), 0, st, (long long)rows, d.din, inputs,
                      model + d.in_mu, model + d.in_sd);
-  hipLaunchKernelGGL(k_colstats, dim3(blocks(d.dout, 64)), dim3(64), 0, st, (long long)rows, d.dout, targets,
+  hipLaunchKernelGGL(k_colstats, dim3(blocks(d.dout, 64)), dim3(CT_WAVES * 64), 0, st, (long long)rows, d.dout, targets,
                      model + d.out_mu, model + d.out_sd);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }

@@ -77,3 +77,25 @@ def test_training_fits_a_teacher_network(torch_cuda):
     losses = net.train(X, T, epochs=30, batch=512, lr=2e-3, lr_final=2e-4, seed=1)
     print("losses", losses, flush=True)
     assert losses[-1] < 0.25 * losses[0] and all(b < a * 1.05 for a, b in zip(losses, losses[1:]))
+
+
+def test_normalizer_matches_column_statistics(torch_cuda):
+    """Column means and standard deviations of the training arrays (ragged column counts, a
+    constant column floored at 1e-6) against numpy."""
+    torch = torch_cuda
+    from paper_2606_26341_amd.mlp import Mlp
+    rng = np.random.default_rng(12)
+    rows, d_in, d_out = 10007, 28, 71
+    x = rng.normal(3.0, 2.0, size=(rows, d_in))
+    t = rng.uniform(-5, 5, size=(rows, d_out))
+    x[:, 4] = 1.25
+    net = Mlp(d_in, d_out, hidden=32, max_batch=64)
+    net.set_normalizer(torch.tensor(x, dtype=torch.float64, device="cuda"),
+                       torch.tensor(t, dtype=torch.float64, device="cuda"))
+    model = net.model.cpu().numpy().astype(np.float64)
+    _, _, in_mu, in_sd, out_mu, out_sd = M.unpack(model, d_in, 32, d_out)
+    sd_x = np.maximum(x.std(axis=0), 1e-6)
+    assert np.allclose(in_mu, x.mean(axis=0), rtol=1e-6, atol=1e-6)
+    assert np.allclose(in_sd, sd_x, rtol=1e-5, atol=1e-7) and in_sd[4] == np.float32(1e-6)
+    assert np.allclose(out_mu, t.mean(axis=0), rtol=1e-6, atol=1e-6)
+    assert np.allclose(out_sd, t.std(axis=0), rtol=1e-5)

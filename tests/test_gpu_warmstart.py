@@ -68,3 +68,23 @@ def test_unusable_warm_points_fall_back_to_cold(torch_cuda, trained):
     assert st["warm_rejected"] == 16
     assert (out["status"][0:16] == cold["status"][0:16]).all()
     assert (out["status"] == 1).mean() >= (cold["status"] == 1).mean() - 0.05
+
+
+def test_warm_start_at_the_oracle_solution_converges_at_once(torch_cuda):
+    """Special case: started from the oracle's own converged (w, y) with a barrier parameter of 1e-6
+    the method is already at the solution up to the barrier term; it must finish within three
+    iterations at the oracle's KKT point."""
+    torch = torch_cuda
+    from paper_2606_26341_amd import hipipm
+    w = W.get("C1")
+    th = w.thetas(0, w.n_inst)
+    o = oracle.solve_quad(w, th, threads=8)
+    assert (o["status"] == oracle.ST_CONVERGED).all()
+    TH = torch.tensor(th, dtype=torch.float64, device="cuda")
+    warm = torch.tensor(np.concatenate([o["x"][:, :w.n_w], o["y"]], axis=1), dtype=torch.float64, device="cuda")
+    s = hipipm.Solver(w, w.n_inst, hipipm.default_options(warm_mu0=1e-6))
+    out = {k: v.cpu().numpy() for k, v in s.solve(TH, warm=warm).items()}
+    say("iterations", np.bincount(out["iters"]), "stats", s.stats())
+    assert (out["status"] == 1).all() and out["iters"].max() <= 3
+    rel = np.abs(out["obj"] - o["obj"]) / np.maximum(1.0, np.abs(o["obj"]))
+    assert rel.max() <= 1e-6 and np.abs(out["x"] - o["x"]).max() <= 1e-5 and out["kkt"].max() <= 1e-8
