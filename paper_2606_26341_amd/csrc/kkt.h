@@ -297,6 +297,14 @@ __device__ __forceinline__ float lane_bcast(float v, int src) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
 }
 
+// FP64 matrix-core product D = A B + C on 16 x 16 tiles with K = 4 (v_mfma_f64_16x16x4f64), one
+// call per wavefront.  Lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16) and holds
+// D(4 r + l / 16, l % 16) in item r.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // In-register Cholesky of an NX x NX SPD candidate held one row per lane (lane i < NX holds
 // c[l] = A_il; the lower part is used).  Right-looking, column j broadcast from lane j.  On
 // success row `lane` of L is in c (lower part) and rinv[j] = 1 / L_jj on every lane.  Returns 0,
@@ -361,7 +369,31 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     T* fr = reinterpret_cast<T*>(s.fac) + (long long)k * FR_LEN;
     if (k > 0) stage_prefetch(c, s, k - 1, lane, reg);   // in flight during this stage
     // ---- Schur update, first half: T = S_{k+1} G_k (13 x 17) ----
-    if (k < N) {
+    // FP64: on the matrix cores, K = 13 padded to 16, columns 0..15 and 16 (a second tile)
+    const int r16 = lane & 15, kq = lane >> 4;
+    if constexpr (sizeof(T) == sizeof(double)) {
+      if (k < N) {
+        dbl4 t0 = {0.0, 0.0, 0.0, 0.0}, t1 = t0;
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
+          const double sv = L.S[(r16 < NX ? r16 : 0) * NX + kc];
+          const double g0 = Gk[kc * NZ + r16], g1 = Gk[kc * NZ + 16];
+          const double a = (kk < NX && r16 < NX) ? sv : 0.0;
+          t0 = mfma64(a, kk < NX ? g0 : 0.0, t0);
+          t1 = mfma64(a, (kk < NX && r16 == 0) ? g1 : 0.0, t1);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * r + kq;
+          if (i < NX) {
+            L.CV[i * NZ + r16] = t0[r];
+            if (r16 == 0) L.CV[i * NZ + 16] = t1[r];
+          }
+        }
+        lds_barrier();
+      }
+    } else if (k < N) {
 #pragma unroll
       for (int t = 0; t < TILE_T; ++t) {
         const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
@@ -373,19 +405,59 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       lds_barrier();
     }
     // ---- stage Hessian (NZ stride): W_k + diag + delta_x I + Hc_k + G_k^T T ----
+    auto h_base = [&](int i, int j) -> T {
+      T h = (!e.lsq && k < N) ? Wk[i * NZ + j] : T(0);
+      h += (i == j && (k < N || i < NX)) ? SD[j] + dx : T(0);
+      h += (k >= 1 && i < 3 && j < 3) ? SD[SD_HC + 3 * (i < 3 ? i : 0) + (j < 3 ? j : 0)] : T(0);
+      return h;
+    };
+    if constexpr (sizeof(T) == sizeof(double)) {
+      // tiles (0,0), (0,1) and (1,1) of the symmetric 17 x 17 result on the matrix cores; row 16
+      // is written from column 16
+      dbl4 h00, h01, h11;
 #pragma unroll
-    for (int t = 0; t < TILE_H; ++t) {
-      const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
-      T h = (!e.lsq && k < N) ? Wk[q] : 0.0;
-      h += (i == j && (k < N || i < NX)) ? SD[j] + dx : 0.0;
-      h += (k >= 1 && i < 3 && j < 3) ? SD[SD_HC + 3 * (i < 3 ? i : 0) + j] : 0.0;
-      if (k < N) {
-        T acc = 0.0;
-#pragma unroll
-        for (int l = 0; l < NX; ++l) acc += Gk[l * NZ + i] * L.CV[l * NZ + j];
-        h += acc;
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + kq;
+        h00[r] = h_base(i, r16);
+        h01[r] = h_base(i, 16);
+        h11[r] = h_base(16, 16);
       }
-      L.H[q] = h;
+      if (k < N) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
+          const double g0 = Gk[kc * NZ + r16], g1 = Gk[kc * NZ + 16];
+          const double c0 = L.CV[kc * NZ + r16], c1 = L.CV[kc * NZ + 16];
+          const double a0 = kk < NX ? g0 : 0.0, a1 = (kk < NX && r16 == 0) ? g1 : 0.0;
+          const double b0 = kk < NX ? c0 : 0.0, b1 = (kk < NX && r16 == 0) ? c1 : 0.0;
+          h00 = mfma64(a0, b0, h00);
+          h01 = mfma64(a0, b1, h01);
+          h11 = mfma64(a1, b1, h11);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + kq;
+        L.H[i * NZ + r16] = h00[r];
+        if (r16 == 0) {
+          L.H[i * NZ + 16] = h01[r];
+          L.H[16 * NZ + i] = h01[r];
+        }
+      }
+      if (lane == 0) L.H[16 * NZ + 16] = h11[0];
+    } else {
+#pragma unroll
+      for (int t = 0; t < TILE_H; ++t) {
+        const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
+        T h = (q < NZ * NZ) ? h_base(i, j) : T(0);
+        if (k < N) {
+          T acc = 0.0;
+#pragma unroll
+          for (int l = 0; l < NX; ++l) acc += Gk[l * NZ + i] * L.CV[l * NZ + j];
+          h += acc;
+        }
+        L.H[q] = h;
+      }
     }
     lds_barrier();
     // ---- control block: Cholesky of Hbar^uu (on every lane, in registers), Y, P ----
@@ -433,13 +505,32 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         }
       }
       lds_barrier();
+      if constexpr (sizeof(T) == sizeof(double)) {
+        // P = H_xx - Y^T Y: one matrix-core product with K = NU
+        const double yv = L.Y[kq * NX + (r16 < NX ? r16 : 0)];
+        const double y = r16 < NX ? yv : 0.0;
+        dbl4 p;
 #pragma unroll
-      for (int t = 0; t < TILE_P; ++t) {
-        const int q = lane + WAVE * t, i = q / NX, j = q % NX;
-        T acc = L.H[i * NZ + j];
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * r + kq;
+          const double hv = L.H[(i < NX ? i : 0) * NZ + (r16 < NX ? r16 : 0)];
+          p[r] = (i < NX && r16 < NX) ? hv : 0.0;
+        }
+        p = mfma64(-y, y, p);
 #pragma unroll
-        for (int a = 0; a < NU; ++a) acc -= L.Y[a * NX + i] * L.Y[a * NX + j];
-        L.P[q] = acc;
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * r + kq;
+          if (i < NX && r16 < NX) L.P[i * NX + r16] = p[r];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < TILE_P; ++t) {
+          const int q = lane + WAVE * t, i = q / NX, j = q % NX;
+          T acc = L.H[i * NZ + j];
+#pragma unroll
+          for (int a = 0; a < NU; ++a) acc -= L.Y[a * NX + i] * L.Y[a * NX + j];
+          L.P[q] = acc;
+        }
       }
     } else {
 #pragma unroll
