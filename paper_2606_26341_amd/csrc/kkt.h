@@ -369,28 +369,30 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     T* fr = reinterpret_cast<T*>(s.fac) + (long long)k * FR_LEN;
     if (k > 0) stage_prefetch(c, s, k - 1, lane, reg);   // in flight during this stage
     // ---- Schur update, first half: T = S_{k+1} G_k (13 x 17) ----
-    // FP64: on the matrix cores, K = 13 padded to 16, columns 0..15 and 16 (a second tile)
-    const int r16 = lane & 15, kq = lane >> 4;
+    // FP64: columns 0..15 on the matrix cores (K = 13 padded to 16; one 16 x 16 x 4 product costs
+    // about as much as eleven FP64 FMAs of a wavefront), column 16 on the vector ALUs, row i on
+    // lane i
+    const int r16 = lane & 15, kq = lane >> 4, li0 = lane < NX ? lane : NX - 1;
     if constexpr (sizeof(T) == sizeof(double)) {
       if (k < N) {
-        dbl4 t0 = {0.0, 0.0, 0.0, 0.0}, t1 = t0;
+        dbl4 t0 = {0.0, 0.0, 0.0, 0.0};
+        double t16 = 0.0;
+#pragma unroll
+        for (int l = 0; l < NX; ++l) t16 += L.S[li0 * NX + l] * Gk[l * NZ + 16];
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
           const double sv = L.S[(r16 < NX ? r16 : 0) * NX + kc];
-          const double g0 = Gk[kc * NZ + r16], g1 = Gk[kc * NZ + 16];
+          const double g0 = Gk[kc * NZ + r16];
           const double a = (kk < NX && r16 < NX) ? sv : 0.0;
           t0 = mfma64(a, kk < NX ? g0 : 0.0, t0);
-          t1 = mfma64(a, (kk < NX && r16 == 0) ? g1 : 0.0, t1);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 4 * r + kq;
-          if (i < NX) {
-            L.CV[i * NZ + r16] = t0[r];
-            if (r16 == 0) L.CV[i * NZ + 16] = t1[r];
-          }
+          if (i < NX) L.CV[i * NZ + r16] = t0[r];
         }
+        if (lane < NX) L.CV[lane * NZ + 16] = t16;
         lds_barrier();
       }
     } else if (k < N) {
@@ -412,39 +414,30 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       return h;
     };
     if constexpr (sizeof(T) == sizeof(double)) {
-      // tiles (0,0), (0,1) and (1,1) of the symmetric 17 x 17 result on the matrix cores; row 16
-      // is written from column 16
-      dbl4 h00, h01, h11;
+      // the leading 16 x 16 tile of the symmetric 17 x 17 result on the matrix cores (the
+      // additive terms as the accumulator's start); column 16 on the vector ALUs, entry i on
+      // lane i, also written as row 16
+      dbl4 h00;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 4 * r + kq;
-        h00[r] = h_base(i, r16);
-        h01[r] = h_base(i, 16);
-        h11[r] = h_base(16, 16);
-      }
+      for (int r = 0; r < 4; ++r) h00[r] = h_base(4 * r + kq, r16);
+      const int ih = lane < NZ ? lane : NZ - 1;
+      double h16 = h_base(ih, 16);
       if (k < N) {
+#pragma unroll
+        for (int l = 0; l < NX; ++l) h16 += Gk[l * NZ + ih] * L.CV[l * NZ + 16];
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
-          const double g0 = Gk[kc * NZ + r16], g1 = Gk[kc * NZ + 16];
-          const double c0 = L.CV[kc * NZ + r16], c1 = L.CV[kc * NZ + 16];
-          const double a0 = kk < NX ? g0 : 0.0, a1 = (kk < NX && r16 == 0) ? g1 : 0.0;
-          const double b0 = kk < NX ? c0 : 0.0, b1 = (kk < NX && r16 == 0) ? c1 : 0.0;
-          h00 = mfma64(a0, b0, h00);
-          h01 = mfma64(a0, b1, h01);
-          h11 = mfma64(a1, b1, h11);
+          const double g0 = Gk[kc * NZ + r16], c0 = L.CV[kc * NZ + r16];
+          h00 = mfma64(kk < NX ? g0 : 0.0, kk < NX ? c0 : 0.0, h00);
         }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 4 * r + kq;
-        L.H[i * NZ + r16] = h00[r];
-        if (r16 == 0) {
-          L.H[i * NZ + 16] = h01[r];
-          L.H[16 * NZ + i] = h01[r];
-        }
+      for (int r = 0; r < 4; ++r) L.H[(4 * r + kq) * NZ + r16] = h00[r];
+      if (lane < NZ) {
+        L.H[lane * NZ + 16] = h16;
+        L.H[16 * NZ + lane] = h16;
       }
-      if (lane == 0) L.H[16 * NZ + 16] = h11[0];
     } else {
 #pragma unroll
       for (int t = 0; t < TILE_H; ++t) {
@@ -578,18 +571,47 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       }
       lds_barrier();
       // S = P - V^T V and M = Delta^{-1/2} C^{-1} Delta^{1/2}, C^{-1} = L_C^{-T} L_C^{-1}
+      if constexpr (sizeof(T) == sizeof(double)) {
+        // both Gram products on the matrix cores (K = 13 padded to 16)
+        const int jc = r16 < NX ? r16 : 0;
+        dbl4 sa, ma = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int t = 0; t < TILE_P; ++t) {
-        const int q = lane + WAVE * t, i = q / NX, j = q % NX;
-        T acc = L.P[q];
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * r + kq;
+          const double pv = L.P[(i < NX ? i : 0) * NX + jc];
+          sa[r] = (i < NX && r16 < NX) ? pv : 0.0;
+        }
 #pragma unroll
-        for (int l = 0; l < NX; ++l) acc -= VV[l * NX + i] * VV[l * NX + j];
-        L.S[q] = acc;
-        const int qi = q < NX * NX ? i : 0;
-        T ci = 0.0;
+        for (int st = 0; st < 4; ++st) {
+          const int l = 4 * st + kq, lc = l < NX ? l : 0;
+          const bool ok = l < NX && r16 < NX;
+          const double vv = VV[lc * NX + jc], li = L.LI[lc * NX + jc];
+          const double v = ok ? vv : 0.0, w = ok ? li : 0.0;
+          sa = mfma64(-v, v, sa);
+          ma = mfma64(w, w, ma);
+        }
 #pragma unroll
-        for (int l = 0; l < NX; ++l) ci += L.LI[l * NX + qi] * L.LI[l * NX + j];
-        if (q < NX * NX) fr[FR_M + q] = ci * L.dh[j] * L.rdh[qi];
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * r + kq;
+          if (i < NX && r16 < NX) {
+            L.S[i * NX + r16] = sa[r];
+            fr[FR_M + i * NX + r16] = ma[r] * L.dh[r16] * L.rdh[i];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < TILE_P; ++t) {
+          const int q = lane + WAVE * t, i = q / NX, j = q % NX;
+          T acc = L.P[q];
+#pragma unroll
+          for (int l = 0; l < NX; ++l) acc -= VV[l * NX + i] * VV[l * NX + j];
+          L.S[q] = acc;
+          const int qi = q < NX * NX ? i : 0;
+          T ci = 0.0;
+#pragma unroll
+          for (int l = 0; l < NX; ++l) ci += L.LI[l * NX + qi] * L.LI[l * NX + j];
+          if (q < NX * NX) fr[FR_M + q] = ci * L.dh[j] * L.rdh[qi];
+        }
       }
     } else {
 #pragma unroll
