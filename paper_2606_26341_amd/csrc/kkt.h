@@ -297,6 +297,29 @@ __device__ __forceinline__ float lane_bcast(float v, int src) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
 }
 
+// value of x on the lane chosen by the DPP pattern CTRL (within rows of 16 lanes)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+// sum over each row of 16 lanes, the same bits on every lane of the row: partners lane ^ 1,
+// lane ^ 2 (quad permutations), then the mirrored lane within 8 and within 16
+template <typename T>
+__device__ __forceinline__ T row16_sum(T x) {
+  x += dpp_mov<0xB1>(x);
+  x += dpp_mov<0x4E>(x);
+  x += dpp_mov<0x141>(x);
+  x += dpp_mov<0x140>(x);
+  return x;
+}
+
 // FP64 matrix-core product D = A B + C on 16 x 16 tiles with K = 4 (v_mfma_f64_16x16x4f64), one
 // call per wavefront.  Lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16) and holds
 // D(4 r + l / 16, l % 16) in item r.
@@ -680,14 +703,13 @@ __device__ __forceinline__ T stage_apply(const T* F, bool has_u, const T (&ra)[N
     if (has_u) {
       if (lane < NX) V.tmp[lane] = b;
       lds_barrier();
+      // (Y b)_a: lane 16 a + i forms Y_ai b_i, each row of 16 lanes sums its four products
+      const int i16 = lane & 15, ic = i16 < NX ? i16 : 0;
+      const T yv = F[FR_Y + (lane >> 4) * NX + ic], tv = V.tmp[ic];
+      const T yb = row16_sum(i16 < NX ? T(yv * tv) : T(0));
       T c2[NU];
 #pragma unroll
-      for (int a2 = 0; a2 < NU; ++a2) {
-        T acc = wu[a2];
-#pragma unroll
-        for (int i = 0; i < NX; ++i) acc -= F[FR_Y + a2 * NX + i] * V.tmp[i];
-        c2[a2] = acc;
-      }
+      for (int a2 = 0; a2 < NU; ++a2) c2[a2] = wu[a2] - lane_bcast(yb, 16 * a2);
 #pragma unroll
       for (int a2 = NU - 1; a2 >= 0; --a2) {
         T acc = c2[a2];
