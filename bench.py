@@ -36,7 +36,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM traffic per launch of the dominant kernel, from the two rocprofv3 --pmc runs (FETCH_SIZE,
 # WRITE_SIZE) scaled by the same counters on a plain device copy of known size; valid only for
 # the kernel sources they were taken on (hash below) and the default C2 run.
-MEASURED_TRAFFIC = {"k_iter": {"csrc": "d32e8a60abe947a4", "workload": "C2", "bytes_per_launch": 1.7642e8}}
+MEASURED_TRAFFIC = {"k_iter": {"csrc": "b3ef696db9886753", "workload": "C2", "bytes_per_launch": 1.7571e8}}
 
 
 def csrc_hash() -> str:
@@ -103,7 +103,7 @@ def kernel_roofline(w, st, kt, slots_launched, rec_bytes=8.0):
 
 
 # oracle sample sizes sized to about 10-30 s of host work (dense FP64 factorizations grow with N^3)
-CPU_SAMPLE = {"C1": 64, "C2": 96, "C4": 32, "C5": 16384}
+CPU_SAMPLE = {"C1": 64, "C2": 48, "C4": 32, "C5": 16384}
 
 
 def cpu_baseline(w, sample: int):
