@@ -123,8 +123,8 @@ def cpu_baseline(w, sample: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--slots", type=int, default=0, help="concurrent slots (default: all instances)")
     ap.add_argument("--instances", type=int, default=0)
