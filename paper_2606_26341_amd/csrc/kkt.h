@@ -76,20 +76,57 @@ __device__ __forceinline__ Iter cur_iter(const Slot& s, bool resto) {
 }
 
 // ----------------------------------------------------------------------------- wave reductions
+// value of v on lane src (src uniform), delivered to every lane through the scalar unit
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, src);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ float lane_bcast(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+
+// value of x on the lane chosen by the DPP pattern CTRL (within rows of 16 lanes)
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+// reduction over each row of 16 lanes with a commutative op, the same bits on every lane of the
+// row: partners lane ^ 1, lane ^ 2 (quad permutations), then the mirrored lane within 8 and 16
+template <typename T, typename Op>
+__device__ __forceinline__ T row16_reduce(T x, Op op) {
+  x = op(x, dpp_mov<0xB1>(x));
+  x = op(x, dpp_mov<0x4E>(x));
+  x = op(x, dpp_mov<0x141>(x));
+  x = op(x, dpp_mov<0x140>(x));
+  return x;
+}
+template <typename T>
+__device__ __forceinline__ T row16_sum(T x) {
+  return row16_reduce(x, [](T a, T b) { return a + b; });
+}
+// whole-wavefront reductions (every lane active): rows by DPP, the four row results combined in a
+// fixed order from the scalar unit, so every lane returns the same bits
+
 __device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  v = row16_sum(v);
+  return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
 }
 __device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
+  v = row16_reduce(v, [](double a, double b) { return fmax(a, b); });
+  return fmax(fmax(lane_bcast(v, 0), lane_bcast(v, 16)), fmax(lane_bcast(v, 32), lane_bcast(v, 48)));
 }
 __device__ __forceinline__ double wmin(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  return v;
+  v = row16_reduce(v, [](double a, double b) { return fmin(a, b); });
+  return fmin(fmin(lane_bcast(v, 0), lane_bcast(v, 16)), fmin(lane_bcast(v, 32), lane_bcast(v, 48)));
 }
 __device__ __forceinline__ int wor(int v) {
 #pragma unroll
@@ -286,39 +323,6 @@ __device__ __forceinline__ float rcp_nr(float x) {
   return fmaf(fmaf(-x, y, 1.0f), y, y);
 }
 
-// value of v on lane src (src uniform), delivered to every lane through the scalar unit
-__device__ __forceinline__ double lane_bcast(double v, int src) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, src);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-__device__ __forceinline__ float lane_bcast(float v, int src) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
-}
-
-// value of x on the lane chosen by the DPP pattern CTRL (within rows of 16 lanes)
-template <int CTRL>
-__device__ __forceinline__ double dpp_mov(double x) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
-  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_mov(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
-}
-// sum over each row of 16 lanes, the same bits on every lane of the row: partners lane ^ 1,
-// lane ^ 2 (quad permutations), then the mirrored lane within 8 and within 16
-template <typename T>
-__device__ __forceinline__ T row16_sum(T x) {
-  x += dpp_mov<0xB1>(x);
-  x += dpp_mov<0x4E>(x);
-  x += dpp_mov<0x141>(x);
-  x += dpp_mov<0x140>(x);
-  return x;
-}
 
 // FP64 matrix-core product D = A B + C on 16 x 16 tiles with K = 4 (v_mfma_f64_16x16x4f64), one
 // call per wavefront.  Lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16) and holds
