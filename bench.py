@@ -36,7 +36,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM traffic per launch of the dominant kernel, from the two rocprofv3 --pmc runs (FETCH_SIZE,
 # WRITE_SIZE) scaled by the same counters on a plain device copy of known size; valid only for
 # the kernel sources they were taken on (hash below) and the default C2 run.
-MEASURED_TRAFFIC = {"k_iter": {"csrc": "b3ef696db9886753", "workload": "C2", "bytes_per_launch": 1.7571e8}}
+MEASURED_TRAFFIC = {"k_iter": {"csrc": "06d33ab38a25685b", "workload": "C2", "bytes_per_launch": 1.7565e8}}
 
 
 def csrc_hash() -> str:
