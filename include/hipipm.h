@@ -151,7 +151,14 @@ int hipipm_bind_workspace(hipipm_ctx* ctx, void* dev_ptr, size_t bytes);
  *             (bound multipliers, zero on unbounded components)
  *   obj_out, kkt_out : device, [n_inst] objective and scaled KKT error E_0 at the result
  *   status_out, iters_out : device, [n_inst] int32
- * Output pointers may be NULL to skip that output (theta may not). */
+ * Output pointers may be NULL to skip that output (theta may not).
+ * The call returns when every instance has finished (it waits on `stream` for the completion
+ * counter, which it polls every options.poll_every passes; one chunk of passes over empty slots
+ * may still be queued and is finished before the return).  One context runs one solve at a time:
+ * its workspace and its pinned counter copies (allocated at the first solve, freed by
+ * hipipm_destroy) are shared by all its calls.  Errors: HIPIPM_ERR_INVALID_ARG (NULL context or
+ * theta, n_inst < 0), HIPIPM_ERR_WORKSPACE (no workspace bound), HIPIPM_ERR_HIP (a HIP call
+ * failed, or the solve exceeded its pass bound; the stream is synchronised first). */
 int hipipm_solve(hipipm_ctx* ctx, int32_t n_inst, const double* theta, const double* warm, double* x_out,
                  double* y_out, double* zl_out, double* zu_out, double* obj_out, double* kkt_out,
                  int32_t* status_out, int32_t* iters_out, void* stream);
