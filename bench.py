@@ -142,7 +142,7 @@ def main():
                     help="unfinished-instance count below which passes use the fused kernel (default: library's)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported (instances are "
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus above 1 is not supported (instances are "
                                    "independent and would shard across GPUs with no exchange)"}))
         sys.exit(2)
 
