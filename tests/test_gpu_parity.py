@@ -256,6 +256,21 @@ def test_batching_is_invariant_to_slot_count(torch_cuda):
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_results_do_not_depend_on_the_poll_period(torch_cuda):
+    """Completion polling is pipelined (the next chunk of passes is queued before the counters of
+    the previous one are read, so empty passes may run after the last result): the poll period,
+    with refill and with the per-phase kernels, must not change a single bit of the results."""
+    w = W.get("C1")
+    TH = w.thetas(200, 20)
+    ref, _ = _gpu_solve(w, TH, slots=6)
+    for opts in (dict(poll_every=1), dict(poll_every=7), dict(poll_every=3, fuse_below=0)):
+        g, st = _gpu_solve(w, TH, slots=6, **opts)
+        say(opts, "passes", st["passes"], "instances", st["instances_done"])
+        assert st["instances_done"] == 20
+        for k in ("x", "y", "zl", "zu", "obj", "kkt", "status", "iters"):
+            assert np.array_equal(ref[k], g[k]), (opts, k)
+
+
 def test_edge_cases(torch_cuda):
     torch = torch_cuda
     from paper_2606_26341_amd import hipipm
