@@ -19,7 +19,8 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = ["bk.c", "quad.c", "ipm.c"]
 
 PH_INIT_Y, PH_REGULAR, PH_RESTO, PH_DONE = 0, 1, 2, 3
-ST_RUNNING, ST_CONVERGED, ST_MAX_ITER, ST_RESTO_FAILED, ST_INFEASIBLE, ST_NUMERICAL, ST_FILTER_OVERFLOW = range(7)
+ST_RUNNING, ST_CONVERGED, ST_MAX_ITER, ST_RESTO_FAILED, ST_INFEASIBLE, ST_NUMERICAL = range(6)
+NSTAT = 11   # per-instance counters of solve_quad (see ipmo_solve_quad)
 
 
 def build() -> str:
@@ -41,7 +42,8 @@ class Opts(C.Structure):
         ("s_theta", C.c_double), ("s_phi", C.c_double), ("eta_phi", C.c_double), ("gamma_alpha", C.c_double),
         ("max_soc", C.c_int32), ("kappa_soc", C.c_double), ("kappa_sigma", C.c_double),
         ("rho_resto", C.c_double), ("kappa_resto", C.c_double), ("bound_mult_reset", C.c_double),
-        ("filter_cap", C.c_int32),
+        ("warm_mu0", C.c_double), ("warm_push", C.c_double), ("warm_iter_cap", C.c_int32),
+        ("warm_gate", C.c_int32),
     ]
 
 
@@ -92,6 +94,18 @@ def lib():
         L.ipmo_quad_kkt_error.argtypes = [C.c_void_p, C.c_void_p, _DP, _DP, _DP, _DP, _DP, C.c_double]
         L.ipmo_quad_kkt_error.restype = C.c_double
         L.ipmo_quad_eval.argtypes = [C.c_void_p, _DP, _DP, _DP, C.c_double, _DP, _DP, _DP, _DP, _DP]
+        L.ipmo_ftb_primal.argtypes = [C.c_int, _DP, _DP, _DP, _DP, C.c_double]
+        L.ipmo_ftb_primal.restype = C.c_double
+        L.ipmo_ftb_dual.argtypes = [C.c_int, _DP, _DP, _DP, _DP, _DP, _DP, C.c_double]
+        L.ipmo_ftb_dual.restype = C.c_double
+        L.ipmo_acceptable.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, _DP, _DP, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _IP]
+        L.ipmo_alpha_min.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
+        L.ipmo_alpha_min.restype = C.c_double
+        L.ipmo_handle_kkt_error.argtypes = [C.c_void_p, C.c_double]
+        L.ipmo_handle_kkt_error.restype = C.c_double
+        L.ipmo_last_soc.argtypes = [C.c_void_p, _DP, _DP, _DP]
+        L.ipmo_last_soc.restype = C.c_int
         assert L.ipmo_sizeof_opts() == C.sizeof(Opts)
         assert L.ipmo_sizeof_desc() == C.sizeof(QuadDesc)
         _lib = L
@@ -216,19 +230,51 @@ def kkt_error(w, theta, x, y, zl, zu, mu=0.0, opts=None):
 
 
 # ----------------------------------------------------------------------------- solves
-def solve_quad(w, thetas: np.ndarray, threads: int = 1, warm_x=None, opts=None) -> dict:
+def solve_quad(w, thetas: np.ndarray, threads: int = 1, warm=None, opts=None) -> dict:
+    """Solve the instances `thetas` of workload w; cold start, or warm from the rows of `warm`
+    ([k][n_w + m] = primal w without slacks, then the equality multipliers y)."""
     thetas = np.ascontiguousarray(thetas, np.float64)
     k = thetas.shape[0]
     d = desc_from(w)
     o = opts or default_opts()
     out = dict(x=np.zeros((k, w.n)), y=np.zeros((k, w.m)), zl=np.zeros((k, w.n)), zu=np.zeros((k, w.n)),
                obj=np.zeros(k), kkt=np.zeros(k), status=np.zeros(k, np.int32), iters=np.zeros(k, np.int32),
-               stats=np.zeros((k, 8), np.int32))
-    wx = None if warm_x is None else np.ascontiguousarray(warm_x, np.float64)
-    lib().ipmo_solve_quad(C.byref(d), C.byref(o), k, _p(thetas), _p(wx), int(threads),
+               stats=np.zeros((k, NSTAT), np.int32))
+    wr = None
+    if warm is not None:
+        wr = np.ascontiguousarray(warm, np.float64)
+        assert wr.shape == (k, w.n_w + w.m)
+    lib().ipmo_solve_quad(C.byref(d), C.byref(o), k, _p(thetas), _p(wr), int(threads),
                           _p(out["x"]), _p(out["y"]), _p(out["zl"]), _p(out["zu"]), _p(out["obj"]),
                           _p(out["kkt"]), _ip(out["status"]), _ip(out["iters"]), _ip(out["stats"]))
     return out
+
+
+# ----------------------------------------------------------------------------- method pieces
+def ftb_primal(x, dx, xl, xu, tau):
+    f = lambda a: _p(np.ascontiguousarray(a, np.float64))
+    return lib().ipmo_ftb_primal(len(x), f(x), f(dx), f(xl), f(xu), float(tau))
+
+
+def ftb_dual(zl, zu, dzl, dzu, xl, xu, tau):
+    f = lambda a: _p(np.ascontiguousarray(a, np.float64))
+    return lib().ipmo_ftb_dual(len(zl), f(zl), f(zu), f(dzl), f(dzu), f(xl), f(xu), float(tau))
+
+
+def acceptable(theta_max, theta_min, filt, thk, phk, gphi, alpha, tht, pht, opts=None):
+    """(accepted, switching condition, Armijo condition) of a trial point; filt: list of (theta, phi)."""
+    o = opts or default_opts()
+    fth = np.array([a for a, _ in filt] + [0.0], np.float64)
+    fph = np.array([b for _, b in filt] + [0.0], np.float64)
+    out = np.zeros(3, np.int32)
+    lib().ipmo_acceptable(C.byref(o), float(theta_max), float(theta_min), len(filt), _p(fth), _p(fph), float(thk),
+                          float(phk), float(gphi), float(alpha), float(tht), float(pht), _ip(out))
+    return bool(out[0]), int(out[1]), int(out[2])
+
+
+def alpha_min(thk, gphi, theta_min, opts=None):
+    o = opts or default_opts()
+    return lib().ipmo_alpha_min(C.byref(o), float(thk), float(gphi), float(theta_min))
 
 
 class Handle:
@@ -240,13 +286,13 @@ class Handle:
         self._keep = keep
 
     @classmethod
-    def quad(cls, w, theta, x0=None, opts=None):
+    def quad(cls, w, theta, warm_row=None, opts=None):
         d = desc_from(w)
         o = opts or default_opts()
         th = np.ascontiguousarray(theta, np.float64)
-        x0a = None if x0 is None else np.ascontiguousarray(x0, np.float64)
-        h = lib().ipmo_create_quad(C.byref(d), C.byref(o), _p(th), _p(x0a))
-        return cls(h, w.n, w.m, keep=(d, o, th, x0a))
+        wr = None if warm_row is None else np.ascontiguousarray(warm_row, np.float64)
+        h = lib().ipmo_create_quad(C.byref(d), C.byref(o), _p(th), _p(wr))
+        return cls(h, w.n, w.m, keep=(d, o, th, wr))
 
     @classmethod
     def generic(cls, n, m, xl, xu, f, grad, c, jac, hess, x0, opts=None):
@@ -322,19 +368,35 @@ class Handle:
         lib().ipmo_last_step(self.h, _p(dx), _p(dy), _p(dzl), _p(dzu))
         return dx, dy[:self.m], dzl, dzu
 
+    def kkt_error(self, mu=0.0) -> float:
+        """E_mu of the current original-problem iterate."""
+        return lib().ipmo_handle_kkt_error(self.h, float(mu))
+
+    def last_soc(self):
+        """Second-order corrections of the last pass: list of (c_soc [m], step [n_v], theta of the trial)."""
+        k = self.m if self.m > 0 else 1
+        nv = self.n + 2 * self.m
+        cs = np.zeros((8, k)); ds = np.zeros((8, nv)); th = np.zeros(8)
+        cnt = lib().ipmo_last_soc(self.h, _p(cs), _p(ds), _p(th))
+        return [(cs[i, :self.m].copy(), ds[i].copy(), th[i]) for i in range(cnt)]
+
     def outputs(self) -> dict:
         n, m = self.n, self.m
         out = dict(x=np.zeros(n), y=np.zeros(max(m, 1)), zl=np.zeros(n), zu=np.zeros(n), obj=np.zeros(1),
                    kkt=np.zeros(1), status=np.zeros(1, np.int32), iters=np.zeros(1, np.int32),
-                   stats=np.zeros(8, np.int32))
+                   stats=np.zeros(NSTAT, np.int32))
         lib().ipmo_outputs(self.h, _p(out["x"]), _p(out["y"]), _p(out["zl"]), _p(out["zu"]), _p(out["obj"]),
                            _p(out["kkt"]), _ip(out["status"]), _ip(out["iters"]), _ip(out["stats"]))
         out["y"] = out["y"][:m]
         return out
 
 
-def unpack_state(s: np.ndarray, n: int, m: int, fcap: int = 128) -> dict:
-    """Split a flat oracle state into named fields (same order as ipmo_state_get)."""
+def unpack_state(s: np.ndarray, n: int, m: int) -> dict:
+    """Split a flat oracle state into named fields (same order as ipmo_state_get); the filter
+    capacity F of the format follows from the length."""
+    rest = len(s) - 16 - (8 + 3 * n + m) - (8 + 3 * (n + 2 * m) + m) - 2 * n
+    assert rest > 0 and rest % 4 == 0, "not a flat state of this problem size"
+    fcap = rest // 4
     hdr = s[:16]
     p = 16
 
@@ -353,4 +415,5 @@ def unpack_state(s: np.ndarray, n: int, m: int, fcap: int = 128) -> dict:
     main, p = sub(p, n)
     rs, p = sub(p, n + 2 * m)
     return dict(phase=int(hdr[0]), iter=int(hdr[1]), status=int(hdr[2]), init_filter=int(hdr[3]),
-                theta_R=hdr[4], main=main, resto=rs, xR=s[p:p + n], DR2=s[p + n:p + 2 * n])
+                theta_R=hdr[4], warm=int(hdr[5]), wstage=int(hdr[6]), main=main, resto=rs, xR=s[p:p + n],
+                DR2=s[p + n:p + 2 * n])

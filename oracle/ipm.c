@@ -34,6 +34,8 @@
 void* quad_nlp_new(const ipmo_quad_desc* d, const double* theta, nlp_t* out);
 void quad_nlp_free(void* p);
 void quad_cold_start(const ipmo_quad_desc* d, const double* theta, double* v);
+void quad_warm_point(const ipmo_quad_desc* d, const double* theta, const double* w, double* v);
+int quad_nw(const ipmo_quad_desc* d);
 
 #define EPS DBL_EPSILON
 
@@ -47,9 +49,8 @@ typedef struct {
     double *x, *y, *zl, *zu; /* zl/zu full length, zero on unbounded components */
     double mu, tau, dx_last, theta_max, theta_min;
     int tiny;
-    int nf, fcap;
+    int nf, fcap;     /* filter entries in use, allocated capacity (grows without limit) */
     double *fth, *fph;
-    int overflow;
 } sub_t;
 
 /* restoration NLP: min rho sum(p+n) + zeta/2 |D_R (x - x_R)|^2 s.t. c(x) - p + n = 0 */
@@ -66,6 +67,15 @@ typedef struct solver_s {
     nlp_t* P;
     ipmo_opts o;
     int phase, status, iter, init_filter;
+    /* learned warm start: warm = 1 while the iterate comes from a warm point (a divergence then
+     * restarts cold); wstage = 1 while the gate's cold reference is being computed, 2 while the
+     * warm point waits for its multipliers and the gate's comparison */
+    int warm, wstage;
+    double e_cold;                      /* gate: E_mu0 of the cold start */
+    double *warm_w, *warm_y;            /* the warm row (copied), NULL for a cold start */
+    double *x_cold, *y_cold;            /* the cold start (before the bound push); gate: its least-squares y */
+    double thmax_cold, thmin_cold;
+    int scap;                           /* filter pairs kept in the flat state (max_iter + 2) */
     sub_t main, rs;
     nlp_t RP;
     resto_ud RU;
@@ -78,37 +88,45 @@ typedef struct solver_s {
     double f;
     /* statistics */
     int st_resto_iter, st_soc_try, st_soc_acc, st_fact, st_resto_entries, st_tiny, st_passes;
+    int st_warm_started, st_warm_rejected, st_warm_restarts;
     double last_dx, last_dc, last_alpha, last_alpha_z;
     int last_soc;
+    /* second-order corrections of the last pass: count, c_soc and step of each, theta of each trial */
+    int soc_n;
+    double *soc_c, *soc_d, *soc_th;
 } solver_t;
 
 /* ------------------------------------------------------------------ */
-static void sub_alloc(sub_t* T, int n, int m, int fcap) {
+static void sub_alloc(sub_t* T, int n, int m) {
     T->n = n; T->m = m;
     T->x = (double*)calloc(n, sizeof(double));
     T->y = (double*)calloc(m > 0 ? m : 1, sizeof(double));
     T->zl = (double*)calloc(n, sizeof(double));
     T->zu = (double*)calloc(n, sizeof(double));
-    T->fcap = fcap;
-    T->fth = (double*)calloc(fcap, sizeof(double));
-    T->fph = (double*)calloc(fcap, sizeof(double));
+    T->fcap = 16;
+    T->fth = (double*)calloc(T->fcap, sizeof(double));
+    T->fph = (double*)calloc(T->fcap, sizeof(double));
     T->nf = 0;
-    T->overflow = 0;
 }
 
 static void sub_free(sub_t* T) {
     free(T->x); free(T->y); free(T->zl); free(T->zu); free(T->fth); free(T->fph);
 }
 
-/* filter F = {(theta_F, phi_F)}: a point is rejected if theta >= theta_F and phi >= phi_F for
- * some entry.  Entries dominated by a new entry are dropped (their forbidden region is
- * contained in the new one), so the semantics do not change. */
+/* filter F = {(theta_F, phi_F)} (Table I row 1): a point is rejected if theta >= theta_F and
+ * phi >= phi_F for some entry.  Entries dominated by a new entry are dropped (their forbidden
+ * region is contained in the new one), so the semantics do not change.  The filter has no
+ * capacity limit: the storage grows as needed. */
 static void filter_add(sub_t* T, double th, double ph) {
     int w = 0;
     for (int i = 0; i < T->nf; ++i)
         if (!(T->fth[i] >= th && T->fph[i] >= ph)) { T->fth[w] = T->fth[i]; T->fph[w] = T->fph[i]; ++w; }
     T->nf = w;
-    if (T->nf >= T->fcap) { T->overflow = 1; return; }
+    if (T->nf >= T->fcap) {
+        T->fcap *= 2;
+        T->fth = (double*)realloc(T->fth, (size_t)T->fcap * sizeof(double));
+        T->fph = (double*)realloc(T->fph, (size_t)T->fcap * sizeof(double));
+    }
     T->fth[T->nf] = th;
     T->fph[T->nf] = ph;
     T->nf++;
@@ -315,6 +333,17 @@ static int acceptable(const sub_t* T, const ipmo_opts* o, double thk, double phk
     return 1;
 }
 
+/* smallest step size the backtracking tries before falling back to restoration (Table I row 1,
+ * constants of the filter method): gamma_alpha times the least of gamma_theta, the step that
+ * would give the required phi decrease, and (when the switching condition can apply) the step
+ * at which the switching condition starts to hold */
+static double alpha_min(const ipmo_opts* o, double thk, double gphi, double theta_min) {
+    if (!(gphi < 0)) return o->gamma_alpha * o->gamma_theta;
+    double t = fmin(o->gamma_theta, o->gamma_phi * thk / (-gphi));
+    if (thk <= theta_min) t = fmin(t, o->delta_sw * pow(thk, o->s_theta) / pow(-gphi, o->s_phi));
+    return o->gamma_alpha * t;
+}
+
 /* monotone barrier update (Table I row 7): decrease mu while the barrier problem is solved to
  * kappa_eps * mu, or once after a tiny step; reset the filter on every decrease. */
 static void mu_update(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
@@ -365,6 +394,17 @@ static int factor_ic(solver_t* S, const nlp_t* P, sub_t* T) {
 
 static void kkt_solve(solver_t* S, int N, double* d) { bk_solve(N, S->K, S->perm, S->blk, d, S->wk); }
 
+/* keep c_soc, the step and the trial theta of a second-order correction for inspection */
+static void soc_record(solver_t* S, int n, int m, double tht) {
+    int k = S->soc_n;
+    if (k >= S->o.max_soc) return;
+    int nmax = S->P->n + 2 * S->P->m, mm = S->P->m > 0 ? S->P->m : 1;
+    memcpy(S->soc_c + (size_t)k * mm, S->csoc, m * sizeof(double));
+    memcpy(S->soc_d + (size_t)k * nmax, S->dxs, n * sizeof(double));
+    S->soc_th[k] = tht;
+    S->soc_n++;
+}
+
 /* one iteration of the barrier method on problem P with iterate T */
 static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
     const ipmo_opts* o = &S->o;
@@ -411,6 +451,7 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
     double ap = amax;
     int augment = 0, accepted = 0;
     S->last_soc = 0;
+    S->soc_n = 0;
     if (tmax < 10.0 * EPS && nrmi(m, S->c) <= 1e-4) {
         for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + ap * S->dx[i];
         T->tiny = 1;
@@ -418,14 +459,7 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
         accepted = 1;
     } else {
         /* backtracking filter line search (Table I rows 1-2) */
-        double amin;
-        if (gphi < 0) {
-            double t = fmin(o->gamma_theta, o->gamma_phi * thk / (-gphi));
-            if (thk <= T->theta_min) t = fmin(t, o->delta_sw * pow(thk, o->s_theta) / pow(-gphi, o->s_phi));
-            amin = o->gamma_alpha * t;
-        } else {
-            amin = o->gamma_alpha * o->gamma_theta;
-        }
+        double amin = alpha_min(o, thk, gphi, T->theta_min);
         double alpha = amax;
         for (int l = 0;; ++l) {
             /* alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point) */
@@ -457,6 +491,7 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
                     asoc = ftb_primal(P, T->x, S->dxs, T->tau);
                     for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + asoc * S->dxs[i];
                     fin = trial_eval(P, T, S->xt, S->ct, &tht, &pht);
+                    soc_record(S, n, m, tht);
                     /* acceptance uses the original step size and direction derivative */
                     if (acceptable(T, o, thk, phk, gphi, alpha, tht, pht, &sw, &arm)) {
                         dz_recover(P, T, S->dxs, S->dzls, S->dzus);
@@ -525,31 +560,115 @@ static void init_y(solver_t* S) {
     }
 }
 
-/* push a starting point into the bounds and set z = 1, mu = mu_0 */
-static void init_point(const nlp_t* P, const ipmo_opts* o, sub_t* T, const double* x0) {
+/* push a starting point into the bounds (bound push kappa_1, kappa_2) and set z = 1 on the
+ * bounded components, y = 0 and the barrier parameter mu0 */
+static void init_point(const nlp_t* P, const ipmo_opts* o, sub_t* T, const double* x0, double k1, double k2,
+                       double mu0) {
     for (int i = 0; i < P->n; ++i) {
         double x = x0[i], l = P->xl[i], u = P->xu[i];
         if (isfinite(l) && isfinite(u)) {
-            double pl = fmin(o->kappa1 * fmax(1.0, fabs(l)), o->kappa2 * (u - l));
-            double pu = fmin(o->kappa1 * fmax(1.0, fabs(u)), o->kappa2 * (u - l));
+            double pl = fmin(k1 * fmax(1.0, fabs(l)), k2 * (u - l));
+            double pu = fmin(k1 * fmax(1.0, fabs(u)), k2 * (u - l));
             x = fmax(x, l + pl);
             x = fmin(x, u - pu);
         } else if (isfinite(l)) {
-            x = fmax(x, l + o->kappa1 * fmax(1.0, fabs(l)));
+            x = fmax(x, l + k1 * fmax(1.0, fabs(l)));
         } else if (isfinite(u)) {
-            x = fmin(x, u - o->kappa1 * fmax(1.0, fabs(u)));
+            x = fmin(x, u - k1 * fmax(1.0, fabs(u)));
         }
         T->x[i] = x;
         T->zl[i] = isfinite(l) ? 1.0 : 0.0;
         T->zu[i] = isfinite(u) ? 1.0 : 0.0;
     }
     memset(T->y, 0, (P->m > 0 ? P->m : 1) * sizeof(double));
-    T->mu = o->mu_init;
+    T->mu = mu0;
     T->tau = fmax(o->tau_min, 1.0 - T->mu);
     T->dx_last = 0.0;
     T->tiny = 0;
     T->nf = 0;
     T->theta_max = T->theta_min = 0.0;
+}
+
+static void cold_point(solver_t* S) {
+    init_point(S->P, &S->o, &S->main, S->x_cold, S->o.kappa1, S->o.kappa2, S->o.mu_init);
+}
+
+/* the warm point: w (with its slacks) pushed into the bounds by warm_push, its multipliers y,
+ * barrier parameter warm_mu0; the bound multipliers are set in the next INIT_Y pass */
+static void warm_point(solver_t* S) {
+    init_point(S->P, &S->o, &S->main, S->warm_w, S->o.warm_push, S->o.warm_push, S->o.warm_mu0);
+    memcpy(S->main.y, S->warm_y, S->P->m * sizeof(double));
+}
+
+/* Warm start, INIT_Y pass at the warm point: bound multipliers from the stationarity residual
+ * r = grad f + A^T y (z_L = max(r, mu0 / (x - x_L)), z_U = max(-r, mu0 / (x_U - x))), filter
+ * bounds from theta at the warm point.  With the gate, the warm start is kept only if
+ * E_mu0(warm) <= E_mu0(cold start) (both at mu0 = warm_mu0); otherwise the cold start computed
+ * in the previous pass takes its place. */
+static void warm_init_pass(solver_t* S) {
+    nlp_t* P = S->P;
+    sub_t* T = &S->main;
+    int n = P->n, m = P->m;
+    eval_point(S, P, T);
+    for (int i = 0; i < n; ++i) S->wk[i] = S->g[i];
+    for (int r = 0; r < m; ++r)
+        for (int i = 0; i < n; ++i) S->wk[i] += S->J[(size_t)r * n + i] * T->y[r];
+    const double mu0 = T->mu;
+    for (int i = 0; i < n; ++i) {
+        double r = S->wk[i];
+        T->zl[i] = isfinite(P->xl[i]) ? fmax(r, mu0 / (T->x[i] - P->xl[i])) : 0.0;
+        T->zu[i] = isfinite(P->xu[i]) ? fmax(-r, mu0 / (P->xu[i] - T->x[i])) : 0.0;
+    }
+    double th0 = nrm1(m, S->c);
+    int keep = 1;
+    if (S->wstage == 2) {
+        double e_warm = kkt_error(P, T, S->g, S->c, S->J, S->o.warm_mu0, &S->o, S->wk);
+        keep = e_warm <= S->e_cold;
+    }
+    if (keep) {
+        T->theta_max = 1e4 * fmax(1.0, th0);
+        T->theta_min = 1e-4 * fmax(1.0, th0);
+    } else {
+        /* rejected by the gate: the cold start of the previous pass */
+        cold_point(S);
+        memcpy(T->y, S->y_cold, m * sizeof(double));
+        T->theta_max = S->thmax_cold;
+        T->theta_min = S->thmin_cold;
+        S->warm = 0;
+        S->st_warm_rejected++;
+    }
+    T->nf = 0;
+    S->wstage = 0;
+    S->init_filter = 0;
+    S->phase = PH_REGULAR;
+}
+
+/* Gate, first pass done (least-squares y at the cold start): record E_mu0 of the cold start and
+ * move to the warm point (the phase stays INIT_Y) */
+static void gate_cold_done(solver_t* S) {
+    nlp_t* P = S->P;
+    sub_t* T = &S->main;
+    int m = P->m;
+    eval_point(S, P, T);
+    S->e_cold = kkt_error(P, T, S->g, S->c, S->J, S->o.warm_mu0, &S->o, S->wk);
+    memcpy(S->y_cold, T->y, m * sizeof(double));
+    S->thmax_cold = T->theta_max;
+    S->thmin_cold = T->theta_min;
+    warm_point(S);
+    S->warm = 1;
+    S->wstage = 2;
+}
+
+/* a warm start that diverged (it needs restoration, or runs past warm_iter_cap iterations)
+ * starts again from the cold start; the iteration count carries on */
+static void cold_restart(solver_t* S) {
+    cold_point(S);
+    S->init_filter = 1;
+    S->theta_R = 0.0;
+    S->warm = 0;
+    S->wstage = 0;
+    S->phase = PH_INIT_Y;
+    S->st_warm_restarts++;
 }
 
 /* enter feasibility restoration (Table I row 6) from the main iterate */
@@ -595,7 +714,6 @@ static int resto_enter(solver_t* S) {
     R->dx_last = 0.0;
     R->tiny = 0;
     R->nf = 0;
-    R->overflow = 0;
     S->RP.c(S->RP.ud, R->x, S->ct);
     double th0 = nrm1(m, S->ct);
     R->theta_max = 1e4 * fmax(1.0, th0);
@@ -642,13 +760,18 @@ static void solver_pass(solver_t* S) {
     S->st_passes++;
     if (S->phase == PH_DONE) return;
     if (S->phase == PH_INIT_Y) {
-        init_y(S);
+        if (S->warm) { warm_init_pass(S); return; }
+        init_y(S);                                   /* least-squares y at the cold start */
+        if (S->wstage == 1) { gate_cold_done(S); return; }
         S->phase = PH_REGULAR;
+        return;
+    }
+    if (S->warm && (S->phase == PH_RESTO || (S->o.warm_iter_cap > 0 && S->iter >= S->o.warm_iter_cap))) {
+        cold_restart(S);
         return;
     }
     if (S->phase == PH_REGULAR) {
         int r = core_iter(S, S->P, &S->main, 0);
-        if (S->main.overflow) { S->status = ST_FILTER_OVERFLOW; S->phase = PH_DONE; return; }
         switch (r) {
         case R_ACCEPT: return;
         case R_CONVERGED: S->status = ST_CONVERGED; S->phase = PH_DONE; return;
@@ -662,7 +785,6 @@ static void solver_pass(solver_t* S) {
     }
     if (S->phase == PH_RESTO) {
         int r = core_iter(S, &S->RP, &S->rs, 1);
-        if (S->rs.overflow || S->main.overflow) { S->status = ST_FILTER_OVERFLOW; S->phase = PH_DONE; return; }
         switch (r) {
         case R_ACCEPT:
             if (resto_try_exit(S)) S->phase = PH_INIT_Y;
@@ -710,14 +832,19 @@ static void grow_buffers(solver_t* S, int nv) {
 }
 
 /* ------------------------------------------------------------------ */
-static solver_t* solver_new(nlp_t* P, const ipmo_opts* o, const double* x0) {
+/* x_cold: the cold starting point; x_warm / y_warm (or NULL): a warm point (all n primal
+ * values) and its equality multipliers.  A warm point with a non-finite entry is rejected and the
+ * solve starts cold. */
+static solver_t* solver_new(nlp_t* P, const ipmo_opts* o, const double* x_cold, const double* x_warm,
+                            const double* y_warm) {
     solver_t* S = (solver_t*)calloc(1, sizeof(solver_t));
     S->P = P;
     S->o = *o;
     int n = P->n, m = P->m;
     int NR = n + 2 * m;                 /* restoration variables */
-    sub_alloc(&S->main, n, m, o->filter_cap);
-    sub_alloc(&S->rs, NR, m, o->filter_cap);
+    sub_alloc(&S->main, n, m);
+    sub_alloc(&S->rs, NR, m);
+    S->scap = o->max_iter + 2;
     S->cap_n = 0;
     grow_buffers(S, n);                 /* grown to the restoration size on first entry */
     /* restoration NLP */
@@ -733,10 +860,36 @@ static solver_t* solver_new(nlp_t* P, const ipmo_opts* o, const double* x0) {
     for (int i = n; i < NR; ++i) { U->xl[i] = 0.0; U->xu[i] = INFINITY; }
     S->RP.n = NR; S->RP.m = m; S->RP.xl = U->xl; S->RP.xu = U->xu; S->RP.ud = U;
     S->RP.f = r_f; S->RP.grad = r_grad; S->RP.c = r_c; S->RP.jac = r_jac; S->RP.hess = r_hess;
-    init_point(P, o, &S->main, x0);
+    S->x_cold = (double*)malloc(n * sizeof(double));
+    S->y_cold = (double*)calloc(m > 0 ? m : 1, sizeof(double));
+    memcpy(S->x_cold, x_cold, n * sizeof(double));
+    S->soc_c = (double*)calloc((size_t)(o->max_soc > 0 ? o->max_soc : 1) * (m > 0 ? m : 1), sizeof(double));
+    S->soc_d = (double*)calloc((size_t)(o->max_soc > 0 ? o->max_soc : 1) * NR, sizeof(double));
+    S->soc_th = (double*)calloc(o->max_soc > 0 ? o->max_soc : 1, sizeof(double));
+    int use_warm = x_warm != NULL && y_warm != NULL;
+    if (use_warm) {
+        for (int i = 0; i < n; ++i) if (!isfinite(x_warm[i])) use_warm = 0;
+        for (int r = 0; r < m; ++r) if (!isfinite(y_warm[r])) use_warm = 0;
+        if (use_warm) {
+            S->warm_w = (double*)malloc(n * sizeof(double));
+            S->warm_y = (double*)calloc(m > 0 ? m : 1, sizeof(double));
+            memcpy(S->warm_w, x_warm, n * sizeof(double));
+            memcpy(S->warm_y, y_warm, m * sizeof(double));
+            S->st_warm_started = 1;
+        } else {
+            S->st_warm_rejected = 1;
+        }
+    }
     S->phase = PH_INIT_Y;
     S->status = ST_RUNNING;
     S->init_filter = 1;
+    if (use_warm && !o->warm_gate) {
+        warm_point(S);
+        S->warm = 1;
+    } else {
+        cold_point(S);
+        if (use_warm) S->wstage = 1;    /* the gate's cold reference first */
+    }
     return S;
 }
 
@@ -748,6 +901,8 @@ static void solver_free(solver_t* S) {
     free(S->dzus); free(S->xt); free(S->ct); free(S->csoc); free(S->gphi); free(S->rx);
     free(S->perm); free(S->blk);
     free(S->RU.xR); free(S->RU.DR2); free(S->RU.xl); free(S->RU.xu); free(S->RU.Jb); free(S->RU.Hb);
+    free(S->x_cold); free(S->y_cold); free(S->warm_w); free(S->warm_y);
+    free(S->soc_c); free(S->soc_d); free(S->soc_th);
     free(S);
 }
 
@@ -766,7 +921,8 @@ void ipmo_default_opts(ipmo_opts* o) {
     o->kappa_plus_bar = 100.0; o->gamma_theta = 1e-5; o->gamma_phi = 1e-8; o->delta_sw = 1.0;
     o->s_theta = 1.1; o->s_phi = 2.3; o->eta_phi = 1e-8; o->gamma_alpha = 0.05; o->max_soc = 4;
     o->kappa_soc = 0.99; o->kappa_sigma = 1e10; o->rho_resto = 1000.0; o->kappa_resto = 0.9;
-    o->bound_mult_reset = 1e3; o->filter_cap = 128;
+    o->bound_mult_reset = 1e3;
+    o->warm_mu0 = 1e-3; o->warm_push = 1e-3; o->warm_iter_cap = 0; o->warm_gate = 1;
 }
 
 int ipmo_sizeof_opts(void) { return (int)sizeof(ipmo_opts); }
@@ -782,8 +938,9 @@ void ipmo_bk_solve(int n, const double* F, const int* perm, const int* blk, doub
 /* outputs of one solve */
 typedef struct {
     double* x; double* y; double* zl; double* zu; double* obj; double* kkt; int32_t* status; int32_t* iters;
-    int32_t* stats; /* 8 ints per instance */
+    int32_t* stats; /* NSTAT ints per instance */
 } outs_t;
+#define NSTAT 11
 
 static void write_outputs(solver_t* S, int idx, const outs_t* O) {
     nlp_t* P = S->P;
@@ -801,9 +958,10 @@ static void write_outputs(solver_t* S, int idx, const outs_t* O) {
     if (O->status) O->status[idx] = S->status;
     if (O->iters) O->iters[idx] = S->iter;
     if (O->stats) {
-        int32_t* s = O->stats + (size_t)idx * 8;
+        int32_t* s = O->stats + (size_t)idx * NSTAT;
         s[0] = S->iter; s[1] = S->st_resto_iter; s[2] = S->st_soc_try; s[3] = S->st_soc_acc;
         s[4] = S->st_fact; s[5] = S->st_resto_entries; s[6] = S->st_tiny; s[7] = S->st_passes;
+        s[8] = S->st_warm_started; s[9] = S->st_warm_rejected; s[10] = S->st_warm_restarts;
     }
 }
 
@@ -812,8 +970,7 @@ typedef struct {
     const ipmo_opts* o;
     int n_inst, n_theta, n;
     const double* theta;
-    const double* warm_x;
-    const double* warm_y;
+    const double* warm;     /* [n_inst][n_w + m] rows (w, y), or NULL */
     outs_t O;
     int next;
     pthread_mutex_t lock;
@@ -824,13 +981,16 @@ static void solve_one_quad(batch_t* B, int i) {
     const double* th = B->theta + (size_t)i * B->n_theta;
     void* Q = quad_nlp_new(B->d, th, &P);
     double* x0 = (double*)malloc(P.n * sizeof(double));
-    if (B->warm_x) memcpy(x0, B->warm_x + (size_t)i * P.n, P.n * sizeof(double));
-    else quad_cold_start(B->d, th, x0);
-    solver_t* S = solver_new(&P, B->o, x0);
+    double* xw = (double*)malloc(P.n * sizeof(double));
+    quad_cold_start(B->d, th, x0);
+    const double* row = B->warm ? B->warm + (size_t)i * (quad_nw(B->d) + P.m) : NULL;
+    if (row) quad_warm_point(B->d, th, row, xw);
+    solver_t* S = solver_new(&P, B->o, x0, row ? xw : NULL, row ? row + quad_nw(B->d) : NULL);
     solver_run(S);
     write_outputs(S, i, &B->O);
     solver_free(S);
     free(x0);
+    free(xw);
     quad_nlp_free(Q);
 }
 
@@ -852,14 +1012,15 @@ static int desc_n_theta(const ipmo_quad_desc* d) {
     return 16 * d->n_agents;
 }
 
-/* Solve n_inst quadrotor NMPC instances (cold start unless warm_x is given), threads workers. */
+/* Solve n_inst quadrotor NMPC instances with `threads` workers: cold start, or warm from the rows
+ * of `warm` ([n_inst][n_w + m]: primal w without slacks, then the equality multipliers y). */
 int ipmo_solve_quad(const ipmo_quad_desc* d, const ipmo_opts* o, int n_inst, const double* theta,
-                    const double* warm_x, int threads, double* x, double* y, double* zl, double* zu,
+                    const double* warm, int threads, double* x, double* y, double* zl, double* zu,
                     double* obj, double* kkt, int32_t* status, int32_t* iters, int32_t* stats) {
     batch_t B;
     memset(&B, 0, sizeof(B));
     B.d = d; B.o = o; B.n_inst = n_inst; B.n_theta = desc_n_theta(d); B.theta = theta;
-    B.warm_x = warm_x;
+    B.warm = warm;
     B.O.x = x; B.O.y = y; B.O.zl = zl; B.O.zu = zu; B.O.obj = obj; B.O.kkt = kkt;
     B.O.status = status; B.O.iters = iters; B.O.stats = stats;
     pthread_mutex_init(&B.lock, NULL);
@@ -882,14 +1043,17 @@ typedef struct {
     solver_t* S;
 } handle_t;
 
-void* ipmo_create_quad(const ipmo_quad_desc* d, const ipmo_opts* o, const double* theta, const double* x0_or_null) {
+/* one instance; warm_row (or NULL): [n_w + m] = (w, y) as in ipmo_solve_quad */
+void* ipmo_create_quad(const ipmo_quad_desc* d, const ipmo_opts* o, const double* theta, const double* warm_row) {
     handle_t* Hd = (handle_t*)calloc(1, sizeof(handle_t));
     Hd->Q = quad_nlp_new(d, theta, &Hd->P);
     double* x0 = (double*)malloc(Hd->P.n * sizeof(double));
-    if (x0_or_null) memcpy(x0, x0_or_null, Hd->P.n * sizeof(double));
-    else quad_cold_start(d, theta, x0);
-    Hd->S = solver_new(&Hd->P, o, x0);
+    double* xw = (double*)malloc(Hd->P.n * sizeof(double));
+    quad_cold_start(d, theta, x0);
+    if (warm_row) quad_warm_point(d, theta, warm_row, xw);
+    Hd->S = solver_new(&Hd->P, o, x0, warm_row ? xw : NULL, warm_row ? warm_row + quad_nw(d) : NULL);
     free(x0);
+    free(xw);
     return Hd;
 }
 
@@ -906,7 +1070,7 @@ void* ipmo_create_generic(int n, int m, const double* xl, const double* xu,
     memcpy(u, xu, n * sizeof(double));
     Hd->P.n = n; Hd->P.m = m; Hd->P.xl = l; Hd->P.xu = u; Hd->P.ud = NULL;
     Hd->P.f = f; Hd->P.grad = grad; Hd->P.c = c; Hd->P.jac = jac; Hd->P.hess = hess;
-    Hd->S = solver_new(&Hd->P, o, x0);
+    Hd->S = solver_new(&Hd->P, o, x0, NULL, NULL);
     return Hd;
 }
 
@@ -941,57 +1105,69 @@ void ipmo_last_info(void* h, double* out) {
 }
 
 /* Flat state (FP64), field order:
- *   header[16] = phase, iter, status, init_filter, theta_R, 0...
- *   main sub-state  : mu, tau, dx_last, theta_max, theta_min, tiny, nf, 0 | x[n] y[m] zl[n] zu[n] | fth[cap] fph[cap]
+ *   header[16] = phase, iter, status, init_filter, theta_R, warm, wstage, 0...
+ *   main sub-state  : mu, tau, dx_last, theta_max, theta_min, tiny, nf, 0 | x[n] y[m] zl[n] zu[n] | fth[F] fph[F]
  *   resto sub-state : same with n_R = n + 2m variables
- *   x_R[n], DR2[n]                                                              */
-static int sub_len(const sub_t* T) { return 8 + 3 * T->n + T->m + 2 * T->fcap; }
+ *   x_R[n], DR2[n]
+ * F = max_iter + 2 filter pairs: every entry of the original problem's filter comes from an
+ * accepted iteration or a restoration entry (each entry but the last followed by an accepted
+ * restoration iteration), every entry of the restoration filter from an accepted restoration
+ * iteration, so neither holds more than max_iter + 1 pairs. */
+static int sub_len(const solver_t* S, const sub_t* T) { return 8 + 3 * T->n + T->m + 2 * S->scap; }
 
 int ipmo_state_len(void* h) {
     solver_t* S = ((handle_t*)h)->S;
-    return 16 + sub_len(&S->main) + sub_len(&S->rs) + 2 * S->P->n;
+    return 16 + sub_len(S, &S->main) + sub_len(S, &S->rs) + 2 * S->P->n;
 }
 
-static double* sub_put(const sub_t* T, double* p) {
+static double* sub_put(const solver_t* S, const sub_t* T, double* p) {
     p[0] = T->mu; p[1] = T->tau; p[2] = T->dx_last; p[3] = T->theta_max; p[4] = T->theta_min;
     p[5] = T->tiny; p[6] = T->nf; p[7] = 0; p += 8;
     memcpy(p, T->x, T->n * sizeof(double)); p += T->n;
     memcpy(p, T->y, T->m * sizeof(double)); p += T->m;
     memcpy(p, T->zl, T->n * sizeof(double)); p += T->n;
     memcpy(p, T->zu, T->n * sizeof(double)); p += T->n;
-    for (int i = 0; i < T->fcap; ++i) p[i] = i < T->nf ? T->fth[i] : 0.0;
-    p += T->fcap;
-    for (int i = 0; i < T->fcap; ++i) p[i] = i < T->nf ? T->fph[i] : 0.0;
-    return p + T->fcap;
+    for (int i = 0; i < S->scap; ++i) p[i] = i < T->nf ? T->fth[i] : 0.0;
+    p += S->scap;
+    for (int i = 0; i < S->scap; ++i) p[i] = i < T->nf ? T->fph[i] : 0.0;
+    return p + S->scap;
 }
-static const double* sub_get(sub_t* T, const double* p) {
+static const double* sub_get(const solver_t* S, sub_t* T, const double* p) {
     T->mu = p[0]; T->tau = p[1]; T->dx_last = p[2]; T->theta_max = p[3]; T->theta_min = p[4];
     T->tiny = (int)p[5]; T->nf = (int)p[6]; p += 8;
     memcpy(T->x, p, T->n * sizeof(double)); p += T->n;
     memcpy(T->y, p, T->m * sizeof(double)); p += T->m;
     memcpy(T->zl, p, T->n * sizeof(double)); p += T->n;
     memcpy(T->zu, p, T->n * sizeof(double)); p += T->n;
-    memcpy(T->fth, p, T->fcap * sizeof(double)); p += T->fcap;
-    memcpy(T->fph, p, T->fcap * sizeof(double));
-    return p + T->fcap;
+    if (T->fcap < S->scap) {
+        T->fcap = S->scap;
+        T->fth = (double*)realloc(T->fth, (size_t)T->fcap * sizeof(double));
+        T->fph = (double*)realloc(T->fph, (size_t)T->fcap * sizeof(double));
+    }
+    memcpy(T->fth, p, S->scap * sizeof(double)); p += S->scap;
+    memcpy(T->fph, p, S->scap * sizeof(double));
+    return p + S->scap;
 }
 
 void ipmo_state_get(void* h, double* out) {
     solver_t* S = ((handle_t*)h)->S;
     memset(out, 0, 16 * sizeof(double));
     out[0] = S->phase; out[1] = S->iter; out[2] = S->status; out[3] = S->init_filter; out[4] = S->theta_R;
-    double* p = sub_put(&S->main, out + 16);
-    p = sub_put(&S->rs, p);
+    out[5] = S->warm; out[6] = S->wstage;
+    double* p = sub_put(S, &S->main, out + 16);
+    p = sub_put(S, &S->rs, p);
     memcpy(p, S->RU.xR, S->P->n * sizeof(double)); p += S->P->n;
     memcpy(p, S->RU.DR2, S->P->n * sizeof(double));
 }
 
+/* load a flat state (a warm start's gate data are not part of it: load states of cold solves) */
 void ipmo_state_set(void* h, const double* in) {
     solver_t* S = ((handle_t*)h)->S;
     S->phase = (int)in[0]; S->iter = (int)in[1]; S->status = (int)in[2]; S->init_filter = (int)in[3];
     S->theta_R = in[4];
-    const double* p = sub_get(&S->main, in + 16);
-    p = sub_get(&S->rs, p);
+    S->warm = (int)in[5]; S->wstage = (int)in[6];
+    const double* p = sub_get(S, &S->main, in + 16);
+    p = sub_get(S, &S->rs, p);
     memcpy(S->RU.xR, p, S->P->n * sizeof(double)); p += S->P->n;
     memcpy(S->RU.DR2, p, S->P->n * sizeof(double));
 }
@@ -1039,4 +1215,60 @@ void ipmo_quad_eval(const ipmo_quad_desc* d, const double* theta, const double* 
     if (J) P.jac(P.ud, v, J);
     if (Hm) P.hess(P.ud, v, objf, y, Hm);
     quad_nlp_free(Q);
+}
+
+
+/* ------------------------------------------------------------------ */
+/* pieces of the method on plain arrays, for hand-computed pins          */
+double ipmo_ftb_primal(int n, const double* x, const double* dx, const double* xl, const double* xu, double tau) {
+    nlp_t P;
+    memset(&P, 0, sizeof(P));
+    P.n = n; P.xl = xl; P.xu = xu;
+    return ftb_primal(&P, x, dx, tau);
+}
+
+double ipmo_ftb_dual(int n, const double* zl, const double* zu, const double* dzl, const double* dzu,
+                     const double* xl, const double* xu, double tau) {
+    nlp_t P;
+    memset(&P, 0, sizeof(P));
+    P.n = n; P.xl = xl; P.xu = xu;
+    return ftb_dual(&P, zl, zu, dzl, dzu, tau);
+}
+
+/* acceptance of a trial point against filter entries (fth, fph)[nf] and theta_max / theta_min;
+ * out[0] = accepted, out[1] = switching condition, out[2] = Armijo condition */
+void ipmo_acceptable(const ipmo_opts* o, double theta_max, double theta_min, int nf, const double* fth,
+                     const double* fph, double thk, double phk, double gphi, double alpha, double tht, double pht,
+                     int32_t* out) {
+    sub_t T;
+    memset(&T, 0, sizeof(T));
+    T.theta_max = theta_max; T.theta_min = theta_min; T.nf = nf;
+    T.fth = (double*)fth; T.fph = (double*)fph;
+    int sw = -1, arm = -1;
+    out[0] = acceptable(&T, o, thk, phk, gphi, alpha, tht, pht, &sw, &arm);
+    out[1] = sw; out[2] = arm;
+}
+
+double ipmo_alpha_min(const ipmo_opts* o, double thk, double gphi, double theta_min) {
+    return alpha_min(o, thk, gphi, theta_min);
+}
+
+/* E_mu of the handle's current original-problem iterate */
+double ipmo_handle_kkt_error(void* h, double mu) {
+    solver_t* S = ((handle_t*)h)->S;
+    eval_point(S, S->P, &S->main);
+    return kkt_error(S->P, &S->main, S->g, S->c, S->J, mu, &S->o, S->wk);
+}
+
+/* the second-order corrections of the last pass: returns their number; c_soc [k][m], step [k][n_v]
+ * (n_v the variables of the phase's problem), theta of each corrected trial point */
+int ipmo_last_soc(void* h, double* csoc, double* dxs, double* th) {
+    solver_t* S = ((handle_t*)h)->S;
+    int nmax = S->P->n + 2 * S->P->m, mm = S->P->m > 0 ? S->P->m : 1;
+    for (int k = 0; k < S->soc_n; ++k) {
+        if (csoc) memcpy(csoc + (size_t)k * S->P->m, S->soc_c + (size_t)k * mm, S->P->m * sizeof(double));
+        if (dxs) memcpy(dxs + (size_t)k * nmax, S->soc_d + (size_t)k * nmax, nmax * sizeof(double));
+        if (th) th[k] = S->soc_th[k];
+    }
+    return S->soc_n;
 }

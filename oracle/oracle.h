@@ -61,7 +61,11 @@ typedef struct {
     double kappa_sigma;                            /* 1e10 */
     double rho_resto, kappa_resto;                 /* 1000, 0.9 */
     double bound_mult_reset;                       /* 1e3 */
-    int32_t filter_cap;                            /* 128 */
+    /* learned warm start (step 14 of the method as built here): bound push, barrier parameter,
+     * divergence cap (0: only restoration counts as divergence), E_mu0 gate on/off */
+    double warm_mu0, warm_push;                    /* 1e-3, 1e-3 */
+    int32_t warm_iter_cap;                         /* 0 */
+    int32_t warm_gate;                             /* 1 */
 } ipmo_opts;
 
 /* ---------------- quadrotor NMPC problem family ---------------- */
@@ -76,6 +80,6 @@ typedef struct {
 
 enum { PH_INIT_Y = 0, PH_REGULAR = 1, PH_RESTO = 2, PH_DONE = 3 };
 enum { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAX_ITER = 2, ST_RESTO_FAILED = 3,
-       ST_INFEASIBLE = 4, ST_NUMERICAL = 5, ST_FILTER_OVERFLOW = 6 };
+       ST_INFEASIBLE = 4, ST_NUMERICAL = 5 };
 
 #endif

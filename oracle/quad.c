@@ -381,3 +381,22 @@ void quad_xdot(const ipmo_quad_desc* d, const double* x, const double* u, double
     quad_f(&P, hx, hu, out);
     for (int i = 0; i < 13; ++i) xd[i] = out[i].a;
 }
+
+/* primal values w without slacks (stage-interleaved), as in the decision vector */
+int quad_nw(const ipmo_quad_desc* d) {
+    int nx = 13 * d->n_agents, nu = 4 * d->n_agents;
+    return (d->N + 1) * nx + d->N * nu;
+}
+
+/* warm point: v = (w, s) with the slacks at s = g(w) (pushed into the bounds later) */
+void quad_warm_point(const ipmo_quad_desc* d, const double* theta, const double* w, double* v) {
+    nlp_t tmp;
+    quad_nlp* Q = (quad_nlp*)quad_nlp_new(d, theta, &tmp);
+    memcpy(v, w, Q->nw * sizeof(double));
+    for (int k = 1; k <= d->N; ++k)
+        for (int j = 0; j < Q->nineq; ++j) {
+            int pa, pb;
+            v[so(Q, k, j)] = ineq_val(Q, v + xo(Q, k), j, &pa, &pb);
+        }
+    quad_nlp_free(Q);
+}

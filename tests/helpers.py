@@ -3,9 +3,6 @@ import numpy as np
 
 import oracle
 
-FCAP = 128
-
-
 def e_v(a, b):
     """Largest scaled elementwise deviation max_i |a_i - b_i| / (1 + |b_i|) (Sec. VI, eq. (8))."""
     a = np.asarray(a, float)
@@ -17,7 +14,7 @@ def e_v(a, b):
 
 def state_fields(s, n, m):
     """Named fields of a flat state (oracle order), for comparisons."""
-    return oracle.unpack_state(np.asarray(s), n, m, FCAP)
+    return oracle.unpack_state(np.asarray(s), n, m)
 
 
 def compare_states(sg, so, n, m):
