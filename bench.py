@@ -2,17 +2,21 @@
 
 A step is one batched solve of the whole workload (every instance run to convergence through
 all method steps: derivatives, KKT assembly + inertia-correcting factorization, step, filter
-line search with SOC, restoration, barrier update, slot refill).  Default workload: C2,
-figure-eight tracking NMPC, 4096 instances, N = 30, 8 obstacles, FP64, cold start.
+line search with SOC, restoration, barrier update, slot refill).  `value` is the plain form:
+C2, figure-eight tracking NMPC, 4096 instances, N = 30, 8 obstacles, FP64, cold start.
 
-`--workload C5` measures the learned warm start: 16384 point-to-point instances (N = 10,
-3 obstacles); outside the timed region the network is trained on cold FP64 solutions of a
-separate training split and the warm barrier parameter is picked on a validation split; a timed
-step is the network's forward pass plus the warm-started solve with the FP32 factor and FP64
-refinement.  The cold/warm x FP64/FP32 variants of the same instances are reported beside it.
+The same run measures the other half of the metric, the warm/mixed form (object `warm_mixed`):
+the learned warm start on 16384 point-to-point instances (N = 10, 3 obstacles).  Outside the
+timed region the network is trained on cold FP64 solutions of a separate training split and the
+warm barrier parameter is picked on a validation split; a timed step is the network's forward
+pass plus the warm-started solve with the FP32 factor and FP64 refinement, beside the cold FP64
+solve of the same instances, and both are checked against the oracle on a subsample.  A third
+leg times one C2 solve with the per-phase kernels so that the factorization and the solve get
+durations and roofline fractions of their own.
 
 Prints one JSON line.  The roofline object is the dominant kernel's algorithmic HBM bytes per
-launch (formula in `kernel_roofline`) over its average launch time from HIP events.
+launch (`kernel_roofline`: bytes per stage of a factorization and of a solve, times the stages
+and the factorizations and solves the launches ran) over its average launch time from HIP events.
 """
 from __future__ import annotations
 
@@ -36,16 +40,17 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM traffic per launch of the dominant kernel, from the two rocprofv3 --pmc runs (FETCH_SIZE,
 # WRITE_SIZE) scaled by the same counters on a plain device copy of known size; valid only for
 # the kernel sources they were taken on (hash below) and the default C2 run.
-MEASURED_TRAFFIC = {"k_iter": {"csrc": "06d33ab38a25685b", "workload": "C2", "bytes_per_launch": 1.7565e8}}
+MEASURED_TRAFFIC = {}
 
 
 def csrc_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2606_26341_amd", "csrc")
-    for f in ("common.h", "model.h", "kkt.h", "kernels.hip"):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -53,71 +58,91 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# per-knot factor record produced on the regular path: L_R (4x4), Y (4x13), P (13x13),
-# Delta^1/2 (13), 1/diag(L_R) (4), flag
-FR_WORDS = 16 + 52 + 169 + 13 + 4 + 1
+# Algorithmic bytes of the KKT factor/solve per stage (single quadrotor, n_x = 13, n_u = 4, FP64
+# words).  A factorization attempt reads the stage Hessian H (17 x 18 / 2 = 153), the dynamics
+# Jacobian G (13 x 17 = 221), the dual regularisation Delta (13) and the stage right-hand side
+# (30), and writes L_u (10), K = L_u^-1 Hbar^ux (52), S (13 x 14 / 2 = 91) and the affine terms
+# (17): 587 words.  A solve reads the factor record (170), G (221) and the right-hand side (30)
+# and writes the step (30): 451 words.  There are N + 1 stages (knots).
+FACTOR_WORDS_PER_STAGE = 153 + 221 + 13 + 30 + 10 + 52 + 91 + 17
+SOLVE_WORDS_PER_STAGE = 170 + 221 + 30 + 30
+# flops per stage of one factorization attempt (Schur update G^T S G, Cholesky of Hbar^uu, the
+# control elimination and P = Hbar^xx - Y^T Y), for the FP64 fraction
+FACTOR_FLOPS_PER_STAGE = 10.8e3
 
 
-def sd_words(n_obs: int) -> int:
-    """Stage data per knot: Hessian diagonal (17), elastic ratios (2 x 13), condensed inequality
-    block (9) and 7 words per inequality row, padded to 8 words."""
-    return ((17 + 26 + 9 + 7 * n_obs + 7) // 8) * 8
+def kernel_roofline(w, st, kt, word_bytes=8.0):
+    """Roofline of the dominant kernel from the live HIP-event timings.
 
-
-def kernel_roofline(w, st, kt, slots_launched, rec_bytes=8.0):
-    """Roofline of the dominant kernel from the live HIP-event timings (algorithmic FP64 bytes).
-
-    One factorization attempt (per slot) reads the stage inputs (G_k 13x17 and W_k 17x17 per
-    interval, the stage data per knot) and writes the factor record per knot.  One solve reads
-    the factor record and stage data per knot, G_k per interval and the right-hand side (n + m),
-    and writes the step (n + m).  k_fac does factorizations only; the fused pass kernel (the
-    last instances of a batch) is charged only the bytes of the factorizations and solves it
-    runs, so its figure is a lower bound of its traffic.  `rec_bytes` is the width of the factor
-    record entries (4 when the factor runs in FP32; the stage data stay FP64).
-    """
-    N = w.N
+    k_fac is charged its factorization attempts, k_sol its solves and the fused pass kernel
+    k_iter both (SOC solves included); the pre-processing and line-search work of k_iter is not
+    charged, so its figure is a lower bound.  `word_bytes` is 4 when the factor runs in FP32."""
+    S = w.N + 1
+    fb = word_bytes * FACTOR_WORDS_PER_STAGE * S
+    sb = word_bytes * SOLVE_WORDS_PER_STAGE * S
     names = ("eval", "pre", "factor", "solve", "linesearch", "fused")
-    tot = {k: kt[k][0] for k in names if k in kt}
-    dom = max(tot, key=tot.get)
-    ms, launches = kt[dom]
-    avg_ms = ms / max(1, launches)
-    sdw = sd_words(w.n_obs)
-    fact_bytes = 8.0 * (N * (13 * 17 + 17 * 17) + (N + 1) * sdw) + rec_bytes * (N + 1) * FR_WORDS
-    solve_bytes = 8.0 * ((N + 1) * sdw + N * 13 * 17 + 2 * (w.n + w.m)) + rec_bytes * (N + 1) * FR_WORDS
-    if dom == "factor":
-        units = st["factorizations"] - st["fused_factorizations"]
-        per_launch = fact_bytes * units / max(1, launches)
-        kernel, unit_desc = "k_fac", f"{units} factorizations x {fact_bytes:.0f} B"
-    elif dom == "fused":
-        per_launch = (fact_bytes * st["fused_factorizations"] + solve_bytes * st["fused_solves"]) / max(1, launches)
-        kernel = "k_iter"
-        unit_desc = (f"{st['fused_factorizations']} factorizations x {fact_bytes:.0f} B + "
-                     f"{st['fused_solves']} solves x {solve_bytes:.0f} B")
-    else:
-        return dict(kernel="k_" + dom, bound="latency", achieved=None, peak=None, unit=None, frac=None,
-                    traffic=None, avg_ms=avg_ms, launches=launches)
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    return dict(kernel=kernel, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=achieved / HBM_PEAK_GBS, traffic=None, avg_ms=avg_ms, launches=launches,
-                bytes_per_launch=per_launch, units=unit_desc)
+    tot = {k: kt[k][0] for k in names if k in kt and kt[k][1] > 0}
+    out = {}
+    for k in tot:
+        ms, launches = kt[k]
+        avg_ms = ms / launches
+        if k == "factor":
+            units = st["factorizations"] - st["fused_factorizations"]
+            per_launch, flops = fb * units / launches, FACTOR_FLOPS_PER_STAGE * S * units / launches
+            desc = f"{units} factorizations x {S} stages x {fb / S:.0f} B"
+        elif k == "solve":
+            units = st["solves"] - st["fused_solves"]
+            per_launch, flops = sb * units / launches, 0.0
+            desc = f"{units} solves x {S} stages x {sb / S:.0f} B"
+        elif k == "fused":
+            per_launch = (fb * st["fused_factorizations"] + sb * st["fused_solves"]) / launches
+            flops = FACTOR_FLOPS_PER_STAGE * S * st["fused_factorizations"] / launches
+            desc = (f"{st['fused_factorizations']} factorizations x {S} stages x {fb / S:.0f} B + "
+                    f"{st['fused_solves']} solves x {S} stages x {sb / S:.0f} B")
+        else:
+            continue
+        ach = per_launch / (avg_ms * 1e-3) / 1e9
+        out["k_" + {"factor": "fac", "solve": "sol", "fused": "iter"}[k]] = dict(
+            bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
+            avg_ms=avg_ms, launches=launches, bytes_per_launch=per_launch, units=desc,
+            fp64_tflops=flops / (avg_ms * 1e-3) / 1e12, fp64_frac=flops / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            share_of_gpu_time=ms / sum(tot.values()))
+    dom = max(out, key=lambda k: out[k]["share_of_gpu_time"]) if out else None
+    return dom, out
 
 
-# oracle sample sizes sized to about 10-30 s of host work (dense FP64 factorizations grow with N^3)
-CPU_SAMPLE = {"C1": 64, "C2": 48, "C4": 32, "C5": 16384}
+def cpu_info():
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
 
 
-def cpu_baseline(w, sample: int):
+def cpu_baseline(w, sample: int, threads: int):
+    """The oracle on a seeded uniform sample of the workload's instances (slow ones included)."""
     import oracle
-    TH = w.thetas(0, sample)
-    threads = os.cpu_count() or 1
+    idx = np.sort(np.random.default_rng(20261203).choice(w.n_inst, size=min(sample, w.n_inst), replace=False))
+    TH = np.stack([w.theta(int(i)) for i in idx])
     t0 = time.perf_counter()
     o = oracle.solve_quad(w, TH, threads=threads)
     dt = time.perf_counter() - t0
     conv = int((o["status"] == oracle.ST_CONVERGED).sum())
-    return dict(value=conv / dt, unit="solves/s", cores=min(threads, sample), kind="oracle",
-                sample=f"{sample} {w.name} instances (0..{sample - 1}), dense FP64 oracle, one instance per "
-                       f"thread, {dt:.1f} s wall, {conv} converged",
-                cpu=platform.processor() or platform.machine())
+    model, _ = cpu_info()
+    return dict(value=conv / dt, unit="solves/s", cores=min(threads, len(idx)), kind="oracle",
+                sample=f"{len(idx)} {w.name} instances drawn uniformly (seeded) from {w.n_inst}, dense FP64 "
+                       f"oracle, one instance per thread, {dt:.1f} s wall, {conv} converged, "
+                       f"{int(o['iters'].sum())} iterations",
+                cpu=model, host_threads=threads)
 
 
 def main():
@@ -125,19 +150,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--workload", default="C2", help="workload of the plain FP64 cold-start leg (`value`)")
     ap.add_argument("--slots", type=int, default=0, help="concurrent slots (default: all instances)")
     ap.add_argument("--instances", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle instances for the CPU baseline (default: about 10-30 s of host work per workload)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm/mixed (C5) leg")
+    ap.add_argument("--no-phase-leg", action="store_true", help="skip the per-phase-kernel leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration) and exit")
     ap.add_argument("--precision", type=int, default=None,
-                    help="KKT factor precision: 0 FP64, 1 FP32 + FP64 refinement (default: the workload's)")
+                    help="KKT factor precision of the plain leg: 0 FP64, 1 FP32 + FP64 refinement (default 0)")
     ap.add_argument("--train", type=int, default=190000, help="warm-start training instances (C5)")
     ap.add_argument("--val", type=int, default=10000, help="warm-start validation instances (C5)")
     ap.add_argument("--epochs", type=int, default=30, help="warm-start training epochs (C5)")
+    ap.add_argument("--oracle-check", type=int, default=1024, help="C5 instances re-solved by the oracle")
     ap.add_argument("--fuse-below", type=int, default=None,
                     help="unfinished-instance count below which passes use the fused kernel (default: library's)")
     args = ap.parse_args()
@@ -162,26 +190,21 @@ def main():
     n_inst = args.instances or w.n_inst
     slots = args.slots or n_inst
     TH = torch.tensor(w.thetas(0, n_inst), dtype=torch.float64, device="cuda:0")
-    opts = dict(timing=1)
-    opts["precision"] = args.precision if args.precision is not None else (1 if w.precision == "fp32ir" else 0)
+    opts = dict(timing=1, precision=args.precision or 0)
     if args.fuse_below is not None:
         opts["fuse_below"] = args.fuse_below
-    log(f"[bench] workload {w.name}: {n_inst} instances, N={w.N}, n={w.n}, m={w.m}, slots={slots}")
-    extra = {}
-    warm_fn = None
-    if w.name == "C5":
-        warm_fn, extra = setup_warm_start(w, TH, slots, opts, args)
+    log(f"[bench] plain leg {w.name}: {n_inst} instances, N={w.N}, n={w.n}, m={w.m}, slots={slots}")
     solver = hipipm.Solver(w, slots, hipipm.default_options(**opts))
-    dt, conv, out, st, kt = time_solves(solver, TH, args.steps, args.warmup, warm_fn)
+    dt, conv, out, st, kt = time_solves(solver, TH, args.steps, args.warmup)
     log(f"[bench] timed {args.steps} steps in {dt:.3f} s; stats {st}; kernel ms {kt}")
-    roof = kernel_roofline(w, st, kt, min(slots, n_inst), rec_bytes=4.0 if opts["precision"] == 1 else 8.0)
-    mt = MEASURED_TRAFFIC.get(roof["kernel"])
+    dom, roofs = kernel_roofline(w, st, kt, word_bytes=4.0 if opts["precision"] == 1 else 8.0)
+    roof = roofs[dom]
+    mt = MEASURED_TRAFFIC.get(dom)
     if mt and mt["csrc"] == csrc_hash() and mt["workload"] == w.name and n_inst == w.n_inst and slots == n_inst:
         roof["traffic"] = mt["bytes_per_launch"]
     kkt = out["kkt"].cpu().numpy()
     status = out["status"].cpu().numpy()
-    desc = {"C2": "C2: figure-eight tracking NMPC, FP64 cold start",
-            "C5": "C5: point-to-point NMPC, learned BF16 warm start + FP32 factor with FP64 refinement"}
+    desc = {"C2": "C2: figure-eight tracking NMPC, FP64 cold start"}
     res = {
         "metric": "converged NLP solves/sec on 1 MI355X at KKT tol 1e-8 (plain vs warm/mixed)",
         "value": conv / dt,
@@ -196,31 +219,103 @@ def main():
         "dtype": "f64" if opts["precision"] == 0 else "f32 factor + f64 refinement",
         "data": "synthetic",
         "config": {"workload": desc.get(w.name, w.name), "instances": n_inst, "horizon_N": w.N, "n_obs": w.n_obs,
-                   "n": w.n, "m": w.m, "slots": slots},
+                   "n": w.n, "m": w.m, "slots": slots,
+                   "obstacles": "centres on the reference path + N(0, 0.5^2 I), kept 0.1 m from the start and "
+                                "0.3 m from the first 0.5 s of the reference"},
         "iterations_per_sec": st["iterations"] / dt,
         "iterations_per_solve": float(out["iters"].float().mean().item()),
         "converged_fraction": float((status == 1).mean()),
+        "status_histogram": {hipipm.STATUS[k]: int((status == k).sum()) for k in sorted(hipipm.STATUS)},
         "max_kkt_converged": float(kkt[status == 1].max()) if (status == 1).any() else None,
         "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-        "roofline_kernel": roof["kernel"],
-        "roofline_detail": {k: roof[k] for k in ("avg_ms", "launches", "bytes_per_launch", "units") if k in roof},
+        "roofline_kernel": dom,
+        "roofline_detail": {k: roof[k] for k in ("avg_ms", "launches", "bytes_per_launch", "units", "fp64_tflops",
+                                                 "fp64_frac", "share_of_gpu_time")},
         "kernel_ms": {k: v[0] for k, v in kt.items()},
+        "stats": {k: st[k] for k in ("iterations", "resto_iterations", "resto_entries", "soc_tried", "soc_accepted",
+                                     "tiny_steps", "factorizations", "passes")},
     }
-    if warm_fn is not None:
-        res["warm_start"] = dict(extra, warm_started=st["warm_started"], warm_rejected=st["warm_rejected"],
-                                 warm_restarts=st["warm_restarts"],
-                                 fallback_rate=(st["warm_rejected"] + st["warm_restarts"]) / max(1, st["instances_done"]))
-        res["variants"] = compare_variants(w, TH, slots, out, args, extra, warm_fn)
-        res["variants"]["warm_fp32ir"] = dict(solves_per_sec=res["value"],
-                                              iterations_per_solve=res["iterations_per_solve"],
-                                              max_iterations=int(out["iters"].max().item()),
-                                              converged_fraction=res["converged_fraction"],
-                                              passes_per_solve=st["passes"] / args.steps,
-                                              fp64_fallbacks=st["fp64_fallbacks"], warm_restarts=st["warm_restarts"])
+    if not args.no_phase_leg:
+        res["per_phase_leg"] = phase_leg(w, TH, slots)
+    if not args.no_warm:
+        res["warm_mixed"] = warm_mixed_leg(args)
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(w, args.cpu_sample or CPU_SAMPLE.get(w.name, 64))
+        _, threads = cpu_info()
+        res["cpu_baseline"] = cpu_baseline(w, args.cpu_sample or CPU_SAMPLE.get(w.name, 64), threads)
     print(json.dumps(res), flush=True)
+
+
+# oracle sample sizes sized to about 10-30 s of host work (dense FP64 factorizations grow with N^3)
+CPU_SAMPLE = {"C1": 64, "C2": 64, "C4": 32}
+
+
+def phase_leg(w, TH, slots):
+    """One solve of the plain workload with the per-phase kernels (no fused pass kernel), so that
+    the factorization (k_fac) and the solve (k_sol) have launch durations and rooflines of their own."""
+    from paper_2606_26341_amd import hipipm
+    s = hipipm.Solver(w, slots, hipipm.default_options(timing=1, fuse_below=0))
+    dt, conv, out, st, kt = time_solves(s, TH, 1, 1)
+    _, roofs = kernel_roofline(w, st, kt)
+    log(f"[bench] per-phase leg: {dt * 1e3:.1f} ms, kernel ms {kt}")
+    return dict(ms_per_step=dt * 1e3, solves_per_sec=conv / dt, kernel_ms={k: v[0] for k, v in kt.items()},
+                rooflines={k: {q: v[q] for q in ("achieved", "frac", "avg_ms", "launches", "bytes_per_launch",
+                                                 "fp64_tflops", "share_of_gpu_time")} for k, v in roofs.items()})
+
+
+def warm_mixed_leg(args):
+    """The warm/mixed form on C5: network forward pass + warm-started FP32-factor / FP64-refinement
+    solve of 16384 instances, beside the cold FP64 solve of the same instances, with the oracle's
+    warm solves from the same network rows on a subsample."""
+    import torch
+    from paper_2606_26341_amd import hipipm, workloads as W
+    w = W.get("C5")
+    TH = torch.tensor(w.thetas(0, w.n_inst), dtype=torch.float64, device="cuda:0")
+    opts = dict(timing=1, precision=1)
+    warm_fn, extra = setup_warm_start(w, TH, opts, args)
+    s = hipipm.Solver(w, w.n_inst, hipipm.default_options(**opts))
+    dt, conv, out, st, kt = time_solves(s, TH, args.steps, args.warmup, warm_fn)
+    log(f"[bench] warm/mixed: {args.steps} steps in {dt:.3f} s; stats {st}")
+    res = dict(workload="C5: point-to-point NMPC, 16384 instances, N = 10, 3 obstacles; learned BF16 warm start "
+                        "+ FP32 factor with FP64 refinement",
+               solves_per_sec=conv / dt, ms_per_step=dt * 1e3 / args.steps,
+               iterations_per_solve=float(out["iters"].float().mean().item()),
+               max_iterations=int(out["iters"].max().item()),
+               converged_fraction=float((out["status"] == 1).float().mean().item()),
+               passes_per_solve=st["passes"] / args.steps,
+               warm_started=st["warm_started"], warm_rejected=st["warm_rejected"],
+               warm_restarts=st["warm_restarts"],
+               fallback_rate=(st["warm_rejected"] + st["warm_restarts"]) / max(1, st["instances_done"]),
+               fp64_refactorizations=st["fp64_fallbacks"], fp32_retakes=st["fp32_retakes"],
+               refine_sweeps_per_solve=st["refine_sweeps"] / max(1, st["solves"] + st["soc_tried"]),
+               setup=extra)
+    res["variants"] = compare_variants(w, TH, out, args, extra, warm_fn)
+    res["oracle_check"] = oracle_check(w, TH, out, warm_fn, extra, args.oracle_check)
+    return res
+
+
+def oracle_check(w, TH, out, warm_fn, extra, count):
+    """The oracle's warm solves from the same network rows (same warm options) on the first `count`
+    instances against the GPU's warm FP32 + refinement results: status, KKT point, and E_0 of the
+    GPU point recomputed by the oracle."""
+    import oracle
+    rows = warm_fn(TH[:count]).cpu().numpy()
+    th = TH[:count].cpu().numpy()
+    _, threads = cpu_info()
+    o = oracle.solve_quad(w, th, threads=threads, warm=rows,
+                          opts=oracle.default_opts(warm_mu0=extra["warm_mu0"], warm_iter_cap=extra["warm_iter_cap"]))
+    g = {k: out[k][:count].cpu().numpy() for k in ("status", "obj", "x", "y", "zl", "zu", "iters")}
+    same_status = int((g["status"] == o["status"]).sum())
+    both = np.flatnonzero((g["status"] == 1) & (o["status"] == 1))
+    rel = np.abs(g["obj"][both] - o["obj"][both]) / np.maximum(1.0, np.abs(o["obj"][both]))
+    dx = np.abs(g["x"][both] - o["x"][both]).max(axis=1)
+    e0 = [oracle.kkt_error(w, th[i], g["x"][i], g["y"][i], g["zl"][i], g["zu"][i]) for i in both]
+    return dict(instances=count, same_status=same_status, both_converged=int(both.size),
+                same_point=int(((rel <= 1e-6) & (dx <= 1e-5)).sum()),
+                max_rel_obj=float(rel.max()) if both.size else None, max_dx=float(dx.max()) if both.size else None,
+                max_e0_gpu_point=float(max(e0)) if e0 else None,
+                same_iterations=int((g["iters"] == o["iters"]).sum()),
+                oracle_warm_rejected=int(o["stats"][:, 9].sum()))
 
 
 def time_solves(solver, TH, steps, warmup, warm_fn=None):
@@ -246,7 +341,7 @@ def time_solves(solver, TH, steps, warmup, warm_fn=None):
     return dt, conv, out, solver.stats(), solver.kernel_times()
 
 
-def setup_warm_start(w, TH, slots, opts, args):
+def setup_warm_start(w, TH, opts, args):
     """Outside the timed region: solve the training and validation splits cold (FP64) on the GPU,
     train the network on the converged training solutions, pick the warm barrier parameter and the
     divergence cap on the validation split.  Returns the warm-point function and a summary."""
@@ -284,7 +379,7 @@ def setup_warm_start(w, TH, slots, opts, args):
     return ws.predict, summary
 
 
-def compare_variants(w, TH, slots, warm_out, args, extra, warm_fn):
+def compare_variants(w, TH, warm_out, args, extra, warm_fn):
     """Cold/warm x FP64/FP32+refinement on the same instances, timed the same way, and the share of
     instances where the warm FP32 solve reaches the cold FP64 solve's KKT point."""
     import torch
@@ -297,7 +392,7 @@ def compare_variants(w, TH, slots, warm_out, args, extra, warm_fn):
         if warm:
             o.update(warm_mu0=extra["warm_mu0"], warm_iter_cap=extra["warm_iter_cap"])
             fn = warm_fn
-        s = hipipm.Solver(w, slots, hipipm.default_options(**o))
+        s = hipipm.Solver(w, TH.shape[0], hipipm.default_options(**o))
         dt, conv, out, st, _ = time_solves(s, TH, args.steps, 1, fn)
         res[name] = dict(solves_per_sec=conv / dt, iterations_per_solve=float(out["iters"].float().mean().item()),
                          max_iterations=int(out["iters"].max().item()),

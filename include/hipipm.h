@@ -54,7 +54,6 @@ extern "C" {
 #define HIPIPM_STATUS_RESTO_FAILED 3    /* restoration could not start or its line search failed */
 #define HIPIPM_STATUS_INFEASIBLE 4      /* restoration converged to a point that is not feasible */
 #define HIPIPM_STATUS_NUMERICAL 5       /* non-finite values in the iterate */
-#define HIPIPM_STATUS_FILTER_OVERFLOW 6 /* more non-dominated filter pairs than filter_cap */
 
 /* ---- problem families ---- */
 #define HIPIPM_FAMILY_QUAD_OBS 0   /* point-to-point with spherical obstacles;
@@ -83,7 +82,6 @@ typedef struct {
     double gamma_theta, gamma_phi, delta_sw, s_theta, s_phi, eta_phi, gamma_alpha;
     int32_t max_soc;
     double kappa_soc, kappa_sigma, rho_resto, kappa_resto, bound_mult_reset;
-    int32_t filter_cap;   /* <= 128 */
     int32_t poll_every;   /* iterations between completion polls (>= 1) */
     int32_t timing;       /* 1: time every kernel launch with HIP events (hipipm_kernel_times) */
     int32_t fuse_below;   /* once at most this many instances are unfinished, each pass runs the
@@ -98,6 +96,10 @@ typedef struct {
     double warm_push;     /* bound push (kappa_1 = kappa_2) of a warm start (default 1e-3) */
     int32_t warm_iter_cap; /* a warm-started instance still running after this many iterations, or
                               entering restoration, restarts cold in its slot (0: only restoration) */
+    int32_t warm_gate;    /* 1 (default): a warm point is kept only if its scaled error E_mu0 at
+                             mu0 = warm_mu0 does not exceed that of the cold start (cold start with
+                             least-squares y, z = 1), which costs the cold start's least-squares
+                             pass; 0: every finite warm point is used */
 } hipipm_options;
 
 typedef struct {
@@ -113,8 +115,10 @@ typedef struct {
     int64_t refine_sweeps;           /* precision 1: refinement sweeps (each one FP32 solve) */
     int64_t fp64_fallbacks;          /* precision 1: iterations refactored in FP64 after refinement failed */
     int64_t warm_started;            /* instances started from a warm point */
-    int64_t warm_rejected;           /* warm points rejected at initialisation (non-finite) -> cold */
+    int64_t warm_rejected;           /* warm points rejected (non-finite, or by the gate) -> cold */
     int64_t warm_restarts;           /* warm starts that diverged and restarted cold */
+    int64_t fp32_retakes;            /* precision 1: FP32 inertia verdicts (wrong inertia, or a pivot
+                                        too close to zero for FP32) taken again in FP64 */
 } hipipm_stats;
 
 typedef struct hipipm_ctx hipipm_ctx;
@@ -176,18 +180,29 @@ int hipipm_kernel_times(const hipipm_ctx* ctx, int32_t* n_kernels, double* total
 
 /* ---- test hooks (one-step replay, Sec. VI "Correctness") ----
  * A flat FP64 state per slot in the oracle's field order:
- *   header[16]: phase, iter, status, init_filter, theta_R
- *   main : mu, tau, dx_last, theta_max, theta_min, tiny, nf, 0 | x[n] y[m] zl[n] zu[n] | fth[128] fph[128]
+ *   header[16]: phase, iter, status, init_filter, theta_R, warm, warm-gate stage, 0...
+ *   main : mu, tau, dx_last, theta_max, theta_min, tiny, nf, 0 | x[n] y[m] zl[n] zu[n] | fth[F] fph[F]
  *   resto: same with n + 2m variables (x, p, n)
  *   x_R[n], DR2[n]
+ * with F = max_iter + 2 filter pairs (the filter is never full: each pair comes from an accepted
+ * iteration or a restoration entry).  A warm start's gate data are not part of the state.
  * hipipm_state_len gives its length.  hipipm_state_import loads `count` states (host pointer,
  * [count][len]) into slots 0..count-1 (theta from the device pointer, [count][n_theta]);
- * hipipm_step runs `passes` passes of the iteration pipeline on those slots without refill;
- * hipipm_state_export copies the slot states back (host pointer). */
+ * hipipm_start instead starts instances 0..count-1 of theta (device, [count][n_theta]) and warm
+ * (device, [count][n_w + m] or NULL; as in hipipm_solve) in slots 0..count-1 without running a
+ * pass; hipipm_step runs `passes` passes of the iteration pipeline on those slots without refill,
+ * with the kernels a solve uses (the fused pass kernel when options.precision = 1 or
+ * options.fuse_below > 0, the per-phase kernels otherwise); theta and warm (device, may be NULL
+ * for warm) are the rows of slot i's instance i, read by a cold restart and by the warm-start gate;
+ * hipipm_state_export copies the slot states back (host pointer).  Errors: INVALID_ARG for a NULL
+ * context, count outside [0, slots], negative passes, NULL theta (count > 0) or states; WORKSPACE
+ * without a bound workspace; HIP when a HIP call fails. */
 int hipipm_state_len(const hipipm_ctx* ctx, int32_t* len);
 int hipipm_state_import(hipipm_ctx* ctx, int32_t count, const double* states_host, const double* theta_dev,
                         void* stream);
-int hipipm_step(hipipm_ctx* ctx, int32_t count, int32_t passes, void* stream);
+int hipipm_start(hipipm_ctx* ctx, int32_t count, const double* theta, const double* warm, void* stream);
+int hipipm_step(hipipm_ctx* ctx, int32_t count, int32_t passes, const double* theta, const double* warm,
+                void* stream);
 int hipipm_state_export(hipipm_ctx* ctx, int32_t count, double* states_host, void* stream);
 
 /* Raw structured KKT factor + solve for kernel parity: for `count` instances (device pointers)

@@ -1,15 +1,20 @@
-"""Build libhipipm.so for gfx950 with hipcc (in-tree, next to this file)."""
+"""Build libhipipm.so for gfx950 with hipcc (in-tree, next to this file).
+
+Each source is compiled to an object of its own in parallel (kernels are launched only from the
+source that defines them), then the objects are linked into the shared library."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhipipm.so")
-SOURCES = [os.path.join(HERE, "csrc", "api.hip"), os.path.join(HERE, "csrc", "kernels.hip"),
-           os.path.join(HERE, "csrc", "mlp.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in
+           ("iter_fp64.hip", "iter_mixed.hip", "kernels.hip", "api.hip", "mlp.hip")]
+BUILD_DIR = os.path.join(HERE, "_build")
 
 
 def hipcc() -> str:
@@ -19,12 +24,26 @@ def hipcc() -> str:
     return "hipcc"
 
 
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         # packed FP32 instructions stay off on this target
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
 def build_library(verbose: bool = False) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = [os.path.join(BUILD_DIR, os.path.basename(s) + ".o") for s in SOURCES]
+
+    def compile_one(pair):
+        src, obj = pair
+        cmd = [hipcc()] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+
+    with ThreadPoolExecutor(len(SOURCES)) as ex:
+        list(ex.map(compile_one, zip(SOURCES, objs)))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           # packed FP32 instructions stay off on this target
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), "-o", tmp] + SOURCES
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

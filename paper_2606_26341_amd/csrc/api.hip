@@ -19,7 +19,7 @@ void launch_eval(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                 Counters* cnt, int refill, hipStream_t st);
 void launch_fac(const Cfg& c, double* ws, int slots, hipStream_t st);
-void launch_sol(const Cfg& c, double* ws, int slots, hipStream_t st);
+void launch_sol(const Cfg& c, double* ws, int slots, const double* warm, hipStream_t st);
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                  Counters* cnt, int refill, hipStream_t st);
@@ -84,7 +84,7 @@ static void layout(Cfg& c) {
   const int n = c.n, m = c.m, N = c.N, NI = c.NI;
   c.o_sc = take(SC_LEN);
   c.o_v = take(n); c.o_y = take(m); c.o_zlu = take(N * NU); c.o_zuu = take(N * NU); c.o_zls = take(N * NI);
-  c.o_th = take(c.n_theta); c.o_fm = take(2 * FCAP); c.o_fr = take(2 * FCAP);
+  c.o_th = take(c.n_theta); c.o_fm = take(2 * c.fc); c.o_fr = take(2 * c.fc);
   c.o_yr = take(m); c.o_rzlu = take(N * NU); c.o_rzuu = take(N * NU); c.o_rzls = take(N * NI);
   c.o_xr = take(n); c.o_p = take(m); c.o_nn = take(m); c.o_zp = take(m); c.o_zn = take(m);
   c.o_F = take(N * NX); c.o_G = take(N * NX * NZ); c.o_HW = take(N * NZ * NZ);
@@ -111,10 +111,10 @@ int hipipm_default_options(hipipm_options* o) {
   o->kappa_minus = 1.0 / 3.0; o->kappa_plus = 8.0; o->kappa_plus_bar = 100.0;
   o->gamma_theta = 1e-5; o->gamma_phi = 1e-8; o->delta_sw = 1.0; o->s_theta = 1.1; o->s_phi = 2.3;
   o->eta_phi = 1e-8; o->gamma_alpha = 0.05; o->max_soc = 4; o->kappa_soc = 0.99; o->kappa_sigma = 1e10;
-  o->rho_resto = 1000.0; o->kappa_resto = 0.9; o->bound_mult_reset = 1e3; o->filter_cap = 128;
+  o->rho_resto = 1000.0; o->kappa_resto = 0.9; o->bound_mult_reset = 1e3;
   o->poll_every = 4; o->timing = 0; o->fuse_below = 1 << 30;
   o->precision = 0; o->refine_max = 3; o->refine_tol = 1e-10;
-  o->warm_mu0 = 1e-3; o->warm_push = 1e-3; o->warm_iter_cap = 0;
+  o->warm_mu0 = 1e-3; o->warm_push = 1e-3; o->warm_iter_cap = 0; o->warm_gate = 1;
   return HIPIPM_OK;
 }
 
@@ -125,9 +125,9 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   if (d->n_agents != 1) return HIPIPM_ERR_UNSUPPORTED;
   if (d->N < 1 || d->N > MAX_N || d->n_obs < 0 || d->n_obs > MAX_OBS) return HIPIPM_ERR_INVALID_ARG;
   if (!(d->dt > 0) || !(d->mass > 0) || !(d->jxx > 0) || !(d->jyy > 0) || !(d->jzz > 0)) return HIPIPM_ERR_INVALID_ARG;
-  if (o->filter_cap < 1 || o->filter_cap > FCAP || o->max_iter < 0 || o->poll_every < 1 || !(o->tol > 0) ||
+  if (o->max_iter < 0 || o->max_iter > (1 << 24) || o->poll_every < 1 || !(o->tol > 0) ||
       o->fuse_below < 0 || o->precision < 0 || o->precision > 1 || o->refine_max < 0 || !(o->refine_tol > 0) ||
-      !(o->warm_mu0 > 0) || !(o->warm_push > 0) || o->warm_iter_cap < 0)
+      !(o->warm_mu0 > 0) || !(o->warm_push > 0) || o->warm_iter_cap < 0 || o->warm_gate < 0 || o->warm_gate > 1)
     return HIPIPM_ERR_INVALID_ARG;
   hipipm_ctx* c = new hipipm_ctx();
   c->desc = *d;
@@ -158,9 +158,9 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   g.gamma_theta = o->gamma_theta; g.gamma_phi = o->gamma_phi; g.delta_sw = o->delta_sw; g.s_theta = o->s_theta;
   g.s_phi = o->s_phi; g.eta_phi = o->eta_phi; g.gamma_alpha = o->gamma_alpha; g.max_soc = o->max_soc;
   g.kappa_soc = o->kappa_soc; g.kappa_sigma = o->kappa_sigma; g.rho_resto = o->rho_resto;
-  g.kappa_resto = o->kappa_resto; g.bound_mult_reset = o->bound_mult_reset; g.fcap = o->filter_cap;
+  g.kappa_resto = o->kappa_resto; g.bound_mult_reset = o->bound_mult_reset; g.fc = o->max_iter + 2;
   g.prec = o->precision; g.refine_max = o->refine_max; g.refine_tol = o->refine_tol;
-  g.warm_mu0 = o->warm_mu0; g.warm_push = o->warm_push; g.warm_cap = o->warm_iter_cap;
+  g.warm_mu0 = o->warm_mu0; g.warm_push = o->warm_push; g.warm_cap = o->warm_iter_cap; g.warm_gate = o->warm_gate;
   layout(g);
   size_t rec = (size_t)g.stride * sizeof(double) * (size_t)slots;
   c->cnt_off = (rec + 255) / 256 * 256;
@@ -264,7 +264,7 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
         if (timing) HIPCHK(c, hipEventRecord(e[2], st));
         launch_fac(c->cfg, c->ws, active, st);
         if (timing) HIPCHK(c, hipEventRecord(e[3], st));
-        launch_sol(c->cfg, c->ws, active, st);
+        launch_sol(c->cfg, c->ws, active, warm, st);
         if (timing) HIPCHK(c, hipEventRecord(e[4], st));
         launch_ls(c->cfg, c->ws, active, st);
         if (timing) HIPCHK(c, hipEventRecord(e[5], st));
@@ -337,6 +337,7 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   c->stats.warm_started += (int64_t)h.st[14];
   c->stats.warm_rejected += (int64_t)h.st[15];
   c->stats.warm_restarts += (int64_t)h.st[16];
+  c->stats.fp32_retakes += (int64_t)h.st[17];
   return HIPIPM_OK;
 }
 
@@ -368,8 +369,8 @@ int hipipm_kernel_times(const hipipm_ctx* c, int32_t* n_kernels, double* total_m
 // ------------------------------------------------------------------ state replay hooks
 static int state_len_of(const Cfg& g) {
   int n = g.n, m = g.m;
-  int sub_main = 8 + 3 * n + m + 2 * FCAP;
-  int sub_resto = 8 + 3 * (n + 2 * m) + m + 2 * FCAP;
+  int sub_main = 8 + 3 * n + m + 2 * g.fc;
+  int sub_resto = 8 + 3 * (n + 2 * m) + m + 2 * g.fc;
   return 16 + sub_main + sub_resto + 2 * n;
 }
 
@@ -414,6 +415,7 @@ int hipipm_state_export(hipipm_ctx* c, int32_t count, double* out, void* stream)
     int ph = (int)sc[SC_PHASE];
     o[0] = ph >= PH_FINISH ? 3 : ph;
     o[1] = sc[SC_ITER]; o[2] = sc[SC_STATUS]; o[3] = sc[SC_INITF]; o[4] = sc[SC_THR];
+    o[5] = sc[SC_WARM]; o[6] = sc[SC_WSTAGE];
     const bool resto = ph == PH_RESTO;
     double* p = o + 16;
     // main
@@ -423,9 +425,9 @@ int hipipm_state_export(hipipm_ctx* c, int32_t count, double* out, void* stream)
     memcpy(p, rec.data() + (resto ? g.o_xr : g.o_v), n * sizeof(double)); p += n;
     memcpy(p, rec.data() + g.o_y, m * sizeof(double)); p += m;
     zfull_from(g, rec.data(), g.o_zlu, g.o_zuu, g.o_zls, p, p + n); p += 2 * n;
-    for (int i = 0; i < FCAP; ++i) { p[i] = rec[g.o_fm + i]; p[FCAP + i] = rec[g.o_fm + FCAP + i]; }
-    for (int i = (int)sc[SC_NF]; i < FCAP; ++i) { p[i] = 0.0; p[FCAP + i] = 0.0; }
-    p += 2 * FCAP;
+    for (int i = 0; i < g.fc; ++i) { p[i] = rec[g.o_fm + i]; p[g.fc + i] = rec[g.o_fm + g.fc + i]; }
+    for (int i = (int)sc[SC_NF]; i < g.fc; ++i) { p[i] = 0.0; p[g.fc + i] = 0.0; }
+    p += 2 * g.fc;
     // restoration
     p[0] = sc[SC_RMU]; p[1] = sc[SC_RTAU]; p[2] = sc[SC_RDXL]; p[3] = sc[SC_RTHMAX]; p[4] = sc[SC_RTHMIN];
     p[5] = sc[SC_RTINY]; p[6] = sc[SC_RNF];
@@ -446,9 +448,9 @@ int hipipm_state_export(hipipm_ctx* c, int32_t count, double* out, void* stream)
       memcpy(p + NR, zu.data(), n * sizeof(double));
     }
     p += 2 * NR;
-    for (int i = 0; i < FCAP; ++i) { p[i] = rec[g.o_fr + i]; p[FCAP + i] = rec[g.o_fr + FCAP + i]; }
-    for (int i = (int)sc[SC_RNF]; i < FCAP; ++i) { p[i] = 0.0; p[FCAP + i] = 0.0; }
-    p += 2 * FCAP;
+    for (int i = 0; i < g.fc; ++i) { p[i] = rec[g.o_fr + i]; p[g.fc + i] = rec[g.o_fr + g.fc + i]; }
+    for (int i = (int)sc[SC_RNF]; i < g.fc; ++i) { p[i] = 0.0; p[g.fc + i] = 0.0; }
+    p += 2 * g.fc;
     memcpy(p, rec.data() + g.o_xr, n * sizeof(double)); p += n;
     for (int i = 0; i < n; ++i) {
       double d = std::fmin(1.0, 1.0 / std::fabs(rec[g.o_xr + i]));
@@ -474,6 +476,7 @@ int hipipm_state_import(hipipm_ctx* c, int32_t count, const double* in, const do
     int ph = (int)o[0];
     sc[SC_PHASE] = ph == 3 ? PH_FINISH : ph;
     sc[SC_ITER] = o[1]; sc[SC_STATUS] = o[2]; sc[SC_INITF] = o[3]; sc[SC_THR] = o[4];
+    sc[SC_WARM] = o[5]; sc[SC_WSTAGE] = o[6];
     sc[SC_INST] = s;
     const bool resto = ph == PH_RESTO;
     const double* p = o + 16;
@@ -484,8 +487,8 @@ int hipipm_state_import(hipipm_ctx* c, int32_t count, const double* in, const do
     p += n;
     memcpy(rec.data() + g.o_y, p, m * sizeof(double)); p += m;
     zfull_to(g, rec.data(), g.o_zlu, g.o_zuu, g.o_zls, p, p + n); p += 2 * n;
-    for (int i = 0; i < 2 * FCAP; ++i) rec[g.o_fm + i] = p[i];
-    p += 2 * FCAP;
+    for (int i = 0; i < 2 * g.fc; ++i) rec[g.o_fm + i] = p[i];
+    p += 2 * g.fc;
     sc[SC_RMU] = p[0]; sc[SC_RTAU] = p[1]; sc[SC_RDXL] = p[2]; sc[SC_RTHMAX] = p[3]; sc[SC_RTHMIN] = p[4];
     sc[SC_RTINY] = p[5]; sc[SC_RNF] = p[6];
     p += 8;
@@ -496,8 +499,8 @@ int hipipm_state_import(hipipm_ctx* c, int32_t count, const double* in, const do
     memcpy(rec.data() + g.o_zp, p + n, m * sizeof(double));
     memcpy(rec.data() + g.o_zn, p + n + m, m * sizeof(double));
     p += 2 * NR;
-    for (int i = 0; i < 2 * FCAP; ++i) rec[g.o_fr + i] = p[i];
-    p += 2 * FCAP;
+    for (int i = 0; i < 2 * g.fc; ++i) rec[g.o_fr + i] = p[i];
+    p += 2 * g.fc;
     memcpy(rec.data() + g.o_xr, p, n * sizeof(double));
     if (resto) {
       memcpy(rec.data() + g.o_v, rx, n * sizeof(double));
@@ -517,18 +520,37 @@ int hipipm_state_import(hipipm_ctx* c, int32_t count, const double* in, const do
   return HIPIPM_OK;
 }
 
-int hipipm_step(hipipm_ctx* c, int32_t count, int32_t passes, void* stream) {
-  if (!c || count < 0 || count > c->slots || passes < 0) return HIPIPM_ERR_INVALID_ARG;
+int hipipm_start(hipipm_ctx* c, int32_t count, const double* theta, const double* warm, void* stream) {
+  if (!c || count < 0 || count > c->slots || (count > 0 && !theta)) return HIPIPM_ERR_INVALID_ARG;
+  if (!c->ws) return fail(c, HIPIPM_ERR_WORKSPACE, "no workspace bound");
+  if (count == 0) return HIPIPM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  launch_setup(c->cfg, c->ws, count, count, theta, warm, st);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(st));
+  return HIPIPM_OK;
+}
+
+int hipipm_step(hipipm_ctx* c, int32_t count, int32_t passes, const double* theta, const double* warm,
+                void* stream) {
+  if (!c || count < 0 || count > c->slots || passes < 0 || (count > 0 && !theta)) return HIPIPM_ERR_INVALID_ARG;
   if (!c->ws) return fail(c, HIPIPM_ERR_WORKSPACE, "no workspace bound");
   if (count == 0) return HIPIPM_OK;
   hipStream_t st = (hipStream_t)stream;
   Outs none{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // the same kernels as a solve: the fused pass kernel (precision 1, or fuse_below > 0), else
+  // the per-phase kernels; no refill (no counter block)
+  const bool fused = c->opts.precision == 1 || c->opts.fuse_below > 0;
   for (int p = 0; p < passes; ++p) {
     launch_eval(c->cfg, c->ws, count, st);
-    launch_pre(c->cfg, c->ws, count, nullptr, nullptr, none, nullptr, 0, st);
-    launch_fac(c->cfg, c->ws, count, st);
-    launch_sol(c->cfg, c->ws, count, st);
-    launch_ls(c->cfg, c->ws, count, st);
+    if (fused) {
+      launch_iter(c->cfg, c->ws, count, theta, warm, none, nullptr, 0, st);
+    } else {
+      launch_pre(c->cfg, c->ws, count, theta, warm, none, nullptr, 0, st);
+      launch_fac(c->cfg, c->ws, count, st);
+      launch_sol(c->cfg, c->ws, count, warm, st);
+      launch_ls(c->cfg, c->ws, count, st);
+    }
   }
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(st));

@@ -9,7 +9,6 @@ constexpr int NX = 13;   // states per quadrotor
 constexpr int NU = 4;    // rotor thrusts
 constexpr int NZ = NX + NU;
 constexpr int WAVE = 64;
-constexpr int FCAP = 128;
 constexpr int MAX_N = 64;
 constexpr int MAX_OBS = 64;
 
@@ -17,7 +16,7 @@ constexpr int MAX_OBS = 64;
 enum : int { PH_INIT_Y = 0, PH_REGULAR = 1, PH_RESTO = 2, PH_FINISH = 3, PH_EMPTY = 4 };
 // instance statuses (same values as the public HIPIPM_STATUS_*)
 enum : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAX_ITER = 2, ST_RESTO_FAILED = 3, ST_INFEASIBLE = 4,
-             ST_NUMERICAL = 5, ST_FILTER_OVERFLOW = 6 };
+             ST_NUMERICAL = 5 };
 // step flags handed from the factor kernel to the line-search kernel
 enum : int { STEP_NONE = 0, STEP_READY = 1, STEP_ICFAIL = 2 };
 // factorization request of the current pass (k_pre -> k_fac -> k_sol)
@@ -27,12 +26,16 @@ enum : int { W_NONE = 0, W_STEP = 1, W_LSQ = 2 };
 enum : int {
   SC_MU = 0, SC_TAU, SC_DXL, SC_THMAX, SC_THMIN, SC_TINY, SC_NF,           // main sub-problem
   SC_RMU = 8, SC_RTAU, SC_RDXL, SC_RTHMAX, SC_RTHMIN, SC_RTINY, SC_RNF,  // restoration sub-problem
-  SC_PHASE = 16, SC_STATUS, SC_ITER, SC_INST, SC_INITF, SC_THR, SC_OVERFLOW,
+  SC_PHASE = 16, SC_STATUS, SC_ITER, SC_INST, SC_INITF, SC_THR,
   SC_STEP = 24, SC_AMAX, SC_THK, SC_PHK, SC_GPHI, SC_FK, SC_STEPMU,
   SC_ST_RESTO = 32, SC_ST_SOCT, SC_ST_SOCA, SC_ST_FACT, SC_ST_RENT, SC_ST_TINY, SC_ST_PASS,
   SC_LDX = 40, SC_LDC, SC_LALPHA, SC_LALPHAZ, SC_LSOC, SC_WORK, SC_FSTAT,
   SC_ST_SOLV, SC_ST_FFACT, SC_ST_FSOLV, SC_FPREC, SC_FORCE64, SC_ST_REF, SC_ST_FB, SC_DXLSAVE,
   SC_WARM, SC_ST_WSTART, SC_ST_WREJ, SC_ST_WRST,
+  // warm-start gate: stage (1 cold reference running, 2 warm point waiting for the comparison),
+  // E_mu0 of the cold start, the cold start's filter bounds
+  SC_WSTAGE, SC_ECOLD, SC_CTHMAX, SC_CTHMIN,
+  SC_ST_RTK,   // FP32 inertia verdicts taken again in FP64
   SC_LEN = 64
 };
 
@@ -54,9 +57,10 @@ struct Cfg {
   double delta_min, delta_0, delta_max, delta_c_bar, kappa_c, kappa_minus, kappa_plus, kappa_plus_bar;
   double gamma_theta, gamma_phi, delta_sw, s_theta, s_phi, eta_phi, gamma_alpha;
   int max_soc; double kappa_soc, kappa_sigma, rho_resto, kappa_resto, bound_mult_reset;
-  int fcap;
+  int fc;                                    // filter capacity: max_iter + 2 pairs (never reached)
   int prec, refine_max; double refine_tol;   // KKT factor precision (1: FP32 + FP64 refinement)
   double warm_mu0, warm_push; int warm_cap;  // warm start: barrier parameter, bound push, iteration cap
+  int warm_gate;                             // keep a warm point only if E_mu0(warm) <= E_mu0(cold)
   // slot record layout, offsets in doubles
   long long stride;
   int o_v, o_y, o_zlu, o_zuu, o_zls, o_th, o_sc, o_fm, o_fr;
@@ -77,7 +81,7 @@ struct Outs {
 // global counters (device): queue head, finished count, stats
 struct Counters {
   int32_t head, done, n_inst, pad;
-  unsigned long long st[17];
+  unsigned long long st[18];
 };
 
 }  // namespace hipipm

@@ -1,22 +1,15 @@
-// gfx950 kernels of one fused batched interior-point iteration (Sec. V): every slot runs its
-// own branch of Table I inside the same launches, one 64-lane wavefront per slot.  One pass is
+// gfx950 kernels of one batched interior-point iteration (Sec. V) launched one per phase, the
+// derivative kernel, slot setup and the kernel-parity hooks, and the host launch wrappers.  One
+// pass is
 //
 //   k_eval   RK4 dynamics, Jacobian and Lagrangian-Hessian contraction per (slot, stage,
 //            direction) -- eq. (4) W and A = grad c
-//   k_pre    phase dispatch, result write-out + slot refill (iteration-level batching, Sec. V),
-//            convergence test (E_0), monotone barrier update (Table I row 7), right-hand side
-//            of eq. (7), perturbation-free stage data of the KKT matrix
-//   k_fac    inertia-correcting structured LDL^T of eq. (7) with slack condensation
-//   k_sol    step, bound-multiplier steps, fraction to the boundary; least-squares multipliers
-//   k_ls     tiny step (row 4), backtracking filter line search (row 1) with second-order
-//            correction (row 2), acceptance, restoration entry/exit (row 6)
+//   k_pre, k_fac, k_sol, k_ls   the per-slot phases of slot.h, one launch each, or
+//   k_iter   all four phases of a slot back to back (iter_fp64.hip, iter_mixed.hip)
 //
 // The factor and solve live in kernels of their own so that each gets the register budget of
-// its own working set.  Once few instances remain, k_iter runs k_pre .. k_ls of a slot back to
-// back in one launch.
-#include "common.h"
-#include "model.h"
-#include "kkt.h"
+// its own working set; the fused k_iter is the default for every pass.
+#include "slot.h"
 
 namespace hipipm {
 
@@ -53,392 +46,9 @@ __global__ __launch_bounds__(256) void k_eval(Cfg c, double* ws, int slots) {
   }
 }
 
-// ============================================================================ per-slot helpers
-__device__ __forceinline__ double fdiv_safe(double a, double b) { return a / b; }
-
-// -c at the current point into rc (restoration: -(c - p + n))
-__device__ __forceinline__ void eval_c(const Cfg& c, const Slot& s, bool resto, int lane) {
-  const int N = c.N, NI = c.NI;
-  for (int r = lane; r < (N + 1) * NX; r += WAVE) {
-    int k = r / NX, i = r % NX;
-    double cv = (k == 0) ? s.v[i] - s.th[i] : s.v[xo(k) + i] - s.F[(k - 1) * NX + i];
-    s.rc[r] = -cv;
-  }
-  for (int q = lane; q < N * NI; q += WAVE) {
-    int k = 1 + q / NI, j = q % NI;
-    const double* o = obs_ptr(c, s.th) + 4 * j;
-    double g = 0.0;
-    for (int t = 0; t < 3; ++t) { double e = s.v[xo(k) + t] - o[t]; g += e * e; }
-    s.rc[go(c, k, j)] = -(g - o[3] * o[3] - s.v[so(c, k, j)]);
-  }
-  __syncthreads();
-  if (resto)
-    for (int r = lane; r < c.m; r += WAVE) s.rc[r] += s.p[r] - s.nn[r];
-  __syncthreads();
-}
-
-// objective gradient g = grad f (regular) or grad f_R (restoration, v part) and A^T y into aty
-__device__ __forceinline__ void eval_grad(const Cfg& c, const Slot& s, const double* yv, bool resto, double zeta, double* aty,
-                          int lane) {
-  const int N = c.N, NI = c.NI;
-  for (int i = lane; i < c.n; i += WAVE) {
-    double gi = 0.0;
-    if (resto) {
-      double d = fmin(1.0, 1.0 / fabs(s.xr[i]));
-      gi = zeta * d * d * (s.v[i] - s.xr[i]);
-    } else if (i < c.n_w) {
-      int k = i / NZ, r = i % NZ;
-      if (r < NX) {
-        gi = 2.0 * c.qw * (s.v[i] - s.ref[k * NX + r]);
-      } else {
-        gi = 2.0 * c.rw * (s.v[i] - c.uh);
-      }
-    }
-    s.g[i] = gi;
-  }
-  // A^T y
-  for (int i = lane; i < c.n; i += WAVE) {
-    double a = 0.0;
-    if (i < c.n_w) {
-      int k = i / NZ, r = i % NZ;
-      if (r < NX) a += yv[k * NX + r];        // +I of the rows defining x_k
-      if (k < N) {
-        const double* Gk = s.G + (long long)k * NX * NZ;
-        for (int l = 0; l < NX; ++l) a -= Gk[l * NZ + r] * yv[(k + 1) * NX + l];
-      }
-      if (r < 3 && k >= 1) {
-        for (int j = 0; j < NI; ++j) {
-          const double* o = obs_ptr(c, s.th) + 4 * j;
-          a += 2.0 * (s.v[i] - o[r]) * yv[go(c, k, j)];
-        }
-      }
-    } else {
-      int q = i - c.n_w;
-      int k = 1 + q / NI, j = q % NI;
-      a = -yv[go(c, k, j)];
-    }
-    aty[i] = a;
-  }
-  __syncthreads();
-}
-
-// z_L / z_U of v component i (0 if unbounded)
-__device__ __forceinline__ void z_of(const Cfg& c, const Iter& it, int i, double& zl, double& zu) {
-  zl = zu = 0.0;
-  if (i < c.n_w) {
-    int k = i / NZ, r = i % NZ;
-    if (r >= NX && k < c.N) { zl = it.zlu[k * NU + r - NX]; zu = it.zuu[k * NU + r - NX]; }
-  } else {
-    zl = it.zls[i - c.n_w];
-  }
-}
-
-struct ErrParts {
-  double dual, prim, y1, z1;
-  int nL, nU;
-};
-
-__device__ __forceinline__ ErrParts err_parts(const Cfg& c, const Slot& s, const Iter& it, const double* aty, int lane) {
-  double dual = 0.0, nanf = 0.0, z1 = 0.0, y1 = 0.0, prim = 0.0;
-    for (int i = lane; i < c.n; i += WAVE) {
-    double zl, zu;
-    z_of(c, it, i, zl, zu);
-    double d = s.g[i] + aty[i] - zl + zu;
-    if (!isfinite(d)) nanf = 1.0;
-    dual = fmax(dual, fabs(d));
-    z1 += fabs(zl) + fabs(zu);
-  }
-    for (int r = lane; r < c.m; r += WAVE) {
-    y1 += fabs(it.y[r]);
-    double pr = fabs(s.rc[r]);
-    if (!isfinite(pr)) nanf = 1.0;
-    prim = fmax(prim, pr);
-    if (it.resto) {
-      double dp = c.rho_resto - it.y[r] - s.zp[r];
-      double dn = c.rho_resto + it.y[r] - s.zn[r];
-      dual = fmax(dual, fmax(fabs(dp), fabs(dn)));
-      z1 += fabs(s.zp[r]) + fabs(s.zn[r]);
-    }
-  }
-  ErrParts e;
-  e.dual = wmax(dual);
-  e.prim = wmax(prim);
-  e.y1 = wsum(y1);
-  e.z1 = wsum(z1);
-  if (wmax(nanf) > 0.0) e.dual = NAN;
-  e.nL = c.N * NU + c.N * c.NI + (it.resto ? 2 * c.m : 0);
-  e.nU = c.N * NU;
-  return e;
-}
-
-// max |s z - mu| over the bounded components
-__device__ __forceinline__ double compl_max(const Cfg& c, const Slot& s, const Iter& it, double mu, int lane) {
-  double cm = 0.0;
-    for (int b = lane; b < c.N * NU; b += WAVE) {
-    int k = b / NU, i = b % NU;
-    double u = s.v[uo(k) + i];
-    cm = fmax(cm, fabs(u * it.zlu[b] - mu));
-    cm = fmax(cm, fabs((c.umax - u) * it.zuu[b] - mu));
-  }
-    for (int q = lane; q < c.N * c.NI; q += WAVE) cm = fmax(cm, fabs(s.v[c.n_w + q] * it.zls[q] - mu));
-  if (it.resto)
-        for (int r = lane; r < c.m; r += WAVE) {
-      cm = fmax(cm, fabs(s.p[r] * s.zp[r] - mu));
-      cm = fmax(cm, fabs(s.nn[r] * s.zn[r] - mu));
-    }
-  return wmax(cm);
-}
-
-__device__ __forceinline__ double kkt_err(const Cfg& c, const ErrParts& e, double cm, int m) {
-  double sd = 1.0, sc = 1.0;
-  if (m + e.nL + e.nU > 0) sd = fmax(c.s_max, (e.y1 + e.z1) / (double)(m + e.nL + e.nU)) / c.s_max;
-  if (e.nL + e.nU > 0) sc = fmax(c.s_max, e.z1 / (double)(e.nL + e.nU)) / c.s_max;
-  double r = e.dual / sd;
-  if (isnan(e.dual)) return NAN;
-  r = fmax(r, e.prim);
-  r = fmax(r, cm / sc);
-  return r;
-}
-
-// objective value at v (regular) -- wave sum
-__device__ __forceinline__ double obj_regular(const Cfg& c, const Slot& s, const double* v, int lane) {
-  double f = 0.0;
-    for (int i = lane; i < c.n_w; i += WAVE) {
-    int k = i / NZ, r = i % NZ;
-    if (r < NX) {
-      double e = v[i] - s.ref[k * NX + r];
-      f += c.qw * e * e;
-    } else {
-      double e = v[i] - c.uh;
-      f += c.rw * e * e;
-    }
-  }
-  return wsum(f);
-}
-
-// restoration objective rho sum(p + n) + zeta/2 |D_R (v - x_R)|^2
-__device__ __forceinline__ double obj_resto(const Cfg& c, const Slot& s, const double* v, const double* p, const double* nn,
-                            double zeta, int lane) {
-  double a = 0.0, q = 0.0;
-    for (int r = lane; r < c.m; r += WAVE) a += p[r] + nn[r];
-    for (int i = lane; i < c.n; i += WAVE) {
-    double d = fmin(1.0, 1.0 / fabs(s.xr[i]));
-    double e = v[i] - s.xr[i];
-    q += d * d * e * e;
-  }
-  return c.rho_resto * wsum(a) + 0.5 * zeta * wsum(q);
-}
-
-// sum of log-slacks of the bounded components; NaN if one is not positive
-__device__ __forceinline__ double log_barrier(const Cfg& c, const double* v, const double* p, const double* nn, bool resto,
-                              int lane) {
-  double b = 0.0, bad = 0.0;
-    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
-    int k = bb / NU, i = bb % NU;
-    double u = v[uo(k) + i];
-    double sl = u, su = c.umax - u;
-    if (!(sl > 0.0) || !(su > 0.0)) bad = 1.0;
-    else b += log(sl) + log(su);
-  }
-    for (int q = lane; q < c.N * c.NI; q += WAVE) {
-    double sv = v[c.n_w + q];
-    if (!(sv > 0.0)) bad = 1.0;
-    else b += log(sv);
-  }
-  if (resto)
-        for (int r = lane; r < c.m; r += WAVE) {
-      if (!(p[r] > 0.0) || !(nn[r] > 0.0)) bad = 1.0;
-      else b += log(p[r]) + log(nn[r]);
-    }
-  if (wmax(bad) > 0.0) return NAN;
-  return wsum(b);
-}
-
-// primal fraction to the boundary over the bounded components of (dv, dp, dn)
-__device__ __forceinline__ double ftb_primal(const Cfg& c, const Slot& s, const double* dv, const double* dp, const double* dn,
-                             bool resto, double tau, int lane) {
-  double a = 1.0;
-    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
-    int k = bb / NU, i = bb % NU;
-    double u = s.v[uo(k) + i], d = dv[uo(k) + i];
-    if (d < 0) a = fmin(a, -tau * u / d);
-    if (d > 0) a = fmin(a, tau * (c.umax - u) / d);
-  }
-    for (int q = lane; q < c.N * c.NI; q += WAVE) {
-    double d = dv[c.n_w + q];
-    if (d < 0) a = fmin(a, -tau * s.v[c.n_w + q] / d);
-  }
-  if (resto)
-        for (int r = lane; r < c.m; r += WAVE) {
-      if (dp[r] < 0) a = fmin(a, -tau * s.p[r] / dp[r]);
-      if (dn[r] < 0) a = fmin(a, -tau * s.nn[r] / dn[r]);
-    }
-  return wmin(a);
-}
-
-// bound-multiplier steps (eq. (6) rows 3-4 eliminated): into dzlu, dzuu, dzls, dzp, dzn
-__device__ __forceinline__ void dz_recover(const Cfg& c, const Slot& s, const Iter& it, double mu, const double* dv,
-                           const double* dp, const double* dn, int lane) {
-  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
-    int k = bb / NU, i = bb % NU;
-    double u = s.v[uo(k) + i], d = dv[uo(k) + i];
-    double sl = u, su = c.umax - u;
-    s.dzlu[bb] = (mu - sl * it.zlu[bb] - it.zlu[bb] * d) / sl;
-    s.dzuu[bb] = (mu - su * it.zuu[bb] + it.zuu[bb] * d) / su;
-  }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) {
-    double sv = s.v[c.n_w + q], d = dv[c.n_w + q];
-    s.dzls[q] = (mu - sv * it.zls[q] - it.zls[q] * d) / sv;
-  }
-  if (it.resto)
-    for (int r = lane; r < c.m; r += WAVE) {
-      s.dzp[r] = (mu - s.p[r] * s.zp[r] - s.zp[r] * dp[r]) / s.p[r];
-      s.dzn[r] = (mu - s.nn[r] * s.zn[r] - s.zn[r] * dn[r]) / s.nn[r];
-    }
-  __syncthreads();
-}
-
-__device__ __forceinline__ double ftb_dual(const Cfg& c, const Slot& s, const Iter& it, double tau, int lane) {
-  double a = 1.0;
-    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
-    if (s.dzlu[bb] < 0) a = fmin(a, -tau * it.zlu[bb] / s.dzlu[bb]);
-    if (s.dzuu[bb] < 0) a = fmin(a, -tau * it.zuu[bb] / s.dzuu[bb]);
-  }
-    for (int q = lane; q < c.N * c.NI; q += WAVE)
-    if (s.dzls[q] < 0) a = fmin(a, -tau * it.zls[q] / s.dzls[q]);
-  if (it.resto)
-        for (int r = lane; r < c.m; r += WAVE) {
-      if (s.dzp[r] < 0) a = fmin(a, -tau * s.zp[r] / s.dzp[r]);
-      if (s.dzn[r] < 0) a = fmin(a, -tau * s.zn[r] / s.dzn[r]);
-    }
-  return wmin(a);
-}
-
-// filter: reject if theta >= theta_F and phi >= phi_F for some entry
-__device__ __forceinline__ bool filter_ok(const double* filt, int nf, double th, double ph, int lane) {
-  int bad = 0;
-    for (int i = lane; i < nf; i += WAVE)
-    if (th >= filt[i] && ph >= filt[FCAP + i]) bad = 1;
-  return wor(bad) == 0;
-}
-
-// add an entry, dropping the entries it dominates; returns the new count (-1 on overflow)
-__device__ __forceinline__ int filter_add(double* filt, int nf, int cap, double th, double ph, int lane) {
-  __shared__ int res;
-  if (lane == 0) {
-    int w = 0;
-    for (int i = 0; i < nf; ++i)
-      if (!(filt[i] >= th && filt[FCAP + i] >= ph)) {
-        filt[w] = filt[i];
-        filt[FCAP + w] = filt[FCAP + i];
-        ++w;
-      }
-    if (w >= cap) {
-      res = -1 - w;
-    } else {
-      filt[w] = th;
-      filt[FCAP + w] = ph;
-      res = w + 1;
-    }
-  }
-  __syncthreads();
-  int r = res;
-  __syncthreads();
-  return r;
-}
-
-// ============================================================================ slot initialisation
-// reference states x_ref,k (k = 0..N) of the cost, tabulated once per instance
-__device__ __forceinline__ void fill_ref(const Cfg& c, const Slot& s, int lane) {
-  for (int k = lane; k <= c.N; k += WAVE) {
-    double xr[NX];
-    ref_state(c, s.th, k, xr);
-#pragma unroll
-    for (int r = 0; r < NX; ++r) s.ref[k * NX + r] = xr[r];
-  }
-  __syncthreads();
-}
-
 __global__ __launch_bounds__(64) void k_prepare(Cfg c, double* ws) {
   Slot s = make_slot(c, ws, blockIdx.x);
   fill_ref(c, s, threadIdx.x);
-}
-
-// Start an instance in a slot: cold (x_k = xbar0, u_k = hover, s = g(xbar0), z = 1; y by least
-// squares in the INIT_Y phase) or warm from (w, y) (rows of `warm`: n_w primal then m multipliers;
-// slacks from g(w), bound multipliers from stationarity in the INIT_Y phase).  Every start is pushed
-// into the bounds (kappa_1, kappa_2; warm_push for a warm start).  `restart`: the cold restart of a
-// diverged warm start (warm is ignored, iterations and counters are kept).
-// the scalar-block words a cold restart of a diverged warm start keeps: iterations and counters
-__device__ __forceinline__ bool kept_on_restart(int q) {
-  return q == SC_ITER || (q >= SC_ST_RESTO && q <= SC_ST_PASS) || q == SC_ST_SOLV || q == SC_ST_FFACT ||
-         q == SC_ST_FSOLV || q == SC_ST_REF || q == SC_ST_FB || q == SC_ST_WSTART;
-}
-
-__device__ __forceinline__ void init_instance(const Cfg& c, const Slot& s, int inst, const double* theta, const double* warm,
-                              int lane, bool restart = false) {
-  const double* th = theta + (long long)inst * c.n_theta;
-  for (int i = lane; i < c.n_theta; i += WAVE) s.th[i] = th[i];
-  const double* wp = (warm && !restart) ? warm + (long long)inst * (c.n_w + c.m) : nullptr;
-  int bad = 0;
-  if (wp)
-    for (int i = lane; i < c.n_w + c.m; i += WAVE)
-      if (!isfinite(wp[i])) bad = 1;
-  const bool use_warm = wp && wor(bad) == 0;
-  // the cold and warm constants are loaded unconditionally and blended by value
-  const double kc1 = c.kappa1, kc2 = c.kappa2, kw = c.warm_push, mc = c.mu_init, mw = c.warm_mu0;
-  const double k1 = use_warm ? kw : kc1, k2 = use_warm ? kw : kc2;
-  __syncthreads();
-  fill_ref(c, s, lane);
-  for (int i = lane; i < c.n; i += WAVE) {
-    double x;
-    if (i < c.n_w) {
-      const int r = i % NZ;
-      x = use_warm ? wp[i] : ((r < NX) ? s.th[r] : c.uh);
-    } else {
-      const int q = i - c.n_w, k = 1 + q / c.NI, j = q % c.NI;
-      const double* o = obs_ptr(c, s.th) + 4 * j;
-      double g = 0.0;
-      for (int t = 0; t < 3; ++t) {
-        const double e = (use_warm ? wp[xo(k) + t] : s.th[t]) - o[t];
-        g += e * e;
-      }
-      x = g - o[3] * o[3];
-    }
-    // push into the bounds
-    if (i < c.n_w) {
-      int k = i / NZ, r = i % NZ;
-      if (r >= NX && k < c.N) {
-        double l = 0.0, u = c.umax;
-        double pl = fmin(k1 * fmax(1.0, fabs(l)), k2 * (u - l));
-        double pu = fmin(k1 * fmax(1.0, fabs(u)), k2 * (u - l));
-        x = fmax(x, l + pl);
-        x = fmin(x, u - pu);
-      }
-    } else {
-      x = fmax(x, 0.0 + k1 * 1.0);
-    }
-    s.v[i] = x;
-  }
-  for (int r = lane; r < c.m; r += WAVE) s.y[r] = use_warm ? wp[c.n_w + r] : 0.0;
-  for (int b = lane; b < c.N * NU; b += WAVE) { s.zlu[b] = 1.0; s.zuu[b] = 1.0; }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) s.zls[q] = 1.0;
-  for (int q = lane; q < SC_LEN; q += WAVE)
-    if (!(restart && kept_on_restart(q))) s.sc[q] = 0.0;
-  __syncthreads();
-  if (lane == 0) {
-    const double mu0 = use_warm ? mw : mc;
-    s.sc[SC_MU] = mu0;
-    s.sc[SC_TAU] = fmax(c.tau_min, 1.0 - mu0);
-    s.sc[SC_PHASE] = PH_INIT_Y;
-    s.sc[SC_STATUS] = ST_RUNNING;
-    s.sc[SC_INST] = inst;
-    s.sc[SC_INITF] = 1.0;
-    s.sc[SC_WARM] = use_warm ? 1.0 : 0.0;
-    if (!restart) s.sc[SC_ST_WSTART] = use_warm ? 1.0 : 0.0;
-    s.sc[SC_ST_WREJ] = (wp && !use_warm) ? 1.0 : 0.0;
-  }
-  __syncthreads();
 }
 
 __global__ __launch_bounds__(64) void k_setup(Cfg c, double* ws, int slots, int n_active, const double* theta,
@@ -454,830 +64,6 @@ __global__ __launch_bounds__(64) void k_setup(Cfg c, double* ws, int slots, int 
   }
 }
 
-// ============================================================================ factor kernel
-// finished instance: write the results (main problem, E_0 at the point), pop the next one
-__device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const double* theta, const double* warm, Outs out,
-                            Counters* cnt, bool refill, int lane) {
-  Iter it = cur_iter(s, false);
-  eval_c(c, s, false, lane);
-  eval_grad(c, s, s.y, false, 0.0, s.vt, lane);
-  ErrParts ep = err_parts(c, s, it, s.vt, lane);
-  double E0 = kkt_err(c, ep, compl_max(c, s, it, 0.0, lane), c.m);
-  double f = obj_regular(c, s, s.v, lane);
-  const int inst = (int)s.sc[SC_INST];
-  const long long b = (long long)inst;
-  for (int i = lane; i < c.n; i += WAVE) {
-    double zl, zu;
-    z_of(c, it, i, zl, zu);
-    if (out.x) out.x[b * c.n + i] = s.v[i];
-    if (out.zl) out.zl[b * c.n + i] = zl;
-    if (out.zu) out.zu[b * c.n + i] = zu;
-  }
-  if (out.y)
-    for (int r = lane; r < c.m; r += WAVE) out.y[b * c.m + r] = s.y[r];
-  __shared__ int next;
-  if (lane == 0) {
-    if (out.obj) out.obj[inst] = f;
-    if (out.kkt) out.kkt[inst] = E0;
-    if (out.status) out.status[inst] = (int)s.sc[SC_STATUS];
-    if (out.iters) out.iters[inst] = (int)s.sc[SC_ITER];
-    if (cnt) {
-      atomicAdd(&cnt->st[0], (unsigned long long)s.sc[SC_ITER]);
-      atomicAdd(&cnt->st[1], (unsigned long long)s.sc[SC_ST_RESTO]);
-      atomicAdd(&cnt->st[2], (unsigned long long)s.sc[SC_ST_SOCT]);
-      atomicAdd(&cnt->st[3], (unsigned long long)s.sc[SC_ST_SOCA]);
-      atomicAdd(&cnt->st[4], (unsigned long long)s.sc[SC_ST_FACT]);
-      atomicAdd(&cnt->st[5], (unsigned long long)s.sc[SC_ST_RENT]);
-      atomicAdd(&cnt->st[6], (unsigned long long)s.sc[SC_ST_TINY]);
-      atomicAdd(&cnt->st[7], (unsigned long long)s.sc[SC_ST_PASS]);
-      atomicAdd(&cnt->st[8], 1ull);
-      atomicAdd(&cnt->st[9], (unsigned long long)s.sc[SC_ST_SOLV]);
-      atomicAdd(&cnt->st[10], (unsigned long long)s.sc[SC_ST_FFACT]);
-      atomicAdd(&cnt->st[11], (unsigned long long)s.sc[SC_ST_FSOLV]);
-      atomicAdd(&cnt->st[12], (unsigned long long)s.sc[SC_ST_REF]);
-      atomicAdd(&cnt->st[13], (unsigned long long)s.sc[SC_ST_FB]);
-      atomicAdd(&cnt->st[14], (unsigned long long)s.sc[SC_ST_WSTART]);
-      atomicAdd(&cnt->st[15], (unsigned long long)s.sc[SC_ST_WREJ]);
-      atomicAdd(&cnt->st[16], (unsigned long long)s.sc[SC_ST_WRST]);
-      atomicAdd(&cnt->done, 1);
-      next = refill ? atomicAdd(&cnt->head, 1) : INT_MAX;
-    } else {
-      next = INT_MAX;
-    }
-  }
-  __syncthreads();
-  const int nx = next;
-  if (cnt && nx < cnt->n_inst) {
-    init_instance(c, s, nx, theta, warm, lane);
-  } else {
-    __syncthreads();
-    if (lane == 0) s.sc[SC_PHASE] = PH_EMPTY;
-  }
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------------------- mixed precision
-// y = K x for the system of eq. (7) with the perturbations of e, slacks (and, in restoration, the
-// elastic p, n) kept as variables of their own: the un-condensed system the condensed factor
-// solves, assembled on the fly from W_k, G_k and the stage data.
-__device__ __forceinline__ void kkt_matvec(const Cfg& c, const Slot& s, const Elim& e, const double* xv,
-                                           const double* xc, const double* xp, const double* xn, double* yv,
-                                           double* yc, double* yp, double* yn, int lane) {
-  const int N = c.N, NI = c.NI, SL = sd_len(c);
-  const double dx = e.lsq ? 0.0 : e.dxp, dc = e.lsq ? 0.0 : e.dcp;
-  // primal rows of the knots
-  for (int q = lane; q < (N + 1) * NZ; q += WAVE) {
-    const int k = q / NZ, i = q % NZ;
-    if (k == N && i >= NX) continue;
-    const double* sdk = s.sd + (long long)k * SL;
-    const int vi = k * NZ + i;
-    double acc = (sdk[i] + dx) * xv[vi];
-    if (k < N) {
-      if (!e.lsq) {
-        const double* W = s.HW + (long long)k * NZ * NZ + i * NZ;
-        for (int j = 0; j < NZ; ++j) acc += W[j] * xv[k * NZ + j];
-      }
-      const double* G = s.G + (long long)k * NX * NZ;
-      for (int l = 0; l < NX; ++l) acc -= G[l * NZ + i] * xc[(k + 1) * NX + l];
-    }
-    if (i < NX) acc += xc[k * NX + i];
-    if (k >= 1 && i < 3)
-      for (int j = 0; j < NI; ++j) {
-        const double* o7 = sdk + SD_HEAD + SD_OBS * j;
-        acc += o7[6] * xv[vi] + o7[3 + i] * xc[go(c, k, j)];
-      }
-    yv[vi] = acc;
-  }
-  // slack rows and inequality rows
-  for (int q = lane; q < N * NI; q += WAVE) {
-    const int k = 1 + q / NI, j = q % NI;
-    const double* o7 = s.sd + (long long)k * SL + SD_HEAD + SD_OBS * j;
-    const int si = so(c, k, j), r = go(c, k, j);
-    yv[si] = (o7[0] + dx) * xv[si] - xc[r];
-    double acc = -xv[si] - dc * xc[r];
-    for (int t = 0; t < 3; ++t) acc += o7[3 + t] * xv[xo(k) + t];
-    if (e.resto) {
-      acc += xn[r] - xp[r];
-      yp[r] = (o7[1] + dx) * xp[r] - xc[r];
-      yn[r] = (o7[2] + dx) * xn[r] + xc[r];
-    }
-    yc[r] = acc;
-  }
-  // rows defining the states
-  for (int r = lane; r < (N + 1) * NX; r += WAVE) {
-    const int k = r / NX, i = r % NX;
-    double acc = xv[xo(k) + i] - dc * xc[r];
-    if (k >= 1) {
-      const double* G = s.G + (long long)(k - 1) * NX * NZ + i * NZ;
-      for (int l = 0; l < NZ; ++l) acc -= G[l] * xv[(k - 1) * NZ + l];
-    }
-    if (e.resto) {
-      const double* sdk = s.sd + (long long)k * SL;
-      acc += xn[r] - xp[r];
-      yp[r] = (sdk[NZ + i] + dx) * xp[r] - xc[r];
-      yn[r] = (sdk[NZ + NX + i] + dx) * xn[r] + xc[r];
-    }
-    yc[r] = acc;
-  }
-  __syncthreads();
-}
-
-// Solve K x = b with the stored factor.  FP64 factor: one solve.  FP32 factor: one FP32 solve,
-// then sweeps of r = b - K x (FP64, full system) and x += K^{-1} r (FP32 solve) until
-// |r|_inf <= refine_tol |b|_inf, at most refine_max sweeps; false if that was not reached.
-__device__ __forceinline__ bool solve_refined(const Cfg& c, const Slot& s, const Elim& e, const double* bv,
-                                              const double* bc, const double* bp, const double* bn, double* xv,
-                                              double* xc, double* xp, double* xn, double* dyn, bool mixed, int lane) {
-  if (!mixed || s.sc[SC_FPREC] == 0.0) {
-    SolLdsT<double> V = sol_lds<double>(c, dyn);
-    kkt_solve(c, s, e, bv, bc, bp, bn, xv, xc, xp, xn, V, lane);
-    return true;
-  }
-  SolLdsT<float> V = sol_lds<float>(c, dyn);
-  kkt_solve(c, s, e, bv, bc, bp, bn, xv, xc, xp, xn, V, lane);
-  const int n = c.n, m = c.m;
-  double bmax = 0.0;
-  for (int i = lane; i < n; i += WAVE) bmax = fmax(bmax, fabs(bv[i]));
-  for (int r = lane; r < m; r += WAVE) {
-    bmax = fmax(bmax, fabs(bc[r]));
-    if (e.resto) bmax = fmax(bmax, fmax(fabs(bp[r]), fabs(bn[r])));
-  }
-  bmax = wmax(bmax);
-  int sweeps = 0;
-  bool ok = false;
-  for (;;) {
-    kkt_matvec(c, s, e, xv, xc, xp, xn, s.qv, s.qc, s.qp, s.qn, lane);
-    double rmax = 0.0;
-    for (int i = lane; i < n; i += WAVE) {
-      const double r = bv[i] - s.qv[i];
-      s.qv[i] = r;
-      rmax = fmax(rmax, fabs(r));
-    }
-    for (int r = lane; r < m; r += WAVE) {
-      const double rc = bc[r] - s.qc[r];
-      s.qc[r] = rc;
-      rmax = fmax(rmax, fabs(rc));
-      if (e.resto) {
-        const double rp = bp[r] - s.qp[r], rn = bn[r] - s.qn[r];
-        s.qp[r] = rp;
-        s.qn[r] = rn;
-        rmax = fmax(rmax, fmax(fabs(rp), fabs(rn)));
-      }
-    }
-    rmax = wmax(rmax);
-    __syncthreads();
-    if (rmax <= c.refine_tol * bmax) { ok = true; break; }
-    if (!isfinite(rmax) || sweeps >= c.refine_max) break;
-    kkt_solve(c, s, e, s.qv, s.qc, s.qp, s.qn, s.ev, s.ec, s.ep, s.en, V, lane);
-    for (int i = lane; i < n; i += WAVE) xv[i] += s.ev[i];
-    for (int r = lane; r < m; r += WAVE) {
-      xc[r] += s.ec[r];
-      if (e.resto) { xp[r] += s.ep[r]; xn[r] += s.en[r]; }
-    }
-    __syncthreads();
-    ++sweeps;
-  }
-  if (lane == 0) s.sc[SC_ST_REF] += sweeps;
-  __syncthreads();
-  return ok;
-}
-
-// the structured factorization in the precision of this iteration
-__device__ __forceinline__ int factor_any(const Cfg& c, const Slot& s, const Elim& e, FacLds& L, bool f32, int lane) {
-  if (f32) return kkt_factor(c, s, e, *reinterpret_cast<FacLdsT<float>*>(&L), lane);   // only mixed kernels
-  return kkt_factor(c, s, e, L, lane);
-}
-
-// ---------------------------------------------------------------------------- k_pre
-// Phase dispatch of one slot: result write-out and refill (FINISH), convergence and iteration
-// limit tests (E_0), the monotone barrier update (Table I row 7), grad phi_mu, the right-hand
-// side of eq. (7), theta_k and phi_k, and the perturbation-free stage data for the factorization.
-// INIT_Y slots set up the least-squares multiplier system [[I, A^T], [A, 0]] instead.
-__device__ __forceinline__ void pre_init_y(const Cfg& c, const Slot& s, int lane) {
-  Iter it = cur_iter(s, false);
-  eval_c(c, s, false, lane);
-  eval_grad(c, s, s.y, false, 0.0, s.vt, lane);
-  if (s.sc[SC_WARM] != 0.0) {
-    // warm start: keep y; bound multipliers from stationarity grad f + A^T y - z_L + z_U = 0,
-    // floored at mu0 / slack; filter bounds from theta_0; no least-squares system
-    const double mu0 = s.sc[SC_MU];
-    for (int b = lane; b < c.N * NU; b += WAVE) {
-      const int vi = uo(b / NU) + b % NU;
-      const double u = s.v[vi], r = s.g[vi] + s.vt[vi];
-      s.zlu[b] = fmax(r, mu0 / u);
-      s.zuu[b] = fmax(-r, mu0 / (c.umax - u));
-    }
-    for (int q = lane; q < c.N * c.NI; q += WAVE) {
-      const int si = c.n_w + q;
-      s.zls[q] = fmax(s.g[si] + s.vt[si], mu0 / s.v[si]);
-    }
-    double th0 = 0.0;
-    for (int r = lane; r < c.m; r += WAVE) th0 += fabs(s.rc[r]);
-    th0 = wsum(th0);
-    __syncthreads();
-    if (lane == 0) {
-      s.sc[SC_THMAX] = 1e4 * fmax(1.0, th0);
-      s.sc[SC_THMIN] = 1e-4 * fmax(1.0, th0);
-      s.sc[SC_NF] = 0.0;
-      s.sc[SC_INITF] = 0.0;
-      s.sc[SC_PHASE] = PH_REGULAR;
-    }
-    __syncthreads();
-    return;
-  }
-  for (int i = lane; i < c.n; i += WAVE) {
-    double zl, zu;
-    z_of(c, it, i, zl, zu);
-    s.rv[i] = -(s.g[i] - zl + zu);
-  }
-  for (int r = lane; r < c.m; r += WAVE) s.dvs[r] = 0.0;   // zero constraint right-hand side
-  Elim e{true, false, 0.0, 0.0, 0.0};
-  kkt_stage_data(c, s, it, e, lane);
-  if (lane == 0) s.sc[SC_WORK] = W_LSQ;
-}
-
-__device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const double* theta, const double* warm,
-                                         Outs out, Counters* cnt, int refill, int lane) {
-  const int ph = (int)s.sc[SC_PHASE];
-  if (ph == PH_EMPTY) return;
-  __syncthreads();
-  if (lane == 0) { s.sc[SC_ST_PASS] += 1.0; s.sc[SC_WORK] = W_NONE; s.sc[SC_FORCE64] = 0.0; }
-  if (ph == PH_FINISH) { finish_slot(c, s, theta, warm, out, cnt, refill != 0, lane); return; }
-  if (ph == PH_INIT_Y) { pre_init_y(c, s, lane); return; }
-
-  const bool resto = (ph == PH_RESTO);
-  if (s.sc[SC_WARM] != 0.0 && (resto || (c.warm_cap > 0 && s.sc[SC_ITER] >= c.warm_cap))) {
-    // the warm start diverged (restoration, or too many iterations): restart cold in this slot,
-    // keeping the iterations and counters spent so far
-    __syncthreads();
-    init_instance(c, s, (int)s.sc[SC_INST], theta, warm, lane, true);
-    if (lane == 0) s.sc[SC_ST_WRST] = 1.0;
-    __syncthreads();
-    return;
-  }
-  Iter it = cur_iter(s, resto);
-  double* sub = it.sub;   // mu, tau, dx_last, theta_max, theta_min, tiny, nf
-  double mu = sub[0];
-  double zeta = resto ? sqrt(mu) : 0.0;
-  eval_c(c, s, resto, lane);
-  eval_grad(c, s, it.y, resto, zeta, s.vt, lane);
-  ErrParts ep = err_parts(c, s, it, s.vt, lane);
-  const double E0 = kkt_err(c, ep, compl_max(c, s, it, 0.0, lane), c.m);
-  __syncthreads();
-  if (!isfinite(E0)) {
-    if (lane == 0) { s.sc[SC_STATUS] = ST_NUMERICAL; s.sc[SC_PHASE] = PH_FINISH; }
-    if (resto) for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
-    return;
-  }
-  if (E0 <= c.tol) {
-    if (!resto) {
-      if (lane == 0) s.sc[SC_STATUS] = ST_CONVERGED;
-      __syncthreads();
-      finish_slot(c, s, theta, warm, out, cnt, refill != 0, lane);
-    } else {
-      for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
-      if (lane == 0) { s.sc[SC_STATUS] = ST_INFEASIBLE; s.sc[SC_PHASE] = PH_FINISH; }
-    }
-    return;
-  }
-  if (s.sc[SC_ITER] >= c.max_iter) {
-    if (!resto) {
-      if (lane == 0) s.sc[SC_STATUS] = ST_MAX_ITER;
-      __syncthreads();
-      finish_slot(c, s, theta, warm, out, cnt, refill != 0, lane);
-    } else {
-      for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
-      if (lane == 0) { s.sc[SC_STATUS] = ST_MAX_ITER; s.sc[SC_PHASE] = PH_FINISH; }
-    }
-    return;
-  }
-  // ---- monotone barrier update (Table I row 7) ----
-  {
-    const double mu_min = c.tol / 10.0;
-    double tau = sub[1];
-    double nf = sub[6];
-    bool tiny = sub[5] != 0.0;
-    for (;;) {
-      double Emu = kkt_err(c, ep, compl_max(c, s, it, mu, lane), c.m);
-      if (!(Emu <= c.kappa_eps * mu || tiny)) break;
-      tiny = false;
-      double nm = fmax(mu_min, fmin(c.kappa_mu * mu, pow(mu, c.theta_mu)));
-      if (!(nm < mu)) break;
-      mu = nm;
-      tau = fmax(c.tau_min, 1.0 - mu);
-      nf = 0.0;
-      if (resto) {
-        zeta = sqrt(mu);
-        eval_grad(c, s, it.y, resto, zeta, s.vt, lane);
-        ep = err_parts(c, s, it, s.vt, lane);
-      }
-    }
-    __syncthreads();
-    if (lane == 0) { sub[0] = mu; sub[1] = tau; sub[5] = tiny ? 1.0 : 0.0; sub[6] = nf; }
-    __syncthreads();
-  }
-  // ---- barrier gradient, right-hand side of eq. (7), theta_k, phi_k ----
-  for (int i = lane; i < c.n; i += WAVE) {
-    double gp = s.g[i];
-    if (i < c.n_w) {
-      int k = i / NZ, r = i % NZ;
-      if (r >= NX && k < c.N) {
-        double u = s.v[i];
-        gp += -mu / u + mu / (c.umax - u);
-      }
-    } else {
-      gp -= mu / s.v[i];
-    }
-    s.g[i] = gp;                       // now grad phi_mu
-    s.rv[i] = -(gp + s.vt[i]);
-  }
-  if (resto)
-    for (int r = lane; r < c.m; r += WAVE) {
-      s.rp[r] = -(c.rho_resto - mu / s.p[r] - it.y[r]);
-      s.rn[r] = -(c.rho_resto - mu / s.nn[r] + it.y[r]);
-    }
-  double thk = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) thk += fabs(s.rc[r]);
-  thk = wsum(thk);
-  double fk = resto ? obj_resto(c, s, s.v, s.p, s.nn, zeta, lane) : obj_regular(c, s, s.v, lane);
-  double phk = fk - mu * log_barrier(c, s.v, s.p, s.nn, resto, lane);
-  Elim e{false, resto, 0.0, 0.0, zeta};
-  kkt_stage_data(c, s, it, e, lane);
-  if (lane == 0) {
-    s.sc[SC_THK] = thk; s.sc[SC_PHK] = phk; s.sc[SC_FK] = fk; s.sc[SC_STEPMU] = mu;
-    s.sc[SC_WORK] = W_STEP;
-  }
-}
-
-// ---------------------------------------------------------------------------- k_fac
-// Inertia-correcting factorization (Sec. IV "Inertia correction"): first without
-// perturbation; on a singular matrix add delta_c = delta_c_bar mu^kappa_c; then grow delta_x
-// from delta_0 (or kappa_minus times the last used value) by kappa_plus_bar / kappa_plus until
-// the inertia is (n, m, 0) or delta_x exceeds delta_max.
-__device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L, bool fused, bool mixed, int lane) {
-  const int work = (int)s.sc[SC_WORK];
-  if (work == W_NONE) return;
-  bool f32 = mixed && c.prec == 1 && s.sc[SC_FORCE64] == 0.0;
-  if (work == W_LSQ) {
-    Elim e{true, false, 0.0, 0.0, 0.0};
-    const int st = factor_any(c, s, e, L, f32, lane);
-    if (lane == 0) { s.sc[SC_FSTAT] = st; s.sc[SC_FPREC] = f32 ? 1.0 : 0.0; }
-    __syncthreads();
-    return;
-  }
-  const bool resto = (int)s.sc[SC_PHASE] == PH_RESTO;
-  double* sub = s.sc + (resto ? SC_RMU : SC_MU);
-  const double mu = sub[0];
-  // an FP64 redo of this iteration's factorization starts from the same delta_x^last
-  const double dxl = (s.sc[SC_FORCE64] != 0.0) ? s.sc[SC_DXLSAVE] : sub[2];
-  Elim e{false, resto, 0.0, 0.0, resto ? sqrt(mu) : 0.0};
-  int st = factor_any(c, s, e, L, f32, lane);
-  int nfact = 1;
-  if (f32 && st != 0) {
-    // the inertia-correction decisions are FP64 ones: an FP32 verdict of wrong inertia is
-    // re-taken in FP64, and the rest of this iteration's correction runs in FP64
-    f32 = false;
-    st = factor_any(c, s, e, L, false, lane);
-    ++nfact;
-  }
-  bool ok = (st == 0);
-  if (!ok) {
-    if (st == 2) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
-    e.dxp = (dxl == 0.0) ? c.delta_0 : fmax(c.delta_min, c.kappa_minus * dxl);
-    for (;;) {
-      st = factor_any(c, s, e, L, f32, lane);
-      ++nfact;
-      if (st == 0) { ok = true; break; }
-      if (st == 2 && e.dcp == 0.0) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
-      e.dxp *= (dxl == 0.0) ? c.kappa_plus_bar : c.kappa_plus;
-      if (e.dxp > c.delta_max) break;
-    }
-  }
-  __syncthreads();
-  if (lane == 0) {
-    s.sc[SC_ST_FACT] += nfact;
-    if (fused) s.sc[SC_ST_FFACT] += nfact;
-    s.sc[SC_DXLSAVE] = dxl;
-    if (ok && (e.dxp != 0.0)) sub[2] = e.dxp;
-    s.sc[SC_FPREC] = f32 ? 1.0 : 0.0;
-    s.sc[SC_LDX] = e.dxp;
-    s.sc[SC_LDC] = e.dcp;
-    s.sc[SC_FSTAT] = ok ? 0.0 : 1.0;
-    s.sc[SC_STEP] = ok ? STEP_READY : STEP_ICFAIL;
-  }
-}
-
-// ---------------------------------------------------------------------------- k_sol
-// least-squares multipliers: keep y if finite and |y|_inf <= lambda_max, else y = 0; the first
-// one also initialises the filter bounds theta_max, theta_min
-__device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, double* sol_dyn, FacLds* L, bool fused,
-                                           bool mixed, int lane) {
-  Elim e{true, false, 0.0, 0.0, 0.0};
-  bool fok = s.sc[SC_FSTAT] == 0.0;
-  if (fok) fok = solve_refined(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, sol_dyn, mixed, lane);
-  if (!fok && L && s.sc[SC_FPREC] != 0.0) {
-    // FP32 refinement failed: the least-squares system again in FP64
-    if (lane == 0) { s.sc[SC_FORCE64] = 1.0; s.sc[SC_ST_FB] += 1.0; }
-    __syncthreads();
-    fac_body(c, s, *L, fused, mixed, lane);
-    fok = s.sc[SC_FSTAT] == 0.0;
-    if (fok) fok = solve_refined(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, sol_dyn, mixed, lane);
-  }
-  double ym = 0.0, bad = fok ? 0.0 : 1.0;
-  if (fok)
-    for (int r = lane; r < c.m; r += WAVE) {
-      ym = fmax(ym, fabs(s.dy[r]));
-      if (!isfinite(s.dy[r])) bad = 1.0;
-    }
-  ym = wmax(ym);
-  const bool keep = wmax(bad) == 0.0 && ym <= c.lam_max;
-  for (int r = lane; r < c.m; r += WAVE) s.y[r] = keep ? s.dy[r] : 0.0;
-  double th0 = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) th0 += fabs(s.rc[r]);
-  th0 = wsum(th0);
-  __syncthreads();
-  if (lane == 0) {
-    if (s.sc[SC_INITF] != 0.0) {
-      s.sc[SC_THMAX] = 1e4 * fmax(1.0, th0);
-      s.sc[SC_THMIN] = 1e-4 * fmax(1.0, th0);
-      s.sc[SC_NF] = 0.0;
-      s.sc[SC_INITF] = 0.0;
-    }
-    s.sc[SC_PHASE] = PH_REGULAR;
-    s.sc[SC_WORK] = W_NONE;
-    if (fok) {
-      s.sc[SC_ST_SOLV] += 1.0;
-      if (fused) s.sc[SC_ST_FSOLV] += 1.0;
-    }
-  }
-  __syncthreads();
-}
-
-// Step of eq. (7) from the stored factor, bound-multiplier steps, fraction to the boundary
-// (primal) and the directional derivative of phi_mu.
-__device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, double* sol_dyn, FacLds* L, bool fused,
-                                         bool mixed, int lane) {
-  const int work = (int)s.sc[SC_WORK];
-  if (work == W_NONE) return;
-  if (work == W_LSQ) { sol_init_y(c, s, sol_dyn, L, fused, mixed, lane); return; }
-  if ((int)s.sc[SC_STEP] != STEP_READY) {
-    __syncthreads();
-    if (lane == 0) s.sc[SC_WORK] = W_NONE;
-    return;
-  }
-  const bool resto = (int)s.sc[SC_PHASE] == PH_RESTO;
-  Iter it = cur_iter(s, resto);
-  const double mu = it.sub[0], tau = it.sub[1];
-  Elim e{false, resto, s.sc[SC_LDX], s.sc[SC_LDC], resto ? sqrt(mu) : 0.0};
-  if (!solve_refined(c, s, e, s.rv, s.rc, s.rp, s.rn, s.dv, s.dy, s.dp, s.dn, sol_dyn, mixed, lane) && L) {
-    // FP32 refinement failed: factor this iteration again in FP64 (same inertia-correction start)
-    if (lane == 0) { s.sc[SC_FORCE64] = 1.0; s.sc[SC_ST_FB] += 1.0; }
-    __syncthreads();
-    fac_body(c, s, *L, fused, mixed, lane);
-    __syncthreads();
-    if ((int)s.sc[SC_STEP] != STEP_READY) {
-      if (lane == 0) s.sc[SC_WORK] = W_NONE;
-      return;
-    }
-    e.dxp = s.sc[SC_LDX];
-    e.dcp = s.sc[SC_LDC];
-    solve_refined(c, s, e, s.rv, s.rc, s.rp, s.rn, s.dv, s.dy, s.dp, s.dn, sol_dyn, mixed, lane);
-  }
-  dz_recover(c, s, it, mu, s.dv, s.dp, s.dn, lane);
-  double amax = ftb_primal(c, s, s.dv, s.dp, s.dn, resto, tau, lane);
-  double gphi = 0.0;
-  for (int i = lane; i < c.n; i += WAVE) gphi += s.g[i] * s.dv[i];
-  if (resto)
-    for (int r = lane; r < c.m; r += WAVE)
-      gphi += (c.rho_resto - mu / s.p[r]) * s.dp[r] + (c.rho_resto - mu / s.nn[r]) * s.dn[r];
-  gphi = wsum(gphi);
-  __syncthreads();
-  if (lane == 0) {
-    s.sc[SC_AMAX] = amax;
-    s.sc[SC_GPHI] = gphi;
-    s.sc[SC_WORK] = W_NONE;
-    s.sc[SC_ST_SOLV] += 1.0;
-    if (fused) s.sc[SC_ST_FSOLV] += 1.0;
-  }
-}
-
-// ============================================================================ line search kernel
-struct Trial {
-  double th, ph;
-  bool fin;
-};
-
-// evaluate the trial point vt (pt, nt): constraints into ct, theta = |ct|_1, phi_mu
-__device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool resto, double mu, double zeta, int lane) {
-  const int N = c.N, NI = c.NI;
-  if (lane < N) {
-    double x[NX], u[NU], F[NX];
-    for (int i = 0; i < NX; ++i) x[i] = s.vt[xo(lane) + i];
-    for (int i = 0; i < NU; ++i) u[i] = s.vt[uo(lane) + i];
-    rk4(c, x, u, F);
-    for (int i = 0; i < NX; ++i) s.ct[(lane + 1) * NX + i] = s.vt[xo(lane + 1) + i] - F[i];
-  }
-  for (int i = lane; i < NX; i += WAVE) s.ct[i] = s.vt[i] - s.th[i];
-  for (int q = lane; q < N * NI; q += WAVE) {
-    int k = 1 + q / NI, j = q % NI;
-    const double* o = obs_ptr(c, s.th) + 4 * j;
-    double g = 0.0;
-    for (int t = 0; t < 3; ++t) { double e = s.vt[xo(k) + t] - o[t]; g += e * e; }
-    s.ct[go(c, k, j)] = g - o[3] * o[3] - s.vt[so(c, k, j)];
-  }
-  __syncthreads();
-  if (resto)
-    for (int r = lane; r < c.m; r += WAVE) s.ct[r] += -s.pt[r] + s.nt[r];
-  __syncthreads();
-  double th = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) th += fabs(s.ct[r]);
-  th = wsum(th);
-  double f = resto ? obj_resto(c, s, s.vt, s.pt, s.nt, zeta, lane) : obj_regular(c, s, s.vt, lane);
-  double ph = f - mu * log_barrier(c, s.vt, s.pt, s.nt, resto, lane);
-  Trial t;
-  t.th = th;
-  t.ph = ph;
-  t.fin = isfinite(th) && isfinite(ph);
-  return t;
-}
-
-__device__ __forceinline__ void make_trial(const Cfg& c, const Slot& s, bool resto, double a, const double* dv,
-                                           const double* dp, const double* dn, int lane) {
-  for (int i = lane; i < c.n; i += WAVE) s.vt[i] = s.v[i] + a * dv[i];
-  if (resto)
-    for (int r = lane; r < c.m; r += WAVE) { s.pt[r] = s.p[r] + a * dp[r]; s.nt[r] = s.nn[r] + a * dn[r]; }
-  __syncthreads();
-}
-
-struct Acc {
-  bool ok, sw, arm;
-};
-
-__device__ __forceinline__ Acc acceptable(const Cfg& c, const double* sub, const double* filt, double thk, double phk, double gphi,
-                          double alpha, const Trial& t, int lane) {
-  Acc r{false, false, false};
-  if (!t.fin) return r;
-  if (t.th > sub[3]) return r;
-  bool sw = gphi < 0 && alpha * pow(-gphi, c.s_phi) > c.delta_sw * pow(thk, c.s_theta);
-  double slack = 10.0 * 2.220446049250313e-16 * fabs(phk);
-  bool arm = (t.ph - (phk + c.eta_phi * alpha * gphi)) <= slack;
-  bool ok;
-  if (sw && thk <= sub[4]) ok = arm;
-  else ok = (t.th <= (1.0 - c.gamma_theta) * thk) || ((t.ph - (phk - c.gamma_phi * thk)) <= slack);
-  if (!ok) return r;
-  if (!filter_ok(filt, (int)sub[6], t.th, t.ph, lane)) return r;
-  r.ok = true;
-  r.sw = sw;
-  r.arm = arm;
-  return r;
-}
-
-// enter feasibility restoration from the main iterate; false if it cannot start
-__device__ __forceinline__ bool resto_enter(const Cfg& c, const Slot& s, int lane) {
-  const double thk = s.sc[SC_THK], phk = s.sc[SC_PHK];
-  if (thk <= c.tol) return false;
-  int nf = filter_add(s.fm, (int)s.sc[SC_NF], c.fcap, (1.0 - c.gamma_theta) * thk, phk - c.gamma_phi * thk, lane);
-  if (nf < 0) {
-    if (lane == 0) { s.sc[SC_OVERFLOW] = 1.0; s.sc[SC_NF] = -1 - nf; }
-    return true;
-  }
-  double cmax = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) cmax = fmax(cmax, fabs(s.rc[r]));
-  cmax = wmax(cmax);
-  const double mu = s.sc[SC_MU];
-  const double muR = fmax(mu, cmax);
-  const double rho = c.rho_resto;
-  for (int i = lane; i < c.n; i += WAVE) s.xr[i] = s.v[i];
-  double th0 = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) {
-    double cv = -s.rc[r];
-    double a = (muR - rho * cv) / (2.0 * rho);
-    double nn = a + sqrt(a * a + muR * cv / (2.0 * rho));
-    double pp = cv + nn;
-    s.p[r] = pp;
-    s.nn[r] = nn;
-    s.zp[r] = muR / pp;
-    s.zn[r] = muR / nn;
-    s.yr[r] = 0.0;
-    th0 += fabs(cv - pp + nn);
-  }
-  th0 = wsum(th0);
-  for (int b = lane; b < c.N * NU; b += WAVE) { s.rzlu[b] = fmin(rho, s.zlu[b]); s.rzuu[b] = fmin(rho, s.zuu[b]); }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) s.rzls[q] = fmin(rho, s.zls[q]);
-  __syncthreads();
-  if (lane == 0) {
-    s.sc[SC_NF] = nf;
-    s.sc[SC_THR] = thk;
-    s.sc[SC_RMU] = muR;
-    s.sc[SC_RTAU] = fmax(c.tau_min, 1.0 - muR);
-    s.sc[SC_RDXL] = 0.0;
-    s.sc[SC_RTINY] = 0.0;
-    s.sc[SC_RNF] = 0.0;
-    s.sc[SC_RTHMAX] = 1e4 * fmax(1.0, th0);
-    s.sc[SC_RTHMIN] = 1e-4 * fmax(1.0, th0);
-    s.sc[SC_ST_RENT] += 1.0;
-    s.sc[SC_PHASE] = PH_RESTO;
-  }
-  __syncthreads();
-  return true;
-}
-
-// after an accepted restoration step: return to the original problem if possible
-__device__ __forceinline__ void resto_try_exit(const Cfg& c, const Slot& s, int lane) {
-  // original constraints and barrier objective at v (main mu)
-  for (int i = lane; i < c.n; i += WAVE) s.vt[i] = s.v[i];
-  __syncthreads();
-  const double mu = s.sc[SC_MU];
-  Trial t = eval_trial(c, s, false, mu, 0.0, lane);
-  if (!t.fin) return;
-  if (!(t.th <= c.kappa_resto * s.sc[SC_THR])) return;
-  if (!filter_ok(s.fm, (int)s.sc[SC_NF], t.th, t.ph, lane)) return;
-  double zmax = 0.0;
-  for (int b = lane; b < c.N * NU; b += WAVE) zmax = fmax(zmax, fmax(s.rzlu[b], s.rzuu[b]));
-  for (int q = lane; q < c.N * c.NI; q += WAVE) zmax = fmax(zmax, s.rzls[q]);
-  zmax = wmax(zmax);
-  const bool reset = zmax > c.bound_mult_reset;
-  for (int b = lane; b < c.N * NU; b += WAVE) {
-    s.zlu[b] = reset ? 1.0 : s.rzlu[b];
-    s.zuu[b] = reset ? 1.0 : s.rzuu[b];
-  }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) s.zls[q] = reset ? 1.0 : s.rzls[q];
-  __syncthreads();
-  if (lane == 0) {
-    s.sc[SC_TINY] = 0.0;
-    s.sc[SC_PHASE] = PH_INIT_Y;
-  }
-  __syncthreads();
-}
-
-__device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol_dyn, bool fused, bool mixed,
-                                        int lane) {
-  const int ph = (int)s.sc[SC_PHASE];
-  if (ph != PH_REGULAR && ph != PH_RESTO) return;
-  const int step = (int)s.sc[SC_STEP];
-  if (step == STEP_NONE) return;
-  __syncthreads();
-  if (lane == 0) s.sc[SC_STEP] = STEP_NONE;
-  const bool resto = (ph == PH_RESTO);
-  Iter it = cur_iter(s, resto);
-  double* sub = it.sub;
-  const double mu = sub[0], tau = sub[1];
-  const double zeta = resto ? sqrt(mu) : 0.0;
-  const double thk = s.sc[SC_THK], phk = s.sc[SC_PHK], gphi = s.sc[SC_GPHI], amax = s.sc[SC_AMAX];
-  bool accepted = false, augment = false, soc_dir = false, tiny = false;
-  double ap = amax;
-  if (step == STEP_READY) {
-    // tiny step (Table I row 4) at a nearly feasible point
-    double tmax = 0.0, cmax = 0.0;
-    for (int i = lane; i < c.n; i += WAVE) tmax = fmax(tmax, fabs(s.dv[i]) / (1.0 + fabs(s.v[i])));
-    if (resto)
-      for (int r = lane; r < c.m; r += WAVE) {
-        tmax = fmax(tmax, fabs(s.dp[r]) / (1.0 + fabs(s.p[r])));
-        tmax = fmax(tmax, fabs(s.dn[r]) / (1.0 + fabs(s.nn[r])));
-      }
-    for (int r = lane; r < c.m; r += WAVE) cmax = fmax(cmax, fabs(s.rc[r]));
-    tmax = wmax(tmax);
-    cmax = wmax(cmax);
-    if (tmax < 10.0 * 2.220446049250313e-16 && cmax <= 1e-4) {
-      make_trial(c, s, resto, amax, s.dv, s.dp, s.dn, lane);
-      tiny = true;
-      accepted = true;
-    } else {
-      double amin;
-      if (gphi < 0) {
-        double t = fmin(c.gamma_theta, c.gamma_phi * thk / (-gphi));
-        if (thk <= sub[4]) t = fmin(t, c.delta_sw * pow(thk, c.s_theta) / pow(-gphi, c.s_phi));
-        amin = c.gamma_alpha * t;
-      } else {
-        amin = c.gamma_alpha * c.gamma_theta;
-      }
-      double alpha = amax;
-      for (int l = 0;; ++l) {
-        // alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point)
-        if (alpha < amin || l >= 60) break;
-        make_trial(c, s, resto, alpha, s.dv, s.dp, s.dn, lane);
-        Trial t = eval_trial(c, s, resto, mu, zeta, lane);
-        Acc a = acceptable(c, sub, it.filt, thk, phk, gphi, alpha, t, lane);
-        if (a.ok) {
-          ap = alpha;
-          augment = !(a.sw && a.arm);
-          accepted = true;
-          break;
-        }
-        if (l == 0 && t.fin && c.max_soc > 0 && t.th >= thk) {
-          // second-order correction with the stored factor (Table I row 2)
-          double asoc = alpha, th_old = 0.0, tht = t.th;
-          bool fin = true;
-          for (int r = lane; r < c.m; r += WAVE) s.csoc[r] = -s.rc[r];
-          __syncthreads();
-          Elim e{false, resto, s.sc[SC_LDX], s.sc[SC_LDC], zeta};
-          for (int p = 0; p < c.max_soc; ++p) {
-            if (p > 0 && !(tht <= c.kappa_soc * th_old)) break;
-            th_old = tht;
-            for (int r = lane; r < c.m; r += WAVE) {
-              s.csoc[r] = asoc * s.csoc[r] + s.ct[r];
-              s.ct[r] = -s.csoc[r];      // right-hand side rows of the constraints
-            }
-            __syncthreads();
-            if (!solve_refined(c, s, e, s.rv, s.ct, s.rp, s.rn, s.dvs, s.dys, s.dps, s.dns, sol_dyn, mixed, lane)) break;
-            if (lane == 0) {
-              s.sc[SC_ST_SOCT] += 1.0;
-              if (fused) s.sc[SC_ST_FSOLV] += 1.0;
-            }
-            asoc = ftb_primal(c, s, s.dvs, s.dps, s.dns, resto, tau, lane);
-            make_trial(c, s, resto, asoc, s.dvs, s.dps, s.dns, lane);
-            Trial ts = eval_trial(c, s, resto, mu, zeta, lane);
-            tht = ts.th;
-            fin = ts.fin;
-            Acc as = acceptable(c, sub, it.filt, thk, phk, gphi, alpha, ts, lane);
-            if (as.ok) {
-              ap = asoc;
-              augment = !(as.sw && as.arm);
-              accepted = true;
-              soc_dir = true;
-              if (lane == 0) s.sc[SC_ST_SOCA] += 1.0;
-              break;
-            }
-            if (!fin) break;
-          }
-          if (accepted) break;
-        }
-        alpha *= 0.5;
-      }
-    }
-  }
-  __syncthreads();
-  if (!accepted) {
-    // line search or inertia correction failed
-    if (!resto) {
-      if (!resto_enter(c, s, lane)) {
-        if (lane == 0) { s.sc[SC_STATUS] = ST_RESTO_FAILED; s.sc[SC_PHASE] = PH_FINISH; }
-      } else if (s.sc[SC_OVERFLOW] != 0.0) {
-        if (lane == 0) { s.sc[SC_STATUS] = ST_FILTER_OVERFLOW; s.sc[SC_PHASE] = PH_FINISH; }
-      }
-    } else {
-      for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
-      if (lane == 0) { s.sc[SC_STATUS] = ST_RESTO_FAILED; s.sc[SC_PHASE] = PH_FINISH; }
-    }
-    __syncthreads();
-    return;
-  }
-  // ---- accept: (Table I) primal and y with the primal step, z with the dual fraction to the boundary
-  if (soc_dir) dz_recover(c, s, it, mu, s.dvs, s.dps, s.dns, lane);
-  const double az = ftb_dual(c, s, it, tau, lane);
-  const double* ady = soc_dir ? s.dys : s.dy;
-  if (augment) {
-    int nf = filter_add(it.filt, (int)sub[6], c.fcap, (1.0 - c.gamma_theta) * thk, phk - c.gamma_phi * thk, lane);
-    if (lane == 0) {
-      if (nf < 0) { s.sc[SC_OVERFLOW] = 1.0; sub[6] = -1 - nf; }
-      else sub[6] = nf;
-    }
-  }
-  for (int r = lane; r < c.m; r += WAVE) it.y[r] += ap * ady[r];
-  for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.vt[i];
-  if (resto)
-    for (int r = lane; r < c.m; r += WAVE) { s.p[r] = s.pt[r]; s.nn[r] = s.nt[r]; }
-  __syncthreads();
-  const double ks = c.kappa_sigma;
-  for (int b = lane; b < c.N * NU; b += WAVE) {
-    int k = b / NU, i = b % NU;
-    double u = s.v[uo(k) + i];
-    double z = it.zlu[b] + az * s.dzlu[b];
-    it.zlu[b] = fmax(fmin(z, ks * mu / u), mu / (ks * u));
-    double su = c.umax - u;
-    z = it.zuu[b] + az * s.dzuu[b];
-    it.zuu[b] = fmax(fmin(z, ks * mu / su), mu / (ks * su));
-  }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) {
-    double sv = s.v[c.n_w + q];
-    double z = it.zls[q] + az * s.dzls[q];
-    it.zls[q] = fmax(fmin(z, ks * mu / sv), mu / (ks * sv));
-  }
-  if (resto)
-    for (int r = lane; r < c.m; r += WAVE) {
-      double z = s.zp[r] + az * s.dzp[r];
-      s.zp[r] = fmax(fmin(z, ks * mu / s.p[r]), mu / (ks * s.p[r]));
-      z = s.zn[r] + az * s.dzn[r];
-      s.zn[r] = fmax(fmin(z, ks * mu / s.nn[r]), mu / (ks * s.nn[r]));
-    }
-  __syncthreads();
-  if (lane == 0) {
-    if (tiny) { sub[5] = 1.0; s.sc[SC_ST_TINY] += 1.0; }
-    s.sc[SC_ITER] += 1.0;
-    if (resto) s.sc[SC_ST_RESTO] += 1.0;
-    s.sc[SC_LALPHA] = ap;
-    s.sc[SC_LALPHAZ] = az;
-    s.sc[SC_LSOC] = soc_dir ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  if (s.sc[SC_OVERFLOW] != 0.0) {
-    if (lane == 0) { s.sc[SC_STATUS] = ST_FILTER_OVERFLOW; s.sc[SC_PHASE] = PH_FINISH; }
-    if (resto) for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
-    return;
-  }
-  if (resto) resto_try_exit(c, s, lane);
-}
-
 // ============================================================================ pass kernels
 __global__ __launch_bounds__(64) void k_pre(Cfg c, double* ws, const double* theta, const double* warm, Outs out,
                                             Counters* cnt, int refill) {
@@ -1287,34 +73,14 @@ __global__ __launch_bounds__(64) void k_fac(Cfg c, double* ws) {
   __shared__ FacLds L;
   fac_body(c, make_slot(c, ws, blockIdx.x), L, false, false, threadIdx.x);
 }
-__global__ __launch_bounds__(64) void k_sol(Cfg c, double* ws) {
+__global__ __launch_bounds__(64) void k_sol(Cfg c, double* ws, const double* warm) {
   HIP_DYNAMIC_SHARED(double, sol_dyn)
-  sol_body(c, make_slot(c, ws, blockIdx.x), sol_dyn, nullptr, false, false, threadIdx.x);
+  sol_body(c, make_slot(c, ws, blockIdx.x), warm, sol_dyn, nullptr, false, false, threadIdx.x);
 }
 __global__ __launch_bounds__(64) void k_ls(Cfg c, double* ws) {
   HIP_DYNAMIC_SHARED(double, sol_dyn)
   ls_body(c, make_slot(c, ws, blockIdx.x), sol_dyn, false, false, threadIdx.x);
 }
-// The four per-slot phases of one iteration in a single launch: each slot runs its phases back
-// to back, instead of every phase waiting for the slowest slot of the previous one, and a pass
-// costs two launches instead of five.  MIXED: the FP32 factor / FP64 refinement variant.
-template <bool MIXED>
-__global__ __launch_bounds__(64) void k_iter(Cfg c, double* ws, const double* theta, const double* warm, Outs out,
-                                             Counters* cnt, int refill) {
-  __shared__ FacLds L;
-  HIP_DYNAMIC_SHARED(double, sol_dyn)
-  const int lane = threadIdx.x;
-  const Slot s = make_slot(c, ws, blockIdx.x);
-  if ((int)s.sc[SC_PHASE] == PH_EMPTY) return;
-  pre_body(c, s, theta, warm, out, cnt, refill, lane);
-  __syncthreads();
-  fac_body(c, s, L, true, MIXED, lane);
-  __syncthreads();
-  sol_body(c, s, sol_dyn, &L, true, MIXED, lane);
-  __syncthreads();
-  ls_body(c, s, sol_dyn, true, MIXED, lane);
-}
-
 // ============================================================================ parity hooks
 __global__ __launch_bounds__(64) void k_stage_derivs(Cfg c, int count, const double* x, const double* u,
                                                      const double* lam, double* F, double* G, double* H) {
@@ -1343,10 +109,16 @@ __global__ __launch_bounds__(64) void k_kkt_test(Cfg c, double* ws, double dxp, 
   kkt_stage_data(c, s, it, e, lane);
   e.dxp = dxp;
   e.dcp = dcp;
-  // precision 1: FP32 factor and FP32 solve with FP64 refinement (no FP64 fallback here: the
-  // caller sees the refined FP32 result); inertia_ok = 1 inertia correct, 2 also refinement converged
-  const bool f32 = c.prec == 1;
-  const int st = factor_any(c, s, e, L, f32, lane);
+  // precision 1: FP32 factor and FP32 solve with FP64 refinement; as in the solver, an FP32
+  // inertia verdict other than "correct" is taken again in FP64 (then the FP64 factor solves; no
+  // refinement-failure fallback here: the caller sees the refined FP32 result).  inertia_ok = 1
+  // inertia correct, 2 also the FP32 factor was used and its refinement converged, 0 wrong
+  bool f32 = c.prec == 1;
+  int st = factor_any(c, s, e, L, f32, lane);
+  if (f32 && st != 0) {
+    f32 = false;
+    st = factor_any(c, s, e, L, false, lane);
+  }
   if (lane == 0) { inertia_ok[slot] = (st == 0) ? 1 : 0; s.sc[SC_FPREC] = f32 ? 1.0 : 0.0; }
   if (st != 0) return;
   const double* b = rhs + (long long)slot * (c.n + c.m);
@@ -1370,7 +142,6 @@ void launch_eval(const Cfg& c, double* ws, int slots, hipStream_t st) {
   if (blocks > 0) hipLaunchKernelGGL(k_eval, dim3(blocks), dim3(256), 0, st, c, ws, slots);
 }
 int sd_len_host(int NI) { return sd_len_of(NI); }
-static size_t sol_bytes(const Cfg& c) { return (size_t)sol_lds_doubles(c.N) * sizeof(double); }
 void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                 Counters* cnt, int refill, hipStream_t st) {
   hipLaunchKernelGGL(k_pre, dim3(slots), dim3(WAVE), 0, st, c, ws, theta, warm, out, cnt, refill);
@@ -1378,18 +149,22 @@ void launch_pre(const Cfg& c, double* ws, int slots, const double* theta, const 
 void launch_fac(const Cfg& c, double* ws, int slots, hipStream_t st) {
   hipLaunchKernelGGL(k_fac, dim3(slots), dim3(WAVE), 0, st, c, ws);
 }
-void launch_sol(const Cfg& c, double* ws, int slots, hipStream_t st) {
-  hipLaunchKernelGGL(k_sol, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws);
+void launch_sol(const Cfg& c, double* ws, int slots, const double* warm, hipStream_t st) {
+  hipLaunchKernelGGL(k_sol, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, warm);
 }
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st) {
   hipLaunchKernelGGL(k_ls, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws);
 }
+void launch_iter_fp64(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
+                      Counters* cnt, int refill, hipStream_t st);
+void launch_iter_mixed(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
+                       Counters* cnt, int refill, hipStream_t st);
 void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                  Counters* cnt, int refill, hipStream_t st) {
   if (c.prec == 1)
-    hipLaunchKernelGGL(k_iter<true>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm, out, cnt, refill);
+    launch_iter_mixed(c, ws, slots, theta, warm, out, cnt, refill, st);
   else
-    hipLaunchKernelGGL(k_iter<false>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm, out, cnt, refill);
+    launch_iter_fp64(c, ws, slots, theta, warm, out, cnt, refill, st);
 }
 void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm,
                   hipStream_t st) {
@@ -1408,3 +183,4 @@ void launch_kkt_test(const Cfg& c, double* ws, int count, double dxp, double dcp
   hipLaunchKernelGGL(k_kkt_test, dim3(count), dim3(WAVE), sol_bytes(c), st, c, ws, dxp, dcp, rhs, sol, inertia_ok);
 }
 }  // namespace hipipm
+

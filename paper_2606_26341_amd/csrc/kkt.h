@@ -332,16 +332,29 @@ __device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// An FP32 pivot that keeps less than this fraction of the diagonal entry it started from has
+// lost most of its significant digits to cancellation: its sign is not a reliable inertia verdict,
+// and the factorization reports status 3 so that the decision is taken again in FP64.
+constexpr float F32_PIVOT_REL = 1e-4f;
+
 // In-register Cholesky of an NX x NX SPD candidate held one row per lane (lane i < NX holds
 // c[l] = A_il; the lower part is used).  Right-looking, column j broadcast from lane j.  On
 // success row `lane` of L is in c (lower part) and rinv[j] = 1 / L_jj on every lane.  Returns 0,
-// 1 (a non-positive pivot) or 2 (an exactly-zero pivot); the result is wave-uniform.
+// 1 (a non-positive pivot), 2 (an exactly-zero pivot) or, in FP32 only, 3 (a positive pivot
+// below F32_PIVOT_REL times its starting diagonal entry); the result is wave-uniform.
 template <typename T>
 __device__ __forceinline__ int chol_rows(T (&c)[NX], T (&rinv)[NX], int lane) {
+  T dg = 0.0;
+  if constexpr (sizeof(T) == sizeof(float)) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) dg = (lane == j) ? c[j] : dg;
+  }
 #pragma unroll
   for (int j = 0; j < NX; ++j) {
     const T d = lane_bcast(c[j], j);
     if (!(d > 0.0)) return d == 0.0 ? 2 : 1;
+    if constexpr (sizeof(T) == sizeof(float))
+      if (d <= F32_PIVOT_REL * lane_bcast(dg, j)) return 3;
     rinv[j] = rsqrt_nr(d);
     c[j] = (lane == j) ? d * rinv[j] : c[j] * rinv[j];
 #pragma unroll
@@ -376,7 +389,8 @@ __device__ __forceinline__ void stage_park(T* buf, int lane, const double* reg) 
 
 // ----------------------------------------------------------------------------- factorization
 // Factor all stage blocks with perturbations (e.dxp, e.dcp); stage data from kkt_stage_data.
-// Returns 0 (inertia correct), 1 (wrong), 2 (singular).  Writes the per-knot factor records.
+// Returns 0 (inertia correct), 1 (wrong), 2 (singular) or, in FP32, 3 (a pivot too close to zero
+// for an FP32 verdict).  Writes the per-knot factor records.
 template <typename T>
 __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Elim& e, FacLdsT<T>& L, int lane) {
   const int N = c.N;
@@ -488,9 +502,12 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
       for (int j = 0; j < NU; ++j) {
         T d = L.H[(NX + j) * NZ + NX + j];
+        const T d0 = d;
 #pragma unroll
         for (int l = 0; l < j; ++l) d -= lr[j * NU + l] * lr[j * NU + l];
         if (bad == 0 && !(d > 0.0)) bad = (d == 0.0) ? 2 : 1;
+        if constexpr (sizeof(T) == sizeof(float))
+          if (bad == 0 && d <= F32_PIVOT_REL * d0) bad = 3;
         rr[j] = rsqrt_nr(d);
         lr[j * NU + j] = d * rr[j];
 #pragma unroll

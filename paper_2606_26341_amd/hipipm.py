@@ -14,8 +14,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhipipm.so")
 
-STATUS = {0: "RUNNING", 1: "CONVERGED", 2: "MAX_ITER", 3: "RESTO_FAILED", 4: "INFEASIBLE", 5: "NUMERICAL",
-          6: "FILTER_OVERFLOW"}
+STATUS = {0: "RUNNING", 1: "CONVERGED", 2: "MAX_ITER", 3: "RESTO_FAILED", 4: "INFEASIBLE", 5: "NUMERICAL"}
 ST_CONVERGED = 1
 KERNELS = ("eval", "pre", "factor", "solve", "linesearch", "fused", "setup")
 
@@ -39,10 +38,10 @@ class Options(C.Structure):
         ("s_theta", C.c_double), ("s_phi", C.c_double), ("eta_phi", C.c_double), ("gamma_alpha", C.c_double),
         ("max_soc", C.c_int32), ("kappa_soc", C.c_double), ("kappa_sigma", C.c_double),
         ("rho_resto", C.c_double), ("kappa_resto", C.c_double), ("bound_mult_reset", C.c_double),
-        ("filter_cap", C.c_int32), ("poll_every", C.c_int32), ("timing", C.c_int32),
+        ("poll_every", C.c_int32), ("timing", C.c_int32),
         ("fuse_below", C.c_int32), ("precision", C.c_int32), ("refine_max", C.c_int32),
         ("refine_tol", C.c_double), ("warm_mu0", C.c_double), ("warm_push", C.c_double),
-        ("warm_iter_cap", C.c_int32),
+        ("warm_iter_cap", C.c_int32), ("warm_gate", C.c_int32),
     ]
 
 
@@ -56,13 +55,13 @@ class Stats(C.Structure):
                                          "factorizations", "resto_entries", "tiny_steps", "passes",
                                          "instances_done", "solves", "fused_factorizations",
                                          "fused_solves", "refine_sweeps", "fp64_fallbacks", "warm_started",
-                                         "warm_rejected", "warm_restarts")]
+                                         "warm_rejected", "warm_restarts", "fp32_retakes")]
 
 
 _lib = None
 EXPORTS = ("hipipm_default_options", "hipipm_create", "hipipm_get_dims", "hipipm_workspace_bytes",
            "hipipm_bind_workspace", "hipipm_solve", "hipipm_stats_get", "hipipm_reset_stats",
-           "hipipm_kernel_times", "hipipm_state_len", "hipipm_state_import", "hipipm_step",
+           "hipipm_kernel_times", "hipipm_state_len", "hipipm_state_import", "hipipm_start", "hipipm_step",
            "hipipm_state_export", "hipipm_kkt_factor_solve", "hipipm_stage_derivs", "hipipm_last_error",
            "hipipm_destroy")
 
@@ -87,7 +86,8 @@ def load(path: str = LIB_PATH):
     L.hipipm_kernel_times.argtypes = [vp, C.POINTER(i32), vp, vp]
     L.hipipm_state_len.argtypes = [vp, C.POINTER(i32)]
     L.hipipm_state_import.argtypes = [vp, i32, vp, vp, vp]
-    L.hipipm_step.argtypes = [vp, i32, i32, vp]
+    L.hipipm_start.argtypes = [vp, i32, vp, vp, vp]
+    L.hipipm_step.argtypes = [vp, i32, i32, vp, vp, vp]
     L.hipipm_state_export.argtypes = [vp, i32, vp, vp]
     L.hipipm_kkt_factor_solve.argtypes = [vp, i32, vp, vp, vp, vp, vp, dp, dp, dp, vp, vp, vp, vp]
     L.hipipm_stage_derivs.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -218,12 +218,27 @@ class Solver:
     def state_import(self, states, theta: torch.Tensor, stream=None):
         import numpy as np
         states = np.ascontiguousarray(states, dtype=np.float64)
+        assert states.ndim == 2 and states.shape[1] == self.state_len(), "state rows of another length"
         count = states.shape[0]
+        assert count <= self.slots and theta.shape == (count, self.dims.n_theta)
         self._check(self.L.hipipm_state_import(self.h, count, states.ctypes.data_as(C.c_void_p),
                                                _ptr(theta.contiguous()), _stream(stream)))
 
-    def step(self, count: int, passes: int = 1, stream=None):
-        self._check(self.L.hipipm_step(self.h, int(count), int(passes), _stream(stream)))
+    def start(self, theta: torch.Tensor, warm: torch.Tensor | None = None, stream=None):
+        """Start the instances of theta (and warm rows) in slots 0..count-1 without solving."""
+        assert theta.shape[0] <= self.slots and theta.shape[1] == self.dims.n_theta
+        assert warm is None or warm.shape == (theta.shape[0], self.dims.n_w + self.dims.m)
+        theta = theta.contiguous()
+        warm = None if warm is None else warm.contiguous()
+        self._check(self.L.hipipm_start(self.h, theta.shape[0], _ptr(theta), _ptr(warm), _stream(stream)))
+
+    def step(self, count: int, passes: int, theta: torch.Tensor, warm: torch.Tensor | None = None, stream=None):
+        """`passes` passes over slots 0..count-1 (theta / warm: the rows of those slots' instances)."""
+        assert 0 <= count <= self.slots and theta.shape[0] >= count and theta.shape[1] == self.dims.n_theta
+        assert warm is None or warm.shape == (theta.shape[0], self.dims.n_w + self.dims.m)
+        theta = theta.contiguous()
+        warm = None if warm is None else warm.contiguous()
+        self._check(self.L.hipipm_step(self.h, int(count), int(passes), _ptr(theta), _ptr(warm), _stream(stream)))
 
     def state_export(self, count: int, stream=None):
         import numpy as np

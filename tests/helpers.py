@@ -2,6 +2,7 @@
 import numpy as np
 
 import oracle
+from paper_2606_26341_amd import workloads as W
 
 def e_v(a, b):
     """Largest scaled elementwise deviation max_i |a_i - b_i| / (1 + |b_i|) (Sec. VI, eq. (8))."""
@@ -40,3 +41,16 @@ def compare_states(sg, so, n, m):
             ev = max(ev, e_v(g[sub]["fth"][:nf], o[sub]["fth"][:nf]))
             ev = max(ev, e_v(g[sub]["fph"][:nf], o[sub]["fph"][:nf]))
     return bad, ev
+
+
+def hover_at_target_workload(N=10):
+    """Point-to-point family with no spheres, started hovering at its own target: the start is the
+    minimiser of every barrier sub-problem (the two log terms of a rotor bound balance at
+    u = u_hover, the middle of [0, 2 u_hover]; the state cost is zero and hover is an equilibrium),
+    so every Newton step is zero up to rounding and the tiny-step rule (Table I row 4) fires."""
+    w = W.Workload("hover", W.FAMILY_QUAD_OBS, 1, N=N, n_obs=0)
+    p = np.array([0.5, -1.0, 2.0])
+    x0 = np.zeros(13)
+    x0[:3] = p
+    x0[3] = 1.0
+    return w, np.concatenate([x0, p])

@@ -40,7 +40,7 @@ def test_struct_sizes_match_header_layout():
     # the ctypes mirrors follow the header's field order: doubles are 8-byte aligned
     assert C.sizeof(hipipm.ProblemDesc) == 4 * 4 + 11 * 8
     o = hipipm.default_options()
-    assert o.tol == 1e-8 and o.max_iter == 1000 and o.filter_cap == 128 and o.poll_every >= 1
+    assert o.tol == 1e-8 and o.max_iter == 1000 and o.warm_gate == 1 and o.poll_every >= 1
 
 
 def test_create_rejects_bad_arguments_without_touching_the_device():
@@ -56,6 +56,6 @@ def test_create_rejects_bad_arguments_without_touching_the_device():
     bad = hipipm.desc_from(W.get("C1"))
     bad.n_agents = 4
     assert L.hipipm_create(C.byref(bad), C.byref(o), 4, C.byref(h)) == -3        # unsupported family size
-    o2 = hipipm.default_options(filter_cap=500)
+    o2 = hipipm.default_options(max_iter=-1)
     assert L.hipipm_create(C.byref(d), C.byref(o2), 4, C.byref(h)) == -1
     assert L.hipipm_create(None, C.byref(o), 4, C.byref(h)) == -1

@@ -11,6 +11,8 @@ import pytest
 import oracle
 from paper_2606_26341_amd import workloads as W
 
+from helpers import hover_at_target_workload
+
 INF = np.inf
 
 
@@ -512,3 +514,23 @@ def test_warm_divergence_restarts_cold_and_keeps_counting():
     assert g["stats"][0, 10] == 1
     assert g["iters"][0] == cold["iters"][0] + 2
     assert np.array_equal(g["x"], cold["x"]) and g["status"][0] == cold["status"][0]
+
+
+def test_tiny_step_fires_at_the_barrier_minimiser():
+    # Table I row 4: at the barrier minimiser the Newton step is zero up to rounding, so the step
+    # is taken without a line search and the next iteration must lower mu; here every iteration
+    # is such a step (the multipliers move, x stays), so the solve is five tiny steps
+    w, th = hover_at_target_workload()
+    h = oracle.Handle.quad(w, th)
+    h.step()                                             # least-squares multipliers
+    s0 = oracle.unpack_state(h.state(), w.n, w.m)
+    h.step()                                             # first iteration
+    s1 = oracle.unpack_state(h.state(), w.n, w.m)
+    assert s1["iter"] == 1 and s1["main"]["tiny"] == 1
+    assert np.abs(s1["main"]["x"] - s0["main"]["x"]).max() <= 1e-14
+    assert s1["main"]["mu"] == s0["main"]["mu"] == 0.1   # mu is lowered at the start of the next one
+    h.step()
+    s2 = oracle.unpack_state(h.state(), w.n, w.m)
+    assert s2["main"]["mu"] < 0.1 and s2["main"]["nf"] == 0
+    o = oracle.solve_quad(w, th[None, :])
+    assert o["status"][0] == oracle.ST_CONVERGED and o["stats"][0, 6] == o["iters"][0] >= 3
