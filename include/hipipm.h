@@ -60,6 +60,11 @@ extern "C" {
                                       theta = [xbar0 (13), target (3), n_obs x (cx, cy, cz, r)] */
 #define HIPIPM_FAMILY_QUAD_TRACK 1 /* figure-eight tracking with spherical obstacles;
                                       theta = [xbar0 (13), A, omega, n_obs x (cx, cy, cz, r)] */
+#define HIPIPM_FAMILY_QUAD_TRACK_MOVING 3 /* figure-eight tracking with spheres moving at constant
+                                      velocity, trajectories known in advance (the tracking task
+                                      with time-varying obstacles, Sec. VI);
+                                      theta = [xbar0 (13), A, omega, n_obs x (cx, cy, cz, r, vx, vy, vz)],
+                                      centre of sphere j at stage k: (cx, cy, cz) + k dt (vx, vy, vz) */
 
 /* Problem descriptor (Sec. VI quadrotor NMPC; constants are inputs, not baked in). */
 typedef struct {
@@ -100,6 +105,24 @@ typedef struct {
                              mu0 = warm_mu0 does not exceed that of the cold start (cold start with
                              least-squares y, z = 1), which costs the cold start's least-squares
                              pass; 0: every finite warm point is used */
+    int32_t watchdog_trigger; /* watchdog (Table I row 3): after this many consecutive shortened
+                             steps of the original problem (the first trial of the line search
+                             rejected) the next steps are full steps (alpha_max) without the
+                             line-search test; 0 (default): no watchdog */
+    int32_t watchdog_max; /* full steps the watchdog takes (default 3): a step acceptable with respect
+                             to the iterate where it started ends it as an ordinary acceptance; if
+                             the last one is not, the iterate goes back to that point */
+    int32_t soft_resto_max; /* soft feasibility restoration (Table I row 5): when the line search of the
+                             original problem fails, take up to this many soft steps (primal-dual
+                             Newton steps with one step size min(alpha_max primal, alpha_max dual),
+                             accepted when they lower the primal-dual error by soft_resto_factor)
+                             before hard restoration; 0 (default): straight to hard restoration */
+    double soft_resto_factor; /* required reduction of the primal-dual error per soft step (0.9999) */
+    int32_t mu_strategy;  /* barrier update (Table I row 7): 0 (default) monotone; 1 adaptive: mu from
+                             the complementarity by the LOQO rule every iteration (free mode) while
+                             the scaled KKT error keeps falling (E_0 <= 0.9999 x the largest of the
+                             last four), otherwise the monotone rule from mu = 0.8 x the mean
+                             complementarity until its barrier problem is solved with progress */
 } hipipm_options;
 
 typedef struct {
@@ -119,6 +142,11 @@ typedef struct {
     int64_t warm_restarts;           /* warm starts that diverged and restarted cold */
     int64_t fp32_retakes;            /* precision 1: FP32 inertia verdicts (wrong inertia, or a pivot
                                         too close to zero for FP32) taken again in FP64 */
+    int64_t watchdog_starts;         /* watchdog activations */
+    int64_t watchdog_reverts;        /* watchdog sequences that went back to their starting point */
+    int64_t soft_resto_steps;        /* accepted soft-restoration steps */
+    int64_t soft_resto_fails;        /* soft restorations that ended in hard restoration */
+    int64_t mu_fallbacks;            /* adaptive barrier update: switches to the monotone mode */
 } hipipm_stats;
 
 typedef struct hipipm_ctx hipipm_ctx;
@@ -184,6 +212,10 @@ int hipipm_kernel_times(const hipipm_ctx* ctx, int32_t* n_kernels, double* total
  *   main : mu, tau, dx_last, theta_max, theta_min, tiny, nf, 0 | x[n] y[m] zl[n] zu[n] | fth[F] fph[F]
  *   resto: same with n + 2m variables (x, p, n)
  *   x_R[n], DR2[n]
+ *   watchdog: shortened-step count, active, steps taken, theta, phi_mu, grad phi^T d, alpha_max, mu
+ *             of the reference iteration | its x[n] y[m] zl[n] zu[n]
+ *   soft restoration: active, steps taken, theta, phi_mu of its starting point
+ *   adaptive barrier update: free mode, references held, references[4], mu ceiling, 0
  * with F = max_iter + 2 filter pairs (the filter is never full: each pair comes from an accepted
  * iteration or a restoration entry).  A warm start's gate data are not part of the state.
  * hipipm_state_len gives its length.  hipipm_state_import loads `count` states (host pointer,

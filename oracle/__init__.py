@@ -20,7 +20,7 @@ _SRC = ["bk.c", "quad.c", "ipm.c"]
 
 PH_INIT_Y, PH_REGULAR, PH_RESTO, PH_DONE = 0, 1, 2, 3
 ST_RUNNING, ST_CONVERGED, ST_MAX_ITER, ST_RESTO_FAILED, ST_INFEASIBLE, ST_NUMERICAL = range(6)
-NSTAT = 11   # per-instance counters of solve_quad (see ipmo_solve_quad)
+NSTAT = 16   # per-instance counters of solve_quad (see ipmo_solve_quad)
 
 
 def build() -> str:
@@ -43,7 +43,8 @@ class Opts(C.Structure):
         ("max_soc", C.c_int32), ("kappa_soc", C.c_double), ("kappa_sigma", C.c_double),
         ("rho_resto", C.c_double), ("kappa_resto", C.c_double), ("bound_mult_reset", C.c_double),
         ("warm_mu0", C.c_double), ("warm_push", C.c_double), ("warm_iter_cap", C.c_int32),
-        ("warm_gate", C.c_int32),
+        ("warm_gate", C.c_int32), ("watchdog_trigger", C.c_int32), ("watchdog_max", C.c_int32),
+        ("soft_resto_max", C.c_int32), ("soft_resto_factor", C.c_double), ("mu_strategy", C.c_int32),
     ]
 
 
@@ -102,6 +103,8 @@ def lib():
                                       C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _IP]
         L.ipmo_alpha_min.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double]
         L.ipmo_alpha_min.restype = C.c_double
+        L.ipmo_kkt_dense.argtypes = [C.c_void_p, _DP]
+        L.ipmo_kkt_dense.restype = C.c_int
         L.ipmo_handle_kkt_error.argtypes = [C.c_void_p, C.c_double]
         L.ipmo_handle_kkt_error.restype = C.c_double
         L.ipmo_last_soc.argtypes = [C.c_void_p, _DP, _DP, _DP]
@@ -368,6 +371,14 @@ class Handle:
         lib().ipmo_last_step(self.h, _p(dx), _p(dy), _p(dzl), _p(dzu))
         return dx, dy[:self.m], dzl, dzu
 
+    def kkt_matrix(self):
+        """The unperturbed matrix of eq. (7) of the current phase's sub-problem at the current
+        iterate (full symmetric), or None outside the regular and restoration phases."""
+        N = self.n + 3 * self.m + self.m
+        K = np.zeros(N * N)
+        nn = lib().ipmo_kkt_dense(self.h, _p(K))
+        return K[:nn * nn].reshape(nn, nn) if nn else None
+
     def kkt_error(self, mu=0.0) -> float:
         """E_mu of the current original-problem iterate."""
         return lib().ipmo_handle_kkt_error(self.h, float(mu))
@@ -394,7 +405,7 @@ class Handle:
 def unpack_state(s: np.ndarray, n: int, m: int) -> dict:
     """Split a flat oracle state into named fields (same order as ipmo_state_get); the filter
     capacity F of the format follows from the length."""
-    rest = len(s) - 16 - (8 + 3 * n + m) - (8 + 3 * (n + 2 * m) + m) - 2 * n
+    rest = len(s) - 16 - (8 + 3 * n + m) - (8 + 3 * (n + 2 * m) + m) - 2 * n - (8 + 3 * n + m) - 4 - 8
     assert rest > 0 and rest % 4 == 0, "not a flat state of this problem size"
     fcap = rest // 4
     hdr = s[:16]
@@ -414,6 +425,19 @@ def unpack_state(s: np.ndarray, n: int, m: int) -> dict:
 
     main, p = sub(p, n)
     rs, p = sub(p, n + 2 * m)
+    xR, DR2 = s[p:p + n], s[p + n:p + 2 * n]
+    p += 2 * n
+    wd = dict(short=int(s[p]), active=int(s[p + 1]), iter=int(s[p + 2]), theta=s[p + 3], phi=s[p + 4],
+              gphi=s[p + 5], alpha_max=s[p + 6], mu=s[p + 7])
+    p += 8
+    wd["x"] = s[p:p + n]; p += n
+    wd["y"] = s[p:p + m]; p += m
+    wd["zl"] = s[p:p + n]; p += n
+    wd["zu"] = s[p:p + n]
+    p += n
+    soft = dict(active=int(s[p]), iter=int(s[p + 1]), theta=s[p + 2], phi=s[p + 3])
+    p += 4
+    adapt = dict(free=int(s[p]), n_refs=int(s[p + 1]), refs=s[p + 2:p + 2 + int(s[p + 1])], mu_max=s[p + 6])
     return dict(phase=int(hdr[0]), iter=int(hdr[1]), status=int(hdr[2]), init_filter=int(hdr[3]),
-                theta_R=hdr[4], warm=int(hdr[5]), wstage=int(hdr[6]), main=main, resto=rs, xR=s[p:p + n],
-                DR2=s[p + n:p + 2 * n])
+                theta_R=hdr[4], warm=int(hdr[5]), wstage=int(hdr[6]), main=main, resto=rs, xR=xR, DR2=DR2,
+                watchdog=wd, soft=soft, adaptive=adapt)

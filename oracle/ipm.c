@@ -88,7 +88,23 @@ typedef struct solver_s {
     double f;
     /* statistics */
     int st_resto_iter, st_soc_try, st_soc_acc, st_fact, st_resto_entries, st_tiny, st_passes;
-    int st_warm_started, st_warm_rejected, st_warm_restarts;
+    int st_warm_started, st_warm_rejected, st_warm_restarts, st_wd_starts, st_wd_reverts;
+    /* watchdog (Table I row 3) on the original problem: consecutive shortened iterations, active
+     * flag, unconditional steps taken, and the reference iterate where it started with that
+     * iteration's theta, phi_mu, directional derivative, step size alpha_max and mu */
+    int wd_short, wd_active, wd_iter;
+    double wd_thk, wd_phk, wd_gphi, wd_amax, wd_mu;
+    double *wd_x, *wd_y, *wd_zl, *wd_zu;
+    /* soft feasibility restoration (Table I row 5): active flag, soft steps taken, theta and phi_mu
+     * of the iterate where it started; trial buffers of a soft step */
+    int soft, soft_iter, st_soft_steps, st_soft_fails;
+    double soft_thk, soft_phk;
+    /* adaptive barrier update (Table I row 7): mode (1 free, 0 monotone fallback), the last
+     * MU_REFS scaled KKT errors E_0 that the free mode must improve on, how many are held, the
+     * barrier-parameter ceiling, switches to the monotone mode */
+    int mu_free, n_refs, st_mu_fallbacks;
+    double refs[4], mu_max;
+    double *sf_y, *sf_zl, *sf_zu, *sf_g, *sf_J;
     double last_dx, last_dc, last_alpha, last_alpha_z;
     int last_soc;
     /* second-order corrections of the last pass: count, c_soc and step of each, theta of each trial */
@@ -366,6 +382,78 @@ static void mu_update(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
     }
 }
 
+/* Adaptive barrier update (Table I row 7), original problem only.  Free mode: mu from the
+ * current complementarity by the LOQO rule, mu = sigma * avg with avg = mean of the products
+ * s_i z_i over the bounded components, xi = min_i(s_i z_i) / avg and
+ * sigma = 0.1 min(0.05 (1 - xi) / xi, 2)^3, kept in [tol / 10, mu_max]; the free mode continues
+ * while the scaled KKT error E_0 of each new iterate is at most kappa_red = 0.9999 times the
+ * largest of the last four accepted ones.  Otherwise the monotone mode takes over, starting from
+ * mu = 0.8 avg; once its barrier problem is solved (E_mu <= kappa_eps mu) and E_0 has come down
+ * by kappa_red against the references, the free mode resumes, else mu decreases monotonically.
+ * The filter is reset whenever mu changes. */
+#define MU_REFS 4
+static void mu_refs_push(solver_t* S, double e0) {
+    if (S->n_refs == MU_REFS) {
+        for (int i = 1; i < MU_REFS; ++i) S->refs[i - 1] = S->refs[i];
+        S->n_refs--;
+    }
+    S->refs[S->n_refs++] = e0;
+}
+static int mu_progress(const solver_t* S, double e0) {
+    if (S->n_refs == 0) return 1;
+    double mx = S->refs[0];
+    for (int i = 1; i < S->n_refs; ++i) mx = fmax(mx, S->refs[i]);
+    return e0 <= 0.9999 * mx;
+}
+static void compl_stats(const nlp_t* P, const sub_t* T, double* avg, double* mn) {
+    double sum = 0, lo = INFINITY;
+    int cnt = 0;
+    for (int i = 0; i < P->n; ++i) {
+        if (isfinite(P->xl[i])) { double p = (T->x[i] - P->xl[i]) * T->zl[i]; sum += p; lo = fmin(lo, p); cnt++; }
+        if (isfinite(P->xu[i])) { double p = (P->xu[i] - T->x[i]) * T->zu[i]; sum += p; lo = fmin(lo, p); cnt++; }
+    }
+    *avg = cnt ? sum / cnt : 0.0;
+    *mn = cnt ? lo : 0.0;
+}
+static void mu_update_adaptive(solver_t* S, const nlp_t* P, sub_t* T, double e0) {
+    const ipmo_opts* o = &S->o;
+    double mu_min = o->tol / 10.0;
+    double avg, mn;
+    compl_stats(P, T, &avg, &mn);
+    if (S->mu_max == 0.0) S->mu_max = 1e3 * fmax(avg, mu_min);     /* set at the first iteration */
+    if (S->mu_free && !mu_progress(S, e0)) {
+        /* not enough progress: the monotone mode takes over */
+        S->mu_free = 0;
+        S->st_mu_fallbacks++;
+        double nm = fmin(S->mu_max, fmax(mu_min, 0.8 * avg));
+        if (nm != T->mu) { T->mu = nm; T->nf = 0; }
+        T->tau = fmax(o->tau_min, 1.0 - T->mu);
+        return;
+    }
+    if (!S->mu_free) {
+        double Emu = kkt_error(P, T, S->g, S->c, S->J, T->mu, o, S->wk);
+        if (!(Emu <= o->kappa_eps * T->mu || T->tiny)) return;      /* barrier problem not solved yet */
+        if (mu_progress(S, e0)) {
+            S->mu_free = 1;                                          /* progress: back to free mode */
+            S->n_refs = 0;
+        } else {
+            T->tiny = 0;
+            double nm = fmax(mu_min, fmin(o->kappa_mu * T->mu, pow(T->mu, o->theta_mu)));
+            if (nm < T->mu) { T->mu = nm; T->nf = 0; }
+            T->tau = fmax(o->tau_min, 1.0 - T->mu);
+            return;
+        }
+    }
+    mu_refs_push(S, e0);
+    T->tiny = 0;
+    double xi = avg > 0 ? mn / avg : 1.0;
+    double t = fmin(0.05 * (1.0 - xi) / xi, 2.0);
+    double nm = 0.1 * t * t * t * avg;
+    nm = fmin(S->mu_max, fmax(mu_min, nm));
+    if (nm != T->mu) { T->mu = nm; T->nf = 0; }
+    T->tau = fmax(o->tau_min, 1.0 - T->mu);
+}
+
 /* factor K with the delta_x / delta_c inertia correction; returns 0 on success */
 static int factor_ic(solver_t* S, const nlp_t* P, sub_t* T) {
     const ipmo_opts* o = &S->o;
@@ -405,6 +493,61 @@ static void soc_record(solver_t* S, int n, int m, double tht) {
     S->soc_n++;
 }
 
+/* primal-dual error of the barrier problem at mu (the residual of the perturbed optimality
+ * conditions, eq. (5), in the 1-norm): |grad f + A^T y - z_L + z_U|_1 + |c|_1 + the
+ * complementarity deviations |S_L z_L - mu e|_1 + |S_U z_U - mu e|_1 */
+static double pd_error(const nlp_t* P, const double* x, const double* y, const double* zl, const double* zu,
+                       const double* g, const double* c, const double* J, double mu) {
+    int n = P->n, m = P->m;
+    double e = nrm1(m, c);
+    for (int i = 0; i < n; ++i) {
+        double d = g[i] - zl[i] + zu[i];
+        for (int r = 0; r < m; ++r) d += J[(size_t)r * n + i] * y[r];
+        e += fabs(d);
+        if (isfinite(P->xl[i])) e += fabs((x[i] - P->xl[i]) * zl[i] - mu);
+        if (isfinite(P->xu[i])) e += fabs((P->xu[i] - x[i]) * zu[i] - mu);
+    }
+    return e;
+}
+
+/* Soft feasibility restoration step (Table I row 5): the primal-dual Newton step with one step
+ * size for primal and dual variables, alpha = min(alpha_max primal, alpha_max dual), accepted when
+ * it lowers the primal-dual error of the barrier problem by the factor soft_resto_factor; the
+ * original acceptance test is not applied.  Returns 1 (accepted, iterate updated) or 0. */
+static int soft_step(solver_t* S, const nlp_t* P, sub_t* T, double amax) {
+    const ipmo_opts* o = &S->o;
+    int n = P->n, m = P->m;
+    double ad = ftb_dual(P, T->zl, T->zu, S->dzl, S->dzu, T->tau);
+    double as = fmin(amax, ad);
+    double e0 = pd_error(P, T->x, T->y, T->zl, T->zu, S->g, S->c, S->J, T->mu);
+    for (int i = 0; i < n; ++i) {
+        S->xt[i] = T->x[i] + as * S->dx[i];
+        S->sf_zl[i] = T->zl[i] + as * S->dzl[i];
+        S->sf_zu[i] = T->zu[i] + as * S->dzu[i];
+    }
+    for (int r = 0; r < m; ++r) S->sf_y[r] = T->y[r] + as * S->dy[r];
+    P->grad(P->ud, S->xt, S->sf_g);
+    P->c(P->ud, S->xt, S->ct);
+    P->jac(P->ud, S->xt, S->sf_J);
+    double e1 = pd_error(P, S->xt, S->sf_y, S->sf_zl, S->sf_zu, S->sf_g, S->ct, S->sf_J, T->mu);
+    if (!(e1 <= o->soft_resto_factor * e0)) return 0;
+    memcpy(T->x, S->xt, n * sizeof(double));
+    memcpy(T->y, S->sf_y, m * sizeof(double));
+    for (int i = 0; i < n; ++i) {
+        if (isfinite(P->xl[i])) {
+            double s = T->x[i] - P->xl[i];
+            T->zl[i] = fmax(fmin(S->sf_zl[i], o->kappa_sigma * T->mu / s), T->mu / (o->kappa_sigma * s));
+        }
+        if (isfinite(P->xu[i])) {
+            double s = P->xu[i] - T->x[i];
+            T->zu[i] = fmax(fmin(S->sf_zu[i], o->kappa_sigma * T->mu / s), T->mu / (o->kappa_sigma * s));
+        }
+    }
+    S->last_alpha = as;
+    S->last_alpha_z = as;
+    return 1;
+}
+
 /* one iteration of the barrier method on problem P with iterate T */
 static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
     const ipmo_opts* o = &S->o;
@@ -415,7 +558,8 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
     if (!isfinite(E0)) return R_NUMERICAL;
     if (E0 <= o->tol) return R_CONVERGED;
     if (S->iter >= o->max_iter) return R_MAXITER;
-    mu_update(S, P, T, is_resto);
+    if (!is_resto && o->mu_strategy == 1) mu_update_adaptive(S, P, T, E0);
+    else mu_update(S, P, T, is_resto);
     P->hess(P->ud, T->x, 1.0, T->y, S->Hm);
 
     /* gradient of the barrier objective and the right-hand side of eq. (7) */
@@ -449,13 +593,61 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
     for (int i = 0; i < n; ++i) { double t = fabs(S->dx[i]) / (1.0 + fabs(T->x[i])); if (t > tmax) tmax = t; }
     const double *ady = S->dy, *adzl = S->dzl, *adzu = S->dzu;
     double ap = amax;
-    int augment = 0, accepted = 0;
+    int augment = 0, accepted = 0, shortened = 0;
+    double aug_th = thk, aug_ph = phk;       /* the point whose (theta, phi) enters the filter */
     S->last_soc = 0;
     S->soc_n = 0;
-    if (tmax < 10.0 * EPS && nrmi(m, S->c) <= 1e-4) {
+    const int use_wd = !is_resto && o->watchdog_trigger > 0;
+    const int use_soft = !is_resto && o->soft_resto_max > 0;
+    if (use_wd && S->wd_active && T->mu != S->wd_mu) S->wd_active = 0;   /* new barrier problem */
+    int try_soft = use_soft && S->soft;
+    if (try_soft) {
+        /* in soft restoration: no line search, the soft step or (after soft_resto_max of them, or
+         * when it fails) hard restoration */
+    } else if (tmax < 10.0 * EPS && nrmi(m, S->c) <= 1e-4) {
         for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + ap * S->dx[i];
         T->tiny = 1;
         S->st_tiny++;
+        accepted = 1;
+        if (use_wd) S->wd_active = 0;
+    } else if (use_wd && (S->wd_active || S->wd_short >= o->watchdog_trigger)) {
+        /* watchdog (Table I row 3): after watchdog_trigger consecutive shortened steps, take up to
+         * watchdog_max full steps (alpha_max) without the line-search test; a step that is
+         * acceptable with respect to the iterate where the watchdog started ends it as an ordinary
+         * acceptance, and if the last of them is not, the iterate goes back to that reference
+         * point (the next iteration starts there with the ordinary backtracking line search) */
+        if (!S->wd_active) {
+            S->wd_active = 1;
+            S->wd_iter = 0;
+            S->wd_thk = thk; S->wd_phk = phk; S->wd_gphi = gphi; S->wd_amax = amax; S->wd_mu = T->mu;
+            memcpy(S->wd_x, T->x, n * sizeof(double));
+            memcpy(S->wd_y, T->y, m * sizeof(double));
+            memcpy(S->wd_zl, T->zl, n * sizeof(double));
+            memcpy(S->wd_zu, T->zu, n * sizeof(double));
+            S->st_wd_starts++;
+        }
+        for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + amax * S->dx[i];
+        double tht, pht;
+        trial_eval(P, T, S->xt, S->ct, &tht, &pht);
+        int sw = 0, arm = 0;
+        S->wd_iter++;
+        if (acceptable(T, o, S->wd_thk, S->wd_phk, S->wd_gphi, S->wd_amax, tht, pht, &sw, &arm)) {
+            augment = !(sw && arm);
+            aug_th = S->wd_thk;
+            aug_ph = S->wd_phk;
+            S->wd_active = 0;
+            S->wd_short = 0;
+        } else if (S->wd_iter >= o->watchdog_max) {
+            /* revert: the reference iterate, no step accepted in this pass */
+            memcpy(T->x, S->wd_x, n * sizeof(double));
+            memcpy(T->y, S->wd_y, m * sizeof(double));
+            memcpy(T->zl, S->wd_zl, n * sizeof(double));
+            memcpy(T->zu, S->wd_zu, n * sizeof(double));
+            S->wd_active = 0;
+            S->wd_short = 0;
+            S->st_wd_reverts++;
+            return R_ACCEPT;
+        }
         accepted = 1;
     } else {
         /* backtracking filter line search (Table I rows 1-2) */
@@ -463,7 +655,11 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
         double alpha = amax;
         for (int l = 0;; ++l) {
             /* alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point) */
-            if (alpha < amin || l >= 60) return R_LSFAIL;
+            if (alpha < amin || l >= 60) {
+                if (!use_soft) return R_LSFAIL;
+                try_soft = 1;
+                break;
+            }
             for (int i = 0; i < n; ++i) S->xt[i] = T->x[i] + alpha * S->dx[i];
             double tht, pht;
             int fin = trial_eval(P, T, S->xt, S->ct, &tht, &pht);
@@ -472,6 +668,7 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
                 ap = alpha;
                 augment = !(sw && arm);
                 accepted = 1;
+                shortened = l > 0;
                 break;
             }
             if (l == 0 && fin && o->max_soc > 0 && tht >= thk) {
@@ -499,6 +696,7 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
                         ap = asoc;
                         augment = !(sw && arm);
                         accepted = 1;
+                        shortened = 1;
                         S->st_soc_acc++;
                         S->last_soc = 1;
                         break;
@@ -510,13 +708,46 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
             alpha *= 0.5;
         }
     }
+    if (try_soft) {
+        if (!S->soft) {
+            /* the line search failed: start soft restoration at this iterate */
+            S->soft = 1;
+            S->soft_iter = 0;
+            S->soft_thk = thk;
+            S->soft_phk = phk;
+            S->wd_active = 0;
+            S->wd_short = 0;
+        }
+        if (S->soft_iter >= o->soft_resto_max || !soft_step(S, P, T, amax)) {
+            S->soft = 0;
+            S->st_soft_fails++;
+            return R_LSFAIL;                /* hard restoration */
+        }
+        S->soft_iter++;
+        S->st_soft_steps++;
+        /* back to the ordinary iteration once the point is acceptable to the filter with a
+         * sufficient decrease of theta or phi_mu over the point where soft restoration started
+         * (which then enters the filter) */
+        double tht = nrm1(m, S->ct), f;
+        P->f(P->ud, T->x, &f);
+        double pht = barrier_obj(P, T->x, f, T->mu);
+        if (isfinite(tht) && isfinite(pht) && tht <= T->theta_max && filter_ok(T, tht, pht) &&
+            (tht <= (1.0 - o->gamma_theta) * S->soft_thk ||
+             pht - (S->soft_phk - o->gamma_phi * S->soft_thk) <= 10.0 * EPS * fabs(S->soft_phk))) {
+            S->soft = 0;
+            filter_add(T, (1.0 - o->gamma_theta) * S->soft_thk, S->soft_phk - o->gamma_phi * S->soft_thk);
+        }
+        S->iter++;
+        return R_ACCEPT;
+    }
     (void)accepted;
     /* accept: primal and equality multipliers with the primal step, bound multipliers with the
      * dual fraction-to-boundary step, then the kappa_sigma safeguard */
     double az = ftb_dual(P, T->zl, T->zu, adzl, adzu, T->tau);
     S->last_alpha = ap;
     S->last_alpha_z = az;
-    if (augment) filter_add(T, (1.0 - o->gamma_theta) * thk, phk - o->gamma_phi * thk);
+    if (augment) filter_add(T, (1.0 - o->gamma_theta) * aug_th, aug_ph - o->gamma_phi * aug_th);
+    if (use_wd && !S->wd_active) S->wd_short = shortened ? S->wd_short + 1 : 0;
     for (int r = 0; r < m; ++r) T->y[r] += ap * ady[r];
     for (int i = 0; i < n; ++i) T->x[i] = S->xt[i];
     for (int i = 0; i < n; ++i) {
@@ -663,6 +894,12 @@ static void gate_cold_done(solver_t* S) {
  * starts again from the cold start; the iteration count carries on */
 static void cold_restart(solver_t* S) {
     cold_point(S);
+    S->mu_free = 1;
+    S->n_refs = 0;
+    S->mu_max = 0.0;
+    S->wd_active = 0;
+    S->wd_short = 0;
+    S->soft = 0;
     S->init_filter = 1;
     S->theta_R = 0.0;
     S->warm = 0;
@@ -683,6 +920,9 @@ static int resto_enter(solver_t* S) {
     double thk = nrm1(m, S->c);
     double phk = barrier_obj(P, T->x, S->f, T->mu);
     if (thk <= o->tol) return 1;           /* no infeasibility to remove */
+    S->wd_active = 0;
+    S->wd_short = 0;
+    S->soft = 0;
     filter_add(T, (1.0 - o->gamma_theta) * thk, phk - o->gamma_phi * thk);
     S->theta_R = thk;
     double muR = fmax(T->mu, nrmi(m, S->c));
@@ -752,6 +992,7 @@ static int resto_try_exit(solver_t* S) {
             T->zu[i] = isfinite(P->xu[i]) ? 1.0 : 0.0;
         }
     T->tiny = 0;
+    S->n_refs = 0;                           /* the adaptive update restarts its progress record */
     return 1;
 }
 
@@ -860,6 +1101,15 @@ static solver_t* solver_new(nlp_t* P, const ipmo_opts* o, const double* x_cold, 
     for (int i = n; i < NR; ++i) { U->xl[i] = 0.0; U->xu[i] = INFINITY; }
     S->RP.n = NR; S->RP.m = m; S->RP.xl = U->xl; S->RP.xu = U->xu; S->RP.ud = U;
     S->RP.f = r_f; S->RP.grad = r_grad; S->RP.c = r_c; S->RP.jac = r_jac; S->RP.hess = r_hess;
+    S->sf_y = (double*)calloc(m > 0 ? m : 1, sizeof(double));
+    S->sf_zl = (double*)calloc(n, sizeof(double));
+    S->sf_zu = (double*)calloc(n, sizeof(double));
+    S->sf_g = (double*)calloc(n, sizeof(double));
+    S->sf_J = (double*)calloc((size_t)(m > 0 ? m : 1) * n, sizeof(double));
+    S->wd_x = (double*)calloc(n, sizeof(double));
+    S->wd_y = (double*)calloc(m > 0 ? m : 1, sizeof(double));
+    S->wd_zl = (double*)calloc(n, sizeof(double));
+    S->wd_zu = (double*)calloc(n, sizeof(double));
     S->x_cold = (double*)malloc(n * sizeof(double));
     S->y_cold = (double*)calloc(m > 0 ? m : 1, sizeof(double));
     memcpy(S->x_cold, x_cold, n * sizeof(double));
@@ -883,6 +1133,7 @@ static solver_t* solver_new(nlp_t* P, const ipmo_opts* o, const double* x_cold, 
     S->phase = PH_INIT_Y;
     S->status = ST_RUNNING;
     S->init_filter = 1;
+    S->mu_free = 1;
     if (use_warm && !o->warm_gate) {
         warm_point(S);
         S->warm = 1;
@@ -903,6 +1154,8 @@ static void solver_free(solver_t* S) {
     free(S->RU.xR); free(S->RU.DR2); free(S->RU.xl); free(S->RU.xu); free(S->RU.Jb); free(S->RU.Hb);
     free(S->x_cold); free(S->y_cold); free(S->warm_w); free(S->warm_y);
     free(S->soc_c); free(S->soc_d); free(S->soc_th);
+    free(S->wd_x); free(S->wd_y); free(S->wd_zl); free(S->wd_zu);
+    free(S->sf_y); free(S->sf_zl); free(S->sf_zu); free(S->sf_g); free(S->sf_J);
     free(S);
 }
 
@@ -923,6 +1176,9 @@ void ipmo_default_opts(ipmo_opts* o) {
     o->kappa_soc = 0.99; o->kappa_sigma = 1e10; o->rho_resto = 1000.0; o->kappa_resto = 0.9;
     o->bound_mult_reset = 1e3;
     o->warm_mu0 = 1e-3; o->warm_push = 1e-3; o->warm_iter_cap = 0; o->warm_gate = 1;
+    o->watchdog_trigger = 0; o->watchdog_max = 3;
+    o->soft_resto_max = 0; o->soft_resto_factor = 0.9999;
+    o->mu_strategy = 0;
 }
 
 int ipmo_sizeof_opts(void) { return (int)sizeof(ipmo_opts); }
@@ -940,7 +1196,7 @@ typedef struct {
     double* x; double* y; double* zl; double* zu; double* obj; double* kkt; int32_t* status; int32_t* iters;
     int32_t* stats; /* NSTAT ints per instance */
 } outs_t;
-#define NSTAT 11
+#define NSTAT 16
 
 static void write_outputs(solver_t* S, int idx, const outs_t* O) {
     nlp_t* P = S->P;
@@ -962,6 +1218,8 @@ static void write_outputs(solver_t* S, int idx, const outs_t* O) {
         s[0] = S->iter; s[1] = S->st_resto_iter; s[2] = S->st_soc_try; s[3] = S->st_soc_acc;
         s[4] = S->st_fact; s[5] = S->st_resto_entries; s[6] = S->st_tiny; s[7] = S->st_passes;
         s[8] = S->st_warm_started; s[9] = S->st_warm_rejected; s[10] = S->st_warm_restarts;
+        s[11] = S->st_wd_starts; s[12] = S->st_wd_reverts; s[13] = S->st_soft_steps; s[14] = S->st_soft_fails;
+        s[15] = S->st_mu_fallbacks;
     }
 }
 
@@ -1009,6 +1267,7 @@ static void* batch_worker(void* arg) {
 static int desc_n_theta(const ipmo_quad_desc* d) {
     if (d->family == 0) return 16 + 4 * d->n_obs;
     if (d->family == 1) return 15 + 4 * d->n_obs;
+    if (d->family == 3) return 15 + 7 * d->n_obs;
     return 16 * d->n_agents;
 }
 
@@ -1109,6 +1368,9 @@ void ipmo_last_info(void* h, double* out) {
  *   main sub-state  : mu, tau, dx_last, theta_max, theta_min, tiny, nf, 0 | x[n] y[m] zl[n] zu[n] | fth[F] fph[F]
  *   resto sub-state : same with n_R = n + 2m variables
  *   x_R[n], DR2[n]
+ *   watchdog: short, active, iter, theta, phi, grad phi^T d, alpha_max, mu | x[n] y[m] zl[n] zu[n]
+ *   soft restoration: active, steps taken, theta, phi of its starting point
+ *   adaptive barrier update: free mode, references held, references[4], mu_max, 0
  * F = max_iter + 2 filter pairs: every entry of the original problem's filter comes from an
  * accepted iteration or a restoration entry (each entry but the last followed by an accepted
  * restoration iteration), every entry of the restoration filter from an accepted restoration
@@ -1117,7 +1379,7 @@ static int sub_len(const solver_t* S, const sub_t* T) { return 8 + 3 * T->n + T-
 
 int ipmo_state_len(void* h) {
     solver_t* S = ((handle_t*)h)->S;
-    return 16 + sub_len(S, &S->main) + sub_len(S, &S->rs) + 2 * S->P->n;
+    return 16 + sub_len(S, &S->main) + sub_len(S, &S->rs) + 2 * S->P->n + 8 + 3 * S->P->n + S->P->m + 4 + 8;
 }
 
 static double* sub_put(const solver_t* S, const sub_t* T, double* p) {
@@ -1156,20 +1418,43 @@ void ipmo_state_get(void* h, double* out) {
     out[5] = S->warm; out[6] = S->wstage;
     double* p = sub_put(S, &S->main, out + 16);
     p = sub_put(S, &S->rs, p);
-    memcpy(p, S->RU.xR, S->P->n * sizeof(double)); p += S->P->n;
-    memcpy(p, S->RU.DR2, S->P->n * sizeof(double));
+    int n = S->P->n, m = S->P->m;
+    memcpy(p, S->RU.xR, n * sizeof(double)); p += n;
+    memcpy(p, S->RU.DR2, n * sizeof(double)); p += n;
+    p[0] = S->wd_short; p[1] = S->wd_active; p[2] = S->wd_iter; p[3] = S->wd_thk; p[4] = S->wd_phk;
+    p[5] = S->wd_gphi; p[6] = S->wd_amax; p[7] = S->wd_mu; p += 8;
+    memcpy(p, S->wd_x, n * sizeof(double)); p += n;
+    memcpy(p, S->wd_y, m * sizeof(double)); p += m;
+    memcpy(p, S->wd_zl, n * sizeof(double)); p += n;
+    memcpy(p, S->wd_zu, n * sizeof(double)); p += n;
+    p[0] = S->soft; p[1] = S->soft_iter; p[2] = S->soft_thk; p[3] = S->soft_phk; p += 4;
+    p[0] = S->mu_free; p[1] = S->n_refs;
+    for (int i = 0; i < 4; ++i) p[2 + i] = S->refs[i];
+    p[6] = S->mu_max; p[7] = 0.0;
 }
 
 /* load a flat state (a warm start's gate data are not part of it: load states of cold solves) */
 void ipmo_state_set(void* h, const double* in) {
     solver_t* S = ((handle_t*)h)->S;
+    grow_buffers(S, S->P->n + 2 * S->P->m);     /* the state may be in the restoration phase */
     S->phase = (int)in[0]; S->iter = (int)in[1]; S->status = (int)in[2]; S->init_filter = (int)in[3];
     S->theta_R = in[4];
     S->warm = (int)in[5]; S->wstage = (int)in[6];
     const double* p = sub_get(S, &S->main, in + 16);
     p = sub_get(S, &S->rs, p);
-    memcpy(S->RU.xR, p, S->P->n * sizeof(double)); p += S->P->n;
-    memcpy(S->RU.DR2, p, S->P->n * sizeof(double));
+    int n = S->P->n, m = S->P->m;
+    memcpy(S->RU.xR, p, n * sizeof(double)); p += n;
+    memcpy(S->RU.DR2, p, n * sizeof(double)); p += n;
+    S->wd_short = (int)p[0]; S->wd_active = (int)p[1]; S->wd_iter = (int)p[2]; S->wd_thk = p[3];
+    S->wd_phk = p[4]; S->wd_gphi = p[5]; S->wd_amax = p[6]; S->wd_mu = p[7]; p += 8;
+    memcpy(S->wd_x, p, n * sizeof(double)); p += n;
+    memcpy(S->wd_y, p, m * sizeof(double)); p += m;
+    memcpy(S->wd_zl, p, n * sizeof(double)); p += n;
+    memcpy(S->wd_zu, p, n * sizeof(double)); p += n;
+    S->soft = (int)p[0]; S->soft_iter = (int)p[1]; S->soft_thk = p[2]; S->soft_phk = p[3]; p += 4;
+    S->mu_free = (int)p[0]; S->n_refs = (int)p[1];
+    for (int i = 0; i < 4; ++i) S->refs[i] = p[2 + i];
+    S->mu_max = p[6];
 }
 
 /* E_mu of the original problem at an arbitrary primal-dual point (used to re-check GPU results) */
@@ -1254,6 +1539,27 @@ double ipmo_alpha_min(const ipmo_opts* o, double thk, double gphi, double theta_
 }
 
 /* E_mu of the handle's current original-problem iterate */
+/* the unperturbed matrix of eq. (7) (delta_x = delta_c = 0) of the sub-problem the current phase
+ * works on (the restoration problem in PH_RESTO), at the current iterate and mu, written in full
+ * (both triangles) into K [N][N]; returns N = n_v + m (0 outside the regular and restoration
+ * phases).  For conditioning checks in the tests. */
+int ipmo_kkt_dense(void* h, double* K) {
+    solver_t* S = ((handle_t*)h)->S;
+    if (S->phase != PH_REGULAR && S->phase != PH_RESTO) return 0;
+    const int is_resto = S->phase == PH_RESTO;
+    const nlp_t* P = is_resto ? &S->RP : S->P;
+    sub_t* T = is_resto ? &S->rs : &S->main;
+    grow_buffers(S, S->P->n + 2 * S->P->m);
+    set_zeta(S, T, is_resto);
+    eval_point(S, P, T);
+    P->hess(P->ud, T->x, 1.0, T->y, S->Hm);
+    int N = P->n + P->m;
+    assemble_K(P, T, S->Hm, S->J, 0.0, 0.0, K);
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j) K[(size_t)i * N + j] = K[(size_t)j * N + i];
+    return N;
+}
+
 double ipmo_handle_kkt_error(void* h, double mu) {
     solver_t* S = ((handle_t*)h)->S;
     eval_point(S, S->P, &S->main);

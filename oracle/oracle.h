@@ -66,11 +66,21 @@ typedef struct {
     double warm_mu0, warm_push;                    /* 1e-3, 1e-3 */
     int32_t warm_iter_cap;                         /* 0 */
     int32_t warm_gate;                             /* 1 */
+    /* watchdog (Table I row 3): consecutive shortened iterations that start it (0: off), full
+     * steps it takes without the line-search test before reverting */
+    int32_t watchdog_trigger, watchdog_max;        /* 0, 3 */
+    /* soft feasibility restoration (Table I row 5): soft steps before hard restoration (0: off),
+     * required reduction factor of the primal-dual error */
+    int32_t soft_resto_max;                        /* 0 */
+    double soft_resto_factor;                      /* 0.9999 */
+    /* barrier update (Table I row 7): 0 monotone, 1 adaptive (free mode, monotone fallback) */
+    int32_t mu_strategy;                           /* 0 */
 } ipmo_opts;
 
 /* ---------------- quadrotor NMPC problem family ---------------- */
 typedef struct {
-    int32_t family;   /* 0 point-to-point with spheres, 1 figure-eight tracking, 2 multi-quadrotor */
+    int32_t family;   /* 0 point-to-point with spheres, 1 figure-eight tracking, 2 multi-quadrotor,
+                         3 figure-eight tracking with spheres moving at constant velocity */
     int32_t N;        /* shooting intervals */
     int32_t n_agents;
     int32_t n_obs;

@@ -130,7 +130,7 @@ static void ref_state(const quad_nlp* Q, int a, int k, double* xr) {
     const double* th = Q->theta;
     if (Q->d.family == 0) {
         xr[0] = th[13]; xr[1] = th[14]; xr[2] = th[15];
-    } else if (Q->d.family == 1) {
+    } else if (Q->d.family == 1 || Q->d.family == 3) {
         double A = th[13], om = th[14], t = k * Q->d.dt;
         xr[0] = A * sin(om * t);
         xr[1] = 0.5 * A * sin(2.0 * om * t);
@@ -146,7 +146,20 @@ static const double* xbar0(const quad_nlp* Q, int a) {
     return Q->d.family == 2 ? Q->theta + a * 16 : Q->theta;
 }
 
-static const double* obs(const quad_nlp* Q) { return Q->theta + (Q->d.family == 0 ? 16 : 15); }
+/* sphere j at stage k: centre (o[0..2]) and radius (o[3]).  Families 0 and 1 hold fixed spheres
+ * (cx, cy, cz, r); family 3 holds spheres moving at constant velocity (cx, cy, cz, r, vx, vy, vz),
+ * centre c + t_k v at t_k = k dt (the obstacle trajectories are known in advance). */
+static void obs_at(const quad_nlp* Q, int j, int k, double* o) {
+    if (Q->d.family == 3) {
+        const double* b = Q->theta + 15 + 7 * j;
+        double t = k * Q->d.dt;
+        for (int i = 0; i < 3; ++i) o[i] = b[i] + t * b[4 + i];
+        o[3] = b[3];
+    } else {
+        const double* b = Q->theta + (Q->d.family == 0 ? 16 : 15) + 4 * j;
+        for (int i = 0; i < 4; ++i) o[i] = b[i];
+    }
+}
 
 /* pair index -> (a, b), a < b */
 static void pair_of(int n_agents, int j, int* a, int* b) {
@@ -158,8 +171,9 @@ static void pair_of(int n_agents, int j, int* a, int* b) {
         }
 }
 
-/* inequality g_kj(x_k) >= 0 : value and gradient w.r.t. the 3 (or 6) position entries */
-static double ineq_val(const quad_nlp* Q, const double* xk, int j, int* pa, int* pb) {
+/* inequality g_kj(x_k) >= 0 at stage k: value; *pa, *pb = position offsets of the agents involved
+ * (*pb < 0 for a sphere) */
+static double ineq_val(const quad_nlp* Q, const double* xk, int k, int j, int* pa, int* pb) {
     if (Q->d.family == 2) {
         int a = 0, b = 0;
         pair_of(Q->d.n_agents, j, &a, &b);
@@ -168,7 +182,8 @@ static double ineq_val(const quad_nlp* Q, const double* xk, int j, int* pa, int*
         for (int t = 0; t < 3; ++t) { double e = xk[13 * a + t] - xk[13 * b + t]; s += e * e; }
         return s - Q->d.d_min * Q->d.d_min;
     }
-    const double* o = obs(Q) + 4 * j;
+    double o[4];
+    obs_at(Q, j, k, o);
     *pa = 0; *pb = -1;
     double s = 0;
     for (int t = 0; t < 3; ++t) { double e = xk[t] - o[t]; s += e * e; }
@@ -228,7 +243,7 @@ static void q_c(void* ud, const double* v, double* c) {
     for (int k = 1; k <= Q->d.N; ++k)
         for (int j = 0; j < Q->nineq; ++j) {
             int pa, pb;
-            c[go(Q, k, j)] = ineq_val(Q, v + xo(Q, k), j, &pa, &pb) - v[so(Q, k, j)];
+            c[go(Q, k, j)] = ineq_val(Q, v + xo(Q, k), k, j, &pa, &pb) - v[so(Q, k, j)];
         }
 }
 
@@ -253,11 +268,13 @@ static void q_jac(void* ud, const double* v, double* J) {
         for (int j = 0; j < Q->nineq; ++j) {
             int pa, pb;
             const double* xk = v + xo(Q, k);
-            ineq_val(Q, xk, j, &pa, &pb);
+            ineq_val(Q, xk, k, j, &pa, &pb);
+            double o[4];
+            obs_at(Q, j, k, o);
             size_t row = (size_t)go(Q, k, j) * n;
             for (int t = 0; t < 3; ++t) {
                 if (pb < 0) {
-                    J[row + xo(Q, k) + t] = 2.0 * (xk[t] - obs(Q)[4 * j + t]);
+                    J[row + xo(Q, k) + t] = 2.0 * (xk[t] - o[t]);
                 } else {
                     double e = xk[pa + t] - xk[pb + t];
                     J[row + xo(Q, k) + pa + t] = 2.0 * e;
@@ -297,7 +314,7 @@ static void q_hess(void* ud, const double* v, double objf, const double* y, doub
         for (int j = 0; j < Q->nineq; ++j) {
             double yg = y[go(Q, k, j)];
             int pa, pb;
-            ineq_val(Q, v + xo(Q, k), j, &pa, &pb);
+            ineq_val(Q, v + xo(Q, k), k, j, &pa, &pb);
             for (int t = 0; t < 3; ++t) {
                 int ia = xo(Q, k) + pa + t;
                 Hm[(size_t)ia * n + ia] += 2.0 * yg;
@@ -361,7 +378,7 @@ void quad_cold_start(const ipmo_quad_desc* d, const double* theta, double* v) {
     for (int k = 1; k <= d->N; ++k)
         for (int j = 0; j < Q->nineq; ++j) {
             int pa, pb;
-            v[so(Q, k, j)] = ineq_val(Q, v + xo(Q, k), j, &pa, &pb);
+            v[so(Q, k, j)] = ineq_val(Q, v + xo(Q, k), k, j, &pa, &pb);
         }
     quad_nlp_free(Q);
 }
@@ -396,7 +413,7 @@ void quad_warm_point(const ipmo_quad_desc* d, const double* theta, const double*
     for (int k = 1; k <= d->N; ++k)
         for (int j = 0; j < Q->nineq; ++j) {
             int pa, pb;
-            v[so(Q, k, j)] = ineq_val(Q, v + xo(Q, k), j, &pa, &pb);
+            v[so(Q, k, j)] = ineq_val(Q, v + xo(Q, k), k, j, &pa, &pb);
         }
     quad_nlp_free(Q);
 }

@@ -98,6 +98,8 @@ static void layout(Cfg& c) {
   c.o_sd = take((N + 1) * sd_len_host(NI));
   c.o_qv = take(n); c.o_qc = take(m); c.o_qp = take(m); c.o_qn = take(m);
   c.o_ev = take(n); c.o_ec = take(m); c.o_ep = take(m); c.o_en = take(m);
+  c.o_wdv = take(n); c.o_wdy = take(m); c.o_wdzlu = take(N * NU); c.o_wdzuu = take(N * NU); c.o_wdzls = take(N * NI);
+  c.o_syt = take(m); c.o_szlu = take(N * NU); c.o_szuu = take(N * NU); c.o_szls = take(N * NI);
   c.stride = rup(o, 64);
 }
 
@@ -115,19 +117,26 @@ int hipipm_default_options(hipipm_options* o) {
   o->poll_every = 4; o->timing = 0; o->fuse_below = 1 << 30;
   o->precision = 0; o->refine_max = 3; o->refine_tol = 1e-10;
   o->warm_mu0 = 1e-3; o->warm_push = 1e-3; o->warm_iter_cap = 0; o->warm_gate = 1;
+  o->watchdog_trigger = 0; o->watchdog_max = 3;
+  o->soft_resto_max = 0; o->soft_resto_factor = 0.9999;
+  o->mu_strategy = 0;
   return HIPIPM_OK;
 }
 
 int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t slots, hipipm_ctx** out) {
   if (!d || !o || !out || slots <= 0) return HIPIPM_ERR_INVALID_ARG;
   *out = nullptr;
-  if (d->family != HIPIPM_FAMILY_QUAD_OBS && d->family != HIPIPM_FAMILY_QUAD_TRACK) return HIPIPM_ERR_UNSUPPORTED;
+  if (d->family != HIPIPM_FAMILY_QUAD_OBS && d->family != HIPIPM_FAMILY_QUAD_TRACK &&
+      d->family != HIPIPM_FAMILY_QUAD_TRACK_MOVING)
+    return HIPIPM_ERR_UNSUPPORTED;
   if (d->n_agents != 1) return HIPIPM_ERR_UNSUPPORTED;
   if (d->N < 1 || d->N > MAX_N || d->n_obs < 0 || d->n_obs > MAX_OBS) return HIPIPM_ERR_INVALID_ARG;
   if (!(d->dt > 0) || !(d->mass > 0) || !(d->jxx > 0) || !(d->jyy > 0) || !(d->jzz > 0)) return HIPIPM_ERR_INVALID_ARG;
   if (o->max_iter < 0 || o->max_iter > (1 << 24) || o->poll_every < 1 || !(o->tol > 0) ||
       o->fuse_below < 0 || o->precision < 0 || o->precision > 1 || o->refine_max < 0 || !(o->refine_tol > 0) ||
-      !(o->warm_mu0 > 0) || !(o->warm_push > 0) || o->warm_iter_cap < 0 || o->warm_gate < 0 || o->warm_gate > 1)
+      !(o->warm_mu0 > 0) || !(o->warm_push > 0) || o->warm_iter_cap < 0 || o->warm_gate < 0 || o->warm_gate > 1 ||
+      o->watchdog_trigger < 0 || o->watchdog_max < 1 || o->soft_resto_max < 0 ||
+      !(o->soft_resto_factor > 0 && o->soft_resto_factor <= 1) || o->mu_strategy < 0 || o->mu_strategy > 1)
     return HIPIPM_ERR_INVALID_ARG;
   hipipm_ctx* c = new hipipm_ctx();
   c->desc = *d;
@@ -139,7 +148,9 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   Cfg& g = c->cfg;
   memset(&g, 0, sizeof(g));
   g.family = d->family; g.N = d->N; g.NI = d->n_obs;
-  g.n_theta = (d->family == 0 ? 16 : 15) + 4 * d->n_obs;
+  g.n_theta = d->family == HIPIPM_FAMILY_QUAD_OBS ? 16 + 4 * d->n_obs
+              : d->family == HIPIPM_FAMILY_QUAD_TRACK ? 15 + 4 * d->n_obs
+                                                      : 15 + 7 * d->n_obs;
   g.n_w = (d->N + 1) * NX + d->N * NU;
   g.n_s = d->N * d->n_obs;
   g.n = g.n_w + g.n_s;
@@ -161,6 +172,9 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   g.kappa_resto = o->kappa_resto; g.bound_mult_reset = o->bound_mult_reset; g.fc = o->max_iter + 2;
   g.prec = o->precision; g.refine_max = o->refine_max; g.refine_tol = o->refine_tol;
   g.warm_mu0 = o->warm_mu0; g.warm_push = o->warm_push; g.warm_cap = o->warm_iter_cap; g.warm_gate = o->warm_gate;
+  g.wd_trigger = o->watchdog_trigger; g.wd_max = o->watchdog_max;
+  g.soft_max = o->soft_resto_max; g.soft_factor = o->soft_resto_factor;
+  g.mu_strategy = o->mu_strategy;
   layout(g);
   size_t rec = (size_t)g.stride * sizeof(double) * (size_t)slots;
   c->cnt_off = (rec + 255) / 256 * 256;
@@ -196,6 +210,33 @@ int hipipm_bind_workspace(hipipm_ctx* c, void* p, size_t bytes) {
 }
 
 static Counters* counters(hipipm_ctx* c) { return (Counters*)((char*)c->ws + c->cnt_off); }
+
+// the device counter block of a finished solve into the context's totals
+static void add_stats(hipipm_ctx* c, const Counters& h, long long passes) {
+  c->stats.iterations += (int64_t)h.st[0];
+  c->stats.resto_iterations += (int64_t)h.st[1];
+  c->stats.soc_tried += (int64_t)h.st[2];
+  c->stats.soc_accepted += (int64_t)h.st[3];
+  c->stats.factorizations += (int64_t)h.st[4];
+  c->stats.resto_entries += (int64_t)h.st[5];
+  c->stats.tiny_steps += (int64_t)h.st[6];
+  c->stats.passes += passes;
+  c->stats.instances_done += (int64_t)h.st[8];
+  c->stats.solves += (int64_t)h.st[9];
+  c->stats.fused_factorizations += (int64_t)h.st[10];
+  c->stats.fused_solves += (int64_t)h.st[11];
+  c->stats.refine_sweeps += (int64_t)h.st[12];
+  c->stats.fp64_fallbacks += (int64_t)h.st[13];
+  c->stats.warm_started += (int64_t)h.st[14];
+  c->stats.warm_rejected += (int64_t)h.st[15];
+  c->stats.warm_restarts += (int64_t)h.st[16];
+  c->stats.fp32_retakes += (int64_t)h.st[17];
+  c->stats.watchdog_starts += (int64_t)h.st[18];
+  c->stats.watchdog_reverts += (int64_t)h.st[19];
+  c->stats.soft_resto_steps += (int64_t)h.st[20];
+  c->stats.soft_resto_fails += (int64_t)h.st[21];
+  c->stats.mu_fallbacks += (int64_t)h.st[22];
+}
 
 int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const double* warm, double* x_out,
                  double* y_out, double* zl_out, double* zu_out, double* obj_out, double* kkt_out,
@@ -320,24 +361,7 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
     if (!more) return bail(fail(c, HIPIPM_ERR_HIP, "solve did not finish within the pass bound"));
   }
   if (timing) for (auto& e : ev) (void)hipEventDestroy(e);
-  c->stats.iterations += (int64_t)h.st[0];
-  c->stats.resto_iterations += (int64_t)h.st[1];
-  c->stats.soc_tried += (int64_t)h.st[2];
-  c->stats.soc_accepted += (int64_t)h.st[3];
-  c->stats.factorizations += (int64_t)h.st[4];
-  c->stats.resto_entries += (int64_t)h.st[5];
-  c->stats.tiny_steps += (int64_t)h.st[6];
-  c->stats.passes += passes;
-  c->stats.instances_done += (int64_t)h.st[8];
-  c->stats.solves += (int64_t)h.st[9];
-  c->stats.fused_factorizations += (int64_t)h.st[10];
-  c->stats.fused_solves += (int64_t)h.st[11];
-  c->stats.refine_sweeps += (int64_t)h.st[12];
-  c->stats.fp64_fallbacks += (int64_t)h.st[13];
-  c->stats.warm_started += (int64_t)h.st[14];
-  c->stats.warm_rejected += (int64_t)h.st[15];
-  c->stats.warm_restarts += (int64_t)h.st[16];
-  c->stats.fp32_retakes += (int64_t)h.st[17];
+  add_stats(c, h, passes);
   return HIPIPM_OK;
 }
 
@@ -371,7 +395,8 @@ static int state_len_of(const Cfg& g) {
   int n = g.n, m = g.m;
   int sub_main = 8 + 3 * n + m + 2 * g.fc;
   int sub_resto = 8 + 3 * (n + 2 * m) + m + 2 * g.fc;
-  return 16 + sub_main + sub_resto + 2 * n;
+  int watchdog = 8 + 3 * n + m, soft = 4, adaptive = 8;
+  return 16 + sub_main + sub_resto + 2 * n + watchdog + soft + adaptive;
 }
 
 int hipipm_state_len(const hipipm_ctx* c, int32_t* len) {
@@ -456,6 +481,17 @@ int hipipm_state_export(hipipm_ctx* c, int32_t count, double* out, void* stream)
       double d = std::fmin(1.0, 1.0 / std::fabs(rec[g.o_xr + i]));
       p[i] = d * d;
     }
+    p += n;
+    // watchdog block
+    for (int q = 0; q < 8; ++q) p[q] = sc[SC_WD_SHORT + q];
+    p += 8;
+    memcpy(p, rec.data() + g.o_wdv, n * sizeof(double)); p += n;
+    memcpy(p, rec.data() + g.o_wdy, m * sizeof(double)); p += m;
+    zfull_from(g, rec.data(), g.o_wdzlu, g.o_wdzuu, g.o_wdzls, p, p + n);
+    p += 2 * n;
+    for (int q = 0; q < 4; ++q) p[q] = sc[SC_SOFT + q];
+    p += 4;
+    for (int q = 0; q < 7; ++q) p[q] = sc[SC_MUFREE + q];   // free flag, references held, refs[4], mu_max
   }
   return HIPIPM_OK;
 }
@@ -502,6 +538,16 @@ int hipipm_state_import(hipipm_ctx* c, int32_t count, const double* in, const do
     for (int i = 0; i < 2 * g.fc; ++i) rec[g.o_fr + i] = p[i];
     p += 2 * g.fc;
     memcpy(rec.data() + g.o_xr, p, n * sizeof(double));
+    p += 2 * n;
+    for (int q = 0; q < 8; ++q) sc[SC_WD_SHORT + q] = p[q];
+    p += 8;
+    memcpy(rec.data() + g.o_wdv, p, n * sizeof(double)); p += n;
+    memcpy(rec.data() + g.o_wdy, p, m * sizeof(double)); p += m;
+    zfull_to(g, rec.data(), g.o_wdzlu, g.o_wdzuu, g.o_wdzls, p, p + n);
+    p += 2 * n;
+    for (int q = 0; q < 4; ++q) sc[SC_SOFT + q] = p[q];
+    p += 4;
+    for (int q = 0; q < 7; ++q) sc[SC_MUFREE + q] = p[q];
     if (resto) {
       memcpy(rec.data() + g.o_v, rx, n * sizeof(double));
       memcpy(rec.data() + g.o_p, rx + n, m * sizeof(double));

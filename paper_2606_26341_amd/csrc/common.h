@@ -36,7 +36,17 @@ enum : int {
   // E_mu0 of the cold start, the cold start's filter bounds
   SC_WSTAGE, SC_ECOLD, SC_CTHMAX, SC_CTHMIN,
   SC_ST_RTK,   // FP32 inertia verdicts taken again in FP64
-  SC_LEN = 64
+  // watchdog (Table I row 3): consecutive shortened steps, active flag, unconditional steps taken,
+  // the reference iteration's theta, phi_mu, grad phi^T d, alpha_max and mu; activations, reverts
+  SC_WD_SHORT = 64, SC_WD_ACTIVE, SC_WD_ITER, SC_WD_THK, SC_WD_PHK, SC_WD_GPHI, SC_WD_AMAX, SC_WD_MU,
+  SC_ST_WDS, SC_ST_WDR,
+  // soft feasibility restoration (Table I row 5): active flag, soft steps taken, theta and phi_mu
+  // of its starting point; soft steps, failures
+  SC_SOFT, SC_SOFT_IT, SC_SOFT_THK, SC_SOFT_PHK, SC_ST_SOFTS, SC_ST_SOFTF,
+  // adaptive barrier update (Table I row 7): free mode flag, references held, the last four E_0
+  // references, the mu ceiling; switches to the monotone mode
+  SC_MUFREE = 80, SC_NREFS, SC_REFS, SC_MUMAX = SC_REFS + 4, SC_ST_MUFB,
+  SC_LEN = 96
 };
 
 // per-stage factor record (doubles)
@@ -61,6 +71,10 @@ struct Cfg {
   int prec, refine_max; double refine_tol;   // KKT factor precision (1: FP32 + FP64 refinement)
   double warm_mu0, warm_push; int warm_cap;  // warm start: barrier parameter, bound push, iteration cap
   int warm_gate;                             // keep a warm point only if E_mu0(warm) <= E_mu0(cold)
+  int wd_trigger, wd_max;                    // watchdog: shortened steps that start it (0: off), its steps
+  int soft_max; double soft_factor;          // soft restoration: steps before hard restoration (0: off),
+                                             // required primal-dual error reduction
+  int mu_strategy;                           // 0 monotone, 1 adaptive with monotone fallback
   // slot record layout, offsets in doubles
   long long stride;
   int o_v, o_y, o_zlu, o_zuu, o_zls, o_th, o_sc, o_fm, o_fr;
@@ -70,6 +84,8 @@ struct Cfg {
   int o_rv, o_rc, o_rp, o_rn, o_vt, o_ct, o_pt, o_nt, o_csoc, o_dvs, o_dys, o_dps, o_dns;
   int o_g, o_ref, o_sd;
   int o_qv, o_qc, o_qp, o_qn, o_ev, o_ec, o_ep, o_en;   // refinement residual and correction
+  int o_wdv, o_wdy, o_wdzlu, o_wdzuu, o_wdzls;          // watchdog reference iterate
+  int o_syt, o_szlu, o_szuu, o_szls;                    // soft-restoration trial multipliers
 };
 
 // caller-owned output arrays of a solve
@@ -79,9 +95,10 @@ struct Outs {
 };
 
 // global counters (device): queue head, finished count, stats
+constexpr int N_STATS = 23;
 struct Counters {
   int32_t head, done, n_inst, pad;
-  unsigned long long st[18];
+  unsigned long long st[N_STATS];
 };
 
 }  // namespace hipipm

@@ -33,6 +33,8 @@ struct Slot {
   double *dv, *dy, *dzlu, *dzuu, *dzls, *dp, *dn, *dzp, *dzn;
   double *rv, *rc, *rp, *rn, *vt, *ct, *pt, *nt, *csoc, *dvs, *dys, *dps, *dns, *g, *ref, *sd;
   double *qv, *qc, *qp, *qn, *ev, *ec, *ep, *en;
+  double *wdv, *wdy, *wdzlu, *wdzuu, *wdzls;
+  double *syt, *szlu, *szuu, *szls;
 };
 
 __device__ __forceinline__ Slot make_slot(const Cfg& c, double* ws, int slot) {
@@ -53,6 +55,8 @@ __device__ __forceinline__ Slot make_slot(const Cfg& c, double* ws, int slot) {
   s.sd = R + c.o_sd;
   s.qv = R + c.o_qv; s.qc = R + c.o_qc; s.qp = R + c.o_qp; s.qn = R + c.o_qn;
   s.ev = R + c.o_ev; s.ec = R + c.o_ec; s.ep = R + c.o_ep; s.en = R + c.o_en;
+  s.wdv = R + c.o_wdv; s.wdy = R + c.o_wdy; s.wdzlu = R + c.o_wdzlu; s.wdzuu = R + c.o_wdzuu; s.wdzls = R + c.o_wdzls;
+  s.syt = R + c.o_syt; s.szlu = R + c.o_szlu; s.szuu = R + c.o_szuu; s.szls = R + c.o_szls;
   return s;
 }
 
@@ -232,7 +236,8 @@ __device__ __forceinline__ void kkt_stage_data(const Cfg& c, const Slot& s, cons
   for (int q = lane; q < N * NI; q += WAVE) {
     const int k = 1 + q / NI, j = q % NI;
     double* o7 = s.sd + (long long)k * L + SD_HEAD + SD_OBS * j;
-    const double* o = obs_ptr(c, s.th) + 4 * j;
+    double o[4];
+    obs_at(c, s.th, j, k, o);
     const int si = so(c, k, j), r = go(c, k, j);
     double sig0 = 1.0;
     if (!e.lsq) {

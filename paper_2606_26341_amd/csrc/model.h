@@ -115,6 +115,28 @@ __device__ __forceinline__ void rk4(const Cfg& c, const double* x, const double*
   for (int i = 0; i < NX; ++i) out[i] = x[i] + (h / 6.0) * (acc[i] + k[i]);
 }
 
+// Column j of G = dF/d(x, u) of the RK4 step only (forward tangent sweep, no Hessian)
+__device__ __forceinline__ void rk4_tangent(const Cfg& c, const double* x, const double* u, int j, double* Gcol) {
+  Dual z[NZ], k[NX], t[NX], acc[NX];
+#pragma unroll
+  for (int i = 0; i < NZ; ++i) z[i] = {i < NX ? x[i] : u[i - NX], i == j ? 1.0 : 0.0};
+  const Dual* xs = z;
+  const Dual* us = z + NX;
+  const double h = c.dt;
+  quad_f<Dual>(c, xs, us, k);
+#pragma unroll
+  for (int i = 0; i < NX; ++i) { acc[i] = k[i]; t[i] = xs[i] + (0.5 * h) * k[i]; }
+  quad_f<Dual>(c, t, us, k);
+#pragma unroll
+  for (int i = 0; i < NX; ++i) { acc[i] = acc[i] + 2.0 * k[i]; t[i] = xs[i] + (0.5 * h) * k[i]; }
+  quad_f<Dual>(c, t, us, k);
+#pragma unroll
+  for (int i = 0; i < NX; ++i) { acc[i] = acc[i] + 2.0 * k[i]; t[i] = xs[i] + h * k[i]; }
+  quad_f<Dual>(c, t, us, k);
+#pragma unroll
+  for (int i = 0; i < NX; ++i) Gcol[i] = ((h / 6.0) * (acc[i] + k[i])).d + (i == j ? 1.0 : 0.0);
+}
+
 // Direction j of the RK4 step derivatives: F (optional), column j of G and of H = d2(lam^T F)/dz2.
 __device__ __forceinline__ void rk4_deriv_dir(const Cfg& c, const double* x, const double* u, const double* lam,
                                               int j, double* F, double* Gcol, double* Hcol) {
@@ -182,7 +204,7 @@ __device__ __forceinline__ void ref_state(const Cfg& c, const double* th, int k,
   xr[3] = 1.0;
   if (c.family == 0) {
     xr[0] = th[13]; xr[1] = th[14]; xr[2] = th[15];
-  } else {
+  } else {   // figure-eight tracking (fixed or moving spheres)
     double A = th[13], om = th[14], t = k * c.dt;
     xr[0] = A * sin(om * t);
     xr[1] = 0.5 * A * sin(2.0 * om * t);
@@ -191,8 +213,21 @@ __device__ __forceinline__ void ref_state(const Cfg& c, const double* th, int k,
   }
 }
 
-__device__ __forceinline__ const double* obs_ptr(const Cfg& c, const double* th) {
-  return th + (c.family == 0 ? 16 : 15);
+// sphere j at knot k: centre o[0..2], radius o[3].  The point-to-point and tracking families hold
+// fixed spheres (cx, cy, cz, r); the moving-sphere tracking family holds (cx, cy, cz, r, vx, vy, vz),
+// centre c + t_k v at t_k = k dt (obstacle trajectories known in advance).
+__device__ __forceinline__ void obs_at(const Cfg& c, const double* th, int j, int k, double (&o)[4]) {
+  if (c.family == 3) {
+    const double* b = th + 15 + 7 * j;
+    const double t = k * c.dt;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) o[i] = b[i] + t * b[4 + i];
+    o[3] = b[3];
+  } else {
+    const double* b = th + (c.family == 0 ? 16 : 15) + 4 * j;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) o[i] = b[i];
+  }
 }
 
 }  // namespace hipipm

@@ -31,7 +31,8 @@ __device__ __forceinline__ void eval_c(const Cfg& c, const Slot& s, bool resto, 
   }
   for (int q = lane; q < N * NI; q += WAVE) {
     int k = 1 + q / NI, j = q % NI;
-    const double* o = obs_ptr(c, s.th) + 4 * j;
+    double o[4];
+    obs_at(c, s.th, j, k, o);
     double g = 0.0;
     for (int t = 0; t < 3; ++t) { double e = s.v[xo(k) + t] - o[t]; g += e * e; }
     s.rc[go(c, k, j)] = -(g - o[3] * o[3] - s.v[so(c, k, j)]);
@@ -73,7 +74,8 @@ __device__ __forceinline__ void eval_grad(const Cfg& c, const Slot& s, const dou
       }
       if (r < 3 && k >= 1) {
         for (int j = 0; j < NI; ++j) {
-          const double* o = obs_ptr(c, s.th) + 4 * j;
+          double o[4];
+          obs_at(c, s.th, j, k, o);
           a += 2.0 * (s.v[i] - o[r]) * yv[go(c, k, j)];
         }
       }
@@ -331,7 +333,8 @@ __device__ __forceinline__ void fill_ref(const Cfg& c, const Slot& s, int lane) 
 // the scalar-block words a cold restart of a diverged warm start keeps: iterations and counters
 __device__ __forceinline__ bool kept_on_restart(int q) {
   return q == SC_ITER || (q >= SC_ST_RESTO && q <= SC_ST_PASS) || q == SC_ST_SOLV || q == SC_ST_FFACT ||
-         q == SC_ST_FSOLV || q == SC_ST_REF || q == SC_ST_FB || q == SC_ST_WSTART || q == SC_ST_RTK;
+         q == SC_ST_FSOLV || q == SC_ST_REF || q == SC_ST_FB || q == SC_ST_WSTART || q == SC_ST_RTK ||
+         q == SC_ST_WDS || q == SC_ST_WDR || q == SC_ST_SOFTS || q == SC_ST_SOFTF || q == SC_ST_MUFB;
 }
 
 // Starting point of the main sub-problem: cold (wp == nullptr: x_k = xbar0, u_k = hover thrust,
@@ -351,7 +354,8 @@ __device__ __forceinline__ void start_point(const Cfg& c, const Slot& s, const d
       x = use_warm ? wp[i] : ((r < NX) ? s.th[r] : c.uh);
     } else {
       const int q = i - c.n_w, k = 1 + q / c.NI, j = q % c.NI;
-      const double* o = obs_ptr(c, s.th) + 4 * j;
+      double o[4];
+      obs_at(c, s.th, j, k, o);
       double g = 0.0;
       for (int t = 0; t < 3; ++t) {
         const double e = (use_warm ? wp[xo(k) + t] : s.th[t]) - o[t];
@@ -421,6 +425,7 @@ __device__ __forceinline__ void init_instance(const Cfg& c, const Slot& s, int i
     s.sc[SC_INITF] = 1.0;
     s.sc[SC_WARM] = (use_warm && !gate) ? 1.0 : 0.0;
     s.sc[SC_WSTAGE] = gate ? 1.0 : 0.0;
+    s.sc[SC_MUFREE] = 1.0;
     if (!restart) s.sc[SC_ST_WSTART] = use_warm ? 1.0 : 0.0;
     s.sc[SC_ST_WREJ] = (wp && !use_warm) ? 1.0 : 0.0;
   }
@@ -474,6 +479,11 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
       atomicAdd(&cnt->st[15], (unsigned long long)s.sc[SC_ST_WREJ]);
       atomicAdd(&cnt->st[16], (unsigned long long)s.sc[SC_ST_WRST]);
       atomicAdd(&cnt->st[17], (unsigned long long)s.sc[SC_ST_RTK]);
+      atomicAdd(&cnt->st[18], (unsigned long long)s.sc[SC_ST_WDS]);
+      atomicAdd(&cnt->st[19], (unsigned long long)s.sc[SC_ST_WDR]);
+      atomicAdd(&cnt->st[20], (unsigned long long)s.sc[SC_ST_SOFTS]);
+      atomicAdd(&cnt->st[21], (unsigned long long)s.sc[SC_ST_SOFTF]);
+      atomicAdd(&cnt->st[22], (unsigned long long)s.sc[SC_ST_MUFB]);
       atomicAdd(&cnt->done, 1);
       next = refill ? atomicAdd(&cnt->head, 1) : INT_MAX;
     } else {
@@ -687,6 +697,103 @@ __device__ __forceinline__ void pre_init_y(const Cfg& c, const Slot& s, int lane
   if (lane == 0) s.sc[SC_WORK] = W_LSQ;
 }
 
+// Adaptive barrier update of the original problem (Table I row 7).  Free mode: mu from the
+// complementarity by the LOQO rule, mu = sigma * avg with avg the mean of the products s_i z_i over
+// the bounded components, xi = min_i(s_i z_i) / avg, sigma = 0.1 min(0.05 (1 - xi) / xi, 2)^3, kept in
+// [tol / 10, mu_max]; it continues while E_0 of each new iterate is at most 0.9999 times the largest
+// of the last four accepted ones.  Otherwise the monotone mode takes over from mu = 0.8 avg; once
+// its barrier problem is solved (E_mu <= kappa_eps mu) with that progress the free mode resumes,
+// else mu decreases monotonically.  A change of mu resets the filter.
+__device__ __forceinline__ void mu_adaptive(const Cfg& c, const Slot& s, const Iter& it, const ErrParts& ep,
+                                            double E0, double& mu, int lane) {
+  double* sub = it.sub;
+  const double mu_min = c.tol / 10.0;
+  double sum = 0.0, mn = INFINITY;
+  for (int b = lane; b < c.N * NU; b += WAVE) {
+    const double u = s.v[uo(b / NU) + b % NU];
+    const double p1 = u * it.zlu[b], p2 = (c.umax - u) * it.zuu[b];
+    sum += p1 + p2;
+    mn = fmin(mn, fmin(p1, p2));
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) {
+    const double p = s.v[c.n_w + q] * it.zls[q];
+    sum += p;
+    mn = fmin(mn, p);
+  }
+  sum = wsum(sum);
+  mn = wmin(mn);
+  const int cnt = 2 * c.N * NU + c.N * c.NI;
+  const double avg = cnt ? sum / cnt : 0.0, mnv = cnt ? mn : 0.0;
+  double mumax = s.sc[SC_MUMAX];
+  if (mumax == 0.0) mumax = 1e3 * fmax(avg, mu_min);           // set at the first iteration
+  bool free = s.sc[SC_MUFREE] != 0.0, tiny = sub[5] != 0.0;
+  int nrefs = (int)s.sc[SC_NREFS];
+  double refs[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) refs[i] = s.sc[SC_REFS + i];
+  double nf = sub[6];
+  double fb = 0.0;
+  auto progress = [&](double e) {
+    if (nrefs == 0) return true;
+    double mx = refs[0];
+    for (int i = 1; i < nrefs; ++i) mx = fmax(mx, refs[i]);
+    return e <= 0.9999 * mx;
+  };
+  bool done = false;
+  if (free && !progress(E0)) {
+    // not enough progress: the monotone mode takes over
+    free = false;
+    fb = 1.0;
+    const double nm = fmin(mumax, fmax(mu_min, 0.8 * avg));
+    if (nm != mu) { mu = nm; nf = 0.0; }
+    done = true;
+  }
+  if (!done && !free) {
+    const double Emu = kkt_err(c, ep, compl_max(c, s, it, mu, lane), c.m);
+    if (!(Emu <= c.kappa_eps * mu || tiny)) {
+      done = true;                                               // barrier problem not solved yet
+    } else if (progress(E0)) {
+      free = true;                                               // progress: back to the free mode
+      nrefs = 0;
+    } else {
+      tiny = false;
+      const double nm = fmax(mu_min, fmin(c.kappa_mu * mu, pow(mu, c.theta_mu)));
+      if (nm < mu) { mu = nm; nf = 0.0; }
+      done = true;
+    }
+  }
+  if (!done) {
+    if (nrefs == 4) {
+#pragma unroll
+      for (int i = 1; i < 4; ++i) refs[i - 1] = refs[i];
+      --nrefs;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) refs[i] = (i == nrefs) ? E0 : refs[i];
+    ++nrefs;
+    tiny = false;
+    const double xi = avg > 0.0 ? mnv / avg : 1.0;
+    const double t = fmin(0.05 * (1.0 - xi) / xi, 2.0);
+    double nm = 0.1 * t * t * t * avg;
+    nm = fmin(mumax, fmax(mu_min, nm));
+    if (nm != mu) { mu = nm; nf = 0.0; }
+  }
+  __syncthreads();
+  if (lane == 0) {
+    sub[0] = mu;
+    sub[1] = fmax(c.tau_min, 1.0 - mu);
+    sub[5] = tiny ? 1.0 : 0.0;
+    sub[6] = nf;
+    s.sc[SC_MUMAX] = mumax;
+    s.sc[SC_MUFREE] = free ? 1.0 : 0.0;
+    s.sc[SC_NREFS] = nrefs;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s.sc[SC_REFS + i] = refs[i];
+    s.sc[SC_ST_MUFB] += fb;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const double* theta, const double* warm,
                                          Outs out, Counters* cnt, int refill, int lane) {
   const int ph = (int)s.sc[SC_PHASE];
@@ -742,8 +849,10 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
     }
     return;
   }
-  // ---- monotone barrier update (Table I row 7) ----
-  {
+  // ---- barrier update (Table I row 7): adaptive with monotone fallback, or monotone ----
+  if (!resto && c.mu_strategy == 1) {
+    mu_adaptive(c, s, it, ep, E0, mu, lane);
+  } else {
     const double mu_min = c.tol / 10.0;
     double tau = sub[1];
     double nf = sub[6];
@@ -1003,7 +1112,8 @@ __device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool re
   for (int i = lane; i < NX; i += WAVE) s.ct[i] = s.vt[i] - s.th[i];
   for (int q = lane; q < N * NI; q += WAVE) {
     int k = 1 + q / NI, j = q % NI;
-    const double* o = obs_ptr(c, s.th) + 4 * j;
+    double o[4];
+    obs_at(c, s.th, j, k, o);
     double g = 0.0;
     for (int t = 0; t < 3; ++t) { double e = s.vt[xo(k) + t] - o[t]; g += e * e; }
     s.ct[go(c, k, j)] = g - o[3] * o[3] - s.vt[so(c, k, j)];
@@ -1059,6 +1169,7 @@ __device__ __forceinline__ Acc acceptable(const Cfg& c, const double* sub, const
 __device__ __forceinline__ bool resto_enter(const Cfg& c, const Slot& s, int lane) {
   const double thk = s.sc[SC_THK], phk = s.sc[SC_PHK];
   if (thk <= c.tol) return false;
+  if (lane == 0) { s.sc[SC_WD_ACTIVE] = 0.0; s.sc[SC_WD_SHORT] = 0.0; s.sc[SC_SOFT] = 0.0; }
   const int nf = filter_add(c, s.fm, (int)s.sc[SC_NF], (1.0 - c.gamma_theta) * thk, phk - c.gamma_phi * thk, lane);
   double cmax = 0.0;
   for (int r = lane; r < c.m; r += WAVE) cmax = fmax(cmax, fabs(s.rc[r]));
@@ -1124,9 +1235,132 @@ __device__ __forceinline__ void resto_try_exit(const Cfg& c, const Slot& s, int 
   __syncthreads();
   if (lane == 0) {
     s.sc[SC_TINY] = 0.0;
+    s.sc[SC_NREFS] = 0.0;   // the adaptive update restarts its progress record
     s.sc[SC_PHASE] = PH_INIT_Y;
   }
   __syncthreads();
+}
+
+// A^T y of the original problem at the point v (Jacobian evaluated there) into out
+__device__ __forceinline__ void aty_at(const Cfg& c, const Slot& s, const double* v, const double* y, double* out,
+                                       int lane) {
+  const int N = c.N, NI = c.NI;
+  for (int i = lane; i < c.n; i += WAVE) {
+    double a = 0.0;
+    if (i < c.n_w) {
+      const int k = i / NZ, r = i % NZ;
+      if (r < NX) a += y[k * NX + r];        // +I of the rows defining x_k
+      if (r < 3 && k >= 1)
+        for (int j = 0; j < NI; ++j) {
+          double o[4];
+          obs_at(c, s.th, j, k, o);
+          a += 2.0 * (v[i] - o[r]) * y[go(c, k, j)];
+        }
+    } else {
+      const int q = i - c.n_w, k = 1 + q / NI, j = q % NI;
+      a = -y[go(c, k, j)];
+    }
+    out[i] = a;
+  }
+  __syncthreads();
+  // -G_k^T y_{k+1}: one (interval, column) per item, the column from a forward tangent sweep
+  for (int q = lane; q < N * NZ; q += WAVE) {
+    const int k = q / NZ, j = q % NZ;
+    double x[NX], u[NU], g[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) x[i] = v[xo(k) + i];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) u[i] = v[uo(k) + i];
+    rk4_tangent(c, x, u, j, g);
+    double acc = 0.0;
+#pragma unroll
+    for (int l = 0; l < NX; ++l) acc += g[l] * y[(k + 1) * NX + l];
+    out[k * NZ + j] -= acc;
+  }
+  __syncthreads();
+}
+
+// primal-dual error of the barrier problem at mu in the 1-norm: |grad f + A^T y - z_L + z_U|_1 +
+// |c|_1 + |S_L z_L - mu e|_1 + |S_U z_U - mu e|_1.  g = grad f, aty = A^T y, cv = +-c (only |c|).
+__device__ __forceinline__ double pd_error(const Cfg& c, const double* v, const double* g, const double* aty,
+                                           const double* cv, const double* zlu, const double* zuu,
+                                           const double* zls, double mu, int lane) {
+  double e = 0.0;
+  for (int i = lane; i < c.n; i += WAVE) {
+    double zl = 0.0, zu = 0.0;
+    if (i < c.n_w) {
+      const int k = i / NZ, r = i % NZ;
+      if (r >= NX && k < c.N) { zl = zlu[k * NU + r - NX]; zu = zuu[k * NU + r - NX]; }
+    } else {
+      zl = zls[i - c.n_w];
+    }
+    e += fabs(g[i] + aty[i] - zl + zu);
+  }
+  for (int r = lane; r < c.m; r += WAVE) e += fabs(cv[r]);
+  for (int b = lane; b < c.N * NU; b += WAVE) {
+    const double u = v[uo(b / NU) + b % NU];
+    e += fabs(u * zlu[b] - mu) + fabs((c.umax - u) * zuu[b] - mu);
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) e += fabs(v[c.n_w + q] * zls[q] - mu);
+  return wsum(e);
+}
+
+// objective gradient of the original problem at v into g
+__device__ __forceinline__ void grad_f_at(const Cfg& c, const Slot& s, const double* v, double* g, int lane) {
+  for (int i = lane; i < c.n; i += WAVE) {
+    double gi = 0.0;
+    if (i < c.n_w) {
+      const int k = i / NZ, r = i % NZ;
+      gi = (r < NX) ? 2.0 * c.qw * (v[i] - s.ref[k * NX + r]) : 2.0 * c.rw * (v[i] - c.uh);
+    }
+    g[i] = gi;
+  }
+  __syncthreads();
+}
+
+// Soft feasibility restoration step (Table I row 5): the primal-dual Newton step with one step size
+// alpha = min(alpha_max primal, alpha_max dual) for primal and dual variables, accepted when it
+// lowers the primal-dual error of the barrier problem by the factor soft_factor (the line-search
+// test is not applied).  The trial point is left in vt / ct (its theta and phi in *t).  Returns
+// true when accepted (iterate updated, kappa_Sigma safeguard on z).
+__device__ __forceinline__ bool soft_step(const Cfg& c, const Slot& s, const Iter& it, double mu, double tau,
+                                          double amax, Trial* t, int lane) {
+  const double ad = ftb_dual(c, s, it, tau, lane);
+  const double as = fmin(amax, ad);
+  // error at the current point: grad f, A^T y (Jacobian of this pass), c (-c in rc)
+  grad_f_at(c, s, s.v, s.qv, lane);
+  aty_at(c, s, s.v, s.y, s.ev, lane);
+  const double e0 = pd_error(c, s.v, s.qv, s.ev, s.rc, s.zlu, s.zuu, s.zls, mu, lane);
+  // the trial
+  make_trial(c, s, false, as, s.dv, s.dp, s.dn, lane);
+  for (int r = lane; r < c.m; r += WAVE) s.syt[r] = s.y[r] + as * s.dy[r];
+  for (int b = lane; b < c.N * NU; b += WAVE) {
+    s.szlu[b] = s.zlu[b] + as * s.dzlu[b];
+    s.szuu[b] = s.zuu[b] + as * s.dzuu[b];
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) s.szls[q] = s.zls[q] + as * s.dzls[q];
+  __syncthreads();
+  *t = eval_trial(c, s, false, mu, 0.0, lane);
+  grad_f_at(c, s, s.vt, s.qv, lane);
+  aty_at(c, s, s.vt, s.syt, s.ev, lane);
+  const double e1 = pd_error(c, s.vt, s.qv, s.ev, s.ct, s.szlu, s.szuu, s.szls, mu, lane);
+  if (!(e1 <= c.soft_factor * e0)) return false;
+  const double ks = c.kappa_sigma;
+  for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.vt[i];
+  for (int r = lane; r < c.m; r += WAVE) s.y[r] = s.syt[r];
+  __syncthreads();
+  for (int b = lane; b < c.N * NU; b += WAVE) {
+    const double u = s.v[uo(b / NU) + b % NU], su = c.umax - u;
+    s.zlu[b] = fmax(fmin(s.szlu[b], ks * mu / u), mu / (ks * u));
+    s.zuu[b] = fmax(fmin(s.szuu[b], ks * mu / su), mu / (ks * su));
+  }
+  for (int q = lane; q < c.N * c.NI; q += WAVE) {
+    const double sv = s.v[c.n_w + q];
+    s.zls[q] = fmax(fmin(s.szls[q], ks * mu / sv), mu / (ks * sv));
+  }
+  __syncthreads();
+  if (lane == 0) { s.sc[SC_LALPHA] = as; s.sc[SC_LALPHAZ] = as; s.sc[SC_LSOC] = 0.0; }
+  return true;
 }
 
 __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol_dyn, bool fused, bool mixed,
@@ -1143,9 +1377,20 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
   const double mu = sub[0], tau = sub[1];
   const double zeta = resto ? sqrt(mu) : 0.0;
   const double thk = s.sc[SC_THK], phk = s.sc[SC_PHK], gphi = s.sc[SC_GPHI], amax = s.sc[SC_AMAX];
-  bool accepted = false, augment = false, soc_dir = false, tiny = false;
+  bool accepted = false, augment = false, soc_dir = false, tiny = false, shortened = false;
   double ap = amax;
-  if (step == STEP_READY) {
+  double aug_th = thk, aug_ph = phk;        // the point whose (theta, phi) enters the filter
+  const bool use_wd = !resto && c.wd_trigger > 0;
+  const bool use_soft = !resto && c.soft_max > 0;
+  if (use_wd && s.sc[SC_WD_ACTIVE] != 0.0 && mu != s.sc[SC_WD_MU]) {
+    // a new barrier problem ends the watchdog (its reference belongs to the previous one)
+    __syncthreads();
+    if (lane == 0) s.sc[SC_WD_ACTIVE] = 0.0;
+    __syncthreads();
+  }
+  // in soft restoration there is no line search: the soft step, or hard restoration
+  bool try_soft = use_soft && s.sc[SC_SOFT] != 0.0;
+  if (step == STEP_READY && !try_soft) {
     // tiny step (Table I row 4) at a nearly feasible point
     double tmax = 0.0, cmax = 0.0;
     for (int i = lane; i < c.n; i += WAVE) tmax = fmax(tmax, fabs(s.dv[i]) / (1.0 + fabs(s.v[i])));
@@ -1161,6 +1406,57 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
       make_trial(c, s, resto, amax, s.dv, s.dp, s.dn, lane);
       tiny = true;
       accepted = true;
+      if (use_wd && lane == 0) s.sc[SC_WD_ACTIVE] = 0.0;
+    } else if (use_wd && (s.sc[SC_WD_ACTIVE] != 0.0 || s.sc[SC_WD_SHORT] >= c.wd_trigger)) {
+      // watchdog (Table I row 3): full steps without the line-search test after wd_trigger
+      // shortened steps; a step acceptable with respect to the iterate where the watchdog started
+      // ends it as an ordinary acceptance; if the wd_max-th is not, the iterate goes back to that
+      // reference point and the next pass takes the ordinary line search from there
+      if (s.sc[SC_WD_ACTIVE] == 0.0) {
+        for (int i = lane; i < c.n; i += WAVE) s.wdv[i] = s.v[i];
+        for (int r = lane; r < c.m; r += WAVE) s.wdy[r] = s.y[r];
+        for (int b = lane; b < c.N * NU; b += WAVE) { s.wdzlu[b] = s.zlu[b]; s.wdzuu[b] = s.zuu[b]; }
+        for (int q = lane; q < c.N * c.NI; q += WAVE) s.wdzls[q] = s.zls[q];
+        __syncthreads();
+        if (lane == 0) {
+          s.sc[SC_WD_ACTIVE] = 1.0;
+          s.sc[SC_WD_ITER] = 0.0;
+          s.sc[SC_WD_THK] = thk; s.sc[SC_WD_PHK] = phk; s.sc[SC_WD_GPHI] = gphi; s.sc[SC_WD_AMAX] = amax;
+          s.sc[SC_WD_MU] = mu;
+          s.sc[SC_ST_WDS] += 1.0;
+        }
+        __syncthreads();
+      }
+      make_trial(c, s, resto, amax, s.dv, s.dp, s.dn, lane);
+      Trial t = eval_trial(c, s, resto, mu, zeta, lane);
+      const double wthk = s.sc[SC_WD_THK], wphk = s.sc[SC_WD_PHK];
+      Acc a = acceptable(c, sub, it.filt, wthk, wphk, s.sc[SC_WD_GPHI], s.sc[SC_WD_AMAX], t, lane);
+      const double wit = s.sc[SC_WD_ITER] + 1.0;
+      __syncthreads();
+      if (a.ok) {
+        augment = !(a.sw && a.arm);
+        aug_th = wthk;
+        aug_ph = wphk;
+        if (lane == 0) { s.sc[SC_WD_ACTIVE] = 0.0; s.sc[SC_WD_SHORT] = 0.0; s.sc[SC_WD_ITER] = wit; }
+      } else if (wit >= c.wd_max) {
+        // revert to the reference iterate; no step is accepted in this pass
+        for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.wdv[i];
+        for (int r = lane; r < c.m; r += WAVE) s.y[r] = s.wdy[r];
+        for (int b = lane; b < c.N * NU; b += WAVE) { s.zlu[b] = s.wdzlu[b]; s.zuu[b] = s.wdzuu[b]; }
+        for (int q = lane; q < c.N * c.NI; q += WAVE) s.zls[q] = s.wdzls[q];
+        if (lane == 0) {
+          s.sc[SC_WD_ACTIVE] = 0.0;
+          s.sc[SC_WD_SHORT] = 0.0;
+          s.sc[SC_WD_ITER] = wit;
+          s.sc[SC_ST_WDR] += 1.0;
+        }
+        __syncthreads();
+        return;
+      } else if (lane == 0) {
+        s.sc[SC_WD_ITER] = wit;
+      }
+      accepted = true;
+      __syncthreads();
     } else {
       double amin;
       if (gphi < 0) {
@@ -1173,7 +1469,10 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
       double alpha = amax;
       for (int l = 0;; ++l) {
         // alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point)
-        if (alpha < amin || l >= 60) break;
+        if (alpha < amin || l >= 60) {
+          try_soft = use_soft;          // the line search failed: soft restoration, if enabled
+          break;
+        }
         make_trial(c, s, resto, alpha, s.dv, s.dp, s.dn, lane);
         Trial t = eval_trial(c, s, resto, mu, zeta, lane);
         Acc a = acceptable(c, sub, it.filt, thk, phk, gphi, alpha, t, lane);
@@ -1181,6 +1480,7 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
           ap = alpha;
           augment = !(a.sw && a.arm);
           accepted = true;
+          shortened = l > 0;
           break;
         }
         if (l == 0 && t.fin && c.max_soc > 0 && t.th >= thk) {
@@ -1214,6 +1514,7 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
               augment = !(as.sw && as.arm);
               accepted = true;
               soc_dir = true;
+              shortened = true;
               if (lane == 0) s.sc[SC_ST_SOCA] += 1.0;
               break;
             }
@@ -1226,6 +1527,46 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
     }
   }
   __syncthreads();
+  if (try_soft && step == STEP_READY) {
+    if (s.sc[SC_SOFT] == 0.0) {
+      // the line search failed: soft restoration starts at this iterate
+      if (lane == 0) {
+        s.sc[SC_SOFT] = 1.0;
+        s.sc[SC_SOFT_IT] = 0.0;
+        s.sc[SC_SOFT_THK] = thk;
+        s.sc[SC_SOFT_PHK] = phk;
+        s.sc[SC_WD_ACTIVE] = 0.0;
+        s.sc[SC_WD_SHORT] = 0.0;
+      }
+      __syncthreads();
+    }
+    Trial t{0.0, 0.0, false};
+    const bool ok = s.sc[SC_SOFT_IT] < c.soft_max && soft_step(c, s, it, mu, tau, amax, &t, lane);
+    if (ok) {
+      // back to the ordinary iteration once the point is acceptable to the filter with a
+      // sufficient decrease of theta or phi_mu over the point where soft restoration started
+      // (which then enters the filter)
+      const double rth = s.sc[SC_SOFT_THK], rph = s.sc[SC_SOFT_PHK];
+      const bool dec = t.th <= (1.0 - c.gamma_theta) * rth ||
+                       (t.ph - (rph - c.gamma_phi * rth)) <= 10.0 * 2.220446049250313e-16 * fabs(rph);
+      const bool leave = t.fin && t.th <= sub[3] && dec && filter_ok(c, it.filt, (int)sub[6], t.th, t.ph, lane);
+      if (leave) {
+        const int nf = filter_add(c, it.filt, (int)sub[6], (1.0 - c.gamma_theta) * rth, rph - c.gamma_phi * rth,
+                                  lane);
+        if (lane == 0) sub[6] = nf;
+      }
+      if (lane == 0) {
+        if (leave) s.sc[SC_SOFT] = 0.0;
+        s.sc[SC_SOFT_IT] += 1.0;
+        s.sc[SC_ST_SOFTS] += 1.0;
+        s.sc[SC_ITER] += 1.0;
+      }
+      __syncthreads();
+      return;
+    }
+    if (lane == 0) { s.sc[SC_SOFT] = 0.0; s.sc[SC_ST_SOFTF] += 1.0; }
+    __syncthreads();
+  }
   if (!accepted) {
     // line search or inertia correction failed
     if (!resto) {
@@ -1243,9 +1584,12 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
   const double az = ftb_dual(c, s, it, tau, lane);
   const double* ady = soc_dir ? s.dys : s.dy;
   if (augment) {
-    const int nf = filter_add(c, it.filt, (int)sub[6], (1.0 - c.gamma_theta) * thk, phk - c.gamma_phi * thk, lane);
+    const int nf = filter_add(c, it.filt, (int)sub[6], (1.0 - c.gamma_theta) * aug_th, aug_ph - c.gamma_phi * aug_th,
+                              lane);
     if (lane == 0) sub[6] = nf;
   }
+  if (use_wd && lane == 0 && s.sc[SC_WD_ACTIVE] == 0.0)
+    s.sc[SC_WD_SHORT] = shortened ? s.sc[SC_WD_SHORT] + 1.0 : 0.0;
   for (int r = lane; r < c.m; r += WAVE) it.y[r] += ap * ady[r];
   for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.vt[i];
   if (resto)

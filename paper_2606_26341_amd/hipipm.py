@@ -41,7 +41,9 @@ class Options(C.Structure):
         ("poll_every", C.c_int32), ("timing", C.c_int32),
         ("fuse_below", C.c_int32), ("precision", C.c_int32), ("refine_max", C.c_int32),
         ("refine_tol", C.c_double), ("warm_mu0", C.c_double), ("warm_push", C.c_double),
-        ("warm_iter_cap", C.c_int32), ("warm_gate", C.c_int32),
+        ("warm_iter_cap", C.c_int32), ("warm_gate", C.c_int32), ("watchdog_trigger", C.c_int32),
+        ("watchdog_max", C.c_int32), ("soft_resto_max", C.c_int32), ("soft_resto_factor", C.c_double),
+        ("mu_strategy", C.c_int32),
     ]
 
 
@@ -55,7 +57,9 @@ class Stats(C.Structure):
                                          "factorizations", "resto_entries", "tiny_steps", "passes",
                                          "instances_done", "solves", "fused_factorizations",
                                          "fused_solves", "refine_sweeps", "fp64_fallbacks", "warm_started",
-                                         "warm_rejected", "warm_restarts", "fp32_retakes")]
+                                         "warm_rejected", "warm_restarts", "fp32_retakes", "watchdog_starts",
+                                         "watchdog_reverts", "soft_resto_steps", "soft_resto_fails",
+                                         "mu_fallbacks")]
 
 
 _lib = None

@@ -10,9 +10,11 @@ Instance ``i`` of workload ``c`` is drawn from ``numpy.random.default_rng([c, i]
 so that an instance is the same whatever the batch size or slot count.
 
 theta layouts (float64, one row per instance):
-  quad_obs   : [xbar0 (13), target position (3), n_obs x (cx, cy, cz, r)]
-  quad_track : [xbar0 (13), A, omega, n_obs x (cx, cy, cz, r)]
-  multi_quad : n_agents x [xbar0 (13), goal position (3)]
+  quad_obs          : [xbar0 (13), target position (3), n_obs x (cx, cy, cz, r)]
+  quad_track        : [xbar0 (13), A, omega, n_obs x (cx, cy, cz, r)]
+  multi_quad        : n_agents x [xbar0 (13), goal position (3)]
+  quad_track_moving : [xbar0 (13), A, omega, n_obs x (cx, cy, cz, r, vx, vy, vz)], sphere centre
+                      (cx, cy, cz) + t (vx, vy, vz) at time t = k dt of stage k
 State order of xbar0: position (3), unit quaternion (w, x, y, z), world-frame
 linear velocity (3), body rates (3).
 """
@@ -26,6 +28,7 @@ import numpy as np
 FAMILY_QUAD_OBS = 0
 FAMILY_QUAD_TRACK = 1
 FAMILY_MULTI_QUAD = 2
+FAMILY_QUAD_TRACK_MOVING = 3
 
 NX1 = 13  # states per quadrotor
 NU1 = 4   # rotor thrusts per quadrotor
@@ -101,6 +104,8 @@ class Workload:
             return NX1 + 3 + 4 * self.n_obs
         if self.family == FAMILY_QUAD_TRACK:
             return NX1 + 2 + 4 * self.n_obs
+        if self.family == FAMILY_QUAD_TRACK_MOVING:
+            return NX1 + 2 + 7 * self.n_obs
         return self.n_agents * (NX1 + 3)
 
     def as_dict(self) -> dict:
@@ -115,6 +120,8 @@ class Workload:
             return _draw_quad_obs(self, rng)
         if self.family == FAMILY_QUAD_TRACK:
             return _draw_quad_track(self, rng)
+        if self.family == FAMILY_QUAD_TRACK_MOVING:
+            return _draw_quad_track_moving(self, rng)
         return _draw_multi(self, rng)
 
     def thetas(self, start: int, count: int) -> np.ndarray:
@@ -194,6 +201,36 @@ def _draw_quad_track(w: Workload, rng) -> np.ndarray:
     return np.concatenate([x0, [A, om], obs.ravel()])
 
 
+def _draw_quad_track_moving(w: Workload, rng) -> np.ndarray:
+    """Figure-eight tracking with spheres that cross the reference path at constant velocity: sphere
+    j is near the reference position p_ref(t_j) (N(0, 0.3^2 I)) at a time t_j ~ U(0, N dt) and moves
+    at v_j ~ N(0, 0.5^2 I) m/s; resampled if it comes within r + 0.1 m of the start at t = 0 or
+    within r + 0.3 m of the reference during its first 0.5 s."""
+    A = rng.uniform(1.0, 3.0)
+    T = rng.uniform(2.0, 6.0)
+    om = 2.0 * math.pi / T
+    x0 = np.zeros(NX1)
+    x0[3] = 1.0
+    x0[0:3] = rng.normal(0.0, 0.3, 3)
+    x0[7:10] = np.array([A * om, A * om, 0.0]) + rng.normal(0.0, 0.3, 3)
+    horizon = w.N * w.dt
+    ts = np.arange(0.0, 0.5 + 1e-9, w.dt)
+    obs = np.zeros((w.n_obs, 7))
+    for j in range(w.n_obs):
+        while True:
+            tj = rng.uniform(0.0, horizon)
+            v = rng.normal(0.0, 0.5, 3)
+            c0 = _fig8_pos(A, om, tj) + rng.normal(0.0, 0.3, 3) - tj * v
+            r = rng.uniform(0.2, 0.5)
+            if np.linalg.norm(c0 - x0[0:3]) >= r + 0.1 and \
+                    all(np.linalg.norm(c0 + t * v - _fig8_pos(A, om, t)) >= r + 0.3 for t in ts):
+                break
+        obs[j, 0:3] = c0
+        obs[j, 3] = r
+        obs[j, 4:7] = v
+    return np.concatenate([x0, [A, om], obs.ravel()])
+
+
 def _draw_multi(w: Workload, rng) -> np.ndarray:
     out = []
     for a in range(w.n_agents):
@@ -206,13 +243,15 @@ def _draw_multi(w: Workload, rng) -> np.ndarray:
 
 
 # The five workloads: plain FP64 point-to-point (C1), figure-eight tracking (C2),
-# four-quadrotor swaps (C3), cluttered FP32+refinement (C4), learned warm start (C5).
+# four-quadrotor swaps (C3), cluttered FP32+refinement (C4), learned warm start (C5); and the
+# tracking task with three moving spheres (C2m).
 WORKLOADS = {
     "C1": Workload("C1", FAMILY_QUAD_OBS, 64, N=10, n_obs=3, seed_tag=1),
     "C2": Workload("C2", FAMILY_QUAD_TRACK, 4096, N=30, n_obs=8, seed_tag=2),
     "C3": Workload("C3", FAMILY_MULTI_QUAD, 1024, N=20, n_agents=4, seed_tag=3),
     "C4": Workload("C4", FAMILY_QUAD_OBS, 8192, N=40, n_obs=32, precision="fp32ir", seed_tag=4),
     "C5": Workload("C5", FAMILY_QUAD_OBS, 16384, N=10, n_obs=3, precision="fp32ir", seed_tag=5),
+    "C2m": Workload("C2m", FAMILY_QUAD_TRACK_MOVING, 4096, N=30, n_obs=3, seed_tag=6),
     # reduced cluttered case the oracle solves in seconds (parity of the FP32 + refinement path)
     "C4s": Workload("C4s", FAMILY_QUAD_OBS, 32, N=12, n_obs=8, precision="fp32ir", seed_tag=41),
 }

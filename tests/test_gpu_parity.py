@@ -120,7 +120,7 @@ def _check_kkt_cases(torch, w, precision, dx, dc, pts, mu=0.1):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("name", ["C1", "C2"])
+@pytest.mark.parametrize("name", ["C1", "C2", "C2m"])
 @pytest.mark.parametrize("dx,dc", [(0.0, 0.0), (1e-2, 0.0), (10.0, 1e-6)])
 def test_kkt_factor_solve_matches_dense_oracle(torch_cuda, name, dx, dc, precision):
     w = W.get(name)
@@ -147,8 +147,8 @@ def test_kkt_inertia_verdicts_on_indefinite_matrices(torch_cuda, name, dx, preci
 
 
 # ----------------------------------------------------------------------------- one-step replay
-def _oracle_trace(w, th, max_passes=400):
-    h = oracle.Handle.quad(w, th)
+def _oracle_trace(w, th, max_passes=400, oopts=None):
+    h = oracle.Handle.quad(w, th, opts=oopts)
     states = [h.state()]
     while h.phase != oracle.PH_DONE and len(states) < max_passes:
         h.step()
@@ -156,8 +156,9 @@ def _oracle_trace(w, th, max_passes=400):
     return states
 
 
-def _replay(torch, w, th, opts, max_passes=400):
-    states = _oracle_trace(w, th, max_passes)
+def _replay(torch, w, th, opts, max_passes=400, oopts=None, states=None):
+    if states is None:
+        states = _oracle_trace(w, th, max_passes, oopts)
     pairs = [(k, states[k], states[k + 1]) for k in range(len(states) - 1)
              if oracle.unpack_state(states[k], w.n, w.m)["phase"] != oracle.PH_DONE]
     s = solver_for(w, len(pairs), **opts)
@@ -167,16 +168,37 @@ def _replay(torch, w, th, opts, max_passes=400):
     out = s.state_export(len(pairs))
     worst = 0.0
     phases = []
-    for j, (k, _, nxt) in enumerate(pairs):
-        ph = oracle.unpack_state(pairs[j][1], w.n, w.m)["phase"]
+    n_singular = 0
+    for j, (k, cur, nxt) in enumerate(pairs):
+        ph = oracle.unpack_state(cur, w.n, w.m)["phase"]
         phases.append(ph)
         bad, ev = compare_states(out[j], nxt, w.n, w.m)
         say(w.name, "pass", k, "phase", ph, "e_v", ev, bad)
         assert not bad, (k, bad)
+        if ev > 1e-8:
+            # allowed only where FP64 cannot decide the step: the matrix of eq. (7) at the pass's
+            # input is singular to working precision (an eigenvalue below 64 eps |K|_2, so its sign,
+            # i.e. the inertia test, and the step along it are not determined by FP64 arithmetic)
+            lam_min, lam_max = _kkt_spectrum(w, th, cur, oopts)
+            say("   |lambda| min", lam_min, "max", lam_max)
+            assert lam_min <= 64 * np.finfo(float).eps * lam_max, (k, ev, lam_min, lam_max)
+            n_singular += 1
+            ev = 0.0
         worst = max(worst, ev)
-    say("worst one-step e_v", worst)
+    say("worst one-step e_v (passes whose matrix FP64 resolves)", worst, "singular to working precision:",
+        n_singular, "of", len(pairs))
     assert worst <= 1e-8
+    assert n_singular <= 0.2 * len(pairs)
     return phases
+
+
+def _kkt_spectrum(w, th, cur, oopts=None):
+    """smallest and largest |eigenvalue| of the oracle's unperturbed matrix of eq. (7) at state cur"""
+    h = oracle.Handle.quad(w, th, opts=oopts)
+    h.set_state(cur)
+    K = h.kkt_matrix()
+    lam = np.abs(np.linalg.eigvalsh(K))
+    return float(lam.min()), float(lam.max())
 
 
 def start_inside_sphere(w, idx=1):
@@ -192,7 +214,8 @@ def start_inside_sphere(w, idx=1):
 # the kernels the benchmark runs (the fused pass kernel) and the per-phase kernels; C1 #0, #5, #6
 # and C2 #0, #10 are plain solves, "resto" passes through restoration entries and exits
 @pytest.mark.parametrize("fused", [1, 0])
-@pytest.mark.parametrize("name,idx", [("C1", 0), ("C1", 5), ("C1", 6), ("C2", 0), ("C2", 10), ("C1", "resto")])
+@pytest.mark.parametrize("name,idx", [("C1", 0), ("C1", 5), ("C1", 6), ("C2", 0), ("C2", 10), ("C1", "resto"),
+                                      ("C2m", 1)])
 def test_one_step_replay_matches_oracle(torch_cuda, name, idx, fused):
     w = W.get(name)
     th = start_inside_sphere(w) if idx == "resto" else w.theta(idx)
@@ -219,6 +242,71 @@ def test_tiny_step_rule_matches_oracle(torch_cuda, fused):
     assert g["iters"][0] == o["iters"][0]
     n_match, n_diff = _compare_solves(w, th[None, :], g, o)
     assert n_match == 1
+
+
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("trigger", [1, 2])
+def test_watchdog_matches_oracle(torch_cuda, trigger, fused):
+    """The watchdog (Table I row 3) on starts inside a sphere, whose line searches shorten step after
+    step: replay through its activations, unconditional full steps and reverts, then whole solves,
+    against the oracle with the same watchdog options."""
+    torch = torch_cuda
+    w = W.get("C1")
+    opts = dict(watchdog_trigger=trigger, watchdog_max=3, fuse_below=(1 << 30) if fused else 0)
+    oopts = oracle.default_opts(watchdog_trigger=trigger, watchdog_max=3)
+    _replay(torch, w, start_inside_sphere(w, 10), opts, oopts=oopts)
+    TH = np.stack([start_inside_sphere(w, i) for i in range(16)])
+    o = oracle.solve_quad(w, TH, threads=THREADS, opts=oopts)
+    g, st = _gpu_solve(w, TH, slots=8, **opts)
+    say("gpu stats", st, "oracle watchdog starts / reverts", o["stats"][:, 11].sum(), o["stats"][:, 12].sum())
+    assert st["watchdog_starts"] == o["stats"][:, 11].sum() >= 4
+    assert st["watchdog_reverts"] == o["stats"][:, 12].sum() >= 3
+    assert np.array_equal(g["iters"], o["iters"]) and np.array_equal(g["status"], o["status"])
+    n_match, n_diff = _compare_solves(w, TH, g, o)
+    assert n_diff == 0
+
+
+@pytest.mark.parametrize("fused", [1, 0])
+def test_soft_restoration_matches_oracle(torch_cuda, fused):
+    """Soft feasibility restoration (Table I row 5), forced by a filter that accepts nothing
+    (theta_max of the original problem set to 1e-300 after the least-squares pass): replay of the
+    oracle's passes through soft steps, their hand-over to hard restoration and the restoration."""
+    w = W.get("C1")
+    th = w.theta(2)
+    oopts = oracle.default_opts(soft_resto_max=3)
+    h = oracle.Handle.quad(w, th, opts=oopts)
+    h.step()
+    st0 = h.state()
+    st0[16 + 3] = 1e-300
+    h.set_state(st0)
+    states = [h.state()]
+    while h.phase != oracle.PH_DONE and len(states) < 40:
+        h.step()
+        states.append(h.state())
+    soft = [oracle.unpack_state(x, w.n, w.m)["soft"]["active"] for x in states]
+    phases = _replay(torch_cuda, w, th, dict(soft_resto_max=3, fuse_below=(1 << 30) if fused else 0),
+                     states=states)
+    say("soft flags", soft, "phases", phases)
+    assert sum(soft) >= 3 and oracle.PH_RESTO in phases
+
+
+@pytest.mark.parametrize("name,idx,count", [("C1", 2, 32), ("C2m", 1, 8), ("C2", 10, 8)])
+def test_adaptive_mu_matches_oracle(torch_cuda, name, idx, count):
+    """Adaptive barrier update with the monotone fallback (Table I row 7): replay of one solve and
+    a sample of whole solves against the oracle with the same strategy (same statuses and iteration
+    counts, same KKT points)."""
+    torch = torch_cuda
+    w = W.get(name)
+    oopts = oracle.default_opts(mu_strategy=1)
+    _replay(torch, w, w.theta(idx), dict(mu_strategy=1), oopts=oopts)
+    TH = w.thetas(0, count)
+    o = oracle.solve_quad(w, TH, threads=THREADS, opts=oopts)
+    g, st = _gpu_solve(w, TH, slots=count, mu_strategy=1)
+    say("gpu stats", st, "oracle fallbacks", o["stats"][:, 15].sum(), "iterations", o["iters"].sum())
+    assert st["mu_fallbacks"] == o["stats"][:, 15].sum()
+    assert np.array_equal(g["iters"], o["iters"])
+    n_match, n_diff = _compare_solves(w, TH, g, o)
+    assert n_diff == 0 and n_match == int((o["status"] == oracle.ST_CONVERGED).sum())
 
 
 def test_one_step_replay_mixed_precision(torch_cuda):
@@ -278,6 +366,19 @@ def test_c2_sample_matches_oracle(torch_cuda):
     n_match, n_diff = _compare_solves(w, TH, g, o)
     say("C2 match", n_match, "different local minimum", n_diff)
     assert n_diff == 0 and n_match == int((o["status"] == oracle.ST_CONVERGED).sum())
+
+
+def test_moving_sphere_sample_matches_oracle(torch_cuda):
+    """The tracking task with spheres moving at constant velocity (sphere centres a function of the
+    stage time): 32 instances against the oracle's solves."""
+    w = W.get("C2m")
+    TH = w.thetas(0, 32)
+    o = oracle.solve_quad(w, TH, threads=THREADS)
+    g, st = _gpu_solve(w, TH, slots=16)
+    say("gpu stats", st, "oracle statuses", np.bincount(o["status"]))
+    n_match, n_diff = _compare_solves(w, TH, g, o)
+    say("C2m match", n_match, "different local minimum", n_diff)
+    assert n_diff == 0 and n_match == int((o["status"] == oracle.ST_CONVERGED).sum()) >= 28
 
 
 def test_mixed_precision_matches_oracle(torch_cuda):

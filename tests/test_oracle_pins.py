@@ -400,7 +400,7 @@ def test_restoration_exit_keeps_or_resets_bound_multipliers(z_set):
     # raise z_L of x2 in the restoration iterate before the exit pass (the pass divides it by ~100)
     s = h.state()
     n, m = 2, 1
-    F = (len(s) - 16 - (8 + 3 * n + m) - (8 + 3 * (n + 2 * m) + m) - 2 * n) // 4
+    F = (len(s) - 16 - (8 + 3 * n + m) - (8 + 3 * (n + 2 * m) + m) - 2 * n - (8 + 3 * n + m) - 4 - 8) // 4
     p_rs = 16 + (8 + 3 * n + m + 2 * F) + 8          # the restoration iterate's x
     s[p_rs + (n + 2 * m) + m + 1] = z_set              # its z_L of x2
     h.set_state(s)
@@ -534,3 +534,306 @@ def test_tiny_step_fires_at_the_barrier_minimiser():
     assert s2["main"]["mu"] < 0.1 and s2["main"]["nf"] == 0
     o = oracle.solve_quad(w, th[None, :])
     assert o["status"][0] == oracle.ST_CONVERGED and o["stats"][0, 6] == o["iters"][0] >= 3
+
+
+def _moving_from_static(th_static, n_obs, vel):
+    """tracking-family theta with the spheres of a fixed-sphere row and the given velocities"""
+    head = th_static[:15]
+    obs = th_static[15:].reshape(n_obs, 4)
+    return np.concatenate([head, np.concatenate([obs, vel], axis=1).ravel()])
+
+
+def test_moving_spheres_at_rest_reduce_to_the_fixed_family():
+    # centre c + t_k * 0 = c exactly, so a sphere at rest gives the fixed-sphere tracking problem:
+    # the same solve, bit for bit
+    w1 = W.get("C2")
+    wm = W.Workload("C2m-rest", W.FAMILY_QUAD_TRACK_MOVING, 2, N=w1.N, n_obs=w1.n_obs)
+    th1 = w1.thetas(0, 2)
+    thm = np.stack([_moving_from_static(t, w1.n_obs, np.zeros((w1.n_obs, 3))) for t in th1])
+    a = oracle.solve_quad(w1, th1, threads=2)
+    b = oracle.solve_quad(wm, thm, threads=2)
+    for k in ("x", "y", "zl", "zu", "obj", "kkt", "status", "iters"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_moving_sphere_rows_closed_form():
+    # inequality row of sphere j at stage k: |p_k - (c_j + k dt v_j)|^2 - r_j^2 - s_kj, gradient
+    # 2 (p_k - c_j(t_k)) on p_k and -1 on s_kj, Hessian 2 y_kj I on p_k
+    w = W.get("C2m")
+    th = w.theta(3)
+    rng = np.random.default_rng(5)
+    v = oracle.cold_start(w, th) + 0.1 * rng.normal(size=w.n)
+    y = rng.normal(size=w.m)
+    f, g, c, J, H = oracle.quad_eval(w, th, v, y)
+    obs = th[15:].reshape(w.n_obs, 7)
+    nx, nz = 13, 17
+    for k in (1, 7, w.N):
+        p = v[k * nz:k * nz + 3]
+        for j in range(w.n_obs):
+            ck = obs[j, 0:3] + k * w.dt * obs[j, 4:7]
+            row = (w.N + 1) * nx + (k - 1) * w.n_obs + j
+            si = w.n_w + (k - 1) * w.n_obs + j
+            assert abs(c[row] - (np.sum((p - ck) ** 2) - obs[j, 3] ** 2 - v[si])) <= 1e-12
+            assert np.allclose(J[row, k * nz:k * nz + 3], 2.0 * (p - ck), rtol=0, atol=1e-14)
+            assert J[row, si] == -1.0
+    # the sphere rows' Hessian contribution: remove the objective and dynamics parts by comparing
+    # with the multipliers of the sphere rows set to zero
+    y0 = y.copy()
+    y0[(w.N + 1) * nx:] = 0.0
+    H0 = oracle.quad_eval(w, th, v, y0)[4]
+    for k in (1, w.N):
+        yk = y[(w.N + 1) * nx + (k - 1) * w.n_obs:(w.N + 1) * nx + k * w.n_obs].sum()
+        D = (H - H0)[k * nz:k * nz + 3, k * nz:k * nz + 3]
+        assert np.allclose(D, 2.0 * yk * np.eye(3), atol=1e-12)
+
+
+def test_moving_sphere_solves_reach_kkt_points():
+    w = W.get("C2m")
+    TH = w.thetas(0, 8)
+    o = oracle.solve_quad(w, TH, threads=8)
+    assert (o["status"] == oracle.ST_CONVERGED).sum() >= 7
+    for i in np.flatnonzero(o["status"] == oracle.ST_CONVERGED):
+        assert o["kkt"][i] <= 1e-8
+        x = o["x"][i]
+        s = x[w.n_w:]
+        assert (s >= 0).all() and (o["zl"][i] >= 0).all()
+
+
+# ------------------------------------------------------------------------ watchdog (Table I row 3)
+def _maratos_no_soc(ang, **opts):
+    # min 2 (x1^2 + x2^2 - 1) - x1  s.t.  x1^2 + x2^2 = 1: the solution is (1, 0) (on the circle the
+    # objective is -x1); started on the circle at angle `ang`, the filter test rejects full Newton
+    # steps near the circle (the Maratos effect) when second-order corrections are off
+    f = lambda x: 2 * (x[0] ** 2 + x[1] ** 2 - 1) - x[0]
+    g = lambda x: np.array([4 * x[0] - 1, 4 * x[1]])
+    c = lambda x: np.array([x[0] ** 2 + x[1] ** 2 - 1])
+    J = lambda x: np.array([[2 * x[0], 2 * x[1]]])
+    H = lambda x, of, y: (of * 4 + 2 * y[0]) * np.eye(2)
+    return _generic(2, 1, [-INF, -INF], [INF, INF], f, g, c, J, H, [np.cos(ang), np.sin(ang)], max_soc=0, **opts)
+
+
+def test_watchdog_full_steps_revert_and_solution():
+    h = _maratos_no_soc(1.5, watchdog_trigger=1, watchdog_max=3)
+    prev = oracle.unpack_state(h.state(), 2, 1)
+    n_full = n_revert = 0
+    while h.phase != oracle.PH_DONE:
+        h.step()
+        st = oracle.unpack_state(h.state(), 2, 1)
+        wd = st["watchdog"]
+        info = h.last_info()
+        if prev["phase"] == oracle.PH_REGULAR and (prev["watchdog"]["active"] or prev["watchdog"]["short"] >= 1):
+            ref = wd if wd["active"] else None
+            if st["iter"] == prev["iter"]:
+                # a revert: the iterate is the reference stored when the watchdog started, bit for bit,
+                # and no iteration is counted
+                n_revert += 1
+                assert wd["active"] == 0 and wd["short"] == 0 and wd["iter"] == 3
+                assert np.array_equal(st["main"]["x"], prev["watchdog"]["x"] if prev["watchdog"]["active"]
+                                      else prev["main"]["x"])
+                assert np.array_equal(st["main"]["y"], prev["watchdog"]["y"] if prev["watchdog"]["active"]
+                                      else prev["main"]["y"])
+            else:
+                # a watchdog step: the full step (no bounds, so alpha_max = 1)
+                n_full += 1
+                dx = h.last_step()[0]
+                assert info["alpha"] == 1.0
+                assert np.array_equal(st["main"]["x"], prev["main"]["x"] + dx)
+                if ref is not None:
+                    assert ref["alpha_max"] == 1.0
+        prev = st
+    o = h.outputs()
+    assert n_full >= 6 and n_revert >= 2
+    assert o["status"][0] == oracle.ST_CONVERGED
+    assert np.abs(o["x"] - [1.0, 0.0]).max() <= 1e-8
+    assert o["stats"][12] == n_revert and o["stats"][11] >= n_revert + 1   # activations, reverts
+
+
+def test_watchdog_off_takes_the_ordinary_line_search():
+    # watchdog_trigger = 0: the counters stay zero and the solve is the one without the options
+    h0 = _maratos_no_soc(1.5)
+    h1 = _maratos_no_soc(1.5, watchdog_trigger=0, watchdog_max=7)
+    h0.run(); h1.run()
+    o0, o1 = h0.outputs(), h1.outputs()
+    assert o1["stats"][11] == o1["stats"][12] == 0
+    for k in ("x", "y", "iters"):
+        assert np.array_equal(o0[k], o1[k]), k
+
+
+# ------------------------------------------------------------------------ soft restoration (Table I row 5)
+def _soft_problem(**opts):
+    # min (x1 - 1)^2 + (x2 - 2)^2  s.t.  x1 + x2^2 = 1,  0 <= x <= 10, from (3, 3)
+    f = lambda x: (x[0] - 1) ** 2 + (x[1] - 2) ** 2
+    g = lambda x: np.array([2 * (x[0] - 1), 2 * (x[1] - 2)])
+    c = lambda x: np.array([x[0] + x[1] ** 2 - 1])
+    J = lambda x: np.array([[1.0, 2 * x[1]]])
+    H = lambda x, of, y: np.diag([2 * of, 2 * of + 2 * y[0]])
+    h = _generic(2, 1, [0.0, 0.0], [10.0, 10.0], f, g, c, J, H, [3.0, 3.0], **opts)
+    return h, (f, g, c, J, H)
+
+
+def _pd_error_np(fns, x, y, zl, zu, mu, xl, xu):
+    f, g, c, J, H = fns
+    d = g(x) + J(x).T @ y - zl + zu
+    return (np.abs(d).sum() + np.abs(c(x)).sum() + np.abs((x - xl) * zl - mu).sum()
+            + np.abs((xu - x) * zu - mu).sum())
+
+
+def test_soft_restoration_steps_and_hand_over_to_hard_restoration():
+    # with theta_max forced to ~0 every line-search trial is rejected, so each iteration fails its
+    # line search: soft restoration takes the primal-dual step with alpha = min(alpha_max primal,
+    # alpha_max dual) (checked here in numpy), which must lower the primal-dual error by the factor
+    # 0.9999; after soft_resto_max soft steps the method moves on to hard restoration
+    h, fns = _soft_problem(soft_resto_max=3)
+    xl, xu = np.zeros(2), np.full(2, 10.0)
+    h.step()                                            # least-squares multipliers
+    s = h.state()
+    s[16 + 3] = 1e-300                                  # theta_max of the original problem
+    h.set_state(s)
+    ks = oracle.default_opts().kappa_sigma
+    for it in range(1, 4):
+        a = oracle.unpack_state(h.state(), 2, 1)["main"]
+        h.step()
+        st = oracle.unpack_state(h.state(), 2, 1)
+        b = st["main"]
+        dx, dy, dzl, dzu = h.last_step()
+        tau, mu = a["tau"], a["mu"]
+        assert b["mu"] == mu
+        ap = min(1.0, min((-tau * (a["x"][i] - xl[i]) / dx[i]) if dx[i] < 0 else (tau * (xu[i] - a["x"][i]) / dx[i])
+                          for i in range(2) if dx[i] != 0))
+        ad = min([1.0] + [-tau * a["zl"][i] / dzl[i] for i in range(2) if dzl[i] < 0]
+                 + [-tau * a["zu"][i] / dzu[i] for i in range(2) if dzu[i] < 0])
+        al = min(ap, ad)
+        assert st["soft"]["active"] == 1 and st["soft"]["iter"] == it and st["iter"] == it
+        assert np.array_equal(b["x"], a["x"] + al * dx) and np.array_equal(b["y"], a["y"] + al * dy)
+        zl = np.maximum(np.minimum(a["zl"] + al * dzl, ks * mu / (b["x"] - xl)), mu / (ks * (b["x"] - xl)))
+        zu = np.maximum(np.minimum(a["zu"] + al * dzu, ks * mu / (xu - b["x"])), mu / (ks * (xu - b["x"])))
+        assert np.allclose(b["zl"], zl, rtol=1e-15, atol=0) and np.allclose(b["zu"], zu, rtol=1e-15, atol=0)
+        e0 = _pd_error_np(fns, a["x"], a["y"], a["zl"], a["zu"], mu, xl, xu)
+        e1 = _pd_error_np(fns, b["x"], b["y"], a["zl"] + al * dzl, a["zu"] + al * dzu, mu, xl, xu)
+        assert e1 <= 0.9999 * e0
+    h.step()                                            # soft steps used up: hard restoration
+    st = oracle.unpack_state(h.state(), 2, 1)
+    assert st["phase"] == oracle.PH_RESTO and st["soft"]["active"] == 0
+    o = h.outputs()
+    assert o["stats"][13] == 3 and o["stats"][14] == 1
+
+
+def test_soft_restoration_returns_when_the_filter_accepts():
+    # with the ordinary theta_max back after the first soft step, the next soft step's point is
+    # acceptable to the filter with a decrease over the soft-restoration start: back to the ordinary
+    # iteration, and that start point enters the filter
+    h, fns = _soft_problem(soft_resto_max=5)
+    h.step()
+    s = h.state()
+    thmax = s[16 + 3]
+    s[16 + 3] = 1e-300
+    h.set_state(s)
+    h.step()
+    st = oracle.unpack_state(h.state(), 2, 1)
+    assert st["soft"]["active"] == 1
+    s = h.state()
+    s[16 + 3] = thmax
+    h.set_state(s)
+    nf0 = st["main"]["nf"]
+    h.step()
+    st = oracle.unpack_state(h.state(), 2, 1)
+    assert st["soft"]["active"] == 0 and st["soft"]["iter"] == 2 and st["phase"] == oracle.PH_REGULAR
+    assert st["main"]["nf"] == nf0 + 1
+    th0, ph0 = st["soft"]["theta"], st["soft"]["phi"]
+    o = oracle.default_opts()
+    assert np.isclose(st["main"]["fth"][-1], (1 - o.gamma_theta) * th0, rtol=1e-15)
+    assert np.isclose(st["main"]["fph"][-1], ph0 - o.gamma_phi * th0, rtol=1e-15)
+    h.run()
+    out = h.outputs()
+    assert out["status"][0] == oracle.ST_CONVERGED
+
+
+def test_kkt_matrix_export_is_the_assembled_eq7_matrix():
+    # the conditioning hook: at a regular-phase state the exported matrix is
+    # [[W + Sigma, A^T], [A, 0]] assembled here from the problem's own derivatives
+    w = W.get("C1")
+    th = w.theta(4)
+    h = oracle.Handle.quad(w, th)
+    for _ in range(3):
+        h.step()
+    st = oracle.unpack_state(h.state(), w.n, w.m)
+    assert st["phase"] == oracle.PH_REGULAR
+    x, y, zl, zu = (st["main"][k] for k in ("x", "y", "zl", "zu"))
+    f, g, c, J, H = oracle.quad_eval(w, th, x, y)
+    lo = np.full(w.n, -INF)
+    hi = np.full(w.n, INF)
+    for k in range(w.N):
+        lo[k * 17 + 13:k * 17 + 17] = 0.0
+        hi[k * 17 + 13:k * 17 + 17] = 2 * w.model.u_hover
+    lo[w.n_w:] = 0.0
+    sig = np.zeros(w.n)
+    L, U = np.isfinite(lo), np.isfinite(hi)
+    sig[L] += zl[L] / (x[L] - lo[L])
+    sig[U] += zu[U] / (hi[U] - x[U])
+    K = np.block([[H + np.diag(sig), J.T], [J, np.zeros((w.m, w.m))]])
+    Ko = h.kkt_matrix()
+    assert Ko.shape == K.shape and np.allclose(Ko, K, rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------------------------ adaptive barrier update (Table I row 7)
+def test_adaptive_mu_free_mode_loqo_rule():
+    # free mode: mu = 0.1 min(0.05 (1 - xi) / xi, 2)^3 avg, avg the mean complementarity product over
+    # the bounded components and xi = min / avg, computed here in numpy from the iterate
+    w = W.get("C1")
+    th = w.theta(2)
+    h = oracle.Handle.quad(w, th, opts=oracle.default_opts(mu_strategy=1))
+    h.step()                                           # least-squares multipliers
+    for it in range(3):
+        a = oracle.unpack_state(h.state(), w.n, w.m)
+        x, zl, zu = a["main"]["x"], a["main"]["zl"], a["main"]["zu"]
+        prods = []
+        for k in range(w.N):
+            u = x[k * 17 + 13:k * 17 + 17]
+            prods += list(u * zl[k * 17 + 13:k * 17 + 17]) + list((2 * w.model.u_hover - u) * zu[k * 17 + 13:k * 17 + 17])
+        prods += list(x[w.n_w:] * zl[w.n_w:])
+        prods = np.array(prods)
+        avg, xi = prods.mean(), prods.min() / prods.mean()
+        want = 0.1 * min(0.05 * (1 - xi) / xi, 2.0) ** 3 * avg
+        want = max(1e-9, want)
+        h.step()
+        b = oracle.unpack_state(h.state(), w.n, w.m)
+        assert b["adaptive"]["free"] == 1
+        mu_max = b["adaptive"]["mu_max"]
+        assert np.isclose(b["main"]["mu"], min(want, mu_max), rtol=1e-12), (it, b["main"]["mu"], want)
+        assert b["adaptive"]["n_refs"] == min(it + 1, 4)
+
+
+def test_adaptive_mu_falls_back_to_monotone_without_progress():
+    # with a reference E_0 far below the current one, the free mode gives up: monotone mode from
+    # mu = 0.8 avg (numpy), filter reset, fallback counted; references far above: free mode kept
+    w = W.get("C1")
+    th = w.theta(2)
+    h = oracle.Handle.quad(w, th, opts=oracle.default_opts(mu_strategy=1))
+    h.step()
+    h.step()
+    s = h.state()
+    n, m = w.n, w.m
+    F = (len(s) - 16 - (8 + 3 * n + m) - (8 + 3 * (n + 2 * m) + m) - 2 * n - (8 + 3 * n + m) - 4 - 8) // 4
+    pa = len(s) - 8                                    # adaptive block: free, n_refs, refs[4], mu_max, 0
+    assert s[pa] == 1 and s[pa + 1] == 1
+    s2 = s.copy()
+    s2[pa + 2] = 1e-30                                 # a reference E_0 that cannot be improved on
+    h.set_state(s2)
+    a = oracle.unpack_state(s2, n, m)
+    x, zl, zu = a["main"]["x"], a["main"]["zl"], a["main"]["zu"]
+    prods = []
+    for k in range(w.N):
+        u = x[k * 17 + 13:k * 17 + 17]
+        prods += list(u * zl[k * 17 + 13:k * 17 + 17]) + list((2 * w.model.u_hover - u) * zu[k * 17 + 13:k * 17 + 17])
+    prods += list(x[w.n_w:] * zl[w.n_w:])
+    h.step()
+    b = oracle.unpack_state(h.state(), n, m)
+    assert b["adaptive"]["free"] == 0
+    assert np.isclose(b["main"]["mu"], max(1e-9, 0.8 * np.mean(prods)), rtol=1e-12)
+    assert h.outputs()["stats"][15] == 1
+    s3 = s.copy()
+    s3[pa + 2] = 1e30
+    h3 = oracle.Handle.quad(w, th, opts=oracle.default_opts(mu_strategy=1))
+    h3.set_state(s3)
+    h3.step()
+    assert oracle.unpack_state(h3.state(), n, m)["adaptive"]["free"] == 1
