@@ -158,6 +158,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm/mixed (C5) leg")
     ap.add_argument("--no-phase-leg", action="store_true", help="skip the per-phase-kernel leg")
+    ap.add_argument("--no-stream", action="store_true",
+                    help="one solve per timed step instead of streaming the steps' batches through the slots")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (HBM counter calibration) and exit")
     ap.add_argument("--precision", type=int, default=None,
@@ -193,10 +195,20 @@ def main():
     opts = dict(timing=1, precision=args.precision or 0)
     if args.fuse_below is not None:
         opts["fuse_below"] = args.fuse_below
-    log(f"[bench] plain leg {w.name}: {n_inst} instances, N={w.N}, n={w.n}, m={w.m}, slots={slots}")
+    log(f"[bench] plain leg {w.name}: {n_inst} instances, N={w.N}, n={w.n}, m={w.m}, slots={slots}, "
+        f"{'streamed' if not args.no_stream else 'one solve per step'}")
     solver = hipipm.Solver(w, slots, hipipm.default_options(**opts))
-    dt, conv, out, st, kt = time_solves(solver, TH, args.steps, args.warmup)
+    dt, conv, out, st, kt = time_solves(solver, TH, args.steps, args.warmup, stream=not args.no_stream)
     log(f"[bench] timed {args.steps} steps in {dt:.3f} s; stats {st}; kernel ms {kt}")
+    # one batch on its own (not streamed), after the timed region: the latency of a single batch,
+    # bounded below by its slowest instance
+    o1 = solver.alloc_outputs(n_inst)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    solver.solve(TH, out=o1)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t1) * 1e3
+    del o1
     dom, roofs = kernel_roofline(w, st, kt, word_bytes=4.0 if opts["precision"] == 1 else 8.0)
     roof = roofs[dom]
     mt = MEASURED_TRAFFIC.get(dom)
@@ -220,8 +232,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc.get(w.name, w.name), "instances": n_inst, "horizon_N": w.N, "n_obs": w.n_obs,
                    "n": w.n, "m": w.m, "slots": slots,
+                   "batches": ("the timed steps streamed through the slots in one solve (iteration-level "
+                               "batching across batches)") if not args.no_stream else "one solve per step",
                    "obstacles": "centres on the reference path + N(0, 0.5^2 I), kept 0.1 m from the start and "
                                 "0.3 m from the first 0.5 s of the reference"},
+        "single_batch_ms": single_ms,
+        "single_batch_solves_per_sec": float((out["status"] == 1).sum().item()) / (single_ms * 1e-3),
         "iterations_per_sec": st["iterations"] / dt,
         "iterations_per_solve": float(out["iters"].float().mean().item()),
         "converged_fraction": float((status == 1).mean()),
@@ -274,7 +290,7 @@ def warm_mixed_leg(args):
     opts = dict(timing=1, precision=1)
     warm_fn, extra = setup_warm_start(w, TH, opts, args)
     s = hipipm.Solver(w, w.n_inst, hipipm.default_options(**opts))
-    dt, conv, out, st, kt = time_solves(s, TH, args.steps, args.warmup, warm_fn)
+    dt, conv, out, st, kt = time_solves(s, TH, args.steps, args.warmup, warm_fn, stream=not args.no_stream)
     log(f"[bench] warm/mixed: {args.steps} steps in {dt:.3f} s; stats {st}")
     res = dict(workload="C5: point-to-point NMPC, 16384 instances, N = 10, 3 obstacles; learned BF16 warm start "
                         "+ FP32 factor with FP64 refinement",
@@ -318,13 +334,38 @@ def oracle_check(w, TH, out, warm_fn, extra, count):
                 oracle_warm_rejected=int(o["stats"][:, 9].sum()))
 
 
-def time_solves(solver, TH, steps, warmup, warm_fn=None):
+def time_solves(solver, TH, steps, warmup, warm_fn=None, stream=False):
     """`warmup` untimed then `steps` timed batched solves of TH (with the warm points computed inside
-    the timed region when `warm_fn` is given); returns (seconds, converged count, outputs, stats,
-    kernel times)."""
+    the timed region when `warm_fn` is given); returns (seconds, converged count, outputs of the last
+    batch, stats, kernel times).
+
+    stream=True: the `steps` batches go through the solver's slots as one stream of
+    steps x len(TH) instances in a single solve (iteration-level batching across batches, Sec. V,
+    Fig. 2: a slot freed by an instance of one batch takes the next instance while the slowest
+    instances of the previous batch still run); warm-up likewise as one stream of `warmup` batches."""
     import torch
     from paper_2606_26341_amd import hipipm
-    out = solver.alloc_outputs(TH.shape[0])
+    n = TH.shape[0]
+    if stream:
+        TS = TH.repeat(max(steps, warmup), 1).contiguous()
+        out = solver.alloc_outputs(TS.shape[0])
+        if warmup:
+            solver.solve(TS[:warmup * n], warm=warm_fn(TS[:warmup * n]) if warm_fn else None,
+                         out={k: v[:warmup * n] for k, v in out.items()})
+            torch.cuda.synchronize()
+            log(f"[bench] warm-up stream of {warmup} batches done")
+        solver.reset_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = TS[:steps * n]
+        o = {k: v[:steps * n] for k, v in out.items()}
+        solver.solve(T, warm=warm_fn(T) if warm_fn else None, out=o)
+        conv = int((o["status"] == hipipm.ST_CONVERGED).sum().item())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        last = {k: v[(steps - 1) * n:steps * n] for k, v in o.items()}
+        return dt, conv, last, solver.stats(), solver.kernel_times()
+    out = solver.alloc_outputs(n)
     for i in range(warmup):
         solver.solve(TH, warm=warm_fn(TH) if warm_fn else None, out=out)
         torch.cuda.synchronize()
@@ -393,7 +434,7 @@ def compare_variants(w, TH, warm_out, args, extra, warm_fn):
             o.update(warm_mu0=extra["warm_mu0"], warm_iter_cap=extra["warm_iter_cap"])
             fn = warm_fn
         s = hipipm.Solver(w, TH.shape[0], hipipm.default_options(**o))
-        dt, conv, out, st, _ = time_solves(s, TH, args.steps, 1, fn)
+        dt, conv, out, st, _ = time_solves(s, TH, args.steps, 1, fn, stream=not args.no_stream)
         res[name] = dict(solves_per_sec=conv / dt, iterations_per_solve=float(out["iters"].float().mean().item()),
                          max_iterations=int(out["iters"].max().item()),
                          converged_fraction=float((out["status"] == 1).float().mean().item()),
