@@ -195,6 +195,25 @@ int hipipm_solve(hipipm_ctx* ctx, int32_t n_inst, const double* theta, const dou
                  double* y_out, double* zl_out, double* zu_out, double* obj_out, double* kkt_out,
                  int32_t* status_out, int32_t* iters_out, void* stream);
 
+/* For callers that cannot allocate device or pinned host memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): hipipm_solve with the library's own
+ * static device workspace of HIPIPM_STATIC_WORKSPACE_BYTES (64 MiB) per GPU instead of the bound
+ * workspace.  Arguments, outputs and results are those of hipipm_solve (same kernels); the
+ * context needs no bound workspace, but hipipm_workspace_bytes() of the context must not exceed
+ * the static size (HIPIPM_ERR_WORKSPACE otherwise: create it with fewer slots; e.g. up to about
+ * 120 slots of the N = 30, 8-sphere tracking family, 350 of the N = 10, 3-sphere point-to-point
+ * family).
+ * The call allocates nothing: no hipMalloc/hipFree, no pinned host buffer, no events (kernel timing
+ * is not recorded); it polls the completion counter with a copy into host stack memory and a wait
+ * on `stream` every options.poll_every passes.  All calls on one GPU share that GPU's static
+ * workspace: calls that overlap in time on one GPU (from several threads or streams) race and
+ * must be serialised by the caller.  The array keeps the last call's contents; the call re-arms
+ * what must start from known values (the counter block, every slot it uses). */
+#define HIPIPM_STATIC_WORKSPACE_BYTES (64ull << 20)
+int hipipm_solve_noalloc(hipipm_ctx* ctx, int32_t n_inst, const double* theta, const double* warm, double* x_out,
+                         double* y_out, double* zl_out, double* zu_out, double* obj_out, double* kkt_out,
+                         int32_t* status_out, int32_t* iters_out, void* stream);
+
 /* Counters accumulated over all solves since creation (or the last hipipm_reset_stats). */
 int hipipm_stats_get(const hipipm_ctx* ctx, hipipm_stats* out);
 int hipipm_reset_stats(hipipm_ctx* ctx);

@@ -8,6 +8,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,7 @@ void launch_stage_derivs(const Cfg& c, int count, const double* x, const double*
 void launch_kkt_test(const Cfg& c, double* ws, int count, double dxp, double dcp, const double* rhs, double* sol,
                      int* inertia_ok, hipStream_t st);
 void launch_prepare(const Cfg& c, double* ws, int count, hipStream_t st);
+void launch_counters_init(Counters* cnt, int head, int n_inst, hipStream_t st);
 int sd_len_host(int NI);
 }  // namespace hipipm
 
@@ -103,6 +105,32 @@ static void layout(Cfg& c) {
   c.stride = rup(o, 64);
 }
 
+// ------------------------------------------------------------------ allocation-free solve
+// The workspace of hipipm_solve_noalloc: one array per GPU, part of the library's code object
+// (each GPU the library runs on holds it until the process ends).  In host code `scratch` is only
+// a stand-in for the symbol; its device address on each GPU comes from hipGetSymbolAddress, taken
+// once per device with that device current (at hipipm_create) and kept in g_scratch.
+static constexpr size_t STATIC_WS_BYTES = (size_t)HIPIPM_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+static constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[MAX_DEVICES];
+
+// device address of the static workspace on the current device `dev` (set up on first use)
+static int scratch_setup(hipipm_ctx* c, int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(c, HIPIPM_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, HIPIPM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = p;
+  }
+  if (out) *out = g_scratch[dev];
+  return HIPIPM_OK;
+}
+
 extern "C" {
 
 int hipipm_default_options(hipipm_options* o) {
@@ -145,6 +173,8 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   c->ws = nullptr;
   c->ws_bound = 0;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return HIPIPM_ERR_HIP; }
+  // device address of the allocation-free solve's static workspace on this device
+  if (scratch_setup(c, c->device, nullptr) != HIPIPM_OK) { delete c; return HIPIPM_ERR_HIP; }
   Cfg& g = c->cfg;
   memset(&g, 0, sizeof(g));
   g.family = d->family; g.N = d->N; g.NI = d->n_obs;
@@ -361,6 +391,62 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
     if (!more) return bail(fail(c, HIPIPM_ERR_HIP, "solve did not finish within the pass bound"));
   }
   if (timing) for (auto& e : ev) (void)hipEventDestroy(e);
+  add_stats(c, h, passes);
+  return HIPIPM_OK;
+}
+
+int hipipm_solve_noalloc(hipipm_ctx* c, int32_t n_inst, const double* theta, const double* warm, double* x_out,
+                         double* y_out, double* zl_out, double* zu_out, double* obj_out, double* kkt_out,
+                         int32_t* status_out, int32_t* iters_out, void* stream) {
+  if (!c) return HIPIPM_ERR_INVALID_ARG;
+  if (n_inst < 0) return fail(c, HIPIPM_ERR_INVALID_ARG, "n_inst < 0");
+  if (n_inst == 0) return HIPIPM_OK;
+  if (!theta) return fail(c, HIPIPM_ERR_INVALID_ARG, "theta is NULL");
+  if (c->need > STATIC_WS_BYTES)
+    return fail(c, HIPIPM_ERR_WORKSPACE,
+                "hipipm_solve_noalloc: the context needs " + std::to_string(c->need) +
+                    " workspace bytes, more than the static workspace of " + std::to_string(STATIC_WS_BYTES) +
+                    " bytes; create the context with fewer slots");
+  HIPCHK(c, hipSetDevice(c->device));
+  void* base = nullptr;
+  if (int rc = scratch_setup(c, c->device, &base)) return rc;
+  double* ws = (double*)base;
+  Counters* dcnt = (Counters*)((char*)base + c->cnt_off);
+  hipStream_t st = (hipStream_t)stream;
+  const int active = n_inst < c->slots ? n_inst : c->slots;
+  // the counter block is the only part of the workspace that must start from known values (every
+  // slot record is written by the setup kernel before it is read); a kernel clears it
+  launch_counters_init(dcnt, active, n_inst, st);
+  launch_setup(c->cfg, ws, active, active, theta, warm, st);
+  HIPCHK(c, hipGetLastError());
+  Outs out{x_out, y_out, zl_out, zu_out, obj_out, kkt_out, status_out, iters_out};
+  const long long max_passes = ((long long)c->opts.max_iter + 8) * 3 * ((n_inst + active - 1) / active) + 64;
+  const int poll = c->opts.poll_every;
+  long long passes = 0;
+  Counters h;
+  memset(&h, 0, sizeof(h));
+  // chunks of `poll` passes, each followed by a copy of the counter block into host memory (the
+  // stack, no pinned buffer) and a wait on the stream
+  for (;;) {
+    const bool fused = c->opts.precision == 1 || (c->opts.fuse_below > 0 && n_inst - h.done <= c->opts.fuse_below);
+    for (int p = 0; p < poll; ++p) {
+      launch_eval(c->cfg, ws, active, st);
+      if (fused) {
+        launch_iter(c->cfg, ws, active, theta, warm, out, dcnt, 1, st);
+      } else {
+        launch_pre(c->cfg, ws, active, theta, warm, out, dcnt, 1, st);
+        launch_fac(c->cfg, ws, active, st);
+        launch_sol(c->cfg, ws, active, warm, st);
+        launch_ls(c->cfg, ws, active, st);
+      }
+    }
+    passes += poll;
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(&h, dcnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (h.done >= n_inst) break;
+    if (passes > max_passes) return fail(c, HIPIPM_ERR_HIP, "solve did not finish within the pass bound");
+  }
   add_stats(c, h, passes);
   return HIPIPM_OK;
 }

@@ -46,6 +46,13 @@ __global__ __launch_bounds__(256) void k_eval(Cfg c, double* ws, int slots) {
   }
 }
 
+// the counter block of a solve: queue head = first instance not yet in a slot, nothing done
+__global__ __launch_bounds__(64) void k_counters_init(Counters* cnt, int head, int n_inst) {
+  const int t = threadIdx.x;
+  if (t == 0) { cnt->head = head; cnt->done = 0; cnt->n_inst = n_inst; cnt->pad = 0; }
+  if (t < N_STATS) cnt->st[t] = 0ull;
+}
+
 __global__ __launch_bounds__(64) void k_prepare(Cfg c, double* ws) {
   Slot s = make_slot(c, ws, blockIdx.x);
   fill_ref(c, s, threadIdx.x);
@@ -174,6 +181,9 @@ void launch_stage_derivs(const Cfg& c, int count, const double* x, const double*
                          double* G, double* H, hipStream_t st) {
   int blocks = (count * NZ + 63) / 64;
   if (blocks > 0) hipLaunchKernelGGL(k_stage_derivs, dim3(blocks), dim3(64), 0, st, c, count, x, u, lam, F, G, H);
+}
+void launch_counters_init(Counters* cnt, int head, int n_inst, hipStream_t st) {
+  hipLaunchKernelGGL(k_counters_init, dim3(1), dim3(WAVE), 0, st, cnt, head, n_inst);
 }
 void launch_prepare(const Cfg& c, double* ws, int count, hipStream_t st) {
   if (count > 0) hipLaunchKernelGGL(k_prepare, dim3(count), dim3(WAVE), 0, st, c, ws);

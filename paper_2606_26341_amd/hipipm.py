@@ -64,7 +64,7 @@ class Stats(C.Structure):
 
 _lib = None
 EXPORTS = ("hipipm_default_options", "hipipm_create", "hipipm_get_dims", "hipipm_workspace_bytes",
-           "hipipm_bind_workspace", "hipipm_solve", "hipipm_stats_get", "hipipm_reset_stats",
+           "hipipm_bind_workspace", "hipipm_solve", "hipipm_solve_noalloc", "hipipm_stats_get", "hipipm_reset_stats",
            "hipipm_kernel_times", "hipipm_state_len", "hipipm_state_import", "hipipm_start", "hipipm_step",
            "hipipm_state_export", "hipipm_kkt_factor_solve", "hipipm_stage_derivs", "hipipm_last_error",
            "hipipm_destroy")
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     L.hipipm_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.hipipm_bind_workspace.argtypes = [vp, vp, C.c_size_t]
     L.hipipm_solve.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.hipipm_solve_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.hipipm_stats_get.argtypes = [vp, vp]
     L.hipipm_reset_stats.argtypes = [vp]
     L.hipipm_kernel_times.argtypes = [vp, C.POINTER(i32), vp, vp]
@@ -195,6 +196,22 @@ class Solver:
         self._check(self.L.hipipm_solve(self.h, n_inst, _ptr(theta), _ptr(warm), _ptr(o["x"]), _ptr(o["y"]),
                                         _ptr(o["zl"]), _ptr(o["zu"]), _ptr(o["obj"]), _ptr(o["kkt"]),
                                         _ptr(o["status"]), _ptr(o["iters"]), _stream(stream)))
+        return o
+
+    def solve_noalloc(self, theta: torch.Tensor, warm: torch.Tensor | None = None, out: dict | None = None,
+                      stream=None) -> dict:
+        """solve() through hipipm_solve_noalloc: the library's static device workspace instead of the
+        bound one, no allocation inside the call (pass `out` to allocate nothing here either)."""
+        assert theta.dtype == torch.float64 and theta.dim() == 2 and theta.shape[1] == self.dims.n_theta
+        theta = theta.contiguous()
+        n_inst = theta.shape[0]
+        if warm is not None:
+            assert warm.shape == (n_inst, self.dims.n_w + self.dims.m) and warm.dtype == torch.float64
+            warm = warm.contiguous()
+        o = out if out is not None else self.alloc_outputs(n_inst)
+        self._check(self.L.hipipm_solve_noalloc(self.h, n_inst, _ptr(theta), _ptr(warm), _ptr(o["x"]), _ptr(o["y"]),
+                                                _ptr(o["zl"]), _ptr(o["zu"]), _ptr(o["obj"]), _ptr(o["kkt"]),
+                                                _ptr(o["status"]), _ptr(o["iters"]), _stream(stream)))
         return o
 
     def stats(self) -> dict:
