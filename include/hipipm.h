@@ -123,6 +123,13 @@ typedef struct {
                              the scaled KKT error keeps falling (E_0 <= 0.9999 x the largest of the
                              last four), otherwise the monotone rule from mu = 0.8 x the mean
                              complementarity until its barrier problem is solved with progress */
+    int32_t async_passes; /* > 0: asynchronous slots -- each launch lets every slot run up to this many
+                             whole passes back to back (its own derivatives included), refilling from
+                             the device queue, with no wait for other slots between passes; the host
+                             polls after each launch.  0 (default): one launch per phase or one fused
+                             launch per pass, every slot advancing one pass per launch.  Results are
+                             the same either way; best with slots = the number of resident
+                             workgroups (one per SIMD) */
 } hipipm_options;
 
 typedef struct {
@@ -147,6 +154,9 @@ typedef struct {
     int64_t soft_resto_steps;        /* accepted soft-restoration steps */
     int64_t soft_resto_fails;        /* soft restorations that ended in hard restoration */
     int64_t mu_fallbacks;            /* adaptive barrier update: switches to the monotone mode */
+    int64_t cycles_eval, cycles_pre, cycles_factor, cycles_solve, cycles_linesearch;
+                                     /* shader-clock cycles summed over slots in the derivatives (asynchronous
+                                        slots only) and the four phases of the fused kernels */
 } hipipm_stats;
 
 typedef struct hipipm_ctx hipipm_ctx;
@@ -219,10 +229,10 @@ int hipipm_stats_get(const hipipm_ctx* ctx, hipipm_stats* out);
 int hipipm_reset_stats(hipipm_ctx* ctx);
 
 /* Kernel timing (options.timing = 1): total milliseconds and launch counts per kernel since the
- * last reset, in the order "eval", "pre", "factor", "solve", "linesearch", "fused", "setup" (the
- * five kernels of a pass, the fused pass kernel used for the last options.fuse_below instances,
- * then the per-solve setup).  *n_kernels: capacity of the arrays on input, number of timed
- * kernels (7) on output. */
+ * last reset, in the order "eval", "pre", "factor", "solve", "linesearch", "fused", "setup",
+ * "async" (the five kernels of a pass, the fused pass kernel used for the last options.fuse_below
+ * instances, the per-solve setup, the asynchronous-slot kernel).  *n_kernels: capacity of the
+ * arrays on input, number of timed kernels (8) on output. */
 int hipipm_kernel_times(const hipipm_ctx* ctx, int32_t* n_kernels, double* total_ms, int64_t* launches);
 
 /* ---- test hooks (one-step replay, Sec. VI "Correctness") ----

@@ -13,8 +13,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhipipm.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
-           ("iter_fp64.hip", "iter_mixed.hip", "kernels.hip", "api.hip", "mlp.hip")]
+           ("iter_fp64.hip", "iter_mixed.hip", "run_fp64.hip", "run_mixed.hip", "kernels.hip", "api.hip",
+            "mlp.hip")]
 BUILD_DIR = os.path.join(HERE, "_build")
+# the asynchronous-slot kernel loops over whole passes: constants hoisted out of that loop would
+# stay live across all of it and spill, so machine-level loop-invariant code motion is off there
+EXTRA = {"run_fp64.hip": ["-mllvm", "-disable-machine-licm"],
+         "run_mixed.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def hipcc() -> str:
@@ -26,7 +31,11 @@ def hipcc() -> str:
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off on this target
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # multiply-adds are fused only where one source expression holds both operations, so
+         # that an instance's rounding does not depend on the kernel its code is inlined into
+         # (the per-phase, fused and asynchronous-slot kernels give bit-identical iterates)
+         "-ffp-contract=on"]
 
 
 def build_library(verbose: bool = False) -> str:
@@ -35,7 +44,8 @@ def build_library(verbose: bool = False) -> str:
 
     def compile_one(pair):
         src, obj = pair
-        cmd = [hipcc()] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-c", "-o", obj, src]
+        cmd = ([hipcc()] + FLAGS + EXTRA.get(os.path.basename(src), [])
+               + ["-I", os.path.join(ROOT, "include"), "-c", "-o", obj, src])
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

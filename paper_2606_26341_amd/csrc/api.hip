@@ -24,6 +24,10 @@ void launch_sol(const Cfg& c, double* ws, int slots, const double* warm, hipStre
 void launch_ls(const Cfg& c, double* ws, int slots, hipStream_t st);
 void launch_iter(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                  Counters* cnt, int refill, hipStream_t st);
+void launch_run_fp64(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
+                     Counters* cnt, int passes, hipStream_t st);
+void launch_run_mixed(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
+                      Counters* cnt, int passes, hipStream_t st);
 void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm,
                   hipStream_t st);
 void launch_stage_derivs(const Cfg& c, int count, const double* x, const double* u, const double* lam, double* F,
@@ -38,10 +42,12 @@ int sd_len_host(int NI);
 using namespace hipipm;
 
 // timed kernels: eval, pre, factor, solve, linesearch (one launch each per pass), fused pass
-// kernel, setup
-static constexpr int NKT = 7;
+// kernel, setup, asynchronous-slot kernel
+static constexpr int NKT = 8;
 static constexpr int NPK = 5;
 static constexpr int KT_FUSED = 5;
+static constexpr int KT_SETUP = 6;
+static constexpr int KT_ASYNC = 7;
 
 struct hipipm_ctx {
   hipipm_problem_desc desc;
@@ -147,7 +153,7 @@ int hipipm_default_options(hipipm_options* o) {
   o->warm_mu0 = 1e-3; o->warm_push = 1e-3; o->warm_iter_cap = 0; o->warm_gate = 1;
   o->watchdog_trigger = 0; o->watchdog_max = 3;
   o->soft_resto_max = 0; o->soft_resto_factor = 0.9999;
-  o->mu_strategy = 0;
+  o->mu_strategy = 0; o->async_passes = 0;
   return HIPIPM_OK;
 }
 
@@ -164,7 +170,8 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
       o->fuse_below < 0 || o->precision < 0 || o->precision > 1 || o->refine_max < 0 || !(o->refine_tol > 0) ||
       !(o->warm_mu0 > 0) || !(o->warm_push > 0) || o->warm_iter_cap < 0 || o->warm_gate < 0 || o->warm_gate > 1 ||
       o->watchdog_trigger < 0 || o->watchdog_max < 1 || o->soft_resto_max < 0 ||
-      !(o->soft_resto_factor > 0 && o->soft_resto_factor <= 1) || o->mu_strategy < 0 || o->mu_strategy > 1)
+      !(o->soft_resto_factor > 0 && o->soft_resto_factor <= 1) || o->mu_strategy < 0 || o->mu_strategy > 1 ||
+      o->async_passes < 0)
     return HIPIPM_ERR_INVALID_ARG;
   hipipm_ctx* c = new hipipm_ctx();
   c->desc = *d;
@@ -204,7 +211,7 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   g.warm_mu0 = o->warm_mu0; g.warm_push = o->warm_push; g.warm_cap = o->warm_iter_cap; g.warm_gate = o->warm_gate;
   g.wd_trigger = o->watchdog_trigger; g.wd_max = o->watchdog_max;
   g.soft_max = o->soft_resto_max; g.soft_factor = o->soft_resto_factor;
-  g.mu_strategy = o->mu_strategy;
+  g.mu_strategy = o->mu_strategy; g.async_passes = o->async_passes;
   layout(g);
   size_t rec = (size_t)g.stride * sizeof(double) * (size_t)slots;
   c->cnt_off = (rec + 255) / 256 * 256;
@@ -266,6 +273,11 @@ static void add_stats(hipipm_ctx* c, const Counters& h, long long passes) {
   c->stats.soft_resto_steps += (int64_t)h.st[20];
   c->stats.soft_resto_fails += (int64_t)h.st[21];
   c->stats.mu_fallbacks += (int64_t)h.st[22];
+  c->stats.cycles_eval += (int64_t)h.st[23];
+  c->stats.cycles_pre += (int64_t)h.st[24];
+  c->stats.cycles_factor += (int64_t)h.st[25];
+  c->stats.cycles_solve += (int64_t)h.st[26];
+  c->stats.cycles_linesearch += (int64_t)h.st[27];
 }
 
 int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const double* warm, double* x_out,
@@ -309,19 +321,35 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
     HIPCHK(c, hipEventSynchronize(ev[1]));
     float ms = 0;
     HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[1]));
-    c->t_ms[NKT - 1] += ms;
-    c->t_n[NKT - 1] += 1;
+    c->t_ms[KT_SETUP] += ms;
+    c->t_n[KT_SETUP] += 1;
   }
   HIPCHK(c, hipGetLastError());
   // every pass advances each running slot by at most one pipeline step; bound the loop
   const long long max_passes = ((long long)c->opts.max_iter + 8) * 3 * ((n_inst + active - 1) / active) + 64;
   long long passes = 0;
-  bool fused_of[2] = {false, false};
+  bool fused_of[2] = {false, false}, async_of[2] = {false, false};
+  const int apasses = c->opts.async_passes;
   // Passes go out in chunks of `poll`; each chunk ends with an asynchronous copy of the counter
   // block into pinned memory.  The next chunk is queued before the host waits for the previous
   // chunk's copy, so the GPU never idles on the poll.  Passes queued after the last instance
   // finished find every slot empty and return at once.
   auto launch_chunk = [&](int par, bool fused) -> int {
+    async_of[par] = apasses > 0;
+    if (apasses > 0) {
+      // asynchronous slots: one launch in which every slot runs up to apasses whole passes
+      hipEvent_t* e = timing ? &ev[2 + par * per_chunk] : nullptr;
+      if (timing) HIPCHK(c, hipEventRecord(e[0], st));
+      if (c->cfg.prec == 1) launch_run_mixed(c->cfg, c->ws, active, theta, warm, out, dcnt, apasses, st);
+      else launch_run_fp64(c->cfg, c->ws, active, theta, warm, out, dcnt, apasses, st);
+      if (timing) HIPCHK(c, hipEventRecord(e[1], st));
+      HIPCHK(c, hipGetLastError());
+      HIPCHK(c, hipMemcpyAsync(&c->hcnt[par], dcnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipEventRecord(c->cev[par], st));
+      fused_of[par] = true;
+      passes += apasses;
+      return HIPIPM_OK;
+    }
     for (int p = 0; p < poll; ++p) {
       hipEvent_t* e = timing ? &ev[2 + par * per_chunk + (NPK + 1) * p] : nullptr;
       if (timing) HIPCHK(c, hipEventRecord(e[0], st));
@@ -352,7 +380,13 @@ int hipipm_solve(hipipm_ctx* c, int32_t n_inst, const double* theta, const doubl
   auto finish_chunk = [&](int par) -> int {
     HIPCHK(c, hipEventSynchronize(c->cev[par]));
     h = c->hcnt[par];
-    if (timing) {
+    if (timing && async_of[par]) {
+      const hipEvent_t* e = &ev[2 + par * per_chunk];
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, e[0], e[1]));
+      c->t_ms[KT_ASYNC] += ms;
+      c->t_n[KT_ASYNC] += 1;
+    } else if (timing) {
       for (int p = 0; p < poll; ++p) {
         const hipEvent_t* e = &ev[2 + par * per_chunk + (NPK + 1) * p];
         const int nk = fused_of[par] ? 2 : NPK;

@@ -46,6 +46,9 @@ enum : int {
   // adaptive barrier update (Table I row 7): free mode flag, references held, the last four E_0
   // references, the mu ceiling; switches to the monotone mode
   SC_MUFREE = 80, SC_NREFS, SC_REFS, SC_MUMAX = SC_REFS + 4, SC_ST_MUFB,
+  // shader-clock cycles this slot spent in the derivatives (asynchronous-slot kernel) and in the
+  // four phases of the fused kernels
+  SC_CYC_EVAL, SC_CYC_PRE, SC_CYC_FAC, SC_CYC_SOL, SC_CYC_LS,
   SC_LEN = 96
 };
 
@@ -75,6 +78,7 @@ struct Cfg {
   int soft_max; double soft_factor;          // soft restoration: steps before hard restoration (0: off),
                                              // required primal-dual error reduction
   int mu_strategy;                           // 0 monotone, 1 adaptive with monotone fallback
+  int async_passes;                          // > 0: asynchronous slots, passes per launch
   // slot record layout, offsets in doubles
   long long stride;
   int o_v, o_y, o_zlu, o_zuu, o_zls, o_th, o_sc, o_fm, o_fr;
@@ -95,7 +99,7 @@ struct Outs {
 };
 
 // global counters (device): queue head, finished count, stats
-constexpr int N_STATS = 23;
+constexpr int N_STATS = 28;
 struct Counters {
   int32_t head, done, n_inst, pad;
   unsigned long long st[N_STATS];

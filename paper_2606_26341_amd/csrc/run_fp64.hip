@@ -1,0 +1,10 @@
+// The asynchronous-slot kernel k_run (each slot runs whole passes back to back), FP64 factor and solve.
+// A translation unit of its own so that it compiles in parallel with the others.
+#include "slot.h"
+
+namespace hipipm {
+void launch_run_fp64(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
+                     Counters* cnt, int passes, hipStream_t st) {
+  hipLaunchKernelGGL(k_run<false>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm, out, cnt, passes);
+}
+}  // namespace hipipm

@@ -293,28 +293,37 @@ __device__ __forceinline__ bool filter_ok(const Cfg& c, const double* filt, int 
 }
 
 // add an entry, dropping the entries it dominates (which does not change what the filter
-// rejects); returns the new count
+// rejects); returns the new count.  A stable compaction, 64 entries at a time: each lane keeps
+// or drops its entry, a ballot gives the kept entries their new places (never above their old
+// ones, so no entry of a later chunk is overwritten before it is read).
 __device__ __forceinline__ int filter_add(const Cfg& c, double* filt, int nf, double th, double ph, int lane) {
-  __shared__ int res;
-  if (lane == 0) {
-    int w = 0;
-    for (int i = 0; i < nf; ++i)
-      if (!(filt[i] >= th && filt[c.fc + i] >= ph)) {
-        filt[w] = filt[i];
-        filt[c.fc + w] = filt[c.fc + i];
-        ++w;
-      }
-    if (w < c.fc) {
+  int w = 0;
+  for (int base = 0; base < nf; base += WAVE) {
+    const int i = base + lane;
+    double a = 0.0, b = 0.0;
+    bool keep = false;
+    if (i < nf) {
+      a = filt[i];
+      b = filt[c.fc + i];
+      keep = !(a >= th && b >= ph);
+    }
+    const unsigned long long kept = __ballot(keep);
+    if (keep) {
+      const int at = w + __popcll(kept & ((1ull << lane) - 1ull));
+      filt[at] = a;
+      filt[c.fc + at] = b;
+    }
+    w += __popcll(kept);
+  }
+  if (w < c.fc) {
+    if (lane == 0) {
       filt[w] = th;
       filt[c.fc + w] = ph;
-      ++w;
     }
-    res = w;
+    ++w;
   }
   __syncthreads();
-  int r = res;
-  __syncthreads();
-  return r;
+  return w;
 }
 
 // ============================================================================ slot initialisation
@@ -334,7 +343,8 @@ __device__ __forceinline__ void fill_ref(const Cfg& c, const Slot& s, int lane) 
 __device__ __forceinline__ bool kept_on_restart(int q) {
   return q == SC_ITER || (q >= SC_ST_RESTO && q <= SC_ST_PASS) || q == SC_ST_SOLV || q == SC_ST_FFACT ||
          q == SC_ST_FSOLV || q == SC_ST_REF || q == SC_ST_FB || q == SC_ST_WSTART || q == SC_ST_RTK ||
-         q == SC_ST_WDS || q == SC_ST_WDR || q == SC_ST_SOFTS || q == SC_ST_SOFTF || q == SC_ST_MUFB;
+         q == SC_ST_WDS || q == SC_ST_WDR || q == SC_ST_SOFTS || q == SC_ST_SOFTF || q == SC_ST_MUFB ||
+         (q >= SC_CYC_EVAL && q <= SC_CYC_LS);
 }
 
 // Starting point of the main sub-problem: cold (wp == nullptr: x_k = xbar0, u_k = hover thrust,
@@ -484,6 +494,8 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
       atomicAdd(&cnt->st[20], (unsigned long long)s.sc[SC_ST_SOFTS]);
       atomicAdd(&cnt->st[21], (unsigned long long)s.sc[SC_ST_SOFTF]);
       atomicAdd(&cnt->st[22], (unsigned long long)s.sc[SC_ST_MUFB]);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) atomicAdd(&cnt->st[23 + q], (unsigned long long)s.sc[SC_CYC_EVAL + q]);
       atomicAdd(&cnt->done, 1);
       next = refill ? atomicAdd(&cnt->head, 1) : INT_MAX;
     } else {
@@ -1632,6 +1644,94 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
 
 __host__ __device__ __forceinline__ size_t sol_bytes(const Cfg& c) { return (size_t)sol_lds_doubles(c.N) * sizeof(double); }
 
+// The four per-slot phases of one pass back to back, with the shader-clock cycles of each added to
+// the slot's counters (the fused and asynchronous-slot kernels).
+template <bool MIXED>
+__device__ __forceinline__ void pass_phases(const Cfg& c, const Slot& s, const double* theta, const double* warm,
+                                            Outs out, Counters* cnt, int refill, FacLds& L, double* sol_dyn,
+                                            int lane) {
+  const long long t0 = clock64();
+  pre_body(c, s, theta, warm, out, cnt, refill, lane);
+  __syncthreads();
+  const long long t1 = clock64();
+  fac_body(c, s, L, true, MIXED, lane);
+  __syncthreads();
+  const long long t2 = clock64();
+  sol_body(c, s, warm, sol_dyn, &L, true, MIXED, lane);
+  __syncthreads();
+  const long long t3 = clock64();
+  ls_body(c, s, sol_dyn, true, MIXED, lane);
+  __syncthreads();
+  const long long t4 = clock64();
+  if (lane == 0 && (int)s.sc[SC_PHASE] != PH_EMPTY) {
+    s.sc[SC_CYC_PRE] += (double)(t1 - t0);
+    s.sc[SC_CYC_FAC] += (double)(t2 - t1);
+    s.sc[SC_CYC_SOL] += (double)(t3 - t2);
+    s.sc[SC_CYC_LS] += (double)(t4 - t3);
+  }
+}
+
+// Derivatives of one slot at its current point (what the derivative kernel computes for it): RK4
+// step F_k, G_k = dF/d(x, u) and W_k = -sum_r y_r Hess F_r per interval, one (interval, direction)
+// item per lane.
+__device__ __forceinline__ void eval_slot(const Cfg& c, const Slot& s, int lane) {
+  const int ph = (int)s.sc[SC_PHASE];
+  const double* yv = (ph == PH_RESTO) ? s.yr : s.y;
+  for (int q = lane; q < c.N * NZ; q += WAVE) {
+    const int k = q / NZ, j = q % NZ;
+    double x[NX], u[NU], lam[NX], Fv[NX], Gc[NX], Hc[NZ];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) x[i] = s.v[xo(k) + i];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) u[i] = s.v[uo(k) + i];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) lam[i] = -yv[(k + 1) * NX + i];
+    rk4_deriv_dir(c, x, u, lam, j, j == 0 ? Fv : nullptr, Gc, Hc);
+    double* G = s.G + (long long)k * NX * NZ;
+    double* H = s.HW + (long long)k * NZ * NZ;
+#pragma unroll
+    for (int i = 0; i < NX; ++i) G[i * NZ + j] = Gc[i];
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) H[i * NZ + j] = Hc[i];
+    if (j == 0) {
+#pragma unroll
+      for (int i = 0; i < NX; ++i) s.F[k * NX + i] = Fv[i];
+    }
+  }
+  __syncthreads();
+}
+
+// Asynchronous slots: each workgroup owns one slot and runs up to `passes` whole passes of it
+// back to back (its derivatives, then the four phases), taking new instances from the device queue
+// as its own finish; no slot waits for another between passes.  A slot that finds nothing left
+// leaves at once, so every wave ends after at most `passes` passes.
+template <bool MIXED>
+__global__ __launch_bounds__(64) void k_run(Cfg c0, double* ws, const double* theta, const double* warm, Outs out,
+                                            Counters* cnt, int passes) {
+  __shared__ FacLds L;
+  HIP_DYNAMIC_SHARED(double, sol_dyn)
+#pragma nounroll
+  for (int p = 0; p < passes; ++p) {
+    // the slot's addresses are rebuilt every pass from an index the compiler cannot see through,
+    // so that nothing derived from them is hoisted out of the loop and kept live across the
+    // derivative evaluation and the four phases
+    int b = blockIdx.x, lane = threadIdx.x;
+    asm volatile("" : "+s"(b), "+v"(lane));
+    typedef const char __attribute__((address_space(4)))* KPtr;
+    KPtr kp = (KPtr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(kp));
+    const Cfg& c = *(const Cfg*)(const Cfg __attribute__((address_space(4)))*)kp;
+    const Slot s = make_slot(c, ws, b);
+    if ((int)s.sc[SC_PHASE] == PH_EMPTY) return;
+    const long long t0 = clock64();
+    eval_slot(c, s, lane);
+    const long long t1 = clock64();
+    pass_phases<MIXED>(c, s, theta, warm, out, cnt, 1, L, sol_dyn, lane);
+    if (lane == 0) s.sc[SC_CYC_EVAL] += (double)(t1 - t0);
+    __syncthreads();
+  }
+}
+
 // The four per-slot phases of one iteration in a single launch: each slot runs its phases back
 // to back, instead of every phase waiting for the slowest slot of the previous one, and a pass
 // costs two launches instead of five.  MIXED: the FP32 factor / FP64 refinement variant.
@@ -1643,13 +1743,7 @@ __global__ __launch_bounds__(64) void k_iter(Cfg c, double* ws, const double* th
   const int lane = threadIdx.x;
   const Slot s = make_slot(c, ws, blockIdx.x);
   if ((int)s.sc[SC_PHASE] == PH_EMPTY) return;
-  pre_body(c, s, theta, warm, out, cnt, refill, lane);
-  __syncthreads();
-  fac_body(c, s, L, true, MIXED, lane);
-  __syncthreads();
-  sol_body(c, s, warm, sol_dyn, &L, true, MIXED, lane);
-  __syncthreads();
-  ls_body(c, s, sol_dyn, true, MIXED, lane);
+  pass_phases<MIXED>(c, s, theta, warm, out, cnt, refill, L, sol_dyn, lane);
 }
 
 }  // namespace hipipm

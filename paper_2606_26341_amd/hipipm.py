@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libhipipm.so")
 
 STATUS = {0: "RUNNING", 1: "CONVERGED", 2: "MAX_ITER", 3: "RESTO_FAILED", 4: "INFEASIBLE", 5: "NUMERICAL"}
 ST_CONVERGED = 1
-KERNELS = ("eval", "pre", "factor", "solve", "linesearch", "fused", "setup")
+KERNELS = ("eval", "pre", "factor", "solve", "linesearch", "fused", "setup", "async")
 
 
 class ProblemDesc(C.Structure):
@@ -43,7 +43,7 @@ class Options(C.Structure):
         ("refine_tol", C.c_double), ("warm_mu0", C.c_double), ("warm_push", C.c_double),
         ("warm_iter_cap", C.c_int32), ("warm_gate", C.c_int32), ("watchdog_trigger", C.c_int32),
         ("watchdog_max", C.c_int32), ("soft_resto_max", C.c_int32), ("soft_resto_factor", C.c_double),
-        ("mu_strategy", C.c_int32),
+        ("mu_strategy", C.c_int32), ("async_passes", C.c_int32),
     ]
 
 
@@ -59,7 +59,8 @@ class Stats(C.Structure):
                                          "fused_solves", "refine_sweeps", "fp64_fallbacks", "warm_started",
                                          "warm_rejected", "warm_restarts", "fp32_retakes", "watchdog_starts",
                                          "watchdog_reverts", "soft_resto_steps", "soft_resto_fails",
-                                         "mu_fallbacks")]
+                                         "mu_fallbacks", "cycles_eval", "cycles_pre", "cycles_factor",
+                                         "cycles_solve", "cycles_linesearch")]
 
 
 _lib = None
