@@ -138,6 +138,34 @@ __device__ __forceinline__ int wor(int v) {
   return v;
 }
 
+// ----------------------------------------------------------------------------- lane loops
+// One wavefront per slot leaves no other wave on the SIMD to hide memory latency behind, and a
+// plain `for (i = lane; i < n; i += WAVE)` loop that loads, waits and stores pays one memory
+// round trip per trip (a store to the slot record may alias the next trip's loads, so the
+// compiler cannot hoist them).  lanes_for runs the same trips in groups of LB: the group's
+// loads (ld, which must not store) are all issued first, from a clamped index so that every
+// lane loads a valid word without a branch, then use(i, value) runs for each trip in order.
+// Results, and the order of every accumulation, are those of the plain loop.
+template <int LB = 4, class Ld, class Use>
+__device__ __forceinline__ void lanes_for(int n, int lane, Ld ld, Use use) {
+  using V = decltype(ld(0));
+  for (int b = lane; b < n; b += LB * WAVE) {
+    V v[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) v[u] = ld(min(b + u * WAVE, n - 1));
+#pragma unroll
+    for (int u = 0; u < LB; ++u)
+      if (b + u * WAVE < n) use(b + u * WAVE, v[u]);
+  }
+}
+// inequality rows of one knot whose loads are issued together
+constexpr int OBS_CHUNK = 8;
+// the loaded values of one trip
+template <int K>
+struct DV {
+  double v[K];
+};
+
 // Workgroup barrier whose fences cover LDS only, so outstanding global loads (prefetches) stay in
 // flight across it.  Used only where no lane reads global memory written by another lane since
 // the last full __syncthreads.
@@ -186,7 +214,7 @@ __device__ __forceinline__ void kkt_condense(const Cfg& c, const Slot& s, const 
     const int a = p < 3 ? 0 : (p < 5 ? 1 : 2), b = p < 3 ? p : (p < 5 ? p - 2 : 2);
     double* sdk = s.sd + (long long)k * SL;
     double acc = 0.0;
-#pragma unroll 4
+#pragma unroll 8
     for (int j = 0; j < NI; ++j) {
       const double* o7 = sdk + SD_HEAD + SD_OBS * j;
       const double sig = o7[0] + (e.lsq ? 0.0 : e.dxp);
@@ -204,7 +232,29 @@ __device__ __forceinline__ void kkt_condense(const Cfg& c, const Slot& s, const 
 __device__ __forceinline__ void kkt_stage_data(const Cfg& c, const Slot& s, const Iter& it, const Elim& e,
                                                int lane) {
   const int N = c.N, NI = c.NI, L = sd_len(c);
-  for (int q = lane; q < (N + 1) * SD_HC; q += WAVE) {
+  // knot entries: the loads of a trip are the control bounds' (v, z_L, z_U), the regulariser's
+  // x_R, or the elastic pair's (z, p) -- whichever the entry needs
+  lanes_for<8>((N + 1) * SD_HC, lane, [&](int q) {
+    const int k = q / SD_HC, i = q % SD_HC;
+    DV<4> t{{0.0, 1.0, 0.0, 0.0}};
+    if (i < NZ) {
+      if ((k < N || i < NX) && !e.lsq) {
+        const int vi = (i < NX) ? xo(k) + i : uo(k) + (i - NX);
+        if (e.resto) t.v[0] = s.xr[vi];
+        if (i >= NX) {
+          const int b = k * NU + (i - NX);
+          t.v[1] = s.v[vi];
+          t.v[2] = it.zlu[b];
+          t.v[3] = it.zuu[b];
+        }
+      }
+    } else if (e.resto) {
+      const int r = k * NX + (i - NZ) % NX;
+      t.v[0] = (i < NZ + NX) ? s.zp[r] : s.zn[r];
+      t.v[1] = (i < NZ + NX) ? s.p[r] : s.nn[r];
+    }
+    return t;
+  }, [&](int q, const DV<4>& t) {
     const int k = q / SD_HC, i = q % SD_HC;
     double* sd = s.sd + (long long)k * L;
     double val = 0.0;
@@ -213,46 +263,59 @@ __device__ __forceinline__ void kkt_stage_data(const Cfg& c, const Slot& s, cons
         if (e.lsq) {
           val = 1.0;
         } else {
-          const int vi = (i < NX) ? xo(k) + i : uo(k) + (i - NX);
           if (e.resto) {
-            double d = fmin(1.0, 1.0 / fabs(s.xr[vi]));
+            double d = fmin(1.0, 1.0 / fabs(t.v[0]));
             val = e.zeta * d * d;
           } else {
             val = (i < NX) ? 2.0 * c.qw : 2.0 * c.rw;
           }
           if (i >= NX) {
-            double u = s.v[vi];
-            int b = k * NU + (i - NX);
-            val += it.zlu[b] / u + it.zuu[b] / (c.umax - u);
+            double u = t.v[1];
+            val += t.v[2] / u + t.v[3] / (c.umax - u);
           }
         }
       }
     } else if (e.resto) {
-      const int r = k * NX + (i - NZ) % NX;
-      val = (i < NZ + NX) ? s.zp[r] / s.p[r] : s.zn[r] / s.nn[r];
+      val = t.v[0] / t.v[1];
     }
     sd[i] = val;
-  }
-  for (int q = lane; q < N * NI; q += WAVE) {
+  });
+  lanes_for(N * NI, lane, [&](int q) {
     const int k = 1 + q / NI, j = q % NI;
-    double* o7 = s.sd + (long long)k * L + SD_HEAD + SD_OBS * j;
+    DV<14> t;
     double o[4];
     obs_at(c, s.th, j, k, o);
     const int si = so(c, k, j), r = go(c, k, j);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t.v[a] = o[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t.v[3 + a] = s.v[xo(k) + a];
+    t.v[6] = it.zls[q];
+    t.v[7] = s.v[si];
+    t.v[8] = e.resto ? s.xr[si] : 1.0;
+    t.v[9] = it.y[r];
+    t.v[10] = e.resto ? s.zp[r] : 0.0;
+    t.v[11] = e.resto ? s.p[r] : 1.0;
+    t.v[12] = e.resto ? s.zn[r] : 0.0;
+    t.v[13] = e.resto ? s.nn[r] : 1.0;
+    return t;
+  }, [&](int q, const DV<14>& t) {
+    const int k = 1 + q / NI, j = q % NI;
+    double* o7 = s.sd + (long long)k * L + SD_HEAD + SD_OBS * j;
     double sig0 = 1.0;
     if (!e.lsq) {
-      sig0 = it.zls[q] / s.v[si];
+      sig0 = t.v[6] / t.v[7];
       if (e.resto) {
-        double d = fmin(1.0, 1.0 / fabs(s.xr[si]));
+        double d = fmin(1.0, 1.0 / fabs(t.v[8]));
         sig0 += e.zeta * d * d;
       }
     }
     o7[0] = sig0;
-    o7[1] = e.resto ? s.zp[r] / s.p[r] : 0.0;
-    o7[2] = e.resto ? s.zn[r] / s.nn[r] : 0.0;
-    for (int t = 0; t < 3; ++t) o7[3 + t] = 2.0 * (s.v[xo(k) + t] - o[t]);
-    o7[6] = e.lsq ? 0.0 : 2.0 * it.y[r];
-  }
+    o7[1] = e.resto ? t.v[10] / t.v[11] : 0.0;
+    o7[2] = e.resto ? t.v[12] / t.v[13] : 0.0;
+    for (int a = 0; a < 3; ++a) o7[3 + a] = 2.0 * (t.v[3 + a] - t.v[a]);
+    o7[6] = e.lsq ? 0.0 : 2.0 * t.v[9];
+  });
   __syncthreads();
   kkt_condense(c, s, e, lane);
 }
@@ -788,29 +851,38 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
   T reg[SPF];
   sol_prefetch(c, s, N, N - 1, lane, reg);      // first backward stage
   // 1. condensed stage right-hand sides (lambda 13, x 13, u 4 per knot) into LDS
-  for (int q = lane; q < (N + 1) * RB_LEN; q += WAVE) {
+  lanes_for<8>((N + 1) * RB_LEN, lane, [&](int q) {
     const int k = q / RB_LEN, i = q % RB_LEN;
-    double val = 0.0;
+    DV<5> t{{0.0, 0.0, 0.0, 1.0, 1.0}};
     if (i < NX) {
       const int r = k * NX + i;
-      val = bc[r];
+      t.v[0] = bc[r];
       if (e.resto) {
         const double* sdk = s.sd + (long long)k * SL;
-        val += bp[r] / (sdk[NZ + i] + e.dxp) - bn[r] / (sdk[NZ + NX + i] + e.dxp);
+        t.v[1] = bp[r];
+        t.v[2] = bn[r];
+        t.v[3] = sdk[NZ + i];
+        t.v[4] = sdk[NZ + NX + i];
       }
     } else if (i < 2 * NX) {
-      val = bv[xo(k) + i - NX];
+      t.v[0] = bv[xo(k) + i - NX];
     } else if (i < 2 * NX + NU && k < N) {
-      val = bv[uo(k) + i - 2 * NX];
+      t.v[0] = bv[uo(k) + i - 2 * NX];
     }
+    return t;
+  }, [&](int q, const DV<5>& t) {
+    const int i = q % RB_LEN;
+    double val = t.v[0];
+    if (i < NX && e.resto) val += t.v[1] / (t.v[3] + e.dxp) - t.v[2] / (t.v[4] + e.dxp);
     V.rb[q] = T(val);
-  }
+  });
   lds_barrier();
   // position rows of x_k gather the slack rows of knot k
   for (int q = lane; q < N * 3; q += WAVE) {
     const int k = 1 + q / 3, t = q % 3;
     const double* sdk = s.sd + (long long)k * SL;
     double acc = 0.0;
+#pragma unroll 8
     for (int j = 0; j < NI; ++j) {
       const double* o7 = sdk + SD_HEAD + SD_OBS * j;
       const int r = go(c, k, j);
@@ -895,30 +967,45 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
   }
   __syncthreads();   // xv is read back by other lanes below
   // 4. recover slack steps, inequality multiplier steps and elastic steps
-  for (int q = lane; q < N * NI; q += WAVE) {
+  lanes_for(N * NI, lane, [&](int q) {
     const int k = 1 + q / NI, j = q % NI;
     const double* o7 = s.sd + (long long)k * SL + SD_HEAD + SD_OBS * j;
+    const int r = go(c, k, j);
+    DV<13> t;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) t.v[a] = o7[a];
+    t.v[12] = bv[so(c, k, j)];
+    t.v[6] = bc[r];
+    t.v[7] = e.resto ? bp[r] : 0.0;
+    t.v[8] = e.resto ? bn[r] : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t.v[9 + a] = xv[xo(k) + a];
+    return t;
+  }, [&](int q, const DV<13>& t) {
+    const int k = 1 + q / NI, j = q % NI;
+    const double* o7 = t.v;
     const int r = go(c, k, j);
     const double sig = o7[0] + (e.lsq ? 0.0 : e.dxp);
     const double d = row_dreg(e, o7[1], o7[2]);
     const double D = sig / (1.0 + sig * d);
-    double bg = bc[r];
-    if (e.resto) bg += bp[r] / (o7[1] + e.dxp) - bn[r] / (o7[2] + e.dxp);
+    double bg = t.v[6];
+    if (e.resto) bg += t.v[7] / (o7[1] + e.dxp) - t.v[8] / (o7[2] + e.dxp);
     double jdx = 0.0;
-    for (int t = 0; t < 3; ++t) jdx += o7[3 + t] * xv[xo(k) + t];
+    for (int a = 0; a < 3; ++a) jdx += o7[3 + a] * t.v[9 + a];
     const int si = so(c, k, j);
-    const double bs = bv[si];
+    const double bs = t.v[12];
     const double dyg = D * (jdx - bs / sig - bg);
     xc[r] = dyg;
     xv[si] = (bs + dyg) / sig;
-  }
+  });
   __syncthreads();
   if (e.resto) {
-    for (int r = lane; r < c.m; r += WAVE) {
-      const double sp = s.zp[r] / s.p[r] + e.dxp, sn = s.zn[r] / s.nn[r] + e.dxp;
-      xp[r] = (bp[r] + xc[r]) / sp;
-      xn[r] = (bn[r] - xc[r]) / sn;
-    }
+    lanes_for(c.m, lane, [&](int r) { return DV<7>{{s.zp[r], s.p[r], s.zn[r], s.nn[r], bp[r], bn[r], xc[r]}}; },
+              [&](int r, const DV<7>& t) {
+                const double sp = t.v[0] / t.v[1] + e.dxp, sn = t.v[2] / t.v[3] + e.dxp;
+                xp[r] = (t.v[4] + t.v[6]) / sp;
+                xn[r] = (t.v[5] - t.v[6]) / sn;
+              });
   }
   __syncthreads();
 }

@@ -24,22 +24,32 @@ __device__ __forceinline__ double fdiv_safe(double a, double b) { return a / b; 
 // -c at the current point into rc (restoration: -(c - p + n))
 __device__ __forceinline__ void eval_c(const Cfg& c, const Slot& s, bool resto, int lane) {
   const int N = c.N, NI = c.NI;
-  for (int r = lane; r < (N + 1) * NX; r += WAVE) {
-    int k = r / NX, i = r % NX;
-    double cv = (k == 0) ? s.v[i] - s.th[i] : s.v[xo(k) + i] - s.F[(k - 1) * NX + i];
-    s.rc[r] = -cv;
-  }
-  for (int q = lane; q < N * NI; q += WAVE) {
-    int k = 1 + q / NI, j = q % NI;
+  lanes_for((N + 1) * NX, lane, [&](int r) {
+    const int k = r / NX, i = r % NX;
+    return DV<2>{{s.v[xo(k) + i], (k == 0) ? s.th[i] : s.F[(k - 1) * NX + i]}};
+  }, [&](int r, const DV<2>& t) { s.rc[r] = -(t.v[0] - t.v[1]); });
+  lanes_for(N * NI, lane, [&](int q) {
+    const int k = 1 + q / NI, j = q % NI;
+    DV<8> t;
     double o[4];
     obs_at(c, s.th, j, k, o);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) t.v[a] = o[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t.v[4 + a] = s.v[xo(k) + a];
+    t.v[7] = s.v[so(c, k, j)];
+    return t;
+  }, [&](int q, const DV<8>& t) {
+    const int k = 1 + q / NI, j = q % NI;
     double g = 0.0;
-    for (int t = 0; t < 3; ++t) { double e = s.v[xo(k) + t] - o[t]; g += e * e; }
-    s.rc[go(c, k, j)] = -(g - o[3] * o[3] - s.v[so(c, k, j)]);
-  }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { double e = t.v[4 + a] - t.v[a]; g += e * e; }
+    s.rc[go(c, k, j)] = -(g - t.v[3] * t.v[3] - t.v[7]);
+  });
   __syncthreads();
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE) s.rc[r] += s.p[r] - s.nn[r];
+    lanes_for(c.m, lane, [&](int r) { return DV<3>{{s.rc[r], s.p[r], s.nn[r]}}; },
+              [&](int r, const DV<3>& t) { s.rc[r] = t.v[0] + (t.v[1] - t.v[2]); });
   __syncthreads();
 }
 
@@ -47,36 +57,68 @@ __device__ __forceinline__ void eval_c(const Cfg& c, const Slot& s, bool resto, 
 __device__ __forceinline__ void eval_grad(const Cfg& c, const Slot& s, const double* yv, bool resto, double zeta, double* aty,
                           int lane) {
   const int N = c.N, NI = c.NI;
-  for (int i = lane; i < c.n; i += WAVE) {
+  lanes_for(c.n, lane, [&](int i) {
+    double w = 0.0;
+    if (resto) {
+      w = s.xr[i];
+    } else if (i < c.n_w) {
+      const int k = i / NZ, r = i % NZ;
+      if (r < NX) w = s.ref[k * NX + r];
+    }
+    return DV<2>{{s.v[i], w}};
+  }, [&](int i, const DV<2>& t) {
     double gi = 0.0;
     if (resto) {
-      double d = fmin(1.0, 1.0 / fabs(s.xr[i]));
-      gi = zeta * d * d * (s.v[i] - s.xr[i]);
+      double d = fmin(1.0, 1.0 / fabs(t.v[1]));
+      gi = zeta * d * d * (t.v[0] - t.v[1]);
     } else if (i < c.n_w) {
-      int k = i / NZ, r = i % NZ;
+      int r = i % NZ;
       if (r < NX) {
-        gi = 2.0 * c.qw * (s.v[i] - s.ref[k * NX + r]);
+        gi = 2.0 * c.qw * (t.v[0] - t.v[1]);
       } else {
-        gi = 2.0 * c.rw * (s.v[i] - c.uh);
+        gi = 2.0 * c.rw * (t.v[0] - c.uh);
       }
     }
     s.g[i] = gi;
-  }
-  // A^T y
+  });
+  // A^T y.  Every load of a trip (the identity row, column r of G_k with y_{k+1}, the first
+  // OBS_CHUNK inequality rows of knot k) is issued before the first use, from valid addresses
+  // on every lane, so that a trip waits for memory once.
   for (int i = lane; i < c.n; i += WAVE) {
     double a = 0.0;
     if (i < c.n_w) {
-      int k = i / NZ, r = i % NZ;
-      if (r < NX) a += yv[k * NX + r];        // +I of the rows defining x_k
+      const int k = i / NZ, r = i % NZ;
+      const int kg = k < N ? k : N - 1, ko = k >= 1 ? k : 1, ro = r < 3 ? r : 0;
+      const double* Gk = s.G + (long long)kg * NX * NZ;
+      const double ys = yv[k * NX + (r < NX ? r : 0)], vi = s.v[i];
+      double gc[NX], yn[NX], oc[OBS_CHUNK], yg[OBS_CHUNK];
+#pragma unroll
+      for (int l = 0; l < NX; ++l) {
+        gc[l] = Gk[l * NZ + r];
+        yn[l] = yv[(kg + 1) * NX + l];
+      }
+      auto load_obs = [&](int j0) {
+#pragma unroll
+        for (int u = 0; u < OBS_CHUNK; ++u) {
+          const int j = min(j0 + u, NI - 1);
+          double o[4];
+          obs_at(c, s.th, j, ko, o);
+          oc[u] = ro == 0 ? o[0] : (ro == 1 ? o[1] : o[2]);
+          yg[u] = yv[go(c, ko, j)];
+        }
+      };
+      if (NI > 0) load_obs(0);
+      if (r < NX) a += ys;        // +I of the rows defining x_k
       if (k < N) {
-        const double* Gk = s.G + (long long)k * NX * NZ;
-        for (int l = 0; l < NX; ++l) a -= Gk[l * NZ + r] * yv[(k + 1) * NX + l];
+#pragma unroll
+        for (int l = 0; l < NX; ++l) a -= gc[l] * yn[l];
       }
       if (r < 3 && k >= 1) {
-        for (int j = 0; j < NI; ++j) {
-          double o[4];
-          obs_at(c, s.th, j, k, o);
-          a += 2.0 * (s.v[i] - o[r]) * yv[go(c, k, j)];
+        for (int j0 = 0; j0 < NI; j0 += OBS_CHUNK) {
+          if (j0 > 0) load_obs(j0);
+#pragma unroll
+          for (int u = 0; u < OBS_CHUNK; ++u)
+            if (j0 + u < NI) a += 2.0 * (vi - oc[u]) * yg[u];
         }
       }
     } else {
@@ -107,26 +149,31 @@ struct ErrParts {
 
 __device__ __forceinline__ ErrParts err_parts(const Cfg& c, const Slot& s, const Iter& it, const double* aty, int lane) {
   double dual = 0.0, nanf = 0.0, z1 = 0.0, y1 = 0.0, prim = 0.0;
-    for (int i = lane; i < c.n; i += WAVE) {
+  lanes_for(c.n, lane, [&](int i) {
     double zl, zu;
     z_of(c, it, i, zl, zu);
-    double d = s.g[i] + aty[i] - zl + zu;
+    return DV<4>{{s.g[i], aty[i], zl, zu}};
+  }, [&](int i, const DV<4>& t) {
+    const double zl = t.v[2], zu = t.v[3];
+    double d = t.v[0] + t.v[1] - zl + zu;
     if (!isfinite(d)) nanf = 1.0;
     dual = fmax(dual, fabs(d));
     z1 += fabs(zl) + fabs(zu);
-  }
-    for (int r = lane; r < c.m; r += WAVE) {
-    y1 += fabs(it.y[r]);
-    double pr = fabs(s.rc[r]);
+  });
+  lanes_for(c.m, lane, [&](int r) {
+    return DV<4>{{it.y[r], s.rc[r], it.resto ? s.zp[r] : 0.0, it.resto ? s.zn[r] : 0.0}};
+  }, [&](int r, const DV<4>& t) {
+    y1 += fabs(t.v[0]);
+    double pr = fabs(t.v[1]);
     if (!isfinite(pr)) nanf = 1.0;
     prim = fmax(prim, pr);
     if (it.resto) {
-      double dp = c.rho_resto - it.y[r] - s.zp[r];
-      double dn = c.rho_resto + it.y[r] - s.zn[r];
+      double dp = c.rho_resto - t.v[0] - t.v[2];
+      double dn = c.rho_resto + t.v[0] - t.v[3];
       dual = fmax(dual, fmax(fabs(dp), fabs(dn)));
-      z1 += fabs(s.zp[r]) + fabs(s.zn[r]);
+      z1 += fabs(t.v[2]) + fabs(t.v[3]);
     }
-  }
+  });
   ErrParts e;
   e.dual = wmax(dual);
   e.prim = wmax(prim);
@@ -141,18 +188,22 @@ __device__ __forceinline__ ErrParts err_parts(const Cfg& c, const Slot& s, const
 // max |s z - mu| over the bounded components
 __device__ __forceinline__ double compl_max(const Cfg& c, const Slot& s, const Iter& it, double mu, int lane) {
   double cm = 0.0;
-    for (int b = lane; b < c.N * NU; b += WAVE) {
-    int k = b / NU, i = b % NU;
-    double u = s.v[uo(k) + i];
-    cm = fmax(cm, fabs(u * it.zlu[b] - mu));
-    cm = fmax(cm, fabs((c.umax - u) * it.zuu[b] - mu));
-  }
-    for (int q = lane; q < c.N * c.NI; q += WAVE) cm = fmax(cm, fabs(s.v[c.n_w + q] * it.zls[q] - mu));
+  lanes_for(c.N * NU, lane, [&](int b) {
+    const int k = b / NU, i = b % NU;
+    return DV<3>{{s.v[uo(k) + i], it.zlu[b], it.zuu[b]}};
+  }, [&](int b, const DV<3>& t) {
+    const double u = t.v[0];
+    cm = fmax(cm, fabs(u * t.v[1] - mu));
+    cm = fmax(cm, fabs((c.umax - u) * t.v[2] - mu));
+  });
+  lanes_for(c.N * c.NI, lane, [&](int q) { return DV<2>{{s.v[c.n_w + q], it.zls[q]}}; },
+            [&](int q, const DV<2>& t) { cm = fmax(cm, fabs(t.v[0] * t.v[1] - mu)); });
   if (it.resto)
-        for (int r = lane; r < c.m; r += WAVE) {
-      cm = fmax(cm, fabs(s.p[r] * s.zp[r] - mu));
-      cm = fmax(cm, fabs(s.nn[r] * s.zn[r] - mu));
-    }
+    lanes_for(c.m, lane, [&](int r) { return DV<4>{{s.p[r], s.zp[r], s.nn[r], s.zn[r]}}; },
+              [&](int r, const DV<4>& t) {
+                cm = fmax(cm, fabs(t.v[0] * t.v[1] - mu));
+                cm = fmax(cm, fabs(t.v[2] * t.v[3] - mu));
+              });
   return wmax(cm);
 }
 
@@ -170,16 +221,19 @@ __device__ __forceinline__ double kkt_err(const Cfg& c, const ErrParts& e, doubl
 // objective value at v (regular) -- wave sum
 __device__ __forceinline__ double obj_regular(const Cfg& c, const Slot& s, const double* v, int lane) {
   double f = 0.0;
-    for (int i = lane; i < c.n_w; i += WAVE) {
-    int k = i / NZ, r = i % NZ;
+  lanes_for(c.n_w, lane, [&](int i) {
+    const int k = i / NZ, r = i % NZ;
+    return DV<2>{{v[i], r < NX ? s.ref[k * NX + r] : 0.0}};
+  }, [&](int i, const DV<2>& t) {
+    int r = i % NZ;
     if (r < NX) {
-      double e = v[i] - s.ref[k * NX + r];
+      double e = t.v[0] - t.v[1];
       f += c.qw * e * e;
     } else {
-      double e = v[i] - c.uh;
+      double e = t.v[0] - c.uh;
       f += c.rw * e * e;
     }
-  }
+  });
   return wsum(f);
 }
 
@@ -187,12 +241,13 @@ __device__ __forceinline__ double obj_regular(const Cfg& c, const Slot& s, const
 __device__ __forceinline__ double obj_resto(const Cfg& c, const Slot& s, const double* v, const double* p, const double* nn,
                             double zeta, int lane) {
   double a = 0.0, q = 0.0;
-    for (int r = lane; r < c.m; r += WAVE) a += p[r] + nn[r];
-    for (int i = lane; i < c.n; i += WAVE) {
-    double d = fmin(1.0, 1.0 / fabs(s.xr[i]));
-    double e = v[i] - s.xr[i];
+  lanes_for(c.m, lane, [&](int r) { return DV<2>{{p[r], nn[r]}}; },
+            [&](int r, const DV<2>& t) { a += t.v[0] + t.v[1]; });
+  lanes_for(c.n, lane, [&](int i) { return DV<2>{{s.xr[i], v[i]}}; }, [&](int i, const DV<2>& t) {
+    double d = fmin(1.0, 1.0 / fabs(t.v[0]));
+    double e = t.v[1] - t.v[0];
     q += d * d * e * e;
-  }
+  });
   return c.rho_resto * wsum(a) + 0.5 * zeta * wsum(q);
 }
 
@@ -200,23 +255,25 @@ __device__ __forceinline__ double obj_resto(const Cfg& c, const Slot& s, const d
 __device__ __forceinline__ double log_barrier(const Cfg& c, const double* v, const double* p, const double* nn, bool resto,
                               int lane) {
   double b = 0.0, bad = 0.0;
-    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
-    int k = bb / NU, i = bb % NU;
-    double u = v[uo(k) + i];
+  lanes_for(c.N * NU, lane, [&](int bb) {
+    const int k = bb / NU, i = bb % NU;
+    return DV<1>{{v[uo(k) + i]}};
+  }, [&](int bb, const DV<1>& t) {
+    double u = t.v[0];
     double sl = u, su = c.umax - u;
     if (!(sl > 0.0) || !(su > 0.0)) bad = 1.0;
     else b += log(sl) + log(su);
-  }
-    for (int q = lane; q < c.N * c.NI; q += WAVE) {
-    double sv = v[c.n_w + q];
+  });
+  lanes_for(c.N * c.NI, lane, [&](int q) { return DV<1>{{v[c.n_w + q]}}; }, [&](int q, const DV<1>& t) {
+    double sv = t.v[0];
     if (!(sv > 0.0)) bad = 1.0;
     else b += log(sv);
-  }
+  });
   if (resto)
-        for (int r = lane; r < c.m; r += WAVE) {
-      if (!(p[r] > 0.0) || !(nn[r] > 0.0)) bad = 1.0;
-      else b += log(p[r]) + log(nn[r]);
-    }
+    lanes_for(c.m, lane, [&](int r) { return DV<2>{{p[r], nn[r]}}; }, [&](int r, const DV<2>& t) {
+      if (!(t.v[0] > 0.0) || !(t.v[1] > 0.0)) bad = 1.0;
+      else b += log(t.v[0]) + log(t.v[1]);
+    });
   if (wmax(bad) > 0.0) return NAN;
   return wsum(b);
 }
@@ -225,59 +282,70 @@ __device__ __forceinline__ double log_barrier(const Cfg& c, const double* v, con
 __device__ __forceinline__ double ftb_primal(const Cfg& c, const Slot& s, const double* dv, const double* dp, const double* dn,
                              bool resto, double tau, int lane) {
   double a = 1.0;
-    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
-    int k = bb / NU, i = bb % NU;
-    double u = s.v[uo(k) + i], d = dv[uo(k) + i];
+  lanes_for(c.N * NU, lane, [&](int bb) {
+    const int k = bb / NU, i = bb % NU;
+    return DV<2>{{s.v[uo(k) + i], dv[uo(k) + i]}};
+  }, [&](int bb, const DV<2>& t) {
+    double u = t.v[0], d = t.v[1];
     if (d < 0) a = fmin(a, -tau * u / d);
     if (d > 0) a = fmin(a, tau * (c.umax - u) / d);
-  }
-    for (int q = lane; q < c.N * c.NI; q += WAVE) {
-    double d = dv[c.n_w + q];
-    if (d < 0) a = fmin(a, -tau * s.v[c.n_w + q] / d);
-  }
+  });
+  lanes_for(c.N * c.NI, lane, [&](int q) { return DV<2>{{dv[c.n_w + q], s.v[c.n_w + q]}}; },
+            [&](int q, const DV<2>& t) {
+              double d = t.v[0];
+              if (d < 0) a = fmin(a, -tau * t.v[1] / d);
+            });
   if (resto)
-        for (int r = lane; r < c.m; r += WAVE) {
-      if (dp[r] < 0) a = fmin(a, -tau * s.p[r] / dp[r]);
-      if (dn[r] < 0) a = fmin(a, -tau * s.nn[r] / dn[r]);
-    }
+    lanes_for(c.m, lane, [&](int r) { return DV<4>{{dp[r], s.p[r], dn[r], s.nn[r]}}; },
+              [&](int r, const DV<4>& t) {
+                if (t.v[0] < 0) a = fmin(a, -tau * t.v[1] / t.v[0]);
+                if (t.v[2] < 0) a = fmin(a, -tau * t.v[3] / t.v[2]);
+              });
   return wmin(a);
 }
 
 // bound-multiplier steps (eq. (6) rows 3-4 eliminated): into dzlu, dzuu, dzls, dzp, dzn
 __device__ __forceinline__ void dz_recover(const Cfg& c, const Slot& s, const Iter& it, double mu, const double* dv,
                            const double* dp, const double* dn, int lane) {
-  for (int bb = lane; bb < c.N * NU; bb += WAVE) {
-    int k = bb / NU, i = bb % NU;
-    double u = s.v[uo(k) + i], d = dv[uo(k) + i];
+  lanes_for(c.N * NU, lane, [&](int bb) {
+    const int k = bb / NU, i = bb % NU;
+    return DV<4>{{s.v[uo(k) + i], dv[uo(k) + i], it.zlu[bb], it.zuu[bb]}};
+  }, [&](int bb, const DV<4>& t) {
+    double u = t.v[0], d = t.v[1], zl = t.v[2], zu = t.v[3];
     double sl = u, su = c.umax - u;
-    s.dzlu[bb] = (mu - sl * it.zlu[bb] - it.zlu[bb] * d) / sl;
-    s.dzuu[bb] = (mu - su * it.zuu[bb] + it.zuu[bb] * d) / su;
-  }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) {
-    double sv = s.v[c.n_w + q], d = dv[c.n_w + q];
-    s.dzls[q] = (mu - sv * it.zls[q] - it.zls[q] * d) / sv;
-  }
+    s.dzlu[bb] = (mu - sl * zl - zl * d) / sl;
+    s.dzuu[bb] = (mu - su * zu + zu * d) / su;
+  });
+  lanes_for(c.N * c.NI, lane, [&](int q) { return DV<3>{{s.v[c.n_w + q], dv[c.n_w + q], it.zls[q]}}; },
+            [&](int q, const DV<3>& t) {
+              double sv = t.v[0], d = t.v[1], z = t.v[2];
+              s.dzls[q] = (mu - sv * z - z * d) / sv;
+            });
   if (it.resto)
-    for (int r = lane; r < c.m; r += WAVE) {
-      s.dzp[r] = (mu - s.p[r] * s.zp[r] - s.zp[r] * dp[r]) / s.p[r];
-      s.dzn[r] = (mu - s.nn[r] * s.zn[r] - s.zn[r] * dn[r]) / s.nn[r];
-    }
+    lanes_for(c.m, lane, [&](int r) { return DV<6>{{s.p[r], s.zp[r], dp[r], s.nn[r], s.zn[r], dn[r]}}; },
+              [&](int r, const DV<6>& t) {
+                s.dzp[r] = (mu - t.v[0] * t.v[1] - t.v[1] * t.v[2]) / t.v[0];
+                s.dzn[r] = (mu - t.v[3] * t.v[4] - t.v[4] * t.v[5]) / t.v[3];
+              });
   __syncthreads();
 }
 
 __device__ __forceinline__ double ftb_dual(const Cfg& c, const Slot& s, const Iter& it, double tau, int lane) {
   double a = 1.0;
-    for (int bb = lane; bb < c.N * NU; bb += WAVE) {
-    if (s.dzlu[bb] < 0) a = fmin(a, -tau * it.zlu[bb] / s.dzlu[bb]);
-    if (s.dzuu[bb] < 0) a = fmin(a, -tau * it.zuu[bb] / s.dzuu[bb]);
-  }
-    for (int q = lane; q < c.N * c.NI; q += WAVE)
-    if (s.dzls[q] < 0) a = fmin(a, -tau * it.zls[q] / s.dzls[q]);
+  lanes_for(c.N * NU, lane, [&](int bb) { return DV<4>{{s.dzlu[bb], it.zlu[bb], s.dzuu[bb], it.zuu[bb]}}; },
+            [&](int bb, const DV<4>& t) {
+              if (t.v[0] < 0) a = fmin(a, -tau * t.v[1] / t.v[0]);
+              if (t.v[2] < 0) a = fmin(a, -tau * t.v[3] / t.v[2]);
+            });
+  lanes_for(c.N * c.NI, lane, [&](int q) { return DV<2>{{s.dzls[q], it.zls[q]}}; }, [&](int q, const DV<2>& t) {
+    if (t.v[0] < 0) a = fmin(a, -tau * t.v[1] / t.v[0]);
+  });
   if (it.resto)
-        for (int r = lane; r < c.m; r += WAVE) {
-      if (s.dzp[r] < 0) a = fmin(a, -tau * s.zp[r] / s.dzp[r]);
-      if (s.dzn[r] < 0) a = fmin(a, -tau * s.zn[r] / s.dzn[r]);
-    }
+    lanes_for(c.m, lane, [&](int r) { return DV<4>{{s.dzp[r], s.zp[r], s.dzn[r], s.zn[r]}}; },
+              [&](int r, const DV<4>& t) {
+                if (t.v[0] < 0) a = fmin(a, -tau * t.v[1] / t.v[0]);
+                if (t.v[2] < 0) a = fmin(a, -tau * t.v[3] / t.v[2]);
+              });
   return wmin(a);
 }
 
@@ -287,8 +355,9 @@ __device__ __forceinline__ double ftb_dual(const Cfg& c, const Slot& s, const It
 // reject if theta >= theta_F and phi >= phi_F for some entry
 __device__ __forceinline__ bool filter_ok(const Cfg& c, const double* filt, int nf, double th, double ph, int lane) {
   int bad = 0;
-  for (int i = lane; i < nf; i += WAVE)
-    if (th >= filt[i] && ph >= filt[c.fc + i]) bad = 1;
+  lanes_for(nf, lane, [&](int i) { return DV<2>{{filt[i], filt[c.fc + i]}}; }, [&](int i, const DV<2>& t) {
+    if (th >= t.v[0] && ph >= t.v[1]) bad = 1;
+  });
   return wor(bad) == 0;
 }
 
@@ -889,27 +958,27 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
     __syncthreads();
   }
   // ---- barrier gradient, right-hand side of eq. (7), theta_k, phi_k ----
-  for (int i = lane; i < c.n; i += WAVE) {
-    double gp = s.g[i];
+  lanes_for(c.n, lane, [&](int i) { return DV<3>{{s.g[i], s.v[i], s.vt[i]}}; }, [&](int i, const DV<3>& t) {
+    double gp = t.v[0];
     if (i < c.n_w) {
       int k = i / NZ, r = i % NZ;
       if (r >= NX && k < c.N) {
-        double u = s.v[i];
+        double u = t.v[1];
         gp += -mu / u + mu / (c.umax - u);
       }
     } else {
-      gp -= mu / s.v[i];
+      gp -= mu / t.v[1];
     }
     s.g[i] = gp;                       // now grad phi_mu
-    s.rv[i] = -(gp + s.vt[i]);
-  }
+    s.rv[i] = -(gp + t.v[2]);
+  });
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE) {
-      s.rp[r] = -(c.rho_resto - mu / s.p[r] - it.y[r]);
-      s.rn[r] = -(c.rho_resto - mu / s.nn[r] + it.y[r]);
-    }
+    lanes_for(c.m, lane, [&](int r) { return DV<3>{{s.p[r], s.nn[r], it.y[r]}}; }, [&](int r, const DV<3>& t) {
+      s.rp[r] = -(c.rho_resto - mu / t.v[0] - t.v[2]);
+      s.rn[r] = -(c.rho_resto - mu / t.v[1] + t.v[2]);
+    });
   double thk = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) thk += fabs(s.rc[r]);
+  lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; }, [&](int r, const DV<1>& t) { thk += fabs(t.v[0]); });
   thk = wsum(thk);
   double fk = resto ? obj_resto(c, s, s.v, s.p, s.nn, zeta, lane) : obj_regular(c, s, s.v, lane);
   double phk = fk - mu * log_barrier(c, s.v, s.p, s.nn, resto, lane);
@@ -1090,10 +1159,13 @@ __device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, const doub
   dz_recover(c, s, it, mu, s.dv, s.dp, s.dn, lane);
   double amax = ftb_primal(c, s, s.dv, s.dp, s.dn, resto, tau, lane);
   double gphi = 0.0;
-  for (int i = lane; i < c.n; i += WAVE) gphi += s.g[i] * s.dv[i];
+  lanes_for(c.n, lane, [&](int i) { return DV<2>{{s.g[i], s.dv[i]}}; },
+            [&](int i, const DV<2>& t) { gphi += t.v[0] * t.v[1]; });
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE)
-      gphi += (c.rho_resto - mu / s.p[r]) * s.dp[r] + (c.rho_resto - mu / s.nn[r]) * s.dn[r];
+    lanes_for(c.m, lane, [&](int r) { return DV<4>{{s.p[r], s.dp[r], s.nn[r], s.dn[r]}}; },
+              [&](int r, const DV<4>& t) {
+                gphi += (c.rho_resto - mu / t.v[0]) * t.v[1] + (c.rho_resto - mu / t.v[2]) * t.v[3];
+              });
   gphi = wsum(gphi);
   __syncthreads();
   if (lane == 0) {
@@ -1122,20 +1194,31 @@ __device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool re
     for (int i = 0; i < NX; ++i) s.ct[(lane + 1) * NX + i] = s.vt[xo(lane + 1) + i] - F[i];
   }
   for (int i = lane; i < NX; i += WAVE) s.ct[i] = s.vt[i] - s.th[i];
-  for (int q = lane; q < N * NI; q += WAVE) {
-    int k = 1 + q / NI, j = q % NI;
+  lanes_for(N * NI, lane, [&](int q) {
+    const int k = 1 + q / NI, j = q % NI;
+    DV<8> t;
     double o[4];
     obs_at(c, s.th, j, k, o);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) t.v[a] = o[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) t.v[4 + a] = s.vt[xo(k) + a];
+    t.v[7] = s.vt[so(c, k, j)];
+    return t;
+  }, [&](int q, const DV<8>& t) {
+    const int k = 1 + q / NI, j = q % NI;
     double g = 0.0;
-    for (int t = 0; t < 3; ++t) { double e = s.vt[xo(k) + t] - o[t]; g += e * e; }
-    s.ct[go(c, k, j)] = g - o[3] * o[3] - s.vt[so(c, k, j)];
-  }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { double e = t.v[4 + a] - t.v[a]; g += e * e; }
+    s.ct[go(c, k, j)] = g - t.v[3] * t.v[3] - t.v[7];
+  });
   __syncthreads();
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE) s.ct[r] += -s.pt[r] + s.nt[r];
+    lanes_for(c.m, lane, [&](int r) { return DV<3>{{s.ct[r], s.pt[r], s.nt[r]}}; },
+              [&](int r, const DV<3>& t) { s.ct[r] = t.v[0] + (-t.v[1] + t.v[2]); });
   __syncthreads();
   double th = 0.0;
-  for (int r = lane; r < c.m; r += WAVE) th += fabs(s.ct[r]);
+  lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.ct[r]}}; }, [&](int r, const DV<1>& t) { th += fabs(t.v[0]); });
   th = wsum(th);
   double f = resto ? obj_resto(c, s, s.vt, s.pt, s.nt, zeta, lane) : obj_regular(c, s, s.vt, lane);
   double ph = f - mu * log_barrier(c, s.vt, s.pt, s.nt, resto, lane);
@@ -1148,9 +1231,13 @@ __device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool re
 
 __device__ __forceinline__ void make_trial(const Cfg& c, const Slot& s, bool resto, double a, const double* dv,
                                            const double* dp, const double* dn, int lane) {
-  for (int i = lane; i < c.n; i += WAVE) s.vt[i] = s.v[i] + a * dv[i];
+  lanes_for(c.n, lane, [&](int i) { return DV<2>{{s.v[i], dv[i]}}; },
+            [&](int i, const DV<2>& t) { s.vt[i] = t.v[0] + a * t.v[1]; });
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE) { s.pt[r] = s.p[r] + a * dp[r]; s.nt[r] = s.nn[r] + a * dn[r]; }
+    lanes_for(c.m, lane, [&](int r) { return DV<4>{{s.p[r], dp[r], s.nn[r], dn[r]}}; }, [&](int r, const DV<4>& t) {
+      s.pt[r] = t.v[0] + a * t.v[1];
+      s.nt[r] = t.v[2] + a * t.v[3];
+    });
   __syncthreads();
 }
 
@@ -1405,13 +1492,16 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
   if (step == STEP_READY && !try_soft) {
     // tiny step (Table I row 4) at a nearly feasible point
     double tmax = 0.0, cmax = 0.0;
-    for (int i = lane; i < c.n; i += WAVE) tmax = fmax(tmax, fabs(s.dv[i]) / (1.0 + fabs(s.v[i])));
+    lanes_for(c.n, lane, [&](int i) { return DV<2>{{s.dv[i], s.v[i]}}; },
+              [&](int i, const DV<2>& t) { tmax = fmax(tmax, fabs(t.v[0]) / (1.0 + fabs(t.v[1]))); });
     if (resto)
-      for (int r = lane; r < c.m; r += WAVE) {
-        tmax = fmax(tmax, fabs(s.dp[r]) / (1.0 + fabs(s.p[r])));
-        tmax = fmax(tmax, fabs(s.dn[r]) / (1.0 + fabs(s.nn[r])));
-      }
-    for (int r = lane; r < c.m; r += WAVE) cmax = fmax(cmax, fabs(s.rc[r]));
+      lanes_for(c.m, lane, [&](int r) { return DV<4>{{s.dp[r], s.p[r], s.dn[r], s.nn[r]}}; },
+                [&](int r, const DV<4>& t) {
+                  tmax = fmax(tmax, fabs(t.v[0]) / (1.0 + fabs(t.v[1])));
+                  tmax = fmax(tmax, fabs(t.v[2]) / (1.0 + fabs(t.v[3])));
+                });
+    lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; },
+              [&](int r, const DV<1>& t) { cmax = fmax(cmax, fabs(t.v[0])); });
     tmax = wmax(tmax);
     cmax = wmax(cmax);
     if (tmax < 10.0 * 2.220446049250313e-16 && cmax <= 1e-4) {
@@ -1499,16 +1589,18 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
           // second-order correction with the stored factor (Table I row 2)
           double asoc = alpha, th_old = 0.0, tht = t.th;
           bool fin = true;
-          for (int r = lane; r < c.m; r += WAVE) s.csoc[r] = -s.rc[r];
+          lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; },
+                    [&](int r, const DV<1>& t) { s.csoc[r] = -t.v[0]; });
           __syncthreads();
           Elim e{false, resto, s.sc[SC_LDX], s.sc[SC_LDC], zeta};
           for (int p = 0; p < c.max_soc; ++p) {
             if (p > 0 && !(tht <= c.kappa_soc * th_old)) break;
             th_old = tht;
-            for (int r = lane; r < c.m; r += WAVE) {
-              s.csoc[r] = asoc * s.csoc[r] + s.ct[r];
-              s.ct[r] = -s.csoc[r];      // right-hand side rows of the constraints
-            }
+            lanes_for(c.m, lane, [&](int r) { return DV<2>{{s.csoc[r], s.ct[r]}}; }, [&](int r, const DV<2>& t) {
+              const double cs = asoc * t.v[0] + t.v[1];
+              s.csoc[r] = cs;
+              s.ct[r] = -cs;      // right-hand side rows of the constraints
+            });
             __syncthreads();
             if (!solve_refined(c, s, e, s.rv, s.ct, s.rp, s.rn, s.dvs, s.dys, s.dps, s.dns, sol_dyn, mixed, lane)) break;
             if (lane == 0) {
@@ -1602,33 +1694,41 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
   }
   if (use_wd && lane == 0 && s.sc[SC_WD_ACTIVE] == 0.0)
     s.sc[SC_WD_SHORT] = shortened ? s.sc[SC_WD_SHORT] + 1.0 : 0.0;
-  for (int r = lane; r < c.m; r += WAVE) it.y[r] += ap * ady[r];
-  for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.vt[i];
+  lanes_for(c.m, lane, [&](int r) { return DV<2>{{it.y[r], ady[r]}}; },
+            [&](int r, const DV<2>& t) { it.y[r] = t.v[0] + ap * t.v[1]; });
+  lanes_for(c.n, lane, [&](int i) { return DV<1>{{s.vt[i]}}; }, [&](int i, const DV<1>& t) { s.v[i] = t.v[0]; });
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE) { s.p[r] = s.pt[r]; s.nn[r] = s.nt[r]; }
+    lanes_for(c.m, lane, [&](int r) { return DV<2>{{s.pt[r], s.nt[r]}}; }, [&](int r, const DV<2>& t) {
+      s.p[r] = t.v[0];
+      s.nn[r] = t.v[1];
+    });
   __syncthreads();
   const double ks = c.kappa_sigma;
-  for (int b = lane; b < c.N * NU; b += WAVE) {
-    int k = b / NU, i = b % NU;
-    double u = s.v[uo(k) + i];
-    double z = it.zlu[b] + az * s.dzlu[b];
+  lanes_for(c.N * NU, lane, [&](int b) {
+    const int k = b / NU, i = b % NU;
+    return DV<5>{{s.v[uo(k) + i], it.zlu[b], s.dzlu[b], it.zuu[b], s.dzuu[b]}};
+  }, [&](int b, const DV<5>& t) {
+    double u = t.v[0];
+    double z = t.v[1] + az * t.v[2];
     it.zlu[b] = fmax(fmin(z, ks * mu / u), mu / (ks * u));
     double su = c.umax - u;
-    z = it.zuu[b] + az * s.dzuu[b];
+    z = t.v[3] + az * t.v[4];
     it.zuu[b] = fmax(fmin(z, ks * mu / su), mu / (ks * su));
-  }
-  for (int q = lane; q < c.N * c.NI; q += WAVE) {
-    double sv = s.v[c.n_w + q];
-    double z = it.zls[q] + az * s.dzls[q];
-    it.zls[q] = fmax(fmin(z, ks * mu / sv), mu / (ks * sv));
-  }
+  });
+  lanes_for(c.N * c.NI, lane, [&](int q) { return DV<3>{{s.v[c.n_w + q], it.zls[q], s.dzls[q]}}; },
+            [&](int q, const DV<3>& t) {
+              double sv = t.v[0];
+              double z = t.v[1] + az * t.v[2];
+              it.zls[q] = fmax(fmin(z, ks * mu / sv), mu / (ks * sv));
+            });
   if (resto)
-    for (int r = lane; r < c.m; r += WAVE) {
-      double z = s.zp[r] + az * s.dzp[r];
-      s.zp[r] = fmax(fmin(z, ks * mu / s.p[r]), mu / (ks * s.p[r]));
-      z = s.zn[r] + az * s.dzn[r];
-      s.zn[r] = fmax(fmin(z, ks * mu / s.nn[r]), mu / (ks * s.nn[r]));
-    }
+    lanes_for(c.m, lane, [&](int r) { return DV<6>{{s.zp[r], s.dzp[r], s.p[r], s.zn[r], s.dzn[r], s.nn[r]}}; },
+              [&](int r, const DV<6>& t) {
+                double z = t.v[0] + az * t.v[1];
+                s.zp[r] = fmax(fmin(z, ks * mu / t.v[2]), mu / (ks * t.v[2]));
+                z = t.v[3] + az * t.v[4];
+                s.zn[r] = fmax(fmin(z, ks * mu / t.v[5]), mu / (ks * t.v[5]));
+              });
   __syncthreads();
   if (lane == 0) {
     if (tiny) { sub[5] = 1.0; s.sc[SC_ST_TINY] += 1.0; }
