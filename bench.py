@@ -37,10 +37,11 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
-# HBM traffic per launch of the dominant kernel, from the two rocprofv3 --pmc runs (FETCH_SIZE,
-# WRITE_SIZE) scaled by the same counters on a plain device copy of known size; valid only for
-# the kernel sources they were taken on (hash below) and the default C2 run.
-MEASURED_TRAFFIC = {}
+# HBM traffic of the dominant kernel from the two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE)
+# scaled by the same counters on a plain device copy of known size, per slot-iteration the
+# launches ran; a run's traffic per launch is that times its iterations per launch.  Valid only
+# for the kernel sources they were taken on (hash below) and the workload named.
+MEASURED_TRAFFIC = {"k_run": {"csrc": "15e65f846ad8f811", "workload": "C2", "bytes_per_iteration": 1.0111e6}}
 
 
 def csrc_hash() -> str:
@@ -75,12 +76,13 @@ def kernel_roofline(w, st, kt, word_bytes=8.0):
     """Roofline of the dominant kernel from the live HIP-event timings.
 
     k_fac is charged its factorization attempts, k_sol its solves and the fused pass kernel
-    k_iter both (SOC solves included); the pre-processing and line-search work of k_iter is not
-    charged, so its figure is a lower bound.  `word_bytes` is 4 when the factor runs in FP32."""
+    k_iter, and the asynchronous-slot kernel k_run, both (SOC solves included); the pre-processing,
+    line-search (and, in k_run, derivative) work is not charged, so their figures are lower bounds.
+    `word_bytes` is 4 when the factor runs in FP32."""
     S = w.N + 1
     fb = word_bytes * FACTOR_WORDS_PER_STAGE * S
     sb = word_bytes * SOLVE_WORDS_PER_STAGE * S
-    names = ("eval", "pre", "factor", "solve", "linesearch", "fused")
+    names = ("eval", "pre", "factor", "solve", "linesearch", "fused", "async")
     tot = {k: kt[k][0] for k in names if k in kt and kt[k][1] > 0}
     out = {}
     for k in tot:
@@ -94,7 +96,7 @@ def kernel_roofline(w, st, kt, word_bytes=8.0):
             units = st["solves"] - st["fused_solves"]
             per_launch, flops = sb * units / launches, 0.0
             desc = f"{units} solves x {S} stages x {sb / S:.0f} B"
-        elif k == "fused":
+        elif k in ("fused", "async"):
             per_launch = (fb * st["fused_factorizations"] + sb * st["fused_solves"]) / launches
             flops = FACTOR_FLOPS_PER_STAGE * S * st["fused_factorizations"] / launches
             desc = (f"{st['fused_factorizations']} factorizations x {S} stages x {fb / S:.0f} B + "
@@ -102,7 +104,7 @@ def kernel_roofline(w, st, kt, word_bytes=8.0):
         else:
             continue
         ach = per_launch / (avg_ms * 1e-3) / 1e9
-        out["k_" + {"factor": "fac", "solve": "sol", "fused": "iter"}[k]] = dict(
+        out["k_" + {"factor": "fac", "solve": "sol", "fused": "iter", "async": "run"}[k]] = dict(
             bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=None,
             avg_ms=avg_ms, launches=launches, bytes_per_launch=per_launch, units=desc,
             fp64_tflops=flops / (avg_ms * 1e-3) / 1e12, fp64_frac=flops / (avg_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
@@ -148,7 +150,7 @@ def cpu_baseline(w, sample: int, threads: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="C2", help="workload of the plain FP64 cold-start leg (`value`)")
     ap.add_argument("--slots", type=int, default=0, help="concurrent slots (default: all instances)")
@@ -168,6 +170,9 @@ def main():
     ap.add_argument("--val", type=int, default=10000, help="warm-start validation instances (C5)")
     ap.add_argument("--epochs", type=int, default=30, help="warm-start training epochs (C5)")
     ap.add_argument("--oracle-check", type=int, default=1024, help="C5 instances re-solved by the oracle")
+    ap.add_argument("--async-passes", type=int, default=16,
+                    help="passes each slot runs per launch of the asynchronous-slot kernel in the plain leg "
+                         "(0: one launch per pass)")
     ap.add_argument("--fuse-below", type=int, default=None,
                     help="unfinished-instance count below which passes use the fused kernel (default: library's)")
     args = ap.parse_args()
@@ -192,7 +197,7 @@ def main():
     n_inst = args.instances or w.n_inst
     slots = args.slots or n_inst
     TH = torch.tensor(w.thetas(0, n_inst), dtype=torch.float64, device="cuda:0")
-    opts = dict(timing=1, precision=args.precision or 0)
+    opts = dict(timing=1, precision=args.precision or 0, async_passes=args.async_passes)
     if args.fuse_below is not None:
         opts["fuse_below"] = args.fuse_below
     log(f"[bench] plain leg {w.name}: {n_inst} instances, N={w.N}, n={w.n}, m={w.m}, slots={slots}, "
@@ -212,8 +217,8 @@ def main():
     dom, roofs = kernel_roofline(w, st, kt, word_bytes=4.0 if opts["precision"] == 1 else 8.0)
     roof = roofs[dom]
     mt = MEASURED_TRAFFIC.get(dom)
-    if mt and mt["csrc"] == csrc_hash() and mt["workload"] == w.name and n_inst == w.n_inst and slots == n_inst:
-        roof["traffic"] = mt["bytes_per_launch"]
+    if mt and mt["csrc"] == csrc_hash() and mt["workload"] == w.name:
+        roof["traffic"] = mt["bytes_per_iteration"] * st["iterations"] / roof["launches"]
     kkt = out["kkt"].cpu().numpy()
     status = out["status"].cpu().numpy()
     desc = {"C2": "C2: figure-eight tracking NMPC, FP64 cold start"}
@@ -234,6 +239,8 @@ def main():
                    "n": w.n, "m": w.m, "slots": slots,
                    "batches": ("the timed steps streamed through the slots in one solve (iteration-level "
                                "batching across batches)") if not args.no_stream else "one solve per step",
+                   "pass_kernel": (f"asynchronous slots: every slot runs up to {args.async_passes} whole passes "
+                                   "per launch" if args.async_passes > 0 else "one launch per pass"),
                    "obstacles": "centres on the reference path + N(0, 0.5^2 I), kept 0.1 m from the start and "
                                 "0.3 m from the first 0.5 s of the reference"},
         "single_batch_ms": single_ms,
