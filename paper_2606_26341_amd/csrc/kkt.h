@@ -399,6 +399,28 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ dbl4 mfma64(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// The FP32 product v_mfma_f32_16x16x4f32 takes A and B the same way but holds D(4 (l / 16) + r,
+// l % 16) in item r.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ flt4 mfma32(float a, float b, flt4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+// the 16 x 16 x 4 product in the factor's precision T: accumulator type, product, and the row of
+// the result that item r of a lane in lane group kq = l / 16 holds
+template <typename T>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef dbl4 acc;
+  static __device__ __forceinline__ acc mma(double a, double b, acc c) { return mfma64(a, b, c); }
+  static __device__ __forceinline__ int row(int r, int kq) { return 4 * r + kq; }
+};
+template <>
+struct Mma<float> {
+  typedef flt4 acc;
+  static __device__ __forceinline__ acc mma(float a, float b, acc c) { return mfma32(a, b, c); }
+  static __device__ __forceinline__ int row(int r, int kq) { return 4 * kq + r; }
+};
 
 // An FP32 pivot that keeps less than this fraction of the diagonal entry it started from has
 // lost most of its significant digits to cancellation: its sign is not a reliable inertia verdict,
@@ -478,41 +500,28 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     T* fr = reinterpret_cast<T*>(s.fac) + (long long)k * FR_LEN;
     if (k > 0) stage_prefetch(c, s, k - 1, lane, reg);   // in flight during this stage
     // ---- Schur update, first half: T = S_{k+1} G_k (13 x 17) ----
-    // FP64: columns 0..15 on the matrix cores (K = 13 padded to 16; one 16 x 16 x 4 product costs
-    // about as much as eleven FP64 FMAs of a wavefront), column 16 on the vector ALUs, row i on
-    // lane i
+    // columns 0..15 on the matrix cores (K = 13 padded to 16; one 16 x 16 x 4 product costs about
+    // as much as eleven FMAs of a wavefront), column 16 on the vector ALUs, row i on lane i
     const int r16 = lane & 15, kq = lane >> 4, li0 = lane < NX ? lane : NX - 1;
-    if constexpr (sizeof(T) == sizeof(double)) {
-      if (k < N) {
-        dbl4 t0 = {0.0, 0.0, 0.0, 0.0};
-        double t16 = 0.0;
+    if (k < N) {
+      typename Mma<T>::acc t0 = {T(0), T(0), T(0), T(0)};
+      T t16 = 0.0;
 #pragma unroll
-        for (int l = 0; l < NX; ++l) t16 += L.S[li0 * NX + l] * Gk[l * NZ + 16];
+      for (int l = 0; l < NX; ++l) t16 += L.S[li0 * NX + l] * Gk[l * NZ + 16];
 #pragma unroll
-        for (int st = 0; st < 4; ++st) {
-          const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
-          const double sv = L.S[(r16 < NX ? r16 : 0) * NX + kc];
-          const double g0 = Gk[kc * NZ + r16];
-          const double a = (kk < NX && r16 < NX) ? sv : 0.0;
-          t0 = mfma64(a, kk < NX ? g0 : 0.0, t0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 4 * r + kq;
-          if (i < NX) L.CV[i * NZ + r16] = t0[r];
-        }
-        if (lane < NX) L.CV[lane * NZ + 16] = t16;
-        lds_barrier();
+      for (int st = 0; st < 4; ++st) {
+        const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
+        const T sv = L.S[(r16 < NX ? r16 : 0) * NX + kc];
+        const T g0 = Gk[kc * NZ + r16];
+        const T a = (kk < NX && r16 < NX) ? sv : T(0);
+        t0 = Mma<T>::mma(a, kk < NX ? g0 : T(0), t0);
       }
-    } else if (k < N) {
 #pragma unroll
-      for (int t = 0; t < TILE_T; ++t) {
-        const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
-        T acc = 0.0;
-#pragma unroll
-        for (int l = 0; l < NX; ++l) acc += L.S[i * NX + l] * Gk[l * NZ + j];
-        L.CV[q] = acc;
+      for (int r = 0; r < 4; ++r) {
+        const int i = Mma<T>::row(r, kq);
+        if (i < NX) L.CV[i * NZ + r16] = t0[r];
       }
+      if (lane < NX) L.CV[lane * NZ + 16] = t16;
       lds_barrier();
     }
     // ---- stage Hessian (NZ stride): W_k + diag + delta_x I + Hc_k + G_k^T T ----
@@ -522,43 +531,30 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       h += (k >= 1 && i < 3 && j < 3) ? SD[SD_HC + 3 * (i < 3 ? i : 0) + (j < 3 ? j : 0)] : T(0);
       return h;
     };
-    if constexpr (sizeof(T) == sizeof(double)) {
+    {
       // the leading 16 x 16 tile of the symmetric 17 x 17 result on the matrix cores (the
       // additive terms as the accumulator's start); column 16 on the vector ALUs, entry i on
       // lane i, also written as row 16
-      dbl4 h00;
+      typename Mma<T>::acc h00;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) h00[r] = h_base(4 * r + kq, r16);
+      for (int r = 0; r < 4; ++r) h00[r] = h_base(Mma<T>::row(r, kq), r16);
       const int ih = lane < NZ ? lane : NZ - 1;
-      double h16 = h_base(ih, 16);
+      T h16 = h_base(ih, 16);
       if (k < N) {
 #pragma unroll
         for (int l = 0; l < NX; ++l) h16 += Gk[l * NZ + ih] * L.CV[l * NZ + 16];
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
-          const double g0 = Gk[kc * NZ + r16], c0 = L.CV[kc * NZ + r16];
-          h00 = mfma64(kk < NX ? g0 : 0.0, kk < NX ? c0 : 0.0, h00);
+          const T g0 = Gk[kc * NZ + r16], c0 = L.CV[kc * NZ + r16];
+          h00 = Mma<T>::mma(kk < NX ? g0 : T(0), kk < NX ? c0 : T(0), h00);
         }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) L.H[(4 * r + kq) * NZ + r16] = h00[r];
+      for (int r = 0; r < 4; ++r) L.H[Mma<T>::row(r, kq) * NZ + r16] = h00[r];
       if (lane < NZ) {
         L.H[lane * NZ + 16] = h16;
         L.H[16 * NZ + lane] = h16;
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < TILE_H; ++t) {
-        const int q = lane + WAVE * t, i = q / NZ, j = q % NZ;
-        T h = (q < NZ * NZ) ? h_base(i, j) : T(0);
-        if (k < N) {
-          T acc = 0.0;
-#pragma unroll
-          for (int l = 0; l < NX; ++l) acc += Gk[l * NZ + i] * L.CV[l * NZ + j];
-          h += acc;
-        }
-        L.H[q] = h;
       }
     }
     lds_barrier();
@@ -610,31 +606,22 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         }
       }
       lds_barrier();
-      if constexpr (sizeof(T) == sizeof(double)) {
+      {
         // P = H_xx - Y^T Y: one matrix-core product with K = NU
-        const double yv = L.Y[kq * NX + (r16 < NX ? r16 : 0)];
-        const double y = r16 < NX ? yv : 0.0;
-        dbl4 p;
+        const T yv = L.Y[kq * NX + (r16 < NX ? r16 : 0)];
+        const T y = r16 < NX ? yv : T(0);
+        typename Mma<T>::acc p;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = 4 * r + kq;
-          const double hv = L.H[(i < NX ? i : 0) * NZ + (r16 < NX ? r16 : 0)];
-          p[r] = (i < NX && r16 < NX) ? hv : 0.0;
+          const int i = Mma<T>::row(r, kq);
+          const T hv = L.H[(i < NX ? i : 0) * NZ + (r16 < NX ? r16 : 0)];
+          p[r] = (i < NX && r16 < NX) ? hv : T(0);
         }
-        p = mfma64(-y, y, p);
+        p = Mma<T>::mma(-y, y, p);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = 4 * r + kq;
+          const int i = Mma<T>::row(r, kq);
           if (i < NX && r16 < NX) L.P[i * NX + r16] = p[r];
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < TILE_P; ++t) {
-          const int q = lane + WAVE * t, i = q / NX, j = q % NX;
-          T acc = L.H[i * NZ + j];
-#pragma unroll
-          for (int a = 0; a < NU; ++a) acc -= L.Y[a * NX + i] * L.Y[a * NX + j];
-          L.P[q] = acc;
         }
       }
     } else {
@@ -683,46 +670,32 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       }
       lds_barrier();
       // S = P - V^T V and M = Delta^{-1/2} C^{-1} Delta^{1/2}, C^{-1} = L_C^{-T} L_C^{-1}
-      if constexpr (sizeof(T) == sizeof(double)) {
+      {
         // both Gram products on the matrix cores (K = 13 padded to 16)
         const int jc = r16 < NX ? r16 : 0;
-        dbl4 sa, ma = {0.0, 0.0, 0.0, 0.0};
+        typename Mma<T>::acc sa, ma = {T(0), T(0), T(0), T(0)};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = 4 * r + kq;
-          const double pv = L.P[(i < NX ? i : 0) * NX + jc];
-          sa[r] = (i < NX && r16 < NX) ? pv : 0.0;
+          const int i = Mma<T>::row(r, kq);
+          const T pv = L.P[(i < NX ? i : 0) * NX + jc];
+          sa[r] = (i < NX && r16 < NX) ? pv : T(0);
         }
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const int l = 4 * st + kq, lc = l < NX ? l : 0;
           const bool ok = l < NX && r16 < NX;
-          const double vv = VV[lc * NX + jc], li = L.LI[lc * NX + jc];
-          const double v = ok ? vv : 0.0, w = ok ? li : 0.0;
-          sa = mfma64(-v, v, sa);
-          ma = mfma64(w, w, ma);
+          const T vv = VV[lc * NX + jc], li = L.LI[lc * NX + jc];
+          const T v = ok ? vv : T(0), w = ok ? li : T(0);
+          sa = Mma<T>::mma(-v, v, sa);
+          ma = Mma<T>::mma(w, w, ma);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = 4 * r + kq;
+          const int i = Mma<T>::row(r, kq);
           if (i < NX && r16 < NX) {
             L.S[i * NX + r16] = sa[r];
             fr[FR_M + i * NX + r16] = ma[r] * L.dh[r16] * L.rdh[i];
           }
-        }
-      } else {
-#pragma unroll
-        for (int t = 0; t < TILE_P; ++t) {
-          const int q = lane + WAVE * t, i = q / NX, j = q % NX;
-          T acc = L.P[q];
-#pragma unroll
-          for (int l = 0; l < NX; ++l) acc -= VV[l * NX + i] * VV[l * NX + j];
-          L.S[q] = acc;
-          const int qi = q < NX * NX ? i : 0;
-          T ci = 0.0;
-#pragma unroll
-          for (int l = 0; l < NX; ++l) ci += L.LI[l * NX + qi] * L.LI[l * NX + j];
-          if (q < NX * NX) fr[FR_M + q] = ci * L.dh[j] * L.rdh[qi];
         }
       }
     } else {
