@@ -5,6 +5,6 @@
 namespace hipipm {
 void launch_iter_mixed(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                        Counters* cnt, int refill, hipStream_t st) {
-  hipLaunchKernelGGL(k_iter<true>, dim3(slots), dim3(WAVE), sol_bytes(c), st, c, ws, theta, warm, out, cnt, refill);
+  hipLaunchKernelGGL(k_iter<true>, dim3(slots), dim3(WAVE), pass_lds_bytes(c), st, c, ws, theta, warm, out, cnt, refill);
 }
 }  // namespace hipipm

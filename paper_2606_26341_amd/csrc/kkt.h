@@ -146,9 +146,11 @@ __device__ __forceinline__ int wor(int v) {
 // loads (ld, which must not store) are all issued first, from a clamped index so that every
 // lane loads a valid word without a branch, then use(i, value) runs for each trip in order.
 // Results, and the order of every accumulation, are those of the plain loop.
-template <int LB = 4, class Ld, class Use>
+template <int LB0 = 0, class Ld, class Use>
 __device__ __forceinline__ void lanes_for(int n, int lane, Ld ld, Use use) {
   using V = decltype(ld(0));
+  constexpr int K = (int)(sizeof(V) / sizeof(double));
+  constexpr int LB = LB0 > 0 ? LB0 : (K >= 32 ? 1 : (32 / K > 4 ? 4 : 32 / K));
   for (int b = lane; b < n; b += LB * WAVE) {
     V v[LB];
 #pragma unroll

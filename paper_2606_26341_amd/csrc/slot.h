@@ -21,6 +21,14 @@ namespace hipipm {
 // ============================================================================ per-slot helpers
 __device__ __forceinline__ double fdiv_safe(double a, double b) { return a / b; }
 
+// The same value, opaque to the optimiser.  A loop body that takes its lane index through this
+// computes everything derived from the index inside the body, instead of having it hoisted out
+// of the loop and kept live (in registers) across all of the loop.
+__device__ __forceinline__ int opaque(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // -c at the current point into rc (restoration: -(c - p + n))
 __device__ __forceinline__ void eval_c(const Cfg& c, const Slot& s, bool resto, int lane) {
   const int N = c.N, NI = c.NI;
@@ -999,42 +1007,47 @@ __device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L,
   const int work = (int)s.sc[SC_WORK];
   if (work == W_NONE) return;
   bool f32 = mixed && c.prec == 1 && s.sc[SC_FORCE64] == 0.0;
-  if (work == W_LSQ) {
-    Elim e{true, false, 0.0, 0.0, 0.0};
-    const int st = factor_any(c, s, e, L, f32, lane);
-    if (lane == 0) { s.sc[SC_FSTAT] = st; s.sc[SC_FPREC] = f32 ? 1.0 : 0.0; }
-    __syncthreads();
-    return;
-  }
-  const bool resto = (int)s.sc[SC_PHASE] == PH_RESTO;
+  // the least-squares multiplier system (INIT_Y): one attempt, its status as the verdict
+  const bool lsq = work == W_LSQ;
+  const bool resto = !lsq && (int)s.sc[SC_PHASE] == PH_RESTO;
   double* sub = s.sc + (resto ? SC_RMU : SC_MU);
   const double mu = sub[0];
   // an FP64 redo of this iteration's factorization starts from the same delta_x^last
   const double dxl = (s.sc[SC_FORCE64] != 0.0) ? s.sc[SC_DXLSAVE] : sub[2];
-  Elim e{false, resto, 0.0, 0.0, resto ? sqrt(mu) : 0.0};
-  int st = factor_any(c, s, e, L, f32, lane);
-  int nfact = 1;
-  if (f32 && st != 0) {
-    // the inertia-correction decisions are FP64 ones: an FP32 verdict of wrong inertia, or a
-    // pivot too close to zero for FP32 to tell its sign (status 3), is taken again in FP64, and
-    // the rest of this iteration's correction runs in FP64
-    f32 = false;
-    st = factor_any(c, s, e, L, false, lane);
+  Elim e{lsq, resto, 0.0, 0.0, resto ? sqrt(mu) : 0.0};
+  // one factorization call site (one inlined copy of the factor): the first attempt, the FP64
+  // retake of an FP32 verdict, then the corrections
+  int nfact = 0, st = 0;
+  bool ok = false, corr = false;
+  const int lane0 = lane;
+  for (;;) {
+    const int lane = opaque(lane0);
+    st = factor_any(c, s, e, L, f32, lane);
     ++nfact;
-    if (lane == 0) s.sc[SC_ST_RTK] += 1.0;
-  }
-  bool ok = (st == 0);
-  if (!ok) {
-    if (st == 2) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
-    e.dxp = (dxl == 0.0) ? c.delta_0 : fmax(c.delta_min, c.kappa_minus * dxl);
-    for (;;) {
-      st = factor_any(c, s, e, L, f32, lane);
-      ++nfact;
-      if (st == 0) { ok = true; break; }
-      if (st == 2 && e.dcp == 0.0) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
-      e.dxp *= (dxl == 0.0) ? c.kappa_plus_bar : c.kappa_plus;
-      if (e.dxp > c.delta_max) break;
+    if (lsq) break;
+    if (st == 0) { ok = true; break; }
+    if (f32) {
+      // the inertia-correction decisions are FP64 ones: an FP32 verdict of wrong inertia, or a
+      // pivot too close to zero for FP32 to tell its sign (status 3), is taken again in FP64, and
+      // the rest of this iteration's correction runs in FP64
+      f32 = false;
+      if (lane == 0) s.sc[SC_ST_RTK] += 1.0;
+      continue;
     }
+    if (!corr) {
+      corr = true;
+      if (st == 2) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
+      e.dxp = (dxl == 0.0) ? c.delta_0 : fmax(c.delta_min, c.kappa_minus * dxl);
+      continue;
+    }
+    if (st == 2 && e.dcp == 0.0) e.dcp = c.delta_c_bar * pow(mu, c.kappa_c);
+    e.dxp *= (dxl == 0.0) ? c.kappa_plus_bar : c.kappa_plus;
+    if (e.dxp > c.delta_max) break;
+  }
+  if (lsq) {
+    if (lane == 0) { s.sc[SC_FSTAT] = st; s.sc[SC_FPREC] = f32 ? 1.0 : 0.0; }
+    __syncthreads();
+    return;
   }
   __syncthreads();
   if (lane == 0) {
@@ -1060,7 +1073,7 @@ __device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, const do
   Elim e{true, false, 0.0, 0.0, 0.0};
   bool fok = s.sc[SC_FSTAT] == 0.0;
   if (fok) fok = solve_refined(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, sol_dyn, mixed, lane);
-  if (!fok && L && s.sc[SC_FPREC] != 0.0) {
+  if (mixed && !fok && L && s.sc[SC_FPREC] != 0.0) {
     // FP32 refinement failed: the least-squares system again in FP64
     if (lane == 0) { s.sc[SC_FORCE64] = 1.0; s.sc[SC_ST_FB] += 1.0; }
     __syncthreads();
@@ -1569,7 +1582,9 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
         amin = c.gamma_alpha * c.gamma_theta;
       }
       double alpha = amax;
+      const int lane0 = lane;
       for (int l = 0;; ++l) {
+        const int lane = opaque(lane0);
         // alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point)
         if (alpha < amin || l >= 60) {
           try_soft = use_soft;          // the line search failed: soft restoration, if enabled
@@ -1594,6 +1609,7 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
           __syncthreads();
           Elim e{false, resto, s.sc[SC_LDX], s.sc[SC_LDC], zeta};
           for (int p = 0; p < c.max_soc; ++p) {
+            const int lane = opaque(lane0);
             if (p > 0 && !(tht <= c.kappa_soc * th_old)) break;
             th_old = tht;
             lanes_for(c.m, lane, [&](int r) { return DV<2>{{s.csoc[r], s.ct[r]}}; }, [&](int r, const DV<2>& t) {
@@ -1743,6 +1759,12 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
 }
 
 __host__ __device__ __forceinline__ size_t sol_bytes(const Cfg& c) { return (size_t)sol_lds_doubles(c.N) * sizeof(double); }
+// The fused kernels' one dynamic LDS region: the factorization's workspace and the solve's, which
+// no phase uses at the same time (the factor records go to the slot record, not LDS).
+__host__ __device__ __forceinline__ size_t pass_lds_bytes(const Cfg& c) {
+  const size_t f = sizeof(FacLds), v = sol_bytes(c);
+  return f > v ? f : v;
+}
 
 // The four per-slot phases of one pass back to back, with the shader-clock cycles of each added to
 // the slot's counters (the fused and asynchronous-slot kernels).
@@ -1808,8 +1830,8 @@ __device__ __forceinline__ void eval_slot(const Cfg& c, const Slot& s, int lane)
 template <bool MIXED>
 __global__ __launch_bounds__(64) void k_run(Cfg c0, double* ws, const double* theta, const double* warm, Outs out,
                                             Counters* cnt, int passes) {
-  __shared__ FacLds L;
   HIP_DYNAMIC_SHARED(double, sol_dyn)
+  FacLds& L = *reinterpret_cast<FacLds*>(sol_dyn);
 #pragma nounroll
   for (int p = 0; p < passes; ++p) {
     // the slot's addresses are rebuilt every pass from an index the compiler cannot see through,
@@ -1838,8 +1860,8 @@ __global__ __launch_bounds__(64) void k_run(Cfg c0, double* ws, const double* th
 template <bool MIXED>
 __global__ __launch_bounds__(64) void k_iter(Cfg c, double* ws, const double* theta, const double* warm, Outs out,
                                              Counters* cnt, int refill) {
-  __shared__ FacLds L;
   HIP_DYNAMIC_SHARED(double, sol_dyn)
+  FacLds& L = *reinterpret_cast<FacLds*>(sol_dyn);
   const int lane = threadIdx.x;
   const Slot s = make_slot(c, ws, blockIdx.x);
   if ((int)s.sc[SC_PHASE] == PH_EMPTY) return;
