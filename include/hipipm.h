@@ -130,6 +130,14 @@ typedef struct {
                              launch per pass, every slot advancing one pass per launch.  Results are
                              the same either way; best with slots = the number of resident
                              workgroups (one per SIMD) */
+    int32_t nested_resto; /* nested hard restoration (Table I row 6): when the restoration phase cannot
+                             make progress (its line search or inertia correction fails) at a point
+                             where its own constraints c(x) - p + n = 0 are violated by more than tol,
+                             restore them -- at fixed x, p and n take the closed form that starts the
+                             restoration phase, at its current mu -- and continue restoring; 1
+                             (default) on, 0: the restoration fails there (status RESTO_FAILED) */
+    int32_t resto_ls_max; /* most backtracking halvings of a restoration-phase line search (default 60,
+                             as in the main phase; 0: a rejected full step fails at once) */
 } hipipm_options;
 
 typedef struct {
@@ -154,6 +162,7 @@ typedef struct {
     int64_t soft_resto_steps;        /* accepted soft-restoration steps */
     int64_t soft_resto_fails;        /* soft restorations that ended in hard restoration */
     int64_t mu_fallbacks;            /* adaptive barrier update: switches to the monotone mode */
+    int64_t nested_restorations;     /* nested restorations of the restoration phase */
     int64_t cycles_eval, cycles_pre, cycles_factor, cycles_solve, cycles_linesearch;
                                      /* shader-clock cycles summed over slots in the derivatives (asynchronous
                                         slots only) and the four phases of the fused kernels */

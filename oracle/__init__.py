@@ -20,7 +20,7 @@ _SRC = ["bk.c", "quad.c", "ipm.c"]
 
 PH_INIT_Y, PH_REGULAR, PH_RESTO, PH_DONE = 0, 1, 2, 3
 ST_RUNNING, ST_CONVERGED, ST_MAX_ITER, ST_RESTO_FAILED, ST_INFEASIBLE, ST_NUMERICAL = range(6)
-NSTAT = 16   # per-instance counters of solve_quad (see ipmo_solve_quad)
+NSTAT = 17   # per-instance counters of solve_quad (see ipmo_solve_quad)
 
 
 def build() -> str:
@@ -45,6 +45,7 @@ class Opts(C.Structure):
         ("warm_mu0", C.c_double), ("warm_push", C.c_double), ("warm_iter_cap", C.c_int32),
         ("warm_gate", C.c_int32), ("watchdog_trigger", C.c_int32), ("watchdog_max", C.c_int32),
         ("soft_resto_max", C.c_int32), ("soft_resto_factor", C.c_double), ("mu_strategy", C.c_int32),
+        ("nested_resto", C.c_int32), ("resto_ls_max", C.c_int32),
     ]
 
 

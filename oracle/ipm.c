@@ -103,6 +103,7 @@ typedef struct solver_s {
      * MU_REFS scaled KKT errors E_0 that the free mode must improve on, how many are held, the
      * barrier-parameter ceiling, switches to the monotone mode */
     int mu_free, n_refs, st_mu_fallbacks;
+    int st_nested;                      /* nested restorations of the restoration phase */
     double refs[4], mu_max;
     double *sf_y, *sf_zl, *sf_zu, *sf_g, *sf_J;
     double last_dx, last_dc, last_alpha, last_alpha_z;
@@ -654,8 +655,9 @@ static int core_iter(solver_t* S, const nlp_t* P, sub_t* T, int is_resto) {
         double amin = alpha_min(o, thk, gphi, T->theta_min);
         double alpha = amax;
         for (int l = 0;; ++l) {
-            /* alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point) */
-            if (alpha < amin || l >= 60) {
+            /* alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point; the
+             * restoration phase takes at most resto_ls_max) */
+            if (alpha < amin || l >= (is_resto ? o->resto_ls_max : 60)) {
                 if (!use_soft) return R_LSFAIL;
                 try_soft = 1;
                 break;
@@ -962,6 +964,45 @@ static int resto_enter(solver_t* S) {
     return 0;
 }
 
+/* Nested hard restoration (Table I row 6): the restoration phase cannot make progress at
+ * (x, p, n).  Its own restoration problem -- minimise the violation of c(x) - p + n = 0 -- is
+ * solved at once: the elastic pair (p, n) is free in it and enters that constraint linearly, so
+ * its minimiser keeps x and takes, for every row, the (p, n) that minimises rho (p + n) -
+ * mu (ln p + ln n) subject to c(x) - p + n = 0 (the closed form that starts the restoration phase,
+ * at the restoration phase's current mu), with z_p = mu / p, z_n = mu / n.  The failing point enters
+ * the restoration filter, as an iterate does when it leaves for restoration.  Counts as a
+ * restoration iteration.  Returns 0 (nothing done) when the restoration constraints already hold
+ * within tol, i.e. when restoring them cannot help. */
+static int nested_resto(solver_t* S) {
+    const ipmo_opts* o = &S->o;
+    nlp_t* P = S->P;
+    sub_t* R = &S->rs;
+    int n = P->n, m = P->m;
+    double fR;
+    S->RP.c(S->RP.ud, R->x, S->ct);
+    S->RP.f(S->RP.ud, R->x, &fR);
+    double th = nrm1(m, S->ct);
+    double ph = barrier_obj(&S->RP, R->x, fR, R->mu);
+    if (!(th > o->tol)) return 0;
+    filter_add(R, (1.0 - o->gamma_theta) * th, ph - o->gamma_phi * th);
+    P->c(P->ud, R->x, S->c);
+    double mu = R->mu, rho = o->rho_resto;
+    for (int r = 0; r < m; ++r) {
+        double c = S->c[r];
+        double a = (mu - rho * c) / (2.0 * rho);
+        double nn = a + sqrt(a * a + mu * c / (2.0 * rho));
+        double pp = c + nn;
+        R->x[n + r] = pp;
+        R->x[n + m + r] = nn;
+        R->zl[n + r] = mu / pp;
+        R->zl[n + m + r] = mu / nn;
+    }
+    S->iter++;
+    S->st_resto_iter++;
+    S->st_nested++;
+    return 1;
+}
+
 /* after an accepted restoration step: return to the original problem when the point is
  * acceptable to the original filter and theta <= kappa_resto theta(x_R) */
 static int resto_try_exit(solver_t* S) {
@@ -1033,7 +1074,9 @@ static void solver_pass(solver_t* S) {
         case R_CONVERGED: S->status = ST_INFEASIBLE; S->phase = PH_DONE; return;
         case R_MAXITER: S->status = ST_MAX_ITER; S->phase = PH_DONE; return;
         case R_NUMERICAL: S->status = ST_NUMERICAL; S->phase = PH_DONE; return;
-        default: S->status = ST_RESTO_FAILED; S->phase = PH_DONE; return;
+        default:
+            if (S->o.nested_resto && nested_resto(S)) return;
+            S->status = ST_RESTO_FAILED; S->phase = PH_DONE; return;
         }
     }
 }
@@ -1179,6 +1222,8 @@ void ipmo_default_opts(ipmo_opts* o) {
     o->watchdog_trigger = 0; o->watchdog_max = 3;
     o->soft_resto_max = 0; o->soft_resto_factor = 0.9999;
     o->mu_strategy = 0;
+    o->nested_resto = 1;
+    o->resto_ls_max = 60;
 }
 
 int ipmo_sizeof_opts(void) { return (int)sizeof(ipmo_opts); }
@@ -1196,7 +1241,7 @@ typedef struct {
     double* x; double* y; double* zl; double* zu; double* obj; double* kkt; int32_t* status; int32_t* iters;
     int32_t* stats; /* NSTAT ints per instance */
 } outs_t;
-#define NSTAT 16
+#define NSTAT 17
 
 static void write_outputs(solver_t* S, int idx, const outs_t* O) {
     nlp_t* P = S->P;
@@ -1220,6 +1265,7 @@ static void write_outputs(solver_t* S, int idx, const outs_t* O) {
         s[8] = S->st_warm_started; s[9] = S->st_warm_rejected; s[10] = S->st_warm_restarts;
         s[11] = S->st_wd_starts; s[12] = S->st_wd_reverts; s[13] = S->st_soft_steps; s[14] = S->st_soft_fails;
         s[15] = S->st_mu_fallbacks;
+        s[16] = S->st_nested;
     }
 }
 

@@ -75,6 +75,11 @@ typedef struct {
     double soft_resto_factor;                      /* 0.9999 */
     /* barrier update (Table I row 7): 0 monotone, 1 adaptive (free mode, monotone fallback) */
     int32_t mu_strategy;                           /* 0 */
+    /* nested hard restoration (Table I row 6): when the restoration phase cannot make progress,
+     * restore its own constraints (1) or fail (0); most backtracking halvings of a restoration
+     * line search (the main phase allows 60) */
+    int32_t nested_resto;                          /* 1 */
+    int32_t resto_ls_max;                          /* 60 */
 } ipmo_opts;
 
 /* ---------------- quadrotor NMPC problem family ---------------- */

@@ -154,6 +154,7 @@ int hipipm_default_options(hipipm_options* o) {
   o->watchdog_trigger = 0; o->watchdog_max = 3;
   o->soft_resto_max = 0; o->soft_resto_factor = 0.9999;
   o->mu_strategy = 0; o->async_passes = 0;
+  o->nested_resto = 1; o->resto_ls_max = 60;
   return HIPIPM_OK;
 }
 
@@ -171,7 +172,7 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
       !(o->warm_mu0 > 0) || !(o->warm_push > 0) || o->warm_iter_cap < 0 || o->warm_gate < 0 || o->warm_gate > 1 ||
       o->watchdog_trigger < 0 || o->watchdog_max < 1 || o->soft_resto_max < 0 ||
       !(o->soft_resto_factor > 0 && o->soft_resto_factor <= 1) || o->mu_strategy < 0 || o->mu_strategy > 1 ||
-      o->async_passes < 0)
+      o->async_passes < 0 || o->nested_resto < 0 || o->nested_resto > 1 || o->resto_ls_max < 0)
     return HIPIPM_ERR_INVALID_ARG;
   hipipm_ctx* c = new hipipm_ctx();
   c->desc = *d;
@@ -212,6 +213,7 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
   g.wd_trigger = o->watchdog_trigger; g.wd_max = o->watchdog_max;
   g.soft_max = o->soft_resto_max; g.soft_factor = o->soft_resto_factor;
   g.mu_strategy = o->mu_strategy; g.async_passes = o->async_passes;
+  g.nested_resto = o->nested_resto; g.resto_ls_max = o->resto_ls_max;
   layout(g);
   size_t rec = (size_t)g.stride * sizeof(double) * (size_t)slots;
   c->cnt_off = (rec + 255) / 256 * 256;
@@ -273,6 +275,7 @@ static void add_stats(hipipm_ctx* c, const Counters& h, long long passes) {
   c->stats.soft_resto_steps += (int64_t)h.st[20];
   c->stats.soft_resto_fails += (int64_t)h.st[21];
   c->stats.mu_fallbacks += (int64_t)h.st[22];
+  c->stats.nested_restorations += (int64_t)h.st[28];
   c->stats.cycles_eval += (int64_t)h.st[23];
   c->stats.cycles_pre += (int64_t)h.st[24];
   c->stats.cycles_factor += (int64_t)h.st[25];

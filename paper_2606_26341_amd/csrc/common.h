@@ -49,6 +49,7 @@ enum : int {
   // shader-clock cycles this slot spent in the derivatives (asynchronous-slot kernel) and in the
   // four phases of the fused kernels
   SC_CYC_EVAL, SC_CYC_PRE, SC_CYC_FAC, SC_CYC_SOL, SC_CYC_LS,
+  SC_ST_NEST,   // nested restorations of the restoration phase
   SC_LEN = 96
 };
 
@@ -78,7 +79,8 @@ struct Cfg {
   int soft_max; double soft_factor;          // soft restoration: steps before hard restoration (0: off),
                                              // required primal-dual error reduction
   int mu_strategy;                           // 0 monotone, 1 adaptive with monotone fallback
-  int async_passes;                          // > 0: asynchronous slots, passes per launch
+  int async_passes;
+  int nested_resto, resto_ls_max;            // nested restoration on/off; restoration backtracking cap                          // > 0: asynchronous slots, passes per launch
   // slot record layout, offsets in doubles
   long long stride;
   int o_v, o_y, o_zlu, o_zuu, o_zls, o_th, o_sc, o_fm, o_fr;
@@ -99,7 +101,7 @@ struct Outs {
 };
 
 // global counters (device): queue head, finished count, stats
-constexpr int N_STATS = 28;
+constexpr int N_STATS = 29;
 struct Counters {
   int32_t head, done, n_inst, pad;
   unsigned long long st[N_STATS];

@@ -421,6 +421,7 @@ __device__ __forceinline__ bool kept_on_restart(int q) {
   return q == SC_ITER || (q >= SC_ST_RESTO && q <= SC_ST_PASS) || q == SC_ST_SOLV || q == SC_ST_FFACT ||
          q == SC_ST_FSOLV || q == SC_ST_REF || q == SC_ST_FB || q == SC_ST_WSTART || q == SC_ST_RTK ||
          q == SC_ST_WDS || q == SC_ST_WDR || q == SC_ST_SOFTS || q == SC_ST_SOFTF || q == SC_ST_MUFB ||
+         q == SC_ST_NEST ||
          (q >= SC_CYC_EVAL && q <= SC_CYC_LS);
 }
 
@@ -573,6 +574,7 @@ __device__ __forceinline__ void finish_slot(const Cfg& c, const Slot& s, const d
       atomicAdd(&cnt->st[22], (unsigned long long)s.sc[SC_ST_MUFB]);
 #pragma unroll
       for (int q = 0; q < 5; ++q) atomicAdd(&cnt->st[23 + q], (unsigned long long)s.sc[SC_CYC_EVAL + q]);
+      atomicAdd(&cnt->st[28], (unsigned long long)s.sc[SC_ST_NEST]);
       atomicAdd(&cnt->done, 1);
       next = refill ? atomicAdd(&cnt->head, 1) : INT_MAX;
     } else {
@@ -1324,6 +1326,42 @@ __device__ __forceinline__ bool resto_enter(const Cfg& c, const Slot& s, int lan
   return true;
 }
 
+// Nested hard restoration (Table I row 6): the restoration phase cannot make progress at
+// (x, p, n).  Its own restoration problem -- minimise the violation of c(x) - p + n = 0 -- has
+// (p, n) free and entering that constraint linearly, so its minimiser keeps x and takes, row by
+// row, the (p, n) that minimises rho (p + n) - mu (ln p + ln n) subject to c(x) - p + n = 0 (the
+// closed form that starts the restoration phase, at the restoration phase's current mu), with
+// z_p = mu / p, z_n = mu / n.  The failing point enters the restoration filter, as an iterate
+// does when it leaves for restoration.  Counts as a restoration iteration.  false (nothing done)
+// when the restoration constraints already hold within tol, where restoring them cannot help.
+__device__ __forceinline__ bool nested_resto(const Cfg& c, const Slot& s, const Iter& it, int lane) {
+  const double thk = s.sc[SC_THK], phk = s.sc[SC_PHK];
+  if (!(thk > c.tol)) return false;
+  double* sub = it.sub;
+  const int nf = filter_add(c, it.filt, (int)sub[6], (1.0 - c.gamma_theta) * thk, phk - c.gamma_phi * thk, lane);
+  eval_c(c, s, false, lane);   // rc = -c(x)
+  const double mu = sub[0], rho = c.rho_resto;
+  for (int r = lane; r < c.m; r += WAVE) {
+    double cv = -s.rc[r];
+    double a = (mu - rho * cv) / (2.0 * rho);
+    double nn = a + sqrt(a * a + mu * cv / (2.0 * rho));
+    double pp = cv + nn;
+    s.p[r] = pp;
+    s.nn[r] = nn;
+    s.zp[r] = mu / pp;
+    s.zn[r] = mu / nn;
+  }
+  __syncthreads();
+  if (lane == 0) {
+    sub[6] = nf;
+    s.sc[SC_ITER] += 1.0;
+    s.sc[SC_ST_RESTO] += 1.0;
+    s.sc[SC_ST_NEST] += 1.0;
+  }
+  __syncthreads();
+  return true;
+}
+
 // after an accepted restoration step: return to the original problem if possible
 __device__ __forceinline__ void resto_try_exit(const Cfg& c, const Slot& s, int lane) {
   // original constraints and barrier objective at v (main mu)
@@ -1585,8 +1623,9 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
       const int lane0 = lane;
       for (int l = 0;; ++l) {
         const int lane = opaque(lane0);
-        // alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point)
-        if (alpha < amin || l >= 60) {
+        // alpha_min, or 60 halvings (alpha_min is 0 at an exactly feasible point; the restoration
+        // phase takes at most resto_ls_max)
+        if (alpha < amin || l >= (resto ? c.resto_ls_max : 60)) {
           try_soft = use_soft;          // the line search failed: soft restoration, if enabled
           break;
         }
@@ -1692,7 +1731,7 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
     if (!resto) {
       if (!resto_enter(c, s, lane))
         if (lane == 0) { s.sc[SC_STATUS] = ST_RESTO_FAILED; s.sc[SC_PHASE] = PH_FINISH; }
-    } else {
+    } else if (!(c.nested_resto && nested_resto(c, s, it, lane))) {
       for (int i = lane; i < c.n; i += WAVE) s.v[i] = s.xr[i];
       if (lane == 0) { s.sc[SC_STATUS] = ST_RESTO_FAILED; s.sc[SC_PHASE] = PH_FINISH; }
     }

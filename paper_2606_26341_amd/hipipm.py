@@ -43,7 +43,8 @@ class Options(C.Structure):
         ("refine_tol", C.c_double), ("warm_mu0", C.c_double), ("warm_push", C.c_double),
         ("warm_iter_cap", C.c_int32), ("warm_gate", C.c_int32), ("watchdog_trigger", C.c_int32),
         ("watchdog_max", C.c_int32), ("soft_resto_max", C.c_int32), ("soft_resto_factor", C.c_double),
-        ("mu_strategy", C.c_int32), ("async_passes", C.c_int32),
+        ("mu_strategy", C.c_int32), ("async_passes", C.c_int32), ("nested_resto", C.c_int32),
+        ("resto_ls_max", C.c_int32),
     ]
 
 
@@ -59,7 +60,7 @@ class Stats(C.Structure):
                                          "fused_solves", "refine_sweeps", "fp64_fallbacks", "warm_started",
                                          "warm_rejected", "warm_restarts", "fp32_retakes", "watchdog_starts",
                                          "watchdog_reverts", "soft_resto_steps", "soft_resto_fails",
-                                         "mu_fallbacks", "cycles_eval", "cycles_pre", "cycles_factor",
+                                         "mu_fallbacks", "nested_restorations", "cycles_eval", "cycles_pre", "cycles_factor",
                                          "cycles_solve", "cycles_linesearch")]
 
 

@@ -481,3 +481,45 @@ def test_edge_cases(torch_cuda):
     # workspace must be bound before solving; bad shapes are rejected by the binding
     with pytest.raises(AssertionError):
         s.solve(torch.zeros((2, w.n_theta + 1), dtype=torch.float64, device="cuda"))
+
+
+# ------------------------------------------------------------------------ nested restoration
+def _perturbed_restoration_pair(w, th, scale, oopts):
+    """(state, oracle's next state): the first restoration iterate of `th` with the elastic p of
+    every row scaled by `scale`, then one oracle pass under `oopts`."""
+    h = oracle.Handle.quad(w, th)
+    for _ in range(400):
+        if h.phase == oracle.PH_RESTO:
+            break
+        h.step()
+    assert h.phase == oracle.PH_RESTO
+    s = h.state()
+    n, m = w.n, w.m
+    F = (len(s) - 16 - (8 + 3 * n + m) - (8 + 3 * (n + 2 * m) + m) - 2 * n - (8 + 3 * n + m) - 4 - 8) // 4
+    p_rs = 16 + (8 + 3 * n + m + 2 * F) + 8          # the restoration iterate: x, p, n
+    s[p_rs + n:p_rs + n + m] *= scale
+    h2 = oracle.Handle.quad(w, th, opts=oopts)
+    h2.set_state(s)
+    h2.step()
+    return s, h2.state()
+
+
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("scale", [1.5, 1.0])
+def test_nested_restoration_replay_matches_oracle(torch_cuda, fused, scale):
+    # a restoration pass that cannot move (resto_ls_max = 0) at a point where c(x) - p + n = 0 is
+    # violated (p scaled by 1.5): the nested restoration re-solves (p, n) in closed form and the
+    # restoration continues; at the restoration's starting point (scale 1) the restoration fails
+    w = W.get("C1")
+    th = start_inside_sphere(w)
+    oopts = oracle.default_opts(resto_ls_max=0)
+    cur, nxt = _perturbed_restoration_pair(w, th, scale, oopts)
+    a, b = oracle.unpack_state(cur, w.n, w.m), oracle.unpack_state(nxt, w.n, w.m)
+    if scale != 1.0:
+        assert b["phase"] == oracle.PH_RESTO and b["iter"] == a["iter"] + 1
+        assert np.array_equal(b["resto"]["x"][:w.n], a["resto"]["x"][:w.n])
+    else:
+        assert b["status"] == oracle.ST_RESTO_FAILED
+    phases = _replay(torch_cuda, w, th, dict(resto_ls_max=0, fuse_below=(1 << 30) if fused else 0),
+                     oopts=oopts, states=[cur, nxt])
+    assert phases == [oracle.PH_RESTO]

@@ -837,3 +837,78 @@ def test_adaptive_mu_falls_back_to_monotone_without_progress():
     h3.set_state(s3)
     h3.step()
     assert oracle.unpack_state(h3.state(), n, m)["adaptive"]["free"] == 1
+
+
+# ------------------------------------------------------------------------ nested restoration
+def _cubic_resto(**opts):
+    # c(x) = x^3 - 2 x + 2 from x = 0.8 (near the local minimum of |c|): the line search fails and
+    # the solve enters feasibility restoration
+    c = lambda x: np.array([x[0] ** 3 - 2 * x[0] + 2])
+    h = _generic(1, 1, [-INF], [INF], lambda x: 0.0 * x[0], lambda x: np.zeros(1), c,
+                 lambda x: np.array([[3 * x[0] ** 2 - 2]]), lambda x, of, y: np.array([[6 * x[0] * y[0]]]), [0.8],
+                 **opts)
+    return h, c
+
+
+def _restoration_state(p_scale):
+    """State of the cubic problem in its first restoration iterate, with the elastic p scaled by
+    p_scale (so that c(x) - p + n = 0 no longer holds when p_scale != 1)."""
+    h, c = _cubic_resto()
+    for _ in range(100):
+        if h.phase == oracle.PH_RESTO:
+            break
+        h.step()
+    assert h.phase == oracle.PH_RESTO
+    s = h.state()
+    n, m = 1, 1
+    F = (len(s) - 16 - (8 + 3 * n + m) - (8 + 3 * (n + 2 * m) + m) - 2 * n - (8 + 3 * n + m) - 4 - 8) // 4
+    p_rs = 16 + (8 + 3 * n + m + 2 * F) + 8          # the restoration iterate: x, p, n
+    s[p_rs + n] *= p_scale
+    return s, c
+
+
+def test_nested_restoration_restores_the_elastic_rows():
+    # The restoration pass cannot move (resto_ls_max = 0: its line search takes no trial point) at
+    # a point where c(x) - p + n != 0.  The nested restoration keeps x and y and re-solves the
+    # elastic pair in closed form: p - n = c(x), and (p, n) minimises rho (p + n) - mu (ln p + ln n)
+    # on that line (2 rho = mu / p + mu / n), z_p = mu / p, z_n = mu / n; the failing point's
+    # (theta, phi) enters the restoration filter with the usual margins; one restoration
+    # iteration is counted and the phase continues.
+    s, c = _restoration_state(1.5)
+    before = oracle.unpack_state(s, 1, 1)
+    h, _ = _cubic_resto(resto_ls_max=0)
+    h.set_state(s)
+    h.step()
+    after = oracle.unpack_state(h.state(), 1, 1)
+    assert after["phase"] == oracle.PH_RESTO and after["status"] == oracle.ST_RUNNING
+    assert after["iter"] == before["iter"] + 1
+    xb, pb, nb = before["resto"]["x"]
+    x, p, nn = after["resto"]["x"]
+    assert x == xb and np.array_equal(after["resto"]["y"], before["resto"]["y"])
+    cx = c([x])[0]
+    assert p > 0 and nn > 0
+    assert abs((p - nn) - cx) <= 1e-13 * max(1.0, abs(cx))
+    mu, rho = after["resto"]["mu"], 1000.0
+    assert abs(mu / p + mu / nn - 2 * rho) <= 1e-10 * 2 * rho
+    assert abs(after["resto"]["zl"][1] - mu / p) <= 1e-15 * mu / p
+    assert abs(after["resto"]["zl"][2] - mu / nn) <= 1e-15 * mu / nn
+    th = abs(cx - pb + nb)
+    assert th > 1e-8
+    gth = (1.0 - 1e-5) * th
+    assert any(abs(t - gth) <= 1e-12 * gth for t in after["resto"]["fth"])
+    assert h.outputs()["stats"][16] == 1
+
+
+def test_nested_restoration_needs_a_violation_and_can_be_off():
+    # at the restoration's own starting point c(x) - p + n = 0 holds, so a restoration that cannot
+    # move there fails (RESTO_FAILED); with nested restoration off it fails at a violated point too
+    s, _ = _restoration_state(1.0)
+    h, _ = _cubic_resto(resto_ls_max=0)
+    h.set_state(s)
+    h.step()
+    assert h.status == oracle.ST_RESTO_FAILED and h.outputs()["stats"][16] == 0
+    s, _ = _restoration_state(1.5)
+    h, _ = _cubic_resto(resto_ls_max=0, nested_resto=0)
+    h.set_state(s)
+    h.step()
+    assert h.status == oracle.ST_RESTO_FAILED and h.outputs()["stats"][16] == 0
