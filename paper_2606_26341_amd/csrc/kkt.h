@@ -461,16 +461,32 @@ __device__ __forceinline__ int chol_rows(T (&c)[NX], T (&rinv)[NX], int lane) {
 // stage k inputs as one flat range: [W_k (k < N) | G_k (k < N) | stage data].  Every lane loads
 // from a valid address (lanes past the end re-read the last word) so that no load sits behind a
 // branch: the registers are consumed only by stage_park, where the wait for the loads lands.
+// Which range the t-th word of every lane falls in is known at compile time once the loop is
+// unrolled; only the groups of 64 words that straddle a boundary select an address per lane.
 __device__ __forceinline__ void stage_prefetch(const Cfg& c, const Slot& s, int k, int lane, double* reg) {
-  const int nW = (k < c.N) ? NZ * NZ : 0, nG = (k < c.N) ? NX * NZ : 0, nS = sd_len(c);
-  const double* W = s.HW + (long long)(k < c.N ? k : 0) * NZ * NZ;
-  const double* G = s.G + (long long)(k < c.N ? k : 0) * NX * NZ;
+  const int nS = sd_len(c);
   const double* D = s.sd + (long long)k * nS;
+  if (k < c.N) {
+    constexpr int EW = NZ * NZ, EG = NZ * NZ + NX * NZ;   // ends of the W_k and G_k words
+    const double* W = s.HW + (long long)k * NZ * NZ;
+    const double* G = s.G + (long long)k * NX * NZ;
 #pragma unroll
-  for (int t = 0; t < PF; ++t) {
-    const int q = lane + WAVE * t;
-    const double* a = (q < nW) ? W + q : (q < nW + nG) ? G + (q - nW) : D + min(q - nW - nG, nS - 1);
-    reg[t] = *a;
+    for (int t = 0; t < PF; ++t) {
+      const int q = lane + WAVE * t, lo = WAVE * t, hi = WAVE * t + WAVE;
+      if (hi <= EW) {
+        reg[t] = W[q];
+      } else if (lo >= EW && hi <= EG) {
+        reg[t] = G[q - EW];
+      } else if (lo >= EG) {
+        reg[t] = D[min(q - EG, nS - 1)];
+      } else {
+        const double* a = (q < EW) ? W + q : (q < EG) ? G + (q - EW) : D + min(q - EG, nS - 1);
+        reg[t] = *a;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < PF; ++t) reg[t] = D[min(lane + WAVE * t, nS - 1)];
   }
 }
 template <typename T>
@@ -799,8 +815,13 @@ __device__ __forceinline__ void sol_prefetch(const Cfg& c, const Slot& s, int kf
   const double* Gp = s.G + (long long)(hg ? kg : 0) * NX * NZ;
 #pragma unroll
   for (int t = 0; t < SPF; ++t) {
-    const int q = lane + WAVE * t;
-    if constexpr (sizeof(T) == sizeof(double)) {
+    // as in stage_prefetch, only the group that straddles the record's end selects per lane
+    const int q = lane + WAVE * t, lo = WAVE * t, hi = WAVE * t + WAVE;
+    if (hi <= FR_LEN) {
+      reg[t] = Fp[q];
+    } else if (lo >= FR_LEN) {
+      reg[t] = T(Gp[min(q - FR_LEN, NX * NZ - 1)]);
+    } else if constexpr (sizeof(T) == sizeof(double)) {
       const double* a = (q < FR_LEN) ? reinterpret_cast<const double*>(Fp) + q : Gp + min(q - FR_LEN, NX * NZ - 1);
       reg[t] = *a;
     } else {
