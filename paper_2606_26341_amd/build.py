@@ -18,8 +18,11 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in
 BUILD_DIR = os.path.join(HERE, "_build")
 # the asynchronous-slot kernel loops over whole passes: constants hoisted out of that loop would
 # stay live across all of it and spill, so machine-level loop-invariant code motion is off there
+# The FP32 + refinement pass kernel holds more small per-lane arrays than the backend's default
+# budget for keeping such arrays in registers; past the budget they would live in scratch memory.
 EXTRA = {"run_fp64.hip": ["-mllvm", "-disable-machine-licm"],
-         "run_mixed.hip": ["-mllvm", "-disable-machine-licm"]}
+         "run_mixed.hip": ["-mllvm", "-disable-machine-licm"],
+         "iter_mixed.hip": ["-mllvm", "-amdgpu-promote-alloca-to-vector-limit=2048"]}
 
 
 def hipcc() -> str:

@@ -162,6 +162,11 @@ __device__ __forceinline__ void lanes_for(int n, int lane, Ld ld, Use use) {
 }
 // inequality rows of one knot whose loads are issued together
 constexpr int OBS_CHUNK = 8;
+// a compile-time case of a stage body (the first and last knots of a sweep)
+template <bool B>
+struct Flag {
+  static constexpr bool value = B;
+};
 // the loaded values of one trip
 template <int K>
 struct DV {
@@ -510,18 +515,22 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
   lds_barrier();
   const T dx = e.lsq ? T(0) : T(e.dxp);
   int status = 0;
-  for (int k = N; k >= 0; --k) {
+  // one knot; the knots with a control (k < N) and with a predecessor (k > 0) are compile-time
+  // cases: knot N, knots N-1..1, knot 0.  Returns true when the factorization stops (status set).
+  auto knot = [&](int k, auto has_u_tag, auto more_tag) -> bool {
+    constexpr bool HAS_U = decltype(has_u_tag)::value, MORE = decltype(more_tag)::value;
+    double reg[PF];          // the next knot's inputs, in flight during this knot
     const T* B = L.buf;      // dead after the barrier that follows the dh read
     const T* Wk = B;
-    const T* Gk = B + ((k < N) ? NZ * NZ : 0);
-    const T* SD = B + ((k < N) ? NZ * NZ + NX * NZ : 0);
+    const T* Gk = B + (HAS_U ? NZ * NZ : 0);
+    const T* SD = B + (HAS_U ? NZ * NZ + NX * NZ : 0);
     T* fr = reinterpret_cast<T*>(s.fac) + (long long)k * FR_LEN;
-    if (k > 0) stage_prefetch(c, s, k - 1, lane, reg);   // in flight during this stage
+    if (MORE) stage_prefetch(c, s, k - 1, lane, reg);   // in flight during this stage
     // ---- Schur update, first half: T = S_{k+1} G_k (13 x 17) ----
     // columns 0..15 on the matrix cores (K = 13 padded to 16; one 16 x 16 x 4 product costs about
     // as much as eleven FMAs of a wavefront), column 16 on the vector ALUs, row i on lane i
     const int r16 = lane & 15, kq = lane >> 4, li0 = lane < NX ? lane : NX - 1;
-    if (k < N) {
+    if (HAS_U) {
       typename Mma<T>::acc t0 = {T(0), T(0), T(0), T(0)};
       T t16 = 0.0;
 #pragma unroll
@@ -544,9 +553,9 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     }
     // ---- stage Hessian (NZ stride): W_k + diag + delta_x I + Hc_k + G_k^T T ----
     auto h_base = [&](int i, int j) -> T {
-      T h = (!e.lsq && k < N) ? Wk[i * NZ + j] : T(0);
-      h += (i == j && (k < N || i < NX)) ? SD[j] + dx : T(0);
-      h += (k >= 1 && i < 3 && j < 3) ? SD[SD_HC + 3 * (i < 3 ? i : 0) + (j < 3 ? j : 0)] : T(0);
+      T h = (!e.lsq && HAS_U) ? Wk[i * NZ + j] : T(0);
+      h += (i == j && (HAS_U || i < NX)) ? SD[j] + dx : T(0);
+      h += (MORE && i < 3 && j < 3) ? SD[SD_HC + 3 * (i < 3 ? i : 0) + (j < 3 ? j : 0)] : T(0);
       return h;
     };
     {
@@ -558,7 +567,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       for (int r = 0; r < 4; ++r) h00[r] = h_base(Mma<T>::row(r, kq), r16);
       const int ih = lane < NZ ? lane : NZ - 1;
       T h16 = h_base(ih, 16);
-      if (k < N) {
+      if (HAS_U) {
 #pragma unroll
         for (int l = 0; l < NX; ++l) h16 += Gk[l * NZ + ih] * L.CV[l * NZ + 16];
 #pragma unroll
@@ -578,7 +587,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     lds_barrier();
     // ---- control block: Cholesky of Hbar^uu (on every lane, in registers), Y, P ----
     const int li = lane < NX ? lane : NX - 1;
-    if (k < N) {
+    if (HAS_U) {
       T lr[NU * NU], rr[NU];
       int bad = 0;
 #pragma unroll
@@ -602,7 +611,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
           lr[i * NU + j] = a * rr[j];
         }
       }
-      if (bad) { status = bad; break; }
+      if (bad) { status = bad; return true; }
       {
         T v = 0.0, w = 0.0;
 #pragma unroll
@@ -663,7 +672,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
       for (int l = 0; l < NX; ++l) cr[l] = dhl * L.P[li * NX + l] * L.dh[l] + (lane == l ? 1.0 : 0.0);
       const int r = chol_rows(cr, ri, lane);
-      if (r) { status = r; break; }
+      if (r) { status = r; return true; }
       if (lane < NX) {
 #pragma unroll
         for (int l = 0; l < NX; ++l) LC[lane * NX + l] = (l <= lane) ? cr[l] : 0.0;
@@ -732,8 +741,15 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     }
     if (lane < NX) fr[FR_DH + lane] = dhl;
     if (lane == 0) fr[FR_FLAG] = pair ? 1.0 : 0.0;
-    if (k > 0) stage_park(L.buf, lane, reg);
+    if (MORE) stage_park(L.buf, lane, reg);
     lds_barrier();
+    return false;
+  };
+  if (!knot(N, Flag<false>{}, Flag<true>{})) {
+    int k = N - 1;
+    for (; k >= 1; --k)
+      if (knot(k, Flag<true>{}, Flag<true>{})) break;
+    if (k == 0) knot(0, Flag<true>{}, Flag<false>{});
   }
   __syncthreads();
   return status;
@@ -893,19 +909,22 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
   }
   sol_park(V.buf, lane, reg);
   lds_barrier();
-  // 2. backward sweep: rbar_k = r_k + G_k^T a_{k+1}
+  // 2. backward sweep: rbar_k = r_k + G_k^T a_{k+1}.  The knots with a control (k < N) and with a
+  //    predecessor (k > 0) are compile-time cases of the stage body: knot N, knots N-1..1, knot 0.
   const int li = lane < NX ? lane : NX - 1;
-  for (int k = N; k >= 0; --k) {
+  auto bwd = [&](int k, auto has_u_tag, auto more_tag) {
+    constexpr bool HAS_U = decltype(has_u_tag)::value, MORE = decltype(more_tag)::value;
+    T reg[SPF];              // the next knot's record, in flight during this knot
     const T* B = V.buf;                  // factor of knot k | G_{k-1}
-    if (k > 0) sol_prefetch(c, s, k - 1, k - 2, lane, reg);
+    if (MORE) sol_prefetch(c, s, k - 1, k - 2, lane, reg);
     const T* rbk = V.rb + k * RB_LEN;
     T ra[NX], ru[NU], cu[NU], bx;
 #pragma unroll
     for (int l = 0; l < NX; ++l) ra[l] = rbk[l];
 #pragma unroll
-    for (int a2 = 0; a2 < NU; ++a2) ru[a2] = (k < N) ? rbk[2 * NX + a2] : 0.0;
-    const T av = stage_apply(B, k < N, ra, rbk[NX + li], ru, false, lane, bx, cu, V);
-    if (k > 0) {
+    for (int a2 = 0; a2 < NU; ++a2) ru[a2] = HAS_U ? rbk[2 * NX + a2] : T(0.0);
+    const T av = stage_apply(B, HAS_U, ra, rbk[NX + li], ru, false, lane, bx, cu, V);
+    if (MORE) {
       T al[NX];
 #pragma unroll
       for (int l = 0; l < NX; ++l) al[l] = lane_bcast(av, l);
@@ -920,18 +939,23 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
       sol_park(V.buf, lane, reg);
     }
     lds_barrier();
-  }
+  };
+  bwd(N, Flag<false>{}, Flag<true>{});
+  for (int k = N - 1; k >= 1; --k) bwd(k, Flag<true>{}, Flag<true>{});
+  bwd(0, Flag<true>{}, Flag<false>{});
   // 3. forward sweep with the lambda rows fed by G_{k-1} (dx_{k-1}, du_{k-1}); the buffer still
-  //    holds the record of knot 0 from the last backward stage
+  //    holds the record of knot 0 from the last backward stage.  Cases: knot 0, knots 1..N-1, knot N.
   T dz[NZ];
 #pragma unroll
   for (int l = 0; l < NZ; ++l) dz[l] = 0.0;
-  for (int k = 0; k <= N; ++k) {
+  auto fwd = [&](int k, auto has_u_tag, auto prev_tag) {
+    constexpr bool HAS_U = decltype(has_u_tag)::value, PREV = decltype(prev_tag)::value;
+    T reg[SPF];              // the next knot's record, in flight during this knot
     const T* B = V.buf;                  // factor of knot k | G_{k-1}
-    if (k < N) sol_prefetch(c, s, k + 1, k, lane, reg);
+    if (HAS_U) sol_prefetch(c, s, k + 1, k, lane, reg);
     const T* rbk = V.rb + k * RB_LEN;
     T rai = rbk[li];
-    if (k > 0) {
+    if (PREV) {
       const T* Gp = B + FR_LEN;
       T w = 0.0;
 #pragma unroll
@@ -942,13 +966,13 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
     for (int l = 0; l < NX; ++l) ra[l] = lane_bcast(rai, l);
 #pragma unroll
-    for (int a2 = 0; a2 < NU; ++a2) ru[a2] = (k < N) ? rbk[2 * NX + a2] : 0.0;
-    const T av = stage_apply(B, k < N, ra, rbk[NX + li], ru, true, lane, bx, cu, V);
+    for (int a2 = 0; a2 < NU; ++a2) ru[a2] = HAS_U ? rbk[2 * NX + a2] : T(0.0);
+    const T av = stage_apply(B, HAS_U, ra, rbk[NX + li], ru, true, lane, bx, cu, V);
     if (lane < NX) {
       xc[k * NX + lane] = av;
       xv[xo(k) + lane] = bx;
     }
-    if (k < N) {
+    if (HAS_U) {
       T u = 0.0;
 #pragma unroll
       for (int a2 = 0; a2 < NU; ++a2) u = (lane == a2) ? cu[a2] : u;
@@ -958,9 +982,12 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
     for (int l = 0; l < NX; ++l) dz[l] = lane_bcast(bx, l);
 #pragma unroll
     for (int a2 = 0; a2 < NU; ++a2) dz[NX + a2] = cu[a2];
-    if (k < N) sol_park(V.buf, lane, reg);    // stage_apply ended with a barrier after its last read
+    if (HAS_U) sol_park(V.buf, lane, reg);    // stage_apply ended with a barrier after its last read
     lds_barrier();
-  }
+  };
+  fwd(0, Flag<true>{}, Flag<false>{});
+  for (int k = 1; k < N; ++k) fwd(k, Flag<true>{}, Flag<true>{});
+  fwd(N, Flag<false>{}, Flag<true>{});
   __syncthreads();   // xv is read back by other lanes below
   // 4. recover slack steps, inequality multiplier steps and elastic steps
   lanes_for(N * NI, lane, [&](int q) {
