@@ -213,25 +213,33 @@ __device__ __forceinline__ double row_dreg(const Elim& e, double sp0, double sn0
 //   Hc_k = sum_j D_kj J_kj^T J_kj + diag(sum_j 2 y_kj) (position rows),
 //   D_kj = sigma / (1 + sigma d),  sigma = sigma0 + delta_x,  d = delta_c + elastic part,
 // which is what eliminating the slack s_kj and its row (and the elastic p/n) leaves on x_k.
-// One (knot, upper-triangle entry) per lane; reads and rewrites the stage data.
+// One knot per lane: the knot's inequality rows are loaded once and D_kj computed once for the six
+// upper-triangle entries.  Reads and rewrites the stage data.
 __device__ __forceinline__ void kkt_condense(const Cfg& c, const Slot& s, const Elim& e, int lane) {
   const int N = c.N, NI = c.NI, SL = sd_len(c);
-  for (int q = lane; q < N * 6; q += WAVE) {
-    const int k = 1 + q / 6, p = q % 6;
-    const int a = p < 3 ? 0 : (p < 5 ? 1 : 2), b = p < 3 ? p : (p < 5 ? p - 2 : 2);
+  for (int q = lane; q < N; q += WAVE) {
+    const int k = 1 + q;
     double* sdk = s.sd + (long long)k * SL;
-    double acc = 0.0;
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
     for (int j = 0; j < NI; ++j) {
       const double* o7 = sdk + SD_HEAD + SD_OBS * j;
       const double sig = o7[0] + (e.lsq ? 0.0 : e.dxp);
       const double d = row_dreg(e, o7[1], o7[2]);
       const double D = sig / (1.0 + sig * d);
-      acc += D * o7[3 + a] * o7[3 + b];
-      if (a == b) acc += o7[6];
+#pragma unroll
+      for (int p = 0; p < 6; ++p) {
+        const int a = p < 3 ? 0 : (p < 5 ? 1 : 2), b = p < 3 ? p : (p < 5 ? p - 2 : 2);
+        acc[p] += D * o7[3 + a] * o7[3 + b];
+        if (a == b) acc[p] += o7[6];
+      }
     }
-    sdk[SD_HC + a * 3 + b] = acc;
-    if (a != b) sdk[SD_HC + b * 3 + a] = acc;
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const int a = p < 3 ? 0 : (p < 5 ? 1 : 2), b = p < 3 ? p : (p < 5 ? p - 2 : 2);
+      sdk[SD_HC + a * 3 + b] = acc[p];
+      if (a != b) sdk[SD_HC + b * 3 + a] = acc[p];
+    }
   }
   __syncthreads();
 }
@@ -239,54 +247,74 @@ __device__ __forceinline__ void kkt_condense(const Cfg& c, const Slot& s, const 
 __device__ __forceinline__ void kkt_stage_data(const Cfg& c, const Slot& s, const Iter& it, const Elim& e,
                                                int lane) {
   const int N = c.N, NI = c.NI, L = sd_len(c);
-  // knot entries: the loads of a trip are the control bounds' (v, z_L, z_U), the regulariser's
-  // x_R, or the elastic pair's (z, p) -- whichever the entry needs
-  lanes_for<8>((N + 1) * SD_HC, lane, [&](int q) {
-    const int k = q / SD_HC, i = q % SD_HC;
-    DV<4> t{{0.0, 1.0, 0.0, 0.0}};
-    if (i < NZ) {
-      if ((k < N || i < NX) && !e.lsq) {
-        const int vi = (i < NX) ? xo(k) + i : uo(k) + (i - NX);
-        if (e.resto) t.v[0] = s.xr[vi];
-        if (i >= NX) {
-          const int b = k * NU + (i - NX);
-          t.v[1] = s.v[vi];
-          t.v[2] = it.zlu[b];
-          t.v[3] = it.zuu[b];
-        }
-      }
-    } else if (e.resto) {
-      const int r = k * NX + (i - NZ) % NX;
-      t.v[0] = (i < NZ + NX) ? s.zp[r] : s.zn[r];
-      t.v[1] = (i < NZ + NX) ? s.p[r] : s.nn[r];
+  if (!e.resto && !e.lsq) {
+    // regular iterations: every knot entry but the controls' is a constant, stored without loads;
+    // the control entries (v, z_L, z_U) in one group of loads
+    for (int q = lane; q < (N + 1) * SD_HC; q += WAVE) {
+      const int k = q / SD_HC, i = q % SD_HC;
+      if (i >= NX && i < NZ && k < N) continue;
+      s.sd[(long long)k * L + i] = (i < NX) ? 2.0 * c.qw : 0.0;
     }
-    return t;
-  }, [&](int q, const DV<4>& t) {
-    const int k = q / SD_HC, i = q % SD_HC;
-    double* sd = s.sd + (long long)k * L;
-    double val = 0.0;
-    if (i < NZ) {
-      if (k < N || i < NX) {
-        if (e.lsq) {
-          val = 1.0;
-        } else {
-          if (e.resto) {
-            double d = fmin(1.0, 1.0 / fabs(t.v[0]));
-            val = e.zeta * d * d;
-          } else {
-            val = (i < NX) ? 2.0 * c.qw : 2.0 * c.rw;
-          }
+    lanes_for(N * NU, lane, [&](int b) {
+      const int k = b / NU, a = b % NU;
+      return DV<3>{{s.v[uo(k) + a], it.zlu[b], it.zuu[b]}};
+    }, [&](int b, const DV<3>& t) {
+      const int k = b / NU, a = b % NU;
+      double val = 2.0 * c.rw;
+      double u = t.v[0];
+      val += t.v[1] / u + t.v[2] / (c.umax - u);
+      s.sd[(long long)k * L + NX + a] = val;
+    });
+  } else {
+    // knot entries: the loads of a trip are the control bounds' (v, z_L, z_U), the regulariser's
+    // x_R, or the elastic pair's (z, p) -- whichever the entry needs
+    lanes_for<8>((N + 1) * SD_HC, lane, [&](int q) {
+      const int k = q / SD_HC, i = q % SD_HC;
+      DV<4> t{{0.0, 1.0, 0.0, 0.0}};
+      if (i < NZ) {
+        if ((k < N || i < NX) && !e.lsq) {
+          const int vi = (i < NX) ? xo(k) + i : uo(k) + (i - NX);
+          if (e.resto) t.v[0] = s.xr[vi];
           if (i >= NX) {
-            double u = t.v[1];
-            val += t.v[2] / u + t.v[3] / (c.umax - u);
+            const int b = k * NU + (i - NX);
+            t.v[1] = s.v[vi];
+            t.v[2] = it.zlu[b];
+            t.v[3] = it.zuu[b];
           }
         }
+      } else if (e.resto) {
+        const int r = k * NX + (i - NZ) % NX;
+        t.v[0] = (i < NZ + NX) ? s.zp[r] : s.zn[r];
+        t.v[1] = (i < NZ + NX) ? s.p[r] : s.nn[r];
       }
-    } else if (e.resto) {
-      val = t.v[0] / t.v[1];
-    }
-    sd[i] = val;
-  });
+      return t;
+    }, [&](int q, const DV<4>& t) {
+      const int k = q / SD_HC, i = q % SD_HC;
+      double* sd = s.sd + (long long)k * L;
+      double val = 0.0;
+      if (i < NZ) {
+        if (k < N || i < NX) {
+          if (e.lsq) {
+            val = 1.0;
+          } else {
+            if (e.resto) {
+              double d = fmin(1.0, 1.0 / fabs(t.v[0]));
+              val = e.zeta * d * d;
+            } else {
+              val = (i < NX) ? 2.0 * c.qw : 2.0 * c.rw;
+            }
+            if (i >= NX) {
+              double u = t.v[1];
+              val += t.v[2] / u + t.v[3] / (c.umax - u);
+            }
+          }
+        }
+      } else if (e.resto) {
+        val = t.v[0] / t.v[1];
+      }
+      sd[i] = val;
+    });
+  }
   lanes_for(N * NI, lane, [&](int q) {
     const int k = 1 + q / NI, j = q % NI;
     DV<14> t;

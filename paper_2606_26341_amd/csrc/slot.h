@@ -90,52 +90,66 @@ __device__ __forceinline__ void eval_grad(const Cfg& c, const Slot& s, const dou
     s.g[i] = gi;
   });
   // A^T y.  Every load of a trip (the identity row, column r of G_k with y_{k+1}, the first
-  // OBS_CHUNK inequality rows of knot k) is issued before the first use, from valid addresses
-  // on every lane, so that a trip waits for memory once.
-  for (int i = lane; i < c.n; i += WAVE) {
-    double a = 0.0;
+  // OBS_CHUNK inequality rows of knot k) is issued before the first use, from valid addresses on
+  // every lane, two trips at a time, so that a pair of trips waits for memory once.
+  struct AtyIn {
+    double ys, vi, gc[NX], yn[NX], oc[OBS_CHUNK], yg[OBS_CHUNK];
+  };
+  auto load_obs = [&](int j0, int ko, int ro, double* oc, double* yg) {
+#pragma unroll
+    for (int u = 0; u < OBS_CHUNK; ++u) {
+      const int j = min(j0 + u, NI - 1);
+      double o[4];
+      obs_at(c, s.th, j, ko, o);
+      oc[u] = ro == 0 ? o[0] : (ro == 1 ? o[1] : o[2]);
+      yg[u] = yv[go(c, ko, j)];
+    }
+  };
+  lanes_for<2>(c.n, lane, [&](int i) {
+    AtyIn t;
     if (i < c.n_w) {
       const int k = i / NZ, r = i % NZ;
       const int kg = k < N ? k : N - 1, ko = k >= 1 ? k : 1, ro = r < 3 ? r : 0;
       const double* Gk = s.G + (long long)kg * NX * NZ;
-      const double ys = yv[k * NX + (r < NX ? r : 0)], vi = s.v[i];
-      double gc[NX], yn[NX], oc[OBS_CHUNK], yg[OBS_CHUNK];
+      t.ys = yv[k * NX + (r < NX ? r : 0)];
+      t.vi = s.v[i];
 #pragma unroll
       for (int l = 0; l < NX; ++l) {
-        gc[l] = Gk[l * NZ + r];
-        yn[l] = yv[(kg + 1) * NX + l];
+        t.gc[l] = Gk[l * NZ + r];
+        t.yn[l] = yv[(kg + 1) * NX + l];
       }
-      auto load_obs = [&](int j0) {
-#pragma unroll
-        for (int u = 0; u < OBS_CHUNK; ++u) {
-          const int j = min(j0 + u, NI - 1);
-          double o[4];
-          obs_at(c, s.th, j, ko, o);
-          oc[u] = ro == 0 ? o[0] : (ro == 1 ? o[1] : o[2]);
-          yg[u] = yv[go(c, ko, j)];
-        }
-      };
-      if (NI > 0) load_obs(0);
-      if (r < NX) a += ys;        // +I of the rows defining x_k
+      if (NI > 0) load_obs(0, ko, ro, t.oc, t.yg);
+    } else {
+      const int q = i - c.n_w;
+      t.ys = yv[go(c, 1 + q / NI, q % NI)];
+    }
+    return t;
+  }, [&](int i, const AtyIn& t) {
+    double a = 0.0;
+    if (i < c.n_w) {
+      const int k = i / NZ, r = i % NZ;
+      if (r < NX) a += t.ys;        // +I of the rows defining x_k
       if (k < N) {
 #pragma unroll
-        for (int l = 0; l < NX; ++l) a -= gc[l] * yn[l];
+        for (int l = 0; l < NX; ++l) a -= t.gc[l] * t.yn[l];
       }
       if (r < 3 && k >= 1) {
-        for (int j0 = 0; j0 < NI; j0 += OBS_CHUNK) {
-          if (j0 > 0) load_obs(j0);
+#pragma unroll
+        for (int u = 0; u < OBS_CHUNK; ++u)
+          if (u < NI) a += 2.0 * (t.vi - t.oc[u]) * t.yg[u];
+        for (int j0 = OBS_CHUNK; j0 < NI; j0 += OBS_CHUNK) {
+          double oc[OBS_CHUNK], yg[OBS_CHUNK];
+          load_obs(j0, k, r, oc, yg);
 #pragma unroll
           for (int u = 0; u < OBS_CHUNK; ++u)
-            if (j0 + u < NI) a += 2.0 * (vi - oc[u]) * yg[u];
+            if (j0 + u < NI) a += 2.0 * (t.vi - oc[u]) * yg[u];
         }
       }
     } else {
-      int q = i - c.n_w;
-      int k = 1 + q / NI, j = q % NI;
-      a = -yv[go(c, k, j)];
+      a = -t.ys;
     }
     aty[i] = a;
-  }
+  });
   __syncthreads();
 }
 
