@@ -890,38 +890,49 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
   const int N = c.N, NI = c.NI, SL = sd_len(c);
   T reg[SPF];
   sol_prefetch(c, s, N, N - 1, lane, reg);      // first backward stage
-  // 1. condensed stage right-hand sides (lambda 13, x 13, u 4 per knot) into LDS
-  lanes_for<8>((N + 1) * RB_LEN, lane, [&](int q) {
-    const int k = q / RB_LEN, i = q % RB_LEN;
-    DV<5> t{{0.0, 0.0, 0.0, 1.0, 1.0}};
-    if (i < NX) {
-      const int r = k * NX + i;
-      t.v[0] = bc[r];
-      if (e.resto) {
+  // 1. condensed stage right-hand sides (lambda 13, x 13, u 4 per knot) into LDS; outside
+  //    restoration an entry is one word of b, all of them in one or two groups of loads
+  if (!e.resto) {
+    lanes_for<16>((N + 1) * RB_LEN, lane, [&](int q) {
+      const int k = q / RB_LEN, i = q % RB_LEN;
+      double v = 0.0;
+      if (i < NX) v = bc[k * NX + i];
+      else if (i < 2 * NX) v = bv[xo(k) + i - NX];
+      else if (i < 2 * NX + NU && k < N) v = bv[uo(k) + i - 2 * NX];
+      return DV<1>{{v}};
+    }, [&](int q, const DV<1>& t) { V.rb[q] = T(t.v[0]); });
+  } else {
+    lanes_for<8>((N + 1) * RB_LEN, lane, [&](int q) {
+      const int k = q / RB_LEN, i = q % RB_LEN;
+      DV<5> t{{0.0, 0.0, 0.0, 1.0, 1.0}};
+      if (i < NX) {
+        const int r = k * NX + i;
         const double* sdk = s.sd + (long long)k * SL;
+        t.v[0] = bc[r];
         t.v[1] = bp[r];
         t.v[2] = bn[r];
         t.v[3] = sdk[NZ + i];
         t.v[4] = sdk[NZ + NX + i];
+      } else if (i < 2 * NX) {
+        t.v[0] = bv[xo(k) + i - NX];
+      } else if (i < 2 * NX + NU && k < N) {
+        t.v[0] = bv[uo(k) + i - 2 * NX];
       }
-    } else if (i < 2 * NX) {
-      t.v[0] = bv[xo(k) + i - NX];
-    } else if (i < 2 * NX + NU && k < N) {
-      t.v[0] = bv[uo(k) + i - 2 * NX];
-    }
-    return t;
-  }, [&](int q, const DV<5>& t) {
-    const int i = q % RB_LEN;
-    double val = t.v[0];
-    if (i < NX && e.resto) val += t.v[1] / (t.v[3] + e.dxp) - t.v[2] / (t.v[4] + e.dxp);
-    V.rb[q] = T(val);
-  });
+      return t;
+    }, [&](int q, const DV<5>& t) {
+      const int i = q % RB_LEN;
+      double val = t.v[0];
+      if (i < NX) val += t.v[1] / (t.v[3] + e.dxp) - t.v[2] / (t.v[4] + e.dxp);
+      V.rb[q] = T(val);
+    });
+  }
   lds_barrier();
-  // position rows of x_k gather the slack rows of knot k
-  for (int q = lane; q < N * 3; q += WAVE) {
-    const int k = 1 + q / 3, t = q % 3;
+  // position rows of x_k gather the slack rows of knot k, one knot per lane (each row's D and
+  // right-hand side once for the three positions)
+  for (int q = lane; q < N; q += WAVE) {
+    const int k = 1 + q;
     const double* sdk = s.sd + (long long)k * SL;
-    double acc = 0.0;
+    double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll 8
     for (int j = 0; j < NI; ++j) {
       const double* o7 = sdk + SD_HEAD + SD_OBS * j;
@@ -931,9 +942,12 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
       const double D = sig / (1.0 + sig * d);
       double bg = bc[r];
       if (e.resto) bg += bp[r] / (o7[1] + e.dxp) - bn[r] / (o7[2] + e.dxp);
-      acc += o7[3 + t] * D * (bv[so(c, k, j)] / sig + bg);
+      const double bj = bv[so(c, k, j)];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) acc[t] += o7[3 + t] * D * (bj / sig + bg);
     }
-    V.rb[k * RB_LEN + NX + t] += T(acc);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) V.rb[k * RB_LEN + NX + t] += T(acc[t]);
   }
   sol_park(V.buf, lane, reg);
   lds_barrier();
