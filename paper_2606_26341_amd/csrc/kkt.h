@@ -142,10 +142,12 @@ __device__ __forceinline__ int wor(int v) {
 // One wavefront per slot leaves no other wave on the SIMD to hide memory latency behind, and a
 // plain `for (i = lane; i < n; i += WAVE)` loop that loads, waits and stores pays one memory
 // round trip per trip (a store to the slot record may alias the next trip's loads, so the
-// compiler cannot hoist them).  lanes_for runs the same trips in groups of LB: the group's
-// loads (ld, which must not store) are all issued first, from a clamped index so that every
-// lane loads a valid word without a branch, then use(i, value) runs for each trip in order.
-// Results, and the order of every accumulation, are those of the plain loop.
+// compiler cannot hoist them).  lanes_for runs the same trips in groups: the group's loads (ld,
+// which must not store) are all issued first, from a clamped index so that every lane loads a
+// valid word without a branch, then use(i, value) runs for each trip in order.  A group holds up
+// to 4 trips and at most 32 loaded words per lane unless LB0 sets its size (larger groups of
+// one-word trips measured slower).  Results, and the order of every accumulation, are those of
+// the plain loop.
 template <int LB0 = 0, class Ld, class Use>
 __device__ __forceinline__ void lanes_for(int n, int lane, Ld ld, Use use) {
   using V = decltype(ld(0));
