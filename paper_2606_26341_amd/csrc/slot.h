@@ -240,23 +240,32 @@ __device__ __forceinline__ double kkt_err(const Cfg& c, const ErrParts& e, doubl
   return r;
 }
 
+// reference value that entry i < n_w of v is weighed against (state rows), 0 for controls
+__device__ __forceinline__ double obj_ref(const Slot& s, int i) {
+  const int k = i / NZ, r = i % NZ;
+  return r < NX ? s.ref[k * NX + r] : 0.0;
+}
+// term of entry i < n_w of the regular objective, added to a lane's partial sum (the lane takes
+// its entries in increasing order, so every caller forms the same partial sums)
+__device__ __forceinline__ void obj_term(const Cfg& c, int i, double vi, double ref, double& f) {
+  if (i % NZ < NX) {
+    double e = vi - ref;
+    f += c.qw * e * e;
+  } else {
+    double e = vi - c.uh;
+    f += c.rw * e * e;
+  }
+}
+// lane partial sum of the regular objective at v
+__device__ __forceinline__ double obj_regular_lane(const Cfg& c, const Slot& s, const double* v, int lane) {
+  double f = 0.0;
+  lanes_for(c.n_w, lane, [&](int i) { return DV<2>{{v[i], obj_ref(s, i)}}; },
+            [&](int i, const DV<2>& t) { obj_term(c, i, t.v[0], t.v[1], f); });
+  return f;
+}
 // objective value at v (regular) -- wave sum
 __device__ __forceinline__ double obj_regular(const Cfg& c, const Slot& s, const double* v, int lane) {
-  double f = 0.0;
-  lanes_for(c.n_w, lane, [&](int i) {
-    const int k = i / NZ, r = i % NZ;
-    return DV<2>{{v[i], r < NX ? s.ref[k * NX + r] : 0.0}};
-  }, [&](int i, const DV<2>& t) {
-    int r = i % NZ;
-    if (r < NX) {
-      double e = t.v[0] - t.v[1];
-      f += c.qw * e * e;
-    } else {
-      double e = t.v[0] - c.uh;
-      f += c.rw * e * e;
-    }
-  });
-  return wsum(f);
+  return wsum(obj_regular_lane(c, s, v, lane));
 }
 
 // restoration objective rho sum(p + n) + zeta/2 |D_R (v - x_R)|^2
@@ -1212,18 +1221,17 @@ struct Trial {
   bool fin;
 };
 
-// evaluate the trial point vt (pt, nt): constraints into ct, theta = |ct|_1, phi_mu
-__device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool resto, double mu, double zeta, int lane) {
+// evaluate the trial point vt (pt, nt): constraints into ct, theta = |ct|_1, phi_mu.  The
+// initial-state rows and the first inequality rows are loaded before the RK4 of each lane's
+// interval, so that their memory round trip overlaps it.  freg: this lane's partial sum of the
+// regular objective at vt (make_trial forms it; unused in restoration).
+__device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool resto, double mu, double zeta, double freg,
+                                            int lane) {
   const int N = c.N, NI = c.NI;
-  if (lane < N) {
-    double x[NX], u[NU], F[NX];
-    for (int i = 0; i < NX; ++i) x[i] = s.vt[xo(lane) + i];
-    for (int i = 0; i < NU; ++i) u[i] = s.vt[uo(lane) + i];
-    rk4(c, x, u, F);
-    for (int i = 0; i < NX; ++i) s.ct[(lane + 1) * NX + i] = s.vt[xo(lane + 1) + i] - F[i];
-  }
-  for (int i = lane; i < NX; i += WAVE) s.ct[i] = s.vt[i] - s.th[i];
-  lanes_for(N * NI, lane, [&](int q) {
+  // rows defining x_0 and the first inequality group: loads issued first
+  const int l0 = lane < NX ? lane : 0;
+  const double x0v = s.vt[l0], x0t = s.th[l0];
+  auto obs_ld = [&](int q) {
     const int k = 1 + q / NI, j = q % NI;
     DV<8> t;
     double o[4];
@@ -1234,22 +1242,52 @@ __device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool re
     for (int a = 0; a < 3; ++a) t.v[4 + a] = s.vt[xo(k) + a];
     t.v[7] = s.vt[so(c, k, j)];
     return t;
-  }, [&](int q, const DV<8>& t) {
+  };
+  auto obs_use = [&](int q, const DV<8>& t) {
     const int k = 1 + q / NI, j = q % NI;
     double g = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) { double e = t.v[4 + a] - t.v[a]; g += e * e; }
-    s.ct[go(c, k, j)] = g - t.v[3] * t.v[3] - t.v[7];
-  });
+    const double cv = g - t.v[3] * t.v[3] - t.v[7];
+    s.ct[go(c, k, j)] = cv;
+  };
+  constexpr int OG = 4;                 // inequality trips per lane loaded ahead
+  const int nq = N * NI;
+  DV<8> og[OG];
+  if (nq > 0) {
+#pragma unroll
+    for (int u = 0; u < OG; ++u) og[u] = obs_ld(min(lane + u * WAVE, nq - 1));
+  }
+  if (lane < N) {
+    double x[NX], u[NU], F[NX], xn[NX];
+    for (int i = 0; i < NX; ++i) x[i] = s.vt[xo(lane) + i];
+    for (int i = 0; i < NU; ++i) u[i] = s.vt[uo(lane) + i];
+    for (int i = 0; i < NX; ++i) xn[i] = s.vt[xo(lane + 1) + i];
+    rk4(c, x, u, F);
+    for (int i = 0; i < NX; ++i) {
+      const double cv = xn[i] - F[i];
+      s.ct[(lane + 1) * NX + i] = cv;
+    }
+  }
+  if (lane < NX) s.ct[lane] = x0v - x0t;
+#pragma unroll
+  for (int u = 0; u < OG; ++u)
+    if (lane + u * WAVE < nq) obs_use(lane + u * WAVE, og[u]);
+  if (nq > OG * WAVE) {
+    const int rest = nq - OG * WAVE;
+    lanes_for(rest, lane, [&](int q) { return obs_ld(OG * WAVE + q); },
+              [&](int q, const DV<8>& t) { obs_use(OG * WAVE + q, t); });
+  }
   __syncthreads();
-  if (resto)
+  if (resto) {
     lanes_for(c.m, lane, [&](int r) { return DV<3>{{s.ct[r], s.pt[r], s.nt[r]}}; },
               [&](int r, const DV<3>& t) { s.ct[r] = t.v[0] + (-t.v[1] + t.v[2]); });
-  __syncthreads();
+    __syncthreads();
+  }
   double th = 0.0;
   lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.ct[r]}}; }, [&](int r, const DV<1>& t) { th += fabs(t.v[0]); });
   th = wsum(th);
-  double f = resto ? obj_resto(c, s, s.vt, s.pt, s.nt, zeta, lane) : obj_regular(c, s, s.vt, lane);
+  double f = resto ? obj_resto(c, s, s.vt, s.pt, s.nt, zeta, lane) : wsum(freg);
   double ph = f - mu * log_barrier(c, s.vt, s.pt, s.nt, resto, lane);
   Trial t;
   t.th = th;
@@ -1258,16 +1296,25 @@ __device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool re
   return t;
 }
 
-__device__ __forceinline__ void make_trial(const Cfg& c, const Slot& s, bool resto, double a, const double* dv,
-                                           const double* dp, const double* dn, int lane) {
-  lanes_for(c.n, lane, [&](int i) { return DV<2>{{s.v[i], dv[i]}}; },
-            [&](int i, const DV<2>& t) { s.vt[i] = t.v[0] + a * t.v[1]; });
+// trial point v + a dv (p + a dp, n + a dn); returns this lane's partial sum of the regular
+// objective at it (0 in restoration)
+__device__ __forceinline__ double make_trial(const Cfg& c, const Slot& s, bool resto, double a, const double* dv,
+                                             const double* dp, const double* dn, int lane) {
+  const int nw = c.n_w;
+  double f = 0.0;
+  lanes_for(c.n, lane, [&](int i) { return DV<3>{{s.v[i], dv[i], !resto && i < nw ? obj_ref(s, i) : 0.0}}; },
+            [&](int i, const DV<3>& t) {
+              const double vt = t.v[0] + a * t.v[1];
+              s.vt[i] = vt;
+              if (!resto && i < nw) obj_term(c, i, vt, t.v[2], f);
+            });
   if (resto)
     lanes_for(c.m, lane, [&](int r) { return DV<4>{{s.p[r], dp[r], s.nn[r], dn[r]}}; }, [&](int r, const DV<4>& t) {
       s.pt[r] = t.v[0] + a * t.v[1];
       s.nt[r] = t.v[2] + a * t.v[3];
     });
   __syncthreads();
+  return f;
 }
 
 struct Acc {
@@ -1382,7 +1429,7 @@ __device__ __forceinline__ void resto_try_exit(const Cfg& c, const Slot& s, int 
   for (int i = lane; i < c.n; i += WAVE) s.vt[i] = s.v[i];
   __syncthreads();
   const double mu = s.sc[SC_MU];
-  Trial t = eval_trial(c, s, false, mu, 0.0, lane);
+  Trial t = eval_trial(c, s, false, mu, 0.0, obj_regular_lane(c, s, s.vt, lane), lane);
   if (!t.fin) return;
   if (!(t.th <= c.kappa_resto * s.sc[SC_THR])) return;
   if (!filter_ok(c, s.fm, (int)s.sc[SC_NF], t.th, t.ph, lane)) return;
@@ -1496,7 +1543,7 @@ __device__ __forceinline__ bool soft_step(const Cfg& c, const Slot& s, const Ite
   aty_at(c, s, s.v, s.y, s.ev, lane);
   const double e0 = pd_error(c, s.v, s.qv, s.ev, s.rc, s.zlu, s.zuu, s.zls, mu, lane);
   // the trial
-  make_trial(c, s, false, as, s.dv, s.dp, s.dn, lane);
+  const double freg = make_trial(c, s, false, as, s.dv, s.dp, s.dn, lane);
   for (int r = lane; r < c.m; r += WAVE) s.syt[r] = s.y[r] + as * s.dy[r];
   for (int b = lane; b < c.N * NU; b += WAVE) {
     s.szlu[b] = s.zlu[b] + as * s.dzlu[b];
@@ -1504,7 +1551,7 @@ __device__ __forceinline__ bool soft_step(const Cfg& c, const Slot& s, const Ite
   }
   for (int q = lane; q < c.N * c.NI; q += WAVE) s.szls[q] = s.zls[q] + as * s.dzls[q];
   __syncthreads();
-  *t = eval_trial(c, s, false, mu, 0.0, lane);
+  *t = eval_trial(c, s, false, mu, 0.0, freg, lane);
   grad_f_at(c, s, s.vt, s.qv, lane);
   aty_at(c, s, s.vt, s.syt, s.ev, lane);
   const double e1 = pd_error(c, s.vt, s.qv, s.ev, s.ct, s.szlu, s.szuu, s.szls, mu, lane);
@@ -1594,8 +1641,8 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
         }
         __syncthreads();
       }
-      make_trial(c, s, resto, amax, s.dv, s.dp, s.dn, lane);
-      Trial t = eval_trial(c, s, resto, mu, zeta, lane);
+      const double freg = make_trial(c, s, resto, amax, s.dv, s.dp, s.dn, lane);
+      Trial t = eval_trial(c, s, resto, mu, zeta, freg, lane);
       const double wthk = s.sc[SC_WD_THK], wphk = s.sc[SC_WD_PHK];
       Acc a = acceptable(c, sub, it.filt, wthk, wphk, s.sc[SC_WD_GPHI], s.sc[SC_WD_AMAX], t, lane);
       const double wit = s.sc[SC_WD_ITER] + 1.0;
@@ -1643,8 +1690,8 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
           try_soft = use_soft;          // the line search failed: soft restoration, if enabled
           break;
         }
-        make_trial(c, s, resto, alpha, s.dv, s.dp, s.dn, lane);
-        Trial t = eval_trial(c, s, resto, mu, zeta, lane);
+        const double freg = make_trial(c, s, resto, alpha, s.dv, s.dp, s.dn, lane);
+        Trial t = eval_trial(c, s, resto, mu, zeta, freg, lane);
         Acc a = acceptable(c, sub, it.filt, thk, phk, gphi, alpha, t, lane);
         if (a.ok) {
           ap = alpha;
@@ -1677,8 +1724,8 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
               if (fused) s.sc[SC_ST_FSOLV] += 1.0;
             }
             asoc = ftb_primal(c, s, s.dvs, s.dps, s.dns, resto, tau, lane);
-            make_trial(c, s, resto, asoc, s.dvs, s.dps, s.dns, lane);
-            Trial ts = eval_trial(c, s, resto, mu, zeta, lane);
+            const double fsoc = make_trial(c, s, resto, asoc, s.dvs, s.dps, s.dns, lane);
+            Trial ts = eval_trial(c, s, resto, mu, zeta, fsoc, lane);
             tht = ts.th;
             fin = ts.fin;
             Acc as = acceptable(c, sub, it.filt, thk, phk, gphi, alpha, ts, lane);
