@@ -786,6 +786,11 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 }
 
 // ----------------------------------------------------------------------------- solve
+// Scheduling fence: the compiler moves no instruction across it.  The sweeps load a knot's words
+// from LDS into registers, then fence, so that the loads are issued as one group and the
+// dependent products below wait once for the group instead of once per pair of words.
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 // Apply M_k^{-1} of stage k (factor record F in LDS) to the stage right-hand side
 // (ra, rx, ru): ra[] holds the lambda part on every lane, rx the x component of row `lane`,
 // ru[] the control part on every lane.  Returns the lambda component a of row `lane`; with
@@ -794,34 +799,65 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 //   w_u = L_R^{-1} r_u,  t = r_x - Y^T w_u - P r_a,
 //   a = t (Delta = 0)  or  a = M t,  M = Delta^{-1/2} C^{-1} Delta^{1/2} from the factor record,
 //   b = r_a + Delta a,  c_u = L_R^{-T} (w_u - Y b)
+// the words of a factor record that lane `li` reads in stage_apply: L_R (strict lower part),
+// the reciprocal pivots, column li of Y, row li of P, Delta^{1/2}_li and the pair-pivot flag
 template <typename T>
-__device__ __forceinline__ T stage_apply(const T* F, bool has_u, const T (&ra)[NX], T rx, const T (&ru)[NU], bool full,
-                                         int lane, T& b, T (&cu)[NU], SolLdsT<T>& V) {
+struct StageWords {
+  T lr[NU * NU], rr[NU], yl[NU], pr[NX], dh;
+  bool reg;
+};
+template <typename T>
+__device__ __forceinline__ StageWords<T> stage_words(const T* F, int li) {
+  StageWords<T> W;
+#pragma unroll
+  for (int a2 = 0; a2 < NU; ++a2) {
+#pragma unroll
+    for (int l = 0; l < a2; ++l) W.lr[a2 * NU + l] = F[FR_LR + a2 * NU + l];
+    W.rr[a2] = F[FR_RR + a2];
+    W.yl[a2] = F[FR_Y + a2 * NX + li];
+  }
+#pragma unroll
+  for (int l = 0; l < NX; ++l) W.pr[l] = F[FR_P + li * NX + l];
+  W.reg = F[FR_FLAG] != 0.0;
+  W.dh = F[FR_DH + li];
+  return W;
+}
+template <typename T>
+__device__ __forceinline__ T stage_apply(const T* F, const StageWords<T>& W, bool has_u, const T (&ra)[NX], T rx,
+                                         const T (&ru)[NU], bool full, int lane, T& b, T (&cu)[NU], SolLdsT<T>& V) {
   const int li = lane < NX ? lane : NX - 1;
-  const bool reg = F[FR_FLAG] != 0.0;
+  const auto& lr = W.lr;
+  const auto& rr = W.rr;
+  const auto& yl = W.yl;
+  const auto& pr = W.pr;
+  const bool reg = W.reg;
+  const T dh = W.dh;
   T wu[NU];
 #pragma unroll
   for (int a2 = 0; a2 < NU; ++a2) {
     T acc = ru[a2];
 #pragma unroll
-    for (int l = 0; l < a2; ++l) acc -= F[FR_LR + a2 * NU + l] * wu[l];
-    wu[a2] = has_u ? acc * F[FR_RR + a2] : 0.0;
+    for (int l = 0; l < a2; ++l) acc -= lr[a2 * NU + l] * wu[l];
+    wu[a2] = has_u ? acc * rr[a2] : 0.0;
   }
   T t = rx;
   if (has_u)
 #pragma unroll
-    for (int a2 = 0; a2 < NU; ++a2) t -= F[FR_Y + a2 * NX + li] * wu[a2];
+    for (int a2 = 0; a2 < NU; ++a2) t -= yl[a2] * wu[a2];
 #pragma unroll
-  for (int l = 0; l < NX; ++l) t -= F[FR_P + li * NX + l] * ra[l];
+  for (int l = 0; l < NX; ++l) t -= pr[l] * ra[l];
   T av = t;
-  const T dh = F[FR_DH + li];
   if (reg) {
+    T mr[NX];
+#pragma unroll
+    for (int l = 0; l < NX; ++l) mr[l] = F[FR_M + li * NX + l];
+    sched_fence();
     T tl[NX];
 #pragma unroll
     for (int l = 0; l < NX; ++l) tl[l] = lane_bcast(t, l);
     T acc = 0.0;
 #pragma unroll
-    for (int l = 0; l < NX; ++l) acc += F[FR_M + li * NX + l] * tl[l];
+    for (int l = 0; l < NX; ++l) acc += mr[l] * tl[l];
     av = acc;
   }
   if (full) {
@@ -840,8 +876,8 @@ __device__ __forceinline__ T stage_apply(const T* F, bool has_u, const T (&ra)[N
       for (int a2 = NU - 1; a2 >= 0; --a2) {
         T acc = c2[a2];
 #pragma unroll
-        for (int l = a2 + 1; l < NU; ++l) acc -= F[FR_LR + l * NU + a2] * cu[l];
-        cu[a2] = acc * F[FR_RR + a2];
+        for (int l = a2 + 1; l < NU; ++l) acc -= lr[l * NU + a2] * cu[l];
+        cu[a2] = acc * rr[a2];
       }
     } else {
 #pragma unroll
@@ -967,17 +1003,27 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
     for (int l = 0; l < NX; ++l) ra[l] = rbk[l];
 #pragma unroll
     for (int a2 = 0; a2 < NU; ++a2) ru[a2] = HAS_U ? rbk[2 * NX + a2] : T(0.0);
-    const T av = stage_apply(B, HAS_U, ra, rbk[NX + li], ru, false, lane, bx, cu, V);
+    const T rx = rbk[NX + li];
+    const StageWords<T> W = stage_words(B, li);
+    // column lz of G_{k-1} and the right-hand side entry it updates
+    const int lz = lane < NZ ? lane : NZ - 1;
+    T gc[NX], rbn = 0.0;
+    if (MORE) {
+#pragma unroll
+      for (int l = 0; l < NX; ++l) gc[l] = B[FR_LEN + l * NZ + lz];
+      rbn = V.rb[(k - 1) * RB_LEN + NX + lz];
+    }
+    sched_fence();
+    const T av = stage_apply(B, W, HAS_U, ra, rx, ru, false, lane, bx, cu, V);
     if (MORE) {
       T al[NX];
 #pragma unroll
       for (int l = 0; l < NX; ++l) al[l] = lane_bcast(av, l);
       if (lane < NZ) {
-        const T* Gp = B + FR_LEN;         // G_{k-1}
         T acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < NX; ++l) acc += Gp[l * NZ + lane] * al[l];
-        V.rb[(k - 1) * RB_LEN + NX + lane] += acc;
+        for (int l = 0; l < NX; ++l) acc += gc[l] * al[l];
+        V.rb[(k - 1) * RB_LEN + NX + lane] = rbn + acc;
       }
       lds_barrier();
       sol_park(V.buf, lane, reg);
@@ -999,19 +1045,26 @@ __device__ __forceinline__ void kkt_solve(const Cfg& c, const Slot& s, const Eli
     if (HAS_U) sol_prefetch(c, s, k + 1, k, lane, reg);
     const T* rbk = V.rb + k * RB_LEN;
     T rai = rbk[li];
+    T gr[NZ];                 // row li of G_{k-1}
     if (PREV) {
-      const T* Gp = B + FR_LEN;
-      T w = 0.0;
 #pragma unroll
-      for (int l = 0; l < NZ; ++l) w += Gp[li * NZ + l] * dz[l];
-      rai += w;
+      for (int l = 0; l < NZ; ++l) gr[l] = B[FR_LEN + li * NZ + l];
     }
     T ra[NX], ru[NU], cu[NU], bx = 0.0;
 #pragma unroll
-    for (int l = 0; l < NX; ++l) ra[l] = lane_bcast(rai, l);
-#pragma unroll
     for (int a2 = 0; a2 < NU; ++a2) ru[a2] = HAS_U ? rbk[2 * NX + a2] : T(0.0);
-    const T av = stage_apply(B, HAS_U, ra, rbk[NX + li], ru, true, lane, bx, cu, V);
+    const T rx = rbk[NX + li];
+    const StageWords<T> W = stage_words(B, li);
+    sched_fence();
+    if (PREV) {
+      T w = 0.0;
+#pragma unroll
+      for (int l = 0; l < NZ; ++l) w += gr[l] * dz[l];
+      rai += w;
+    }
+#pragma unroll
+    for (int l = 0; l < NX; ++l) ra[l] = lane_bcast(rai, l);
+    const T av = stage_apply(B, W, HAS_U, ra, rx, ru, true, lane, bx, cu, V);
     if (lane < NX) {
       xc[k * NX + lane] = av;
       xv[xo(k) + lane] = bx;
