@@ -184,6 +184,12 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Scheduling fence: the compiler moves no instruction across it.  The factorization and the
+// sweeps load a step's words from LDS into registers, then fence, so that the loads are issued as
+// one group and the dependent products after it wait once for the group instead of once per
+// pair of words (left to itself, the scheduler interleaves each read with its use).
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 // ----------------------------------------------------------------------------- stage data
 // Perturbation-free diagonal data of knot k (written once per factorization request):
 //   [0, NZ)            objective Hessian diagonal + bound Sigma of (x_k, u_k) (identity in LSQ mode)
@@ -534,7 +540,7 @@ __device__ __forceinline__ void stage_park(T* buf, int lane, const double* reg) 
 // Factor all stage blocks with perturbations (e.dxp, e.dcp); stage data from kkt_stage_data.
 // Returns 0 (inertia correct), 1 (wrong), 2 (singular) or, in FP32, 3 (a pivot too close to zero
 // for an FP32 verdict).  Writes the per-knot factor records.
-template <typename T>
+template <typename T, bool FENCE = true>
 __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Elim& e, FacLdsT<T>& L, int lane) {
   const int N = c.N;
   double reg[PF];   // FP64 inputs, rounded to T when parked
@@ -562,16 +568,28 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     const int r16 = lane & 15, kq = lane >> 4, li0 = lane < NX ? lane : NX - 1;
     if (HAS_U) {
       typename Mma<T>::acc t0 = {T(0), T(0), T(0), T(0)};
-      T t16 = 0.0;
+      // operands first, as one group of LDS reads
+      T sr[NX], gc[NX], sv[4], g0[4];
 #pragma unroll
-      for (int l = 0; l < NX; ++l) t16 += L.S[li0 * NX + l] * Gk[l * NZ + 16];
+      for (int l = 0; l < NX; ++l) {
+        sr[l] = L.S[li0 * NX + l];
+        gc[l] = Gk[l * NZ + 16];
+      }
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
         const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
-        const T sv = L.S[(r16 < NX ? r16 : 0) * NX + kc];
-        const T g0 = Gk[kc * NZ + r16];
-        const T a = (kk < NX && r16 < NX) ? sv : T(0);
-        t0 = Mma<T>::mma(a, kk < NX ? g0 : T(0), t0);
+        sv[st] = L.S[(r16 < NX ? r16 : 0) * NX + kc];
+        g0[st] = Gk[kc * NZ + r16];
+      }
+      if constexpr (FENCE) sched_fence();
+      T t16 = 0.0;
+#pragma unroll
+      for (int l = 0; l < NX; ++l) t16 += sr[l] * gc[l];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int kk = 4 * st + kq;
+        const T a = (kk < NX && r16 < NX) ? sv[st] : T(0);
+        t0 = Mma<T>::mma(a, kk < NX ? g0[st] : T(0), t0);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -582,29 +600,53 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
       lds_barrier();
     }
     // ---- stage Hessian (NZ stride): W_k + diag + delta_x I + Hc_k + G_k^T T ----
-    auto h_base = [&](int i, int j) -> T {
-      T h = (!e.lsq && HAS_U) ? Wk[i * NZ + j] : T(0);
-      h += (i == j && (HAS_U || i < NX)) ? SD[j] + dx : T(0);
-      h += (MORE && i < 3 && j < 3) ? SD[SD_HC + 3 * (i < 3 ? i : 0) + (j < 3 ? j : 0)] : T(0);
+    // the words of entry (i, j): W_ij, the diagonal term of column j, the condensed block's entry
+    struct HW3 {
+      T w, d, hc;
+    };
+    auto h_words = [&](int i, int j) -> HW3 {
+      return {(!e.lsq && HAS_U) ? Wk[i * NZ + j] : T(0), SD[j], SD[SD_HC + 3 * (i < 3 ? i : 0) + (j < 3 ? j : 0)]};
+    };
+    auto h_base = [&](int i, int j, const HW3& b) -> T {
+      T h = b.w;
+      h += (i == j && (HAS_U || i < NX)) ? b.d + dx : T(0);
+      h += (MORE && i < 3 && j < 3) ? b.hc : T(0);
       return h;
     };
     {
       // the leading 16 x 16 tile of the symmetric 17 x 17 result on the matrix cores (the
       // additive terms as the accumulator's start); column 16 on the vector ALUs, entry i on
-      // lane i, also written as row 16
-      typename Mma<T>::acc h00;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h00[r] = h_base(Mma<T>::row(r, kq), r16);
+      // lane i, also written as row 16.  Operands first, as one group of LDS reads.
       const int ih = lane < NZ ? lane : NZ - 1;
-      T h16 = h_base(ih, 16);
+      HW3 hb[4], hb16 = h_words(ih, 16);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) hb[r] = h_words(Mma<T>::row(r, kq), r16);
+      T gi[NX], cv[NX], g0[4], c0[4];
       if (HAS_U) {
 #pragma unroll
-        for (int l = 0; l < NX; ++l) h16 += Gk[l * NZ + ih] * L.CV[l * NZ + 16];
+        for (int l = 0; l < NX; ++l) {
+          gi[l] = Gk[l * NZ + ih];
+          cv[l] = L.CV[l * NZ + 16];
+        }
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
-          const T g0 = Gk[kc * NZ + r16], c0 = L.CV[kc * NZ + r16];
-          h00 = Mma<T>::mma(kk < NX ? g0 : T(0), kk < NX ? c0 : T(0), h00);
+          g0[st] = Gk[kc * NZ + r16];
+          c0[st] = L.CV[kc * NZ + r16];
+        }
+      }
+      if constexpr (FENCE) sched_fence();
+      typename Mma<T>::acc h00;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h00[r] = h_base(Mma<T>::row(r, kq), r16, hb[r]);
+      T h16 = h_base(ih, 16, hb16);
+      if (HAS_U) {
+#pragma unroll
+        for (int l = 0; l < NX; ++l) h16 += gi[l] * cv[l];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int kk = 4 * st + kq;
+          h00 = Mma<T>::mma(kk < NX ? g0[st] : T(0), kk < NX ? c0[st] : T(0), h00);
         }
       }
 #pragma unroll
@@ -619,10 +661,19 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     const int li = lane < NX ? lane : NX - 1;
     if (HAS_U) {
       T lr[NU * NU], rr[NU];
+      // the control block's lower triangle and this lane's column of H_ux, as one group of reads
+      T huu[NU * NU], hux[NU];
+#pragma unroll
+      for (int j = 0; j < NU; ++j) {
+#pragma unroll
+        for (int i = j; i < NU; ++i) huu[i * NU + j] = L.H[(NX + i) * NZ + NX + j];
+        hux[j] = L.H[(NX + j) * NZ + li];
+      }
+      if constexpr (FENCE) sched_fence();
       int bad = 0;
 #pragma unroll
       for (int j = 0; j < NU; ++j) {
-        T d = L.H[(NX + j) * NZ + NX + j];
+        T d = huu[j * NU + j];
         const T d0 = d;
 #pragma unroll
         for (int l = 0; l < j; ++l) d -= lr[j * NU + l] * lr[j * NU + l];
@@ -635,7 +686,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         for (int i = 0; i < NU; ++i) {
           if (i < j) lr[i * NU + j] = 0.0;
           if (i <= j) continue;
-          T a = L.H[(NX + i) * NZ + NX + j];
+          T a = huu[i * NU + j];
 #pragma unroll
           for (int l = 0; l < j; ++l) a -= lr[i * NU + l] * lr[j * NU + l];
           lr[i * NU + j] = a * rr[j];
@@ -655,7 +706,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         T y[NU];
 #pragma unroll
         for (int a = 0; a < NU; ++a) {
-          T acc = L.H[(NX + a) * NZ + lane];
+          T acc = hux[a];
 #pragma unroll
           for (int l = 0; l < a; ++l) acc -= lr[a * NU + l] * y[l];
           y[a] = acc * rr[a];
@@ -698,9 +749,15 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     T* VV = L.CV + NX * NX;
     if (pair) {
       // C = I + Delta^1/2 P Delta^1/2, one row per lane, factored in registers
-      T cr[NX], ri[NX];
+      T cr[NX], ri[NX], pr[NX], dhv[NX];
 #pragma unroll
-      for (int l = 0; l < NX; ++l) cr[l] = dhl * L.P[li * NX + l] * L.dh[l] + (lane == l ? 1.0 : 0.0);
+      for (int l = 0; l < NX; ++l) {
+        pr[l] = L.P[li * NX + l];
+        dhv[l] = L.dh[l];
+      }
+      if constexpr (FENCE) sched_fence();
+#pragma unroll
+      for (int l = 0; l < NX; ++l) cr[l] = dhl * pr[l] * dhv[l] + (lane == l ? 1.0 : 0.0);
       const int r = chol_rows(cr, ri, lane);
       if (r) { status = r; return true; }
       if (lane < NX) {
@@ -717,9 +774,15 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         T v[NX];
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
-          T acc = inv ? (i == col ? 1.0 : 0.0) : L.dh[i] * L.P[i * NX + col];
+          // row i of L_C and the right-hand side entry, as one group of reads
+          T lc[NX];
+          const T di = L.dh[i], pic = L.P[i * NX + col];
 #pragma unroll
-          for (int l = 0; l < i; ++l) acc -= LC[i * NX + l] * v[l];
+          for (int l = 0; l < i; ++l) lc[l] = LC[i * NX + l];
+          if constexpr (FENCE) sched_fence();
+          T acc = inv ? (i == col ? 1.0 : 0.0) : di * pic;
+#pragma unroll
+          for (int l = 0; l < i; ++l) acc -= lc[l] * v[l];
           v[i] = acc * ri[i];
           if (inv) L.LI[i * NX + col] = v[i];
           else VV[i * NX + col] = v[i];
@@ -731,18 +794,31 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         // both Gram products on the matrix cores (K = 13 padded to 16)
         const int jc = r16 < NX ? r16 : 0;
         typename Mma<T>::acc sa, ma = {T(0), T(0), T(0), T(0)};
+        T pv[4], vv[4], lv[4], dr[4], rd[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = Mma<T>::row(r, kq);
-          const T pv = L.P[(i < NX ? i : 0) * NX + jc];
-          sa[r] = (i < NX && r16 < NX) ? pv : T(0);
+          const int i = Mma<T>::row(r, kq), ic = i < NX ? i : 0;
+          pv[r] = L.P[ic * NX + jc];
+          dr[r] = L.dh[jc];
+          rd[r] = L.rdh[ic];
         }
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const int l = 4 * st + kq, lc = l < NX ? l : 0;
+          vv[st] = VV[lc * NX + jc];
+          lv[st] = L.LI[lc * NX + jc];
+        }
+        if constexpr (FENCE) sched_fence();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = Mma<T>::row(r, kq);
+          sa[r] = (i < NX && r16 < NX) ? pv[r] : T(0);
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int l = 4 * st + kq;
           const bool ok = l < NX && r16 < NX;
-          const T vv = VV[lc * NX + jc], li = L.LI[lc * NX + jc];
-          const T v = ok ? vv : T(0), w = ok ? li : T(0);
+          const T v = ok ? vv[st] : T(0), w = ok ? lv[st] : T(0);
           sa = Mma<T>::mma(-v, v, sa);
           ma = Mma<T>::mma(w, w, ma);
         }
@@ -751,7 +827,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
           const int i = Mma<T>::row(r, kq);
           if (i < NX && r16 < NX) {
             L.S[i * NX + r16] = sa[r];
-            fr[FR_M + i * NX + r16] = ma[r] * L.dh[r16] * L.rdh[i];
+            fr[FR_M + i * NX + r16] = ma[r] * dr[r] * rd[r];
           }
         }
       }
@@ -786,11 +862,6 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 }
 
 // ----------------------------------------------------------------------------- solve
-// Scheduling fence: the compiler moves no instruction across it.  The sweeps load a knot's words
-// from LDS into registers, then fence, so that the loads are issued as one group and the
-// dependent products below wait once for the group instead of once per pair of words.
-__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
-
 // Apply M_k^{-1} of stage k (factor record F in LDS) to the stage right-hand side
 // (ra, rx, ru): ra[] holds the lambda part on every lane, rx the x component of row `lane`,
 // ru[] the control part on every lane.  Returns the lambda component a of row `lane`; with

@@ -741,10 +741,13 @@ __device__ __forceinline__ bool solve_refined(const Cfg& c, const Slot& s, const
   return ok;
 }
 
-// the structured factorization in the precision of this iteration
+// the structured factorization in the precision of this iteration.  FENCE64: the FP64 factor
+// groups its LDS reads behind scheduling fences (the mixed kernels, whose FP64 factor is the
+// fallback path, leave its scheduling to the compiler: the fences cost them registers)
+template <bool FENCE64 = true>
 __device__ __forceinline__ int factor_any(const Cfg& c, const Slot& s, const Elim& e, FacLds& L, bool f32, int lane) {
   if (f32) return kkt_factor(c, s, e, *reinterpret_cast<FacLdsT<float>*>(&L), lane);   // only mixed kernels
-  return kkt_factor(c, s, e, L, lane);
+  return kkt_factor<double, FENCE64>(c, s, e, L, lane);
 }
 
 // ---------------------------------------------------------------------------- k_pre
@@ -1028,6 +1031,7 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
 // perturbation; on a singular matrix add delta_c = delta_c_bar mu^kappa_c; then grow delta_x
 // from delta_0 (or kappa_minus times the last used value) by kappa_plus_bar / kappa_plus until
 // the inertia is (n, m, 0) or delta_x exceeds delta_max.
+template <bool FENCE64 = true>
 __device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L, bool fused, bool mixed, int lane) {
   const int work = (int)s.sc[SC_WORK];
   if (work == W_NONE) return;
@@ -1047,7 +1051,7 @@ __device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L,
   const int lane0 = lane;
   for (;;) {
     const int lane = opaque(lane0);
-    st = factor_any(c, s, e, L, f32, lane);
+    st = factor_any<FENCE64>(c, s, e, L, f32, lane);
     ++nfact;
     if (lsq) break;
     if (st == 0) { ok = true; break; }
@@ -1093,6 +1097,7 @@ __device__ __forceinline__ void fac_body(const Cfg& c, const Slot& s, FacLds& L,
 // one also initialises the filter bounds theta_max, theta_min.  At the cold start of a gated warm
 // start, E_mu0 of the cold start is recorded as the gate's reference and the warm point (row of
 // `warm`) is loaded for the next INIT_Y pass.
+template <bool FENCE64 = true>
 __device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, const double* warm, double* sol_dyn,
                                            FacLds* L, bool fused, bool mixed, int lane) {
   Elim e{true, false, 0.0, 0.0, 0.0};
@@ -1102,7 +1107,7 @@ __device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, const do
     // FP32 refinement failed: the least-squares system again in FP64
     if (lane == 0) { s.sc[SC_FORCE64] = 1.0; s.sc[SC_ST_FB] += 1.0; }
     __syncthreads();
-    fac_body(c, s, *L, fused, mixed, lane);
+    fac_body<FENCE64>(c, s, *L, fused, mixed, lane);
     fok = s.sc[SC_FSTAT] == 0.0;
     if (fok) fok = solve_refined(c, s, e, s.rv, s.dvs, nullptr, nullptr, s.dv, s.dy, nullptr, nullptr, sol_dyn, mixed, lane);
   }
@@ -1166,11 +1171,12 @@ __device__ __forceinline__ void sol_init_y(const Cfg& c, const Slot& s, const do
 
 // Step of eq. (7) from the stored factor, bound-multiplier steps, fraction to the boundary
 // (primal) and the directional derivative of phi_mu.
+template <bool FENCE64 = true>
 __device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, const double* warm, double* sol_dyn, FacLds* L,
                                          bool fused, bool mixed, int lane) {
   const int work = (int)s.sc[SC_WORK];
   if (work == W_NONE) return;
-  if (work == W_LSQ) { sol_init_y(c, s, warm, sol_dyn, L, fused, mixed, lane); return; }
+  if (work == W_LSQ) { sol_init_y<FENCE64>(c, s, warm, sol_dyn, L, fused, mixed, lane); return; }
   if ((int)s.sc[SC_STEP] != STEP_READY) {
     __syncthreads();
     if (lane == 0) s.sc[SC_WORK] = W_NONE;
@@ -1184,7 +1190,7 @@ __device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, const doub
     // FP32 refinement failed: factor this iteration again in FP64 (same inertia-correction start)
     if (lane == 0) { s.sc[SC_FORCE64] = 1.0; s.sc[SC_ST_FB] += 1.0; }
     __syncthreads();
-    fac_body(c, s, *L, fused, mixed, lane);
+    fac_body<FENCE64>(c, s, *L, fused, mixed, lane);
     __syncthreads();
     if ((int)s.sc[SC_STEP] != STEP_READY) {
       if (lane == 0) s.sc[SC_WORK] = W_NONE;
@@ -1876,10 +1882,10 @@ __device__ __forceinline__ void pass_phases(const Cfg& c, const Slot& s, const d
   pre_body(c, s, theta, warm, out, cnt, refill, lane);
   __syncthreads();
   const long long t1 = clock64();
-  fac_body(c, s, L, true, MIXED, lane);
+  fac_body<!MIXED>(c, s, L, true, MIXED, lane);
   __syncthreads();
   const long long t2 = clock64();
-  sol_body(c, s, warm, sol_dyn, &L, true, MIXED, lane);
+  sol_body<!MIXED>(c, s, warm, sol_dyn, &L, true, MIXED, lane);
   __syncthreads();
   const long long t3 = clock64();
   ls_body(c, s, sol_dyn, true, MIXED, lane);
