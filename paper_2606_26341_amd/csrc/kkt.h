@@ -659,6 +659,10 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     lds_barrier();
     // ---- control block: Cholesky of Hbar^uu (on every lane, in registers), Y, P ----
     const int li = lane < NX ? lane : NX - 1;
+    // pair pivot with the dual regularisation Delta_k of the rows defining x_k (Delta > 0 on every
+    // row exactly when delta_c > 0 or the elastic variables are eliminated); without it S_k = P_k,
+    // written where P is formed
+    const bool pair = !e.lsq && (e.resto || e.dcp > 0.0);
     if (HAS_U) {
       T lr[NU * NU], rr[NU];
       // the control block's lower triangle and this lane's column of H_ux, as one group of reads
@@ -711,6 +715,7 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
           for (int l = 0; l < a; ++l) acc -= lr[a * NU + l] * y[l];
           y[a] = acc * rr[a];
           L.Y[a * NX + lane] = y[a];
+          fr[FR_Y + a * NX + lane] = y[a];
         }
       }
       lds_barrier();
@@ -729,19 +734,25 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = Mma<T>::row(r, kq);
-          if (i < NX && r16 < NX) L.P[i * NX + r16] = p[r];
+          if (i < NX && r16 < NX) {
+            L.P[i * NX + r16] = p[r];
+            fr[FR_P + i * NX + r16] = p[r];
+            if (!pair) L.S[i * NX + r16] = p[r];
+          }
         }
       }
     } else {
 #pragma unroll
       for (int t = 0; t < TILE_P; ++t) {
         const int q = lane + WAVE * t;
-        L.P[q] = L.H[(q / NX) * NZ + q % NX];
+        const T pv = L.H[(q / NX) * NZ + q % NX];
+        L.P[q] = pv;
+        if (q < NX * NX) fr[FR_P + q] = pv;
+        if (!pair) L.S[q] = pv;
       }
+      if (lane < NU * NX) fr[FR_Y + lane] = T(0);
     }
     // ---- pair pivot with the dual regularisation Delta_k of the rows defining x_k ----
-    // (Delta > 0 on every row exactly when delta_c > 0 or the elastic variables are eliminated)
-    const bool pair = !e.lsq && (e.resto || e.dcp > 0.0);
     const T dhl = pair ? T(sqrt(row_dreg(e, SD[NZ + li], SD[NZ + NX + li]))) : T(0);
     if (lane < NX) L.dh[lane] = dhl;
     lds_barrier();
@@ -831,20 +842,8 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
           }
         }
       }
-    } else {
-#pragma unroll
-      for (int t = 0; t < TILE_P; ++t) {
-        const int q = lane + WAVE * t;
-        L.S[q] = L.P[q];
-      }
     }
-    // ---- store the stage factor ----
-    if (lane < NU * NX) fr[FR_Y + lane] = L.Y[lane];
-#pragma unroll
-    for (int t = 0; t < TILE_P; ++t) {
-      const int q = lane + WAVE * t;
-      if (q < NX * NX) fr[FR_P + q] = L.P[q];
-    }
+    // ---- store the rest of the stage factor (Y and P were stored where formed) ----
     if (lane < NX) fr[FR_DH + lane] = dhl;
     if (lane == 0) fr[FR_FLAG] = pair ? 1.0 : 0.0;
     if (MORE) stage_park(L.buf, lane, reg);
