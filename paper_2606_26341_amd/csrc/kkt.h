@@ -566,8 +566,14 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
     // columns 0..15 on the matrix cores (K = 13 padded to 16; one 16 x 16 x 4 product costs about
     // as much as eleven FMAs of a wavefront), column 16 on the vector ALUs, row i on lane i
     const int r16 = lane & 15, kq = lane >> 4, li0 = lane < NX ? lane : NX - 1;
+    // In FP64 the product's item st on lane l is T(4 st + l/16, l%16), the B operand of step st of
+    // G^T T below, so T stays in registers (column 16 is broadcast from its lanes); the FP32
+    // product's items are laid out differently and pass through LDS, as they do in the unfenced
+    // FP64 fallback of the mixed kernels (fewer registers).
+    constexpr bool REG_T = sizeof(T) == sizeof(double) && FENCE;
+    typename Mma<T>::acc t0 = {T(0), T(0), T(0), T(0)};
+    T t16 = 0.0;
     if (HAS_U) {
-      typename Mma<T>::acc t0 = {T(0), T(0), T(0), T(0)};
       // operands first, as one group of LDS reads
       T sr[NX], gc[NX], sv[4], g0[4];
 #pragma unroll
@@ -582,7 +588,6 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         g0[st] = Gk[kc * NZ + r16];
       }
       if constexpr (FENCE) sched_fence();
-      T t16 = 0.0;
 #pragma unroll
       for (int l = 0; l < NX; ++l) t16 += sr[l] * gc[l];
 #pragma unroll
@@ -591,13 +596,15 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
         const T a = (kk < NX && r16 < NX) ? sv[st] : T(0);
         t0 = Mma<T>::mma(a, kk < NX ? g0[st] : T(0), t0);
       }
+      if constexpr (!REG_T) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = Mma<T>::row(r, kq);
-        if (i < NX) L.CV[i * NZ + r16] = t0[r];
+        for (int r = 0; r < 4; ++r) {
+          const int i = Mma<T>::row(r, kq);
+          if (i < NX) L.CV[i * NZ + r16] = t0[r];
+        }
+        if (lane < NX) L.CV[lane * NZ + 16] = t16;
+        lds_barrier();
       }
-      if (lane < NX) L.CV[lane * NZ + 16] = t16;
-      lds_barrier();
     }
     // ---- stage Hessian (NZ stride): W_k + diag + delta_x I + Hc_k + G_k^T T ----
     // the words of entry (i, j): W_ij, the diagonal term of column j, the condensed block's entry
@@ -626,13 +633,15 @@ __device__ __forceinline__ int kkt_factor(const Cfg& c, const Slot& s, const Eli
 #pragma unroll
         for (int l = 0; l < NX; ++l) {
           gi[l] = Gk[l * NZ + ih];
-          cv[l] = L.CV[l * NZ + 16];
+          if constexpr (REG_T) cv[l] = lane_bcast(t16, l);
+          else cv[l] = L.CV[l * NZ + 16];
         }
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
           const int kk = 4 * st + kq, kc = kk < NX ? kk : 0;
           g0[st] = Gk[kc * NZ + r16];
-          c0[st] = L.CV[kc * NZ + r16];
+          if constexpr (REG_T) c0[st] = t0[st];
+          else c0[st] = L.CV[kc * NZ + r16];
         }
       }
       if constexpr (FENCE) sched_fence();
