@@ -65,35 +65,12 @@ __device__ __forceinline__ void eval_c(const Cfg& c, const Slot& s, bool resto, 
 __device__ __forceinline__ void eval_grad(const Cfg& c, const Slot& s, const double* yv, bool resto, double zeta, double* aty,
                           int lane) {
   const int N = c.N, NI = c.NI;
-  lanes_for(c.n, lane, [&](int i) {
-    double w = 0.0;
-    if (resto) {
-      w = s.xr[i];
-    } else if (i < c.n_w) {
-      const int k = i / NZ, r = i % NZ;
-      if (r < NX) w = s.ref[k * NX + r];
-    }
-    return DV<2>{{s.v[i], w}};
-  }, [&](int i, const DV<2>& t) {
-    double gi = 0.0;
-    if (resto) {
-      double d = fmin(1.0, 1.0 / fabs(t.v[1]));
-      gi = zeta * d * d * (t.v[0] - t.v[1]);
-    } else if (i < c.n_w) {
-      int r = i % NZ;
-      if (r < NX) {
-        gi = 2.0 * c.qw * (t.v[0] - t.v[1]);
-      } else {
-        gi = 2.0 * c.rw * (t.v[0] - c.uh);
-      }
-    }
-    s.g[i] = gi;
-  });
-  // A^T y.  Every load of a trip (the identity row, column r of G_k with y_{k+1}, the first
+  // grad f (into g) and A^T y (into aty) in one lane loop.  Every load of a trip (v_i and its
+  // reference or restoration point, the identity row, column r of G_k with y_{k+1}, the first
   // OBS_CHUNK inequality rows of knot k) is issued before the first use, from valid addresses on
   // every lane, two trips at a time, so that a pair of trips waits for memory once.
   struct AtyIn {
-    double ys, vi, gc[NX], yn[NX], oc[OBS_CHUNK], yg[OBS_CHUNK];
+    double ys, vi, wi, gc[NX], yn[NX], oc[OBS_CHUNK], yg[OBS_CHUNK];
   };
   auto load_obs = [&](int j0, int ko, int ro, double* oc, double* yg) {
 #pragma unroll
@@ -107,12 +84,19 @@ __device__ __forceinline__ void eval_grad(const Cfg& c, const Slot& s, const dou
   };
   lanes_for<2>(c.n, lane, [&](int i) {
     AtyIn t;
+    t.vi = s.v[i];
+    t.wi = 0.0;
+    if (resto) {
+      t.wi = s.xr[i];
+    } else if (i < c.n_w) {
+      const int k = i / NZ, r = i % NZ;
+      if (r < NX) t.wi = s.ref[k * NX + r];
+    }
     if (i < c.n_w) {
       const int k = i / NZ, r = i % NZ;
       const int kg = k < N ? k : N - 1, ko = k >= 1 ? k : 1, ro = r < 3 ? r : 0;
       const double* Gk = s.G + (long long)kg * NX * NZ;
       t.ys = yv[k * NX + (r < NX ? r : 0)];
-      t.vi = s.v[i];
 #pragma unroll
       for (int l = 0; l < NX; ++l) {
         t.gc[l] = Gk[l * NZ + r];
@@ -125,6 +109,19 @@ __device__ __forceinline__ void eval_grad(const Cfg& c, const Slot& s, const dou
     }
     return t;
   }, [&](int i, const AtyIn& t) {
+    double gi = 0.0;
+    if (resto) {
+      double d = fmin(1.0, 1.0 / fabs(t.wi));
+      gi = zeta * d * d * (t.vi - t.wi);
+    } else if (i < c.n_w) {
+      int r = i % NZ;
+      if (r < NX) {
+        gi = 2.0 * c.qw * (t.vi - t.wi);
+      } else {
+        gi = 2.0 * c.rw * (t.vi - c.uh);
+      }
+    }
+    s.g[i] = gi;
     double a = 0.0;
     if (i < c.n_w) {
       const int k = i / NZ, r = i % NZ;
@@ -994,7 +991,11 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
     __syncthreads();
   }
   // ---- barrier gradient, right-hand side of eq. (7), theta_k, phi_k ----
-  lanes_for(c.n, lane, [&](int i) { return DV<3>{{s.g[i], s.v[i], s.vt[i]}}; }, [&](int i, const DV<3>& t) {
+  // (the same lane loop forms this lane's partial sum of the regular objective at v)
+  double freg = 0.0;
+  lanes_for(c.n, lane, [&](int i) {
+    return DV<4>{{s.g[i], s.v[i], s.vt[i], !resto && i < c.n_w ? obj_ref(s, i) : 0.0}};
+  }, [&](int i, const DV<4>& t) {
     double gp = t.v[0];
     if (i < c.n_w) {
       int k = i / NZ, r = i % NZ;
@@ -1002,6 +1003,7 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
         double u = t.v[1];
         gp += -mu / u + mu / (c.umax - u);
       }
+      if (!resto) obj_term(c, i, t.v[1], t.v[3], freg);
     } else {
       gp -= mu / t.v[1];
     }
@@ -1016,7 +1018,7 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
   double thk = 0.0;
   lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; }, [&](int r, const DV<1>& t) { thk += fabs(t.v[0]); });
   thk = wsum(thk);
-  double fk = resto ? obj_resto(c, s, s.v, s.p, s.nn, zeta, lane) : obj_regular(c, s, s.v, lane);
+  double fk = resto ? obj_resto(c, s, s.v, s.p, s.nn, zeta, lane) : wsum(freg);
   double phk = fk - mu * log_barrier(c, s.v, s.p, s.nn, resto, lane);
   Elim e{false, resto, 0.0, 0.0, zeta};
   kkt_stage_data(c, s, it, e, lane);
