@@ -1904,18 +1904,32 @@ __device__ __forceinline__ void pass_phases(const Cfg& c, const Slot& s, const d
 // Derivatives of one slot at its current point (what the derivative kernel computes for it): RK4
 // step F_k, G_k = dF/d(x, u) and W_k = -sum_r y_r Hess F_r per interval, one (interval, direction)
 // item per lane.
-__device__ __forceinline__ void eval_slot(const Cfg& c, const Slot& s, int lane) {
+// The stage points (x_k, u_k) and the multipliers y_{k+1}, k < N, are first copied into LDS (lds:
+// the pass's dynamic LDS region, free before the factorization) in a few groups of loads, so that
+// each of the directions a lane evaluates in turn reads its inputs from LDS, not from memory.
+constexpr int EVAL_LDS_DOUBLES = MAX_N * (NZ + NX);
+static_assert(EVAL_LDS_DOUBLES * sizeof(double) <= sizeof(FacLds), "derivative inputs exceed the pass LDS region");
+__device__ __forceinline__ void eval_slot(const Cfg& c, const Slot& s, double* lds, int lane) {
   const int ph = (int)s.sc[SC_PHASE];
   const double* yv = (ph == PH_RESTO) ? s.yr : s.y;
+  const int nz = c.N * NZ, ny = c.N * NX;
+  double* lv = lds;            // v[0, N NZ): x_k, u_k
+  double* ly = lds + nz;       // y[NX, (N+1) NX): y_{k+1}
+  lanes_for(nz, lane, [&](int q) { return DV<2>{{s.v[q], yv[NX + min(q, ny - 1)]}}; },
+            [&](int q, const DV<2>& t) {
+              lv[q] = t.v[0];
+              if (q < ny) ly[q] = t.v[1];
+            });
+  __syncthreads();
   for (int q = lane; q < c.N * NZ; q += WAVE) {
     const int k = q / NZ, j = q % NZ;
     double x[NX], u[NU], lam[NX], Fv[NX], Gc[NX], Hc[NZ];
 #pragma unroll
-    for (int i = 0; i < NX; ++i) x[i] = s.v[xo(k) + i];
+    for (int i = 0; i < NX; ++i) x[i] = lv[xo(k) + i];
 #pragma unroll
-    for (int i = 0; i < NU; ++i) u[i] = s.v[uo(k) + i];
+    for (int i = 0; i < NU; ++i) u[i] = lv[uo(k) + i];
 #pragma unroll
-    for (int i = 0; i < NX; ++i) lam[i] = -yv[(k + 1) * NX + i];
+    for (int i = 0; i < NX; ++i) lam[i] = -ly[k * NX + i];
     rk4_deriv_dir(c, x, u, lam, j, j == 0 ? Fv : nullptr, Gc, Hc);
     double* G = s.G + (long long)k * NX * NZ;
     double* H = s.HW + (long long)k * NZ * NZ;
@@ -1954,7 +1968,7 @@ __global__ __launch_bounds__(64) void k_run(Cfg c0, double* ws, const double* th
     const Slot s = make_slot(c, ws, b);
     if ((int)s.sc[SC_PHASE] == PH_EMPTY) return;
     const long long t0 = clock64();
-    eval_slot(c, s, lane);
+    eval_slot(c, s, sol_dyn, lane);
     const long long t1 = clock64();
     pass_phases<MIXED>(c, s, theta, warm, out, cnt, 1, L, sol_dyn, lane);
     if (lane == 0) s.sc[SC_CYC_EVAL] += (double)(t1 - t0);
