@@ -176,8 +176,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=30, help="warm-start training epochs (C5)")
     ap.add_argument("--oracle-check", type=int, default=1024, help="C5 instances re-solved by the oracle")
     ap.add_argument("--async-passes", type=int, default=64,
-                    help="passes each slot runs per launch of the asynchronous-slot kernel in the plain leg "
-                         "(0: one launch per pass)")
+                    help="passes each slot runs per launch of the asynchronous-slot kernel, plain and warm/mixed "
+                         "legs (0: one launch per pass)")
     ap.add_argument("--fuse-below", type=int, default=None,
                     help="unfinished-instance count below which passes use the fused kernel (default: library's)")
     args = ap.parse_args()
@@ -299,7 +299,7 @@ def warm_mixed_leg(args):
     from paper_2606_26341_amd import hipipm, workloads as W
     w = W.get("C5")
     TH = torch.tensor(w.thetas(0, w.n_inst), dtype=torch.float64, device="cuda:0")
-    opts = dict(timing=1, precision=1)
+    opts = dict(timing=1, precision=1, async_passes=args.async_passes)
     warm_fn, extra = setup_warm_start(w, TH, opts, args)
     s = hipipm.Solver(w, w.n_inst, hipipm.default_options(**opts))
     dt, conv, out, st, kt = time_solves(s, TH, args.steps, args.warmup, warm_fn, stream=not args.no_stream)
@@ -440,7 +440,7 @@ def compare_variants(w, TH, warm_out, args, extra, warm_fn):
     res = {}
     ref = None
     for name, prec, warm in (("cold_fp64", 0, False), ("cold_fp32ir", 1, False), ("warm_fp64", 0, True)):
-        o = dict(timing=0, precision=prec)
+        o = dict(timing=0, precision=prec, async_passes=args.async_passes)
         fn = None
         if warm:
             o.update(warm_mu0=extra["warm_mu0"], warm_iter_cap=extra["warm_iter_cap"])
