@@ -4,8 +4,9 @@ A step is one batched solve of the whole workload (every instance run to converg
 all method steps: derivatives, KKT assembly + inertia-correcting factorization, step, filter
 line search with SOC, restoration, barrier update, slot refill).  `value` is the plain form:
 C2, figure-eight tracking NMPC, 4096 instances, N = 30, 8 obstacles, FP64, cold start; the timed
-batches are streamed one after another through 16384 slots (four batches in flight), each slot
-running up to 64 passes per launch of the asynchronous-slot kernel.
+batches are streamed one after another through as many slots as the GPU keeps resident in the
+asynchronous-slot kernel (hipipm_resident_slots), in one launch: every slot runs passes back to
+back and refills from the device queue until the stream is done.
 
 The same run measures the other half of the metric, the warm/mixed form (object `warm_mixed`):
 the learned warm start on 16384 point-to-point instances (N = 10, 3 obstacles).  Outside the
@@ -157,8 +158,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="C2", help="workload of the plain FP64 cold-start leg (`value`)")
     ap.add_argument("--slots", type=int, default=0,
-                    help="slots of the plain leg (default: four times the instances of a batch, so that four "
-                         "batches of the stream are in flight)")
+                    help="slots of the plain and warm/mixed legs (default: the slots the GPU keeps resident in the "
+                         "asynchronous-slot kernel, hipipm_resident_slots)")
     ap.add_argument("--instances", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="oracle instances for the CPU baseline (default: about 10-30 s of host work per workload)")
@@ -175,7 +176,7 @@ def main():
     ap.add_argument("--val", type=int, default=10000, help="warm-start validation instances (C5)")
     ap.add_argument("--epochs", type=int, default=30, help="warm-start training epochs (C5)")
     ap.add_argument("--oracle-check", type=int, default=1024, help="C5 instances re-solved by the oracle")
-    ap.add_argument("--async-passes", type=int, default=64,
+    ap.add_argument("--async-passes", type=int, default=1 << 20,
                     help="passes each slot runs per launch of the asynchronous-slot kernel, plain and warm/mixed "
                          "legs (0: one launch per pass)")
     ap.add_argument("--fuse-below", type=int, default=None,
@@ -200,11 +201,11 @@ def main():
 
     w = W.get(args.workload)
     n_inst = args.instances or w.n_inst
-    slots = args.slots or 4 * n_inst
     TH = torch.tensor(w.thetas(0, n_inst), dtype=torch.float64, device="cuda:0")
     opts = dict(timing=1, precision=args.precision or 0, async_passes=args.async_passes)
     if args.fuse_below is not None:
         opts["fuse_below"] = args.fuse_below
+    slots = args.slots or hipipm.resident_slots(w, hipipm.default_options(**opts))
     log(f"[bench] plain leg {w.name}: {n_inst} instances, N={w.N}, n={w.n}, m={w.m}, slots={slots}, "
         f"{'streamed' if not args.no_stream else 'one solve per step'}")
     solver = hipipm.Solver(w, slots, hipipm.default_options(**opts))
@@ -245,7 +246,8 @@ def main():
                    "batches": ("the timed steps streamed through the slots in one solve (iteration-level "
                                "batching across batches)") if not args.no_stream else "one solve per step",
                    "pass_kernel": (f"asynchronous slots: every slot runs up to {args.async_passes} whole passes "
-                                   "per launch" if args.async_passes > 0 else "one launch per pass"),
+                                   "per launch, refilling from the device queue" if args.async_passes > 0
+                                   else "one launch per pass"),
                    "obstacles": "centres on the reference path + N(0, 0.5^2 I), kept 0.1 m from the start and "
                                 "0.3 m from the first 0.5 s of the reference"},
         "single_batch_ms": single_ms,
@@ -301,12 +303,13 @@ def warm_mixed_leg(args):
     TH = torch.tensor(w.thetas(0, w.n_inst), dtype=torch.float64, device="cuda:0")
     opts = dict(timing=1, precision=1, async_passes=args.async_passes)
     warm_fn, extra = setup_warm_start(w, TH, opts, args)
-    s = hipipm.Solver(w, w.n_inst, hipipm.default_options(**opts))
+    slots = args.slots or hipipm.resident_slots(w, hipipm.default_options(**opts))
+    s = hipipm.Solver(w, slots, hipipm.default_options(**opts))
     dt, conv, out, st, kt = time_solves(s, TH, args.steps, args.warmup, warm_fn, stream=not args.no_stream)
     log(f"[bench] warm/mixed: {args.steps} steps in {dt:.3f} s; stats {st}")
     res = dict(workload="C5: point-to-point NMPC, 16384 instances, N = 10, 3 obstacles; learned BF16 warm start "
                         "+ FP32 factor with FP64 refinement",
-               solves_per_sec=conv / dt, ms_per_step=dt * 1e3 / args.steps,
+               slots=slots, solves_per_sec=conv / dt, ms_per_step=dt * 1e3 / args.steps,
                iterations_per_solve=float(out["iters"].float().mean().item()),
                max_iterations=int(out["iters"].max().item()),
                converged_fraction=float((out["status"] == 1).float().mean().item()),
@@ -445,7 +448,8 @@ def compare_variants(w, TH, warm_out, args, extra, warm_fn):
         if warm:
             o.update(warm_mu0=extra["warm_mu0"], warm_iter_cap=extra["warm_iter_cap"])
             fn = warm_fn
-        s = hipipm.Solver(w, TH.shape[0], hipipm.default_options(**o))
+        slots = args.slots or hipipm.resident_slots(w, hipipm.default_options(**o))
+        s = hipipm.Solver(w, slots, hipipm.default_options(**o))
         dt, conv, out, st, _ = time_solves(s, TH, args.steps, 1, fn, stream=not args.no_stream)
         res[name] = dict(solves_per_sec=conv / dt, iterations_per_solve=float(out["iters"].float().mean().item()),
                          max_iterations=int(out["iters"].max().item()),

@@ -181,6 +181,14 @@ int hipipm_create(const hipipm_problem_desc* d, const hipipm_options* o, int32_t
 /* Sizes of one instance (n variables incl. slacks, m constraints, theta length, ...). */
 int hipipm_get_dims(const hipipm_ctx* ctx, hipipm_dims* out);
 
+/* Slots the context's device runs at once in the asynchronous-slot kernel (options.async_passes >
+ * 0) for this problem and precision: the kernel's workgroups per compute unit (registers, LDS)
+ * times the compute units.  A context with this many slots and a large async_passes keeps every
+ * slot resident for the whole solve, in one launch: no slot's instance waits for a compute unit
+ * and no launch ends with some units idle while the last slots finish.  Queries the device;
+ * allocates nothing.  For callers sizing a persistent solve. */
+int hipipm_resident_slots(const hipipm_ctx* ctx, int32_t* slots);
+
 /* Device workspace needed for the context's slot count, in bytes (256-byte aligned base). */
 int hipipm_workspace_bytes(const hipipm_ctx* ctx, size_t* bytes);
 

@@ -28,6 +28,8 @@ void launch_run_fp64(const Cfg& c, double* ws, int slots, const double* theta, c
                      Counters* cnt, int passes, hipStream_t st);
 void launch_run_mixed(const Cfg& c, double* ws, int slots, const double* theta, const double* warm, Outs out,
                       Counters* cnt, int passes, hipStream_t st);
+int occupancy_run_fp64(const Cfg& c);
+int occupancy_run_mixed(const Cfg& c);
 void launch_setup(const Cfg& c, double* ws, int slots, int n_active, const double* theta, const double* warm,
                   hipStream_t st);
 void launch_stage_derivs(const Cfg& c, int count, const double* x, const double* u, const double* lam, double* F,
@@ -230,6 +232,15 @@ int hipipm_get_dims(const hipipm_ctx* c, hipipm_dims* out) {
   out->n = c->cfg.n; out->m = c->cfg.m; out->n_w = c->cfg.n_w; out->n_s = c->cfg.n_s;
   out->n_theta = c->cfg.n_theta; out->n_lower = c->cfg.n_lower; out->n_upper = c->cfg.n_upper;
   out->N = c->cfg.N; out->nx = NX; out->nu = NU; out->n_ineq = c->cfg.NI;
+  return HIPIPM_OK;
+}
+
+int hipipm_resident_slots(const hipipm_ctx* c, int32_t* slots) {
+  if (!c || !slots) return HIPIPM_ERR_INVALID_ARG;
+  const int per_cu = c->opts.precision == 1 ? occupancy_run_mixed(c->cfg) : occupancy_run_fp64(c->cfg);
+  hipDeviceProp_t p;
+  if (per_cu < 0 || hipGetDeviceProperties(&p, c->device) != hipSuccess) return HIPIPM_ERR_HIP;
+  *slots = per_cu * p.multiProcessorCount;
   return HIPIPM_OK;
 }
 

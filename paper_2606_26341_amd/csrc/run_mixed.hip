@@ -7,4 +7,10 @@ void launch_run_mixed(const Cfg& c, double* ws, int slots, const double* theta, 
                       Counters* cnt, int passes, hipStream_t st) {
   hipLaunchKernelGGL(k_run<true>, dim3(slots), dim3(WAVE), pass_lds_bytes(c), st, c, ws, theta, warm, out, cnt, passes);
 }
+// workgroups of k_run<true> one compute unit holds at once (registers and LDS); -1 on a HIP error
+int occupancy_run_mixed(const Cfg& c) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_run<true>, WAVE, pass_lds_bytes(c)) != hipSuccess) return -1;
+  return nb;
+}
 }  // namespace hipipm

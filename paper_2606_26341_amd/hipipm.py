@@ -65,7 +65,7 @@ class Stats(C.Structure):
 
 
 _lib = None
-EXPORTS = ("hipipm_default_options", "hipipm_create", "hipipm_get_dims", "hipipm_workspace_bytes",
+EXPORTS = ("hipipm_default_options", "hipipm_create", "hipipm_get_dims", "hipipm_resident_slots", "hipipm_workspace_bytes",
            "hipipm_bind_workspace", "hipipm_solve", "hipipm_solve_noalloc", "hipipm_stats_get", "hipipm_reset_stats",
            "hipipm_kernel_times", "hipipm_state_len", "hipipm_state_import", "hipipm_start", "hipipm_step",
            "hipipm_state_export", "hipipm_kkt_factor_solve", "hipipm_stage_derivs", "hipipm_last_error",
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
     L.hipipm_default_options.argtypes = [vp]
     L.hipipm_create.argtypes = [vp, vp, i32, C.POINTER(vp)]
     L.hipipm_get_dims.argtypes = [vp, vp]
+    L.hipipm_resident_slots.argtypes = [vp, C.POINTER(i32)]
     L.hipipm_workspace_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
     L.hipipm_bind_workspace.argtypes = [vp, vp, C.c_size_t]
     L.hipipm_solve.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -135,6 +136,30 @@ def _stream(stream):
 
 class HipipmError(RuntimeError):
     pass
+
+
+def resident_slots(workload, options: Options | None = None, device=None) -> int:
+    """Slots the GPU runs at once in the asynchronous-slot kernel for this workload and options
+    (hipipm_resident_slots): with that many slots and a large async_passes a solve is one launch
+    with every slot resident."""
+    if not torch.cuda.is_available():
+        raise HipipmError("hipipm needs a ROCm GPU (torch.cuda.is_available() is False)")
+    L = load()
+    torch.cuda.set_device(torch.device(device if device is not None else "cuda:0"))
+    desc = desc_from(workload)
+    opts = options if options is not None else default_options()
+    h = C.c_void_p()
+    rc = L.hipipm_create(C.byref(desc), C.byref(opts), 1, C.byref(h))
+    if rc != 0:
+        raise HipipmError(f"hipipm_create failed with {rc}")
+    n = C.c_int32()
+    try:
+        rc = L.hipipm_resident_slots(h, C.byref(n))
+        if rc != 0:
+            raise HipipmError(f"hipipm_resident_slots failed with {rc}: {L.hipipm_last_error(h).decode()}")
+    finally:
+        L.hipipm_destroy(h)
+    return int(n.value)
 
 
 class Solver:

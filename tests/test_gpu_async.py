@@ -42,3 +42,23 @@ def test_async_slots_match_pass_kernels(torch_cuda, name, n_inst, slots, prec, p
               "factorizations"):
         assert st[k] == st_ref[k], k
     say("statuses", np.bincount(got["status"], minlength=6), "iterations", st["iterations"])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_resident_slots_single_launch_matches_pass_kernels(torch_cuda, prec):
+    """hipipm_resident_slots: a whole number of workgroups per compute unit (at least one); a
+    solve through exactly that many slots with an unbounded pass count (one launch, every slot
+    resident, instances outnumbering the slots) equals the per-pass kernels bit for bit."""
+    torch = torch_cuda
+    from paper_2606_26341_amd import hipipm
+    w = W.get("C2")
+    n = hipipm.resident_slots(w, hipipm.default_options(precision=prec))
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    say("resident slots", n, "compute units", cus, "precision", prec)
+    assert n >= cus and n % cus == 0
+    TH = torch.tensor(w.thetas(0, n + n // 2 + 7), dtype=torch.float64, device="cuda")
+    ref, st_ref = _solve(torch, w, TH, n, precision=prec)
+    got, st = _solve(torch, w, TH, n, precision=prec, async_passes=1 << 20)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k], equal_nan=True), k
+    assert st["iterations"] == st_ref["iterations"]
