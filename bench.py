@@ -44,8 +44,8 @@ FP64_PEAK_TFLOPS = 78.6
 # scaled by the same counters on a plain device copy of known size, per slot-iteration the
 # launches ran; a run's traffic per launch is that times its iterations per launch.  Valid only
 # for the kernel sources they were taken on (hash below), the workload and the slot count named.
-MEASURED_TRAFFIC = {"k_run": {"csrc": "9c54ce98183376c7", "workload": "C2", "slots": 16384,
-                              "bytes_per_iteration": 1.0326e6}}
+MEASURED_TRAFFIC = {"k_run": {"csrc": "e1a9b8be6276f41b", "workload": "C2", "slots": 1024,
+                              "bytes_per_iteration": 1.0481e6}}
 
 
 def csrc_hash() -> str:
@@ -263,7 +263,7 @@ def main():
                                                  "fp64_frac", "share_of_gpu_time")},
         "kernel_ms": {k: v[0] for k, v in kt.items()},
         "stats": {k: st[k] for k in ("iterations", "resto_iterations", "resto_entries", "soc_tried", "soc_accepted",
-                                     "tiny_steps", "factorizations", "passes")},
+                                     "tiny_steps", "factorizations")},
     }
     if not args.no_phase_leg:
         res["per_phase_leg"] = phase_leg(w, TH, n_inst)
@@ -313,7 +313,6 @@ def warm_mixed_leg(args):
                iterations_per_solve=float(out["iters"].float().mean().item()),
                max_iterations=int(out["iters"].max().item()),
                converged_fraction=float((out["status"] == 1).float().mean().item()),
-               passes_per_solve=st["passes"] / args.steps,
                warm_started=st["warm_started"], warm_rejected=st["warm_rejected"],
                warm_restarts=st["warm_restarts"],
                fallback_rate=(st["warm_rejected"] + st["warm_restarts"]) / max(1, st["instances_done"]),
@@ -454,7 +453,7 @@ def compare_variants(w, TH, warm_out, args, extra, warm_fn):
         res[name] = dict(solves_per_sec=conv / dt, iterations_per_solve=float(out["iters"].float().mean().item()),
                          max_iterations=int(out["iters"].max().item()),
                          converged_fraction=float((out["status"] == 1).float().mean().item()),
-                         passes_per_solve=st["passes"] / args.steps, fp64_fallbacks=st["fp64_fallbacks"],
+                         fp64_fallbacks=st["fp64_fallbacks"],
                          warm_restarts=st["warm_restarts"])
         if name == "cold_fp64":
             ref = {k: v.clone() for k, v in out.items()}
