@@ -129,7 +129,8 @@ typedef struct {
                              polls after each launch.  0 (default): one launch per phase or one fused
                              launch per pass, every slot advancing one pass per launch.  Results are
                              the same either way; best with slots = the number of resident
-                             workgroups (one per SIMD) */
+                             workgroups (hipipm_resident_slots) and a pass count large enough
+                             for the whole solve to be one launch */
     int32_t nested_resto; /* nested hard restoration (Table I row 6): when the restoration phase cannot
                              make progress (its line search or inertia correction fails) at a point
                              where its own constraints c(x) - p + n = 0 are violated by more than tol,
