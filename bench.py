@@ -220,6 +220,24 @@ def main():
     torch.cuda.synchronize()
     single_ms = (time.perf_counter() - t1) * 1e3
     del o1
+    # the stream's marginal rate (context, not `value`): a stream of half the timed batches beside
+    # the timed one; the difference is the cost of the extra batches without the stream's end,
+    # which is the slowest instance's own latency
+    marginal = None
+    if not args.no_stream and args.steps >= 4:
+        half = args.steps // 2
+        TSh = TH.repeat(half, 1).contiguous()
+        oh = solver.alloc_outputs(TSh.shape[0])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        solver.solve(TSh, out=oh)
+        torch.cuda.synchronize()
+        half_s = time.perf_counter() - t2
+        conv_half = int((oh["status"] == 1).sum().item())
+        del oh, TSh
+        if dt > half_s:
+            marginal = dict(batches=[half, args.steps], seconds=[half_s, dt],
+                            solves_per_sec=(conv - conv_half) / (dt - half_s))
     dom, roofs = kernel_roofline(w, st, kt, word_bytes=4.0 if opts["precision"] == 1 else 8.0)
     roof = roofs[dom]
     mt = MEASURED_TRAFFIC.get(dom)
@@ -251,6 +269,7 @@ def main():
                    "obstacles": "centres on the reference path + N(0, 0.5^2 I), kept 0.1 m from the start and "
                                 "0.3 m from the first 0.5 s of the reference"},
         "single_batch_ms": single_ms,
+        "stream_marginal": marginal,
         "single_batch_solves_per_sec": float((out["status"] == 1).sum().item()) / (single_ms * 1e-3),
         "iterations_per_sec": st["iterations"] / dt,
         "iterations_per_solve": float(out["iters"].float().mean().item()),
