@@ -44,18 +44,21 @@ FP64_PEAK_TFLOPS = 78.6
 # scaled by the same counters on a plain device copy of known size, per slot-iteration the
 # launches ran; a run's traffic per launch is that times its iterations per launch.  Valid only
 # for the kernel sources they were taken on (hash below), the workload and the slot count named.
-MEASURED_TRAFFIC = {"k_run": {"csrc": "e1a9b8be6276f41b", "workload": "C2", "slots": 1024,
+MEASURED_TRAFFIC = {"k_run": {"csrc": "cb4ca52405764b10", "workload": "C2", "slots": 1024,
                               "bytes_per_iteration": 1.0481e6}}
+
+
+# the sources the FP64 asynchronous-slot kernel k_run<false> is built from
+K_RUN_SOURCES = ("common.h", "kkt.h", "model.h", "slot.h", "run_fp64.hip")
 
 
 def csrc_hash() -> str:
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2606_26341_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".h", ".hip")):
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in K_RUN_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -1,7 +1,7 @@
 // The warm-start network (a multilayer perceptron from instance parameters to a primal trajectory
 // and equality multipliers): d_in -> H -> H -> H -> d_out, GELU after each hidden layer.
 // Weights and activations enter the matrix products in BF16, every product accumulates in FP32
-// on the matrix cores (v_mfma_f32_16x16x16_bf16); biases, pre-activations, the loss, gradients
+// on the matrix cores (v_mfma_f32_16x16x32_bf16); biases, pre-activations, the loss, gradients
 // and the Adam state are FP32.  Inputs and targets are normalised per column with statistics
 // stored in the model buffer.
 //
@@ -60,58 +60,53 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __builtin_bit_ca
 // ---------------------------------------------------------------------------- GEMM
 // C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m*sam + k*sak], B(k, n) = B[k*sbk + n*sbn] (BF16),
 // C FP32 row major (ldc).  A workgroup of four wavefronts owns a 64 x 64 tile of C, each wavefront
-// a 32 x 32 quarter as 2 x 2 MFMA blocks of 16 x 16; K advances 16 at a time.  MFMA operand
-// layout (16x16x16): lane l holds A(i, k) and B(k, j) for i = j = l % 16 and k = 4 (l / 16) + 0..3,
-// and receives C(4 (l / 16) + 0..3, l % 16).
+// a 32 x 32 quarter as 2 x 2 MFMA blocks of 16 x 16; K advances 32 at a time on gfx950's
+// v_mfma_f32_16x16x32_bf16.  Operand layout: lane l holds A(i, k) and B(k, j) for i = j = l % 16
+// and k = 8 (l / 16) + 0..7, and receives C(4 (l / 16) + 0..3, l % 16).
 // AK / BK: the operand is contiguous along k with rows aligned to 4 elements and K % 4 == 0, so a
-// lane's four k values are one 8-byte load (the network's forward products); otherwise four
+// lane's eight k values are two 8-byte loads (the network's forward products); otherwise eight
 // 2-byte loads.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+template <bool CONTIG>
+__device__ __forceinline__ bf16x8 load_k8(const uint16_t* __restrict__ P, int row, int rows, long long srow,
+                                          long long sk, int k, int K) {
+  bf16x4 lo = {0, 0, 0, 0}, hi = {0, 0, 0, 0};
+  if constexpr (CONTIG) {
+    // K % 4 == 0: each half is wholly inside or wholly outside [0, K)
+    if (row < rows && k < K) lo = *reinterpret_cast<const bf16x4*>(P + row * srow + k);
+    if (row < rows && k + 4 < K) hi = *reinterpret_cast<const bf16x4*>(P + row * srow + k + 4);
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      lo[t] = (row < rows && k + t < K) ? (short)P[row * srow + (k + t) * sk] : (short)0;
+      hi[t] = (row < rows && k + 4 + t < K) ? (short)P[row * srow + (k + 4 + t) * sk] : (short)0;
+    }
+  }
+  const short __attribute__((ext_vector_type(8))) v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, v);
+}
 template <bool AK, bool BK>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t* __restrict__ A, long long sam,
                                               long long sak, const uint16_t* __restrict__ B, long long sbk,
                                               long long sbn, float* __restrict__ C, long long ldc) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m0 = blockIdx.y * 64 + (wv >> 1) * 32, n0 = blockIdx.x * 64 + (wv & 1) * 32;
-  const int r16 = lane & 15, kq = (lane >> 4) * 4;
+  const int r16 = lane & 15, k8 = (lane >> 4) * 8, c4 = (lane >> 4) * 4;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4 a[2], b[2];
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    bf16x8 a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int m = m0 + 16 * i + r16;
-      if constexpr (AK) {
-        const int k = k0 + kq;
-        a[i] = (m < M && k < K) ? *reinterpret_cast<const bf16x4*>(A + m * sam + k) : bf16x4{0, 0, 0, 0};
-      } else {
+    for (int i = 0; i < 2; ++i) a[i] = load_k8<AK>(A, m0 + 16 * i + r16, M, sam, sak, k0 + k8, K);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int k = k0 + kq + t;
-          a[i][t] = (m < M && k < K) ? (short)A[m * sam + k * sak] : (short)0;
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = n0 + 16 * j + r16;
-      if constexpr (BK) {
-        const int k = k0 + kq;
-        b[j] = (n < N && k < K) ? *reinterpret_cast<const bf16x4*>(B + n * sbn + k) : bf16x4{0, 0, 0, 0};
-      } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int k = k0 + kq + t;
-          b[j][t] = (n < N && k < K) ? (short)B[k * sbk + n * sbn] : (short)0;
-        }
-      }
-    }
+    for (int j = 0; j < 2; ++j) b[j] = load_k8<BK>(B, n0 + 16 * j + r16, N, sbn, sbk, k0 + k8, K);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -119,7 +114,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int m = m0 + 16 * i + kq + t, n = n0 + 16 * j + r16;
+        const int m = m0 + 16 * i + c4 + t, n = n0 + 16 * j + r16;
         if (m < M && n < N) C[m * ldc + n] = acc[i][j][t];
       }
 }
