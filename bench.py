@@ -44,8 +44,8 @@ FP64_PEAK_TFLOPS = 78.6
 # scaled by the same counters on a plain device copy of known size, per slot-iteration the
 # launches ran; a run's traffic per launch is that times its iterations per launch.  Valid only
 # for the kernel sources they were taken on (hash below), the workload and the slot count named.
-MEASURED_TRAFFIC = {"k_run": {"csrc": "cb4ca52405764b10", "workload": "C2", "slots": 1024,
-                              "bytes_per_iteration": 1.0481e6}}
+MEASURED_TRAFFIC = {"k_run": {"csrc": "4229ab4a956f632a", "workload": "C2", "slots": 1024,
+                              "bytes_per_iteration": 1.0454e6}}
 
 
 # the sources the FP64 asynchronous-slot kernel k_run<false> is built from

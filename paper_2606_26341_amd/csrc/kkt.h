@@ -145,9 +145,11 @@ __device__ __forceinline__ int wor(int v) {
 // compiler cannot hoist them).  lanes_for runs the same trips in groups: the group's loads (ld,
 // which must not store) are all issued first, from a clamped index so that every lane loads a
 // valid word without a branch, then use(i, value) runs for each trip in order.  A group holds up
-// to 4 trips and at most 32 loaded words per lane unless LB0 sets its size (larger groups of
-// one-word trips measured slower).  Results, and the order of every accumulation, are those of
-// the plain loop.
+// to 4 trips and at most 32 loaded words per lane unless LB0 sets its size: the loops over all
+// constraint rows or variables that load one to three words per trip and sit on a slot's critical
+// path (theta sums, trial points, the accept update) use 12, one group for a few hundred entries;
+// a larger default for every loop measured slower (registers).  Results, and the order of every
+// accumulation, are those of the plain loop.
 template <int LB0 = 0, class Ld, class Use>
 __device__ __forceinline__ void lanes_for(int n, int lane, Ld ld, Use use) {
   using V = decltype(ld(0));

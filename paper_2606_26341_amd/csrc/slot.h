@@ -1016,7 +1016,7 @@ __device__ __forceinline__ void pre_body(const Cfg& c, const Slot& s, const doub
       s.rn[r] = -(c.rho_resto - mu / t.v[1] + t.v[2]);
     });
   double thk = 0.0;
-  lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; }, [&](int r, const DV<1>& t) { thk += fabs(t.v[0]); });
+  lanes_for<12>(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; }, [&](int r, const DV<1>& t) { thk += fabs(t.v[0]); });
   thk = wsum(thk);
   double fk = resto ? obj_resto(c, s, s.v, s.p, s.nn, zeta, lane) : wsum(freg);
   double phk = fk - mu * log_barrier(c, s.v, s.p, s.nn, resto, lane);
@@ -1205,7 +1205,7 @@ __device__ __forceinline__ void sol_body(const Cfg& c, const Slot& s, const doub
   dz_recover(c, s, it, mu, s.dv, s.dp, s.dn, lane);
   double amax = ftb_primal(c, s, s.dv, s.dp, s.dn, resto, tau, lane);
   double gphi = 0.0;
-  lanes_for(c.n, lane, [&](int i) { return DV<2>{{s.g[i], s.dv[i]}}; },
+  lanes_for<12>(c.n, lane, [&](int i) { return DV<2>{{s.g[i], s.dv[i]}}; },
             [&](int i, const DV<2>& t) { gphi += t.v[0] * t.v[1]; });
   if (resto)
     lanes_for(c.m, lane, [&](int r) { return DV<4>{{s.p[r], s.dp[r], s.nn[r], s.dn[r]}}; },
@@ -1293,7 +1293,7 @@ __device__ __forceinline__ Trial eval_trial(const Cfg& c, const Slot& s, bool re
     __syncthreads();
   }
   double th = 0.0;
-  lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.ct[r]}}; }, [&](int r, const DV<1>& t) { th += fabs(t.v[0]); });
+  lanes_for<12>(c.m, lane, [&](int r) { return DV<1>{{s.ct[r]}}; }, [&](int r, const DV<1>& t) { th += fabs(t.v[0]); });
   th = wsum(th);
   double f = resto ? obj_resto(c, s, s.vt, s.pt, s.nt, zeta, lane) : wsum(freg);
   double ph = f - mu * log_barrier(c, s.vt, s.pt, s.nt, resto, lane);
@@ -1310,7 +1310,7 @@ __device__ __forceinline__ double make_trial(const Cfg& c, const Slot& s, bool r
                                              const double* dp, const double* dn, int lane) {
   const int nw = c.n_w;
   double f = 0.0;
-  lanes_for(c.n, lane, [&](int i) { return DV<3>{{s.v[i], dv[i], !resto && i < nw ? obj_ref(s, i) : 0.0}}; },
+  lanes_for<12>(c.n, lane, [&](int i) { return DV<3>{{s.v[i], dv[i], !resto && i < nw ? obj_ref(s, i) : 0.0}}; },
             [&](int i, const DV<3>& t) {
               const double vt = t.v[0] + a * t.v[1];
               s.vt[i] = vt;
@@ -1620,7 +1620,7 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
                   tmax = fmax(tmax, fabs(t.v[0]) / (1.0 + fabs(t.v[1])));
                   tmax = fmax(tmax, fabs(t.v[2]) / (1.0 + fabs(t.v[3])));
                 });
-    lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; },
+    lanes_for<12>(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; },
               [&](int r, const DV<1>& t) { cmax = fmax(cmax, fabs(t.v[0])); });
     tmax = wmax(tmax);
     cmax = wmax(cmax);
@@ -1712,7 +1712,7 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
           // second-order correction with the stored factor (Table I row 2)
           double asoc = alpha, th_old = 0.0, tht = t.th;
           bool fin = true;
-          lanes_for(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; },
+          lanes_for<12>(c.m, lane, [&](int r) { return DV<1>{{s.rc[r]}}; },
                     [&](int r, const DV<1>& t) { s.csoc[r] = -t.v[0]; });
           __syncthreads();
           Elim e{false, resto, s.sc[SC_LDX], s.sc[SC_LDC], zeta};
@@ -1720,7 +1720,7 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
             const int lane = opaque(lane0);
             if (p > 0 && !(tht <= c.kappa_soc * th_old)) break;
             th_old = tht;
-            lanes_for(c.m, lane, [&](int r) { return DV<2>{{s.csoc[r], s.ct[r]}}; }, [&](int r, const DV<2>& t) {
+            lanes_for<12>(c.m, lane, [&](int r) { return DV<2>{{s.csoc[r], s.ct[r]}}; }, [&](int r, const DV<2>& t) {
               const double cs = asoc * t.v[0] + t.v[1];
               s.csoc[r] = cs;
               s.ct[r] = -cs;      // right-hand side rows of the constraints
@@ -1818,9 +1818,9 @@ __device__ __forceinline__ void ls_body(const Cfg& c, const Slot& s, double* sol
   }
   if (use_wd && lane == 0 && s.sc[SC_WD_ACTIVE] == 0.0)
     s.sc[SC_WD_SHORT] = shortened ? s.sc[SC_WD_SHORT] + 1.0 : 0.0;
-  lanes_for(c.m, lane, [&](int r) { return DV<2>{{it.y[r], ady[r]}}; },
+  lanes_for<12>(c.m, lane, [&](int r) { return DV<2>{{it.y[r], ady[r]}}; },
             [&](int r, const DV<2>& t) { it.y[r] = t.v[0] + ap * t.v[1]; });
-  lanes_for(c.n, lane, [&](int i) { return DV<1>{{s.vt[i]}}; }, [&](int i, const DV<1>& t) { s.v[i] = t.v[0]; });
+  lanes_for<12>(c.n, lane, [&](int i) { return DV<1>{{s.vt[i]}}; }, [&](int i, const DV<1>& t) { s.v[i] = t.v[0]; });
   if (resto)
     lanes_for(c.m, lane, [&](int r) { return DV<2>{{s.pt[r], s.nt[r]}}; }, [&](int r, const DV<2>& t) {
       s.p[r] = t.v[0];
